@@ -1,0 +1,35 @@
+"""Error measures used by the parity tests (numpy, float64).
+
+Per particle i with reference value a_i and magnitude sum A_i = sum_j |a_ij|:
+  rel_i  = |da_i| / |a_i|           (the relative error the gates name)
+  cond_i = |da_i| / A_i             (error on the scale that rounding sets)
+and over all rows: the RMS and max of rel_i, and the normwise
+||da|| / ||a||.
+"""
+import numpy as np
+
+
+def vec_err(got, ref, absum):
+    got = np.asarray(got, dtype=np.float64).reshape(ref.shape)
+    d = got - ref
+    if ref.ndim == 2:
+        dn = np.linalg.norm(d, axis=1)
+        rn = np.linalg.norm(ref, axis=1)
+    else:
+        dn = np.abs(d)
+        rn = np.abs(ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(rn > 0, dn / rn, np.where(dn > 0, np.inf, 0.0))
+        cond = np.where(absum > 0, dn / absum, np.where(dn > 0, np.inf, 0.0))
+    normwise = float(np.linalg.norm(d) / np.linalg.norm(ref)) if np.linalg.norm(ref) > 0 else float(np.linalg.norm(d))
+    return dict(rms=float(np.sqrt(np.mean(rel ** 2))) if rel.size else 0.0,
+                max=float(rel.max()) if rel.size else 0.0,
+                median=float(np.median(rel)) if rel.size else 0.0,
+                cond_max=float(cond.max()) if cond.size else 0.0,
+                normwise=normwise)
+
+
+def all_errs(acc, jerk, pot, ref):
+    return dict(acc=vec_err(acc, ref["acc"], ref["abs_acc"]),
+                jerk=vec_err(jerk, ref["jerk"], ref["abs_jerk"]),
+                pot=vec_err(pot, ref["pot"], ref["abs_pot"]))
