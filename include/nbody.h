@@ -1,0 +1,222 @@
+/*
+ * nbody.h -- C ABI of the MI355X direct-summation N-body library.
+ *
+ * What the library computes (paper: Portegies Zwart & Bedorf,
+ * "Computational Gravitational Dynamics with Modern Numerical Accelerators",
+ * section "Optimizations for the GPU"): the particles are split into
+ * j-particles, which exert a force, and i-particles, which receive it; the
+ * i-forces are independent sums over the j-set, so they are computed in
+ * parallel, and when the i-set is small the j-set is also split into subsets
+ * whose partial forces are summed by a second kernel.  The forces drive the
+ * 4th-order Hermite predictor-corrector with block time steps that the paper
+ * names for its direct code (sections "Simulating Collisional systems with
+ * direct force evaluation methods" and "Simulating galaxy mergers with
+ * supermassive black holes").  The paper writes none of the formulas; the
+ * library uses G = 1, Plummer softening and the Makino-Aarseth Hermite form:
+ *
+ *   r = x_j - x_i,  u = v_j - v_i,  s = |r|^2 + eps2,
+ *   a_i    =  sum_{j != i} m_j r s^{-3/2}
+ *   jdot_i =  sum_{j != i} m_j [u s^{-3/2} - 3 (r.u) r s^{-5/2}]
+ *   phi_i  = -sum_{j != i} m_j s^{-1/2}
+ *
+ * The self pair is excluded by index.  With eps2 == 0 a pair at s == 0
+ * (coincident distinct particles) contributes nothing.
+ *
+ * Conventions for every entry point
+ *  - Return value: NB_OK (0) or a negative nb_status; nb_last_error(ctx)
+ *    then describes the failure.  Argument errors are detected on the host
+ *    before anything is launched, so no output is written.  No exception or
+ *    abort crosses the ABI.
+ *  - Every array pointer is a DEVICE pointer (e.g. a torch tensor's
+ *    data_ptr() on the context's GPU) owned by the caller; the library keeps
+ *    no reference to it after the call returns.  Arrays of 3-vectors are
+ *    row-major [n][3] doubles (torch shape (n, 3), contiguous).
+ *  - Calls are asynchronous on the context's stream (nb_set_stream); outputs
+ *    are valid once that stream has been synchronised.  A context is used
+ *    by one host thread at a time.
+ *  - Index arrays are int32; an index outside [0, N) is an error only where
+ *    stated (device-resident indices cannot be checked without a copy).
+ *  - The context owns only its launch table, a workspace for j-split
+ *    partial sums (grown on demand with hipMalloc outside any stream capture)
+ *    and a few bytes of device scratch.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+enum nb_status {
+    NB_OK = 0,
+    NB_EINVAL = -1,    /* bad argument (size, null pointer, range, NaN eps2 ...) */
+    NB_ENOMEM = -2,    /* device allocation failed */
+    NB_EDEVICE = -3,   /* HIP runtime error (launch, stream, device) */
+    NB_ENOTSUP = -6    /* combination not supported by this build */
+};
+
+enum nb_precision {
+    NB_PREC_FP64 = 0,  /* every pair in IEEE double */
+    NB_PREC_MIXED = 1  /* r formed in double and rounded to float; the pair
+                          arithmetic in float; per-tile float sums folded
+                          into a double-precision accumulator */
+};
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` (>= 0) computing in `precision`.
+ * Fails with NB_EINVAL for a bad device or precision, NB_EDEVICE when the
+ * device cannot be initialised (no GPU, missing gfx950 code object). */
+int nb_create(nb_ctx **out, int device, int precision);
+int nb_destroy(nb_ctx *ctx);
+/* Stream for all later launches (a hipStream_t; NULL = the null stream). */
+int nb_set_stream(nb_ctx *ctx, void *hip_stream);
+int nb_set_precision(nb_ctx *ctx, int precision);
+int nb_get_precision(const nb_ctx *ctx);
+const char *nb_last_error(const nb_ctx *ctx);
+/* Library version string (static storage). */
+const char *nb_version(void);
+
+/* ---- launch configuration (the j-split of the paper) --------------------
+ * K = i-particles per lane (1, 2, 4); L = lanes sharing one i-particle, each
+ * taking every L-th j of a tile, combined by cross-lane and cross-wave
+ * reduction (1, 2, 4, ..., 256); S = j-subsets, one workgroup each, whose
+ * partial sums a second kernel adds in fixed order (>= 1).  The paper's rule
+ * is that the device is saturated once N_i times the number of j-subsets
+ * exceeds the number of threads.
+ * nb_set_launch forces one configuration for every later force call
+ * (K = 0 returns to automatic choice); nb_get_launch reports the
+ * configuration the context would use for (N, n_active). */
+int nb_set_launch(nb_ctx *ctx, int K, int L, int S);
+int nb_get_launch(nb_ctx *ctx, int64_t N, int64_t n_active, int *K, int *L, int *S);
+/* Install one entry of the automatic table: for this precision, N >= n_min
+ * and n_active in [act_min, act_max], use (K, L, S); S = 0 means "choose S
+ * by the saturation rule".  Later entries take precedence.  Used by the
+ * autotuner front end to load its cache. */
+int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int64_t act_max,
+                int K, int L, int S);
+int nb_tune_clear(nb_ctx *ctx);
+/* Time the force kernel for one configuration on the caller's arrays:
+ * `reps` launches after one warm-up, on the context stream, with HIP
+ * events; returns the mean milliseconds per launch in *ms.  Synchronises
+ * the stream.  This is the measurement primitive of the autotuner. */
+int nb_time_forces(nb_ctx *ctx, int K, int L, int S,
+                   const double *pos, const double *vel, const double *mass, int64_t N,
+                   const int32_t *active_idx, int64_t n_active, double eps2,
+                   double *acc, double *jerk, double *pot, int reps, double *ms);
+
+/* ---- forces --------------------------------------------------------------
+ * nbody_forces: acceleration, jerk and potential of the i-set
+ * active_idx[0..n_active) in the field of all N particles.
+ *   pos, vel  [N][3]  positions and velocities of the j-set (the i-particles
+ *                     use their own rows of the same arrays)
+ *   mass      [N]     masses (zero allowed: such a particle receives forces
+ *                     but exerts none -- the way to express an i-set that is
+ *                     not part of the j-set)
+ *   active_idx[n_active] rows receiving forces; duplicates allowed
+ *   eps2      Plummer softening squared, finite and >= 0
+ *   acc, jerk [n_active][3], pot [n_active]: compact outputs, row k for
+ *             particle active_idx[k]
+ * Errors: NB_EINVAL for N < 1 or N >= 2^31, n_active < 0, negative or
+ * non-finite eps2, a null pointer when n_active > 0.  n_active == 0 does
+ * nothing.  active_idx is device memory and is not range-checked: every
+ * entry must lie in [0, N). */
+int nbody_forces(nb_ctx *ctx, const double *pos, const double *vel, const double *mass, int64_t N,
+                 const int32_t *active_idx, int64_t n_active, double eps2,
+                 double *acc, double *jerk, double *pot);
+
+/* Same, with the active count read from device memory (*n_active_dev) when
+ * the kernels run, so a captured graph can replay it for any count.
+ * max_active bounds *n_active_dev and sizes the launch; the launch
+ * configuration is chosen on the device per call from the count. */
+int nbody_forces_devcount(nb_ctx *ctx, const double *pos, const double *vel, const double *mass,
+                          int64_t N, const int32_t *active_idx, const int32_t *n_active_dev,
+                          int64_t max_active, double eps2, double *acc, double *jerk, double *pot);
+
+/* Batched forces over C independent systems (clusters) stored back to back:
+ * system c owns rows offsets[c] .. offsets[c+1]-1 of pos/vel/mass (host
+ * array offsets[C+1], offsets[0] = 0, non-decreasing) and has softening
+ * eps2[c] (host array).  Its i-set is active_idx[act_offsets[c] ..
+ * act_offsets[c+1]) (device array of GLOBAL row numbers inside system c;
+ * act_offsets is a host array), outputs are compact in the same order.
+ * Pairs across systems never interact.  One launch covers every system:
+ * the work list (system, i-block, j-chunk) is built on the host and the
+ * persistent kernel walks it.  Errors as nbody_forces, plus NB_EINVAL for
+ * decreasing offsets or act_offsets or C < 1. */
+int nbody_forces_batch(nb_ctx *ctx, const int64_t *offsets, int64_t C, const double *eps2,
+                       const double *pos, const double *vel, const double *mass,
+                       const int32_t *active_idx, const int64_t *act_offsets,
+                       double *acc, double *jerk, double *pot);
+
+/* ---- Hermite block steps --------------------------------------------------
+ * Time is kept in int64 ticks of dt_min = dt_max 2^-max_level; particle i
+ * has time t_tick[i] and level dt_level[i] (its step is dt_max 2^-level,
+ * i.e. 2^(max_level - level) ticks).  max_level must be in [0, 62]. */
+
+/* Predict every particle to t_next: d = (t_next_tick - t_tick[i]) dt_min,
+ * pos_p = pos + vel d + acc d^2/2 + jerk d^3/6, vel_p = vel + acc d + jerk d^2/2.
+ * Inputs [N][3] and t_tick [N]; outputs [N][3] (may not alias the inputs). */
+int hermite_predict(nb_ctx *ctx, const double *pos, const double *vel, const double *acc,
+                    const double *jerk, const int64_t *t_tick, int64_t t_next_tick,
+                    double dt_min, int64_t N, double *pos_p, double *vel_p);
+
+/* Correct the active particles after their new forces acc1/jerk1 (compact
+ * [n_active][3], row k for active_idx[k]) were evaluated at the predicted
+ * state pos_p/vel_p ([N][3]).  For each active i with dt = its current step:
+ *   a2 = [-6(a0-a1) - dt(4 j0 + 2 j1)]/dt^2,  a3 = [12(a0-a1) + 6 dt(j0+j1)]/dt^3
+ *   x = x_p + a2 dt^4/24 + a3 dt^5/120,        v = v_p + a2 dt^3/6 + a3 dt^4/24
+ * then acc/jerk <- acc1/jerk1, t_tick += 2^(max_level-level), and the new
+ * level from Aarseth's criterion
+ *   dt* = sqrt(eta (|a1||a2e| + |j1|^2)/(|j1||a3| + |a2e|^2)), a2e = a2 + a3 dt
+ * (dt* = dt_max when the denominator is 0): halve while dt > dt*; else
+ * double once if dt* >= 2 dt, level > 0 and the new time is a multiple of
+ * 2 dt.  Levels beyond max_level are clamped to it and counted in
+ * *clamp_count_dev (device int64, may be NULL; not reset by the call).
+ * pos, vel, acc, jerk [N][3], t_tick, dt_level [N] are updated in place for
+ * the active rows only.  active_idx must not repeat an index. */
+int hermite_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active,
+                    const double *pos_p, const double *vel_p, const double *acc1, const double *jerk1,
+                    double *pos, double *vel, double *acc, double *jerk,
+                    int64_t *t_tick, int32_t *dt_level, double eta, double dt_max, int32_t max_level,
+                    int64_t *clamp_count_dev);
+
+/* Start-up levels at a common time: level = smallest k >= 0 with
+ * dt_max 2^-k <= eta |acc|/|jerk| (0 when jerk = 0), clamped to max_level.
+ * acc, jerk [N][3] -> dt_level [N]. */
+int hermite_startup(nb_ctx *ctx, const double *acc, const double *jerk, int64_t N,
+                    double eta, double dt_max, int32_t max_level, int32_t *dt_level);
+
+/* Block scheduler: t_next = min_i (t_tick[i] + 2^(max_level - dt_level[i]));
+ * active_idx <- every i with t_tick[i] + step == t_next, ascending (a stable
+ * compaction); writes sched[0] = t_next, sched[1] = n_active (device int64
+ * array of at least 2).  active_idx has room for N entries. */
+int nb_schedule(nb_ctx *ctx, const int64_t *t_tick, const int32_t *dt_level, int64_t N,
+                int32_t max_level, int32_t *active_idx, int64_t *sched);
+
+/* One whole block step with no host synchronisation (capturable in a HIP
+ * graph): schedule -> predict all -> forces on the active set (device
+ * count) -> correct.  State arrays as above; work arrays supplied by the
+ * caller: pos_p, vel_p [N][3]; active_idx [N]; acc1, jerk1 [N][3]; pot1 [N];
+ * sched (device int64 [4]): after the call sched[0] = t_next,
+ * sched[1] = n_active, sched[2] += 1 (steps), sched[3] += clamps. */
+int nb_block_step(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
+                  const double *mass, double *pos, double *vel, double *acc, double *jerk,
+                  int64_t *t_tick, int32_t *dt_level,
+                  double *pos_p, double *vel_p, int32_t *active_idx,
+                  double *acc1, double *jerk1, double *pot1, int64_t *sched);
+
+/* Energy and momenta of a synchronised system, summed in double in a fixed
+ * order: out (device double [8]) = K, W, Px, Py, Pz, Lx, Ly, Lz with
+ * K = sum m v^2/2, W = sum m phi / 2 (phi from a force call over all
+ * particles), P = sum m v, L = sum m x cross v. */
+int nb_energy(nb_ctx *ctx, const double *pos, const double *vel, const double *mass,
+              const double *pot, int64_t N, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

@@ -1,0 +1,282 @@
+"""Python binding of the MI355X direct-summation N-body library.
+
+A thin ctypes layer over ``libnbody.so`` (the C ABI in ``include/nbody.h``):
+argument marshalling only -- every step of the computation runs in the HIP
+kernels.  PyTorch provides device memory and streams; arrays are torch
+tensors on the context's GPU (float64 (n,3) / (n,) contiguous, int32 index
+arrays, int64 tick arrays).
+
+If the shared library has not been built this module raises ImportError:
+there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import torch
+
+__all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "lib_path", "library",
+           "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
+           "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy"]
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+_PREC_NAMES = {"fp64": PREC_FP64, "f64": PREC_FP64, "mixed": PREC_MIXED}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(_HERE, "libnbody.so")
+
+if not os.path.exists(lib_path):
+    raise ImportError(f"{lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+
+_lib = ctypes.CDLL(lib_path)
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_dbl = ctypes.c_double
+_int = ctypes.c_int
+
+
+def _sig(name, *args):
+    f = getattr(_lib, name)
+    f.restype = _int
+    f.argtypes = list(args)
+    return f
+
+
+_lib.nb_version.restype = ctypes.c_char_p
+_lib.nb_version.argtypes = []
+_lib.nb_last_error.restype = ctypes.c_char_p
+_lib.nb_last_error.argtypes = [_vp]
+_sig("nb_create", ctypes.POINTER(_vp), _int, _int)
+_sig("nb_destroy", _vp)
+_sig("nb_set_stream", _vp, _vp)
+_sig("nb_set_precision", _vp, _int)
+_lib.nb_get_precision.restype = _int
+_lib.nb_get_precision.argtypes = [_vp]
+_sig("nb_set_launch", _vp, _int, _int, _int)
+_sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int))
+_sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int)
+_sig("nb_tune_clear", _vp)
+_sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
+     ctypes.POINTER(_dbl))
+_sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("nbody_forces_devcount", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
+_sig("hermite_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp)
+_sig("hermite_startup", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
+_sig("nb_schedule", _vp, _vp, _vp, _i64, _i32, _vp, _vp)
+_sig("nb_block_step", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+     _vp, _vp, _vp, _vp)
+_sig("nb_energy", _vp, _vp, _vp, _vp, _vp, _i64, _vp)
+if hasattr(_lib, "nbody_forces_batch"):
+    _sig("nbody_forces_batch", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+
+
+def library():
+    """The loaded ctypes library (for tests that check the exported symbols)."""
+    return _lib
+
+
+class NbodyError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nbody error {code}: {msg}")
+        self.code = code
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_vec(t, n, name, dev):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != dev:
+        raise TypeError(f"{name}: float64 tensor on {dev} required")
+    if t.shape != (n, 3) or not t.is_contiguous():
+        raise ValueError(f"{name}: contiguous ({n}, 3) required, got {tuple(t.shape)}")
+
+
+def _check_1d(t, n, name, dtype, dev):
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.device != dev:
+        raise TypeError(f"{name}: {dtype} tensor on {dev} required")
+    if t.shape != (n,) or not t.is_contiguous():
+        raise ValueError(f"{name}: contiguous ({n},) required, got {tuple(t.shape)}")
+
+
+class Context:
+    """One library context on one GPU (``nb_create``)."""
+
+    def __init__(self, device=0, precision="fp64", stream=None):
+        prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        h = ctypes.c_void_p()
+        rc = _lib.nb_create(ctypes.byref(h), int(device), prec)
+        if rc != 0:
+            raise NbodyError(rc, "nb_create failed (no usable gfx950 device?)")
+        self._h = h
+        self.device = torch.device("cuda", int(device))
+        self.set_stream(stream)
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise NbodyError(rc, _lib.nb_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.nb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_stream(self, stream=None):
+        """Launch on ``stream`` (a torch.cuda.Stream), default torch's current stream."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._stream = s
+        self._chk(_lib.nb_set_stream(self._h, ctypes.c_void_p(s.cuda_stream)))
+
+    @property
+    def precision(self):
+        return _lib.nb_get_precision(self._h)
+
+    def set_precision(self, precision):
+        prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        self._chk(_lib.nb_set_precision(self._h, prec))
+
+    def set_launch(self, K=0, L=1, S=0):
+        self._chk(_lib.nb_set_launch(self._h, int(K), int(L), int(S)))
+
+    def get_launch(self, N, n_active):
+        K, L, S = _int(), _int(), _int()
+        self._chk(_lib.nb_get_launch(self._h, int(N), int(n_active), ctypes.byref(K), ctypes.byref(L),
+                                     ctypes.byref(S)))
+        return K.value, L.value, S.value
+
+    def tune_add(self, precision, n_min, act_min, act_max, K, L, S=0):
+        prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        self._chk(_lib.nb_tune_add(self._h, prec, int(n_min), int(act_min), int(act_max), int(K), int(L), int(S)))
+
+    def tune_clear(self):
+        self._chk(_lib.nb_tune_clear(self._h))
+
+    # ---- forces -------------------------------------------------------------
+    def forces(self, pos, vel, mass, active, eps2, acc=None, jerk=None, pot=None):
+        n = mass.shape[0]
+        na = active.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        _check_vec(vel, n, "vel", self.device)
+        _check_1d(mass, n, "mass", torch.float64, self.device)
+        _check_1d(active, na, "active_idx", torch.int32, self.device)
+        if acc is None:
+            acc = torch.empty((na, 3), dtype=torch.float64, device=self.device)
+        if jerk is None:
+            jerk = torch.empty((na, 3), dtype=torch.float64, device=self.device)
+        if pot is None:
+            pot = torch.empty((na,), dtype=torch.float64, device=self.device)
+        _check_vec(acc, na, "acc", self.device)
+        _check_vec(jerk, na, "jerk", self.device)
+        _check_1d(pot, na, "pot", torch.float64, self.device)
+        self._chk(_lib.nbody_forces(self._h, _p(pos), _p(vel), _p(mass), n, _p(active), na, float(eps2),
+                                    _p(acc), _p(jerk), _p(pot)))
+        return acc, jerk, pot
+
+    def forces_devcount(self, pos, vel, mass, active, n_active_dev, max_active, eps2, acc, jerk, pot):
+        n = mass.shape[0]
+        _check_1d(n_active_dev, 1, "n_active_dev", torch.int32, self.device)
+        self._chk(_lib.nbody_forces_devcount(self._h, _p(pos), _p(vel), _p(mass), n, _p(active), _p(n_active_dev),
+                                             int(max_active), float(eps2), _p(acc), _p(jerk), _p(pot)))
+        return acc, jerk, pot
+
+    def time_forces(self, K, L, S, pos, vel, mass, active, eps2, acc, jerk, pot, reps=5):
+        ms = _dbl()
+        self._chk(_lib.nb_time_forces(self._h, int(K), int(L), int(S), _p(pos), _p(vel), _p(mass),
+                                      mass.shape[0], _p(active), active.shape[0], float(eps2), _p(acc), _p(jerk),
+                                      _p(pot), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def forces_batch(self, offsets, eps2, pos, vel, mass, active, act_offsets, acc, jerk, pot):
+        """offsets, act_offsets: host int64 sequences of length C+1; eps2: host floats of length C."""
+        import numpy as np
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        aoff = np.ascontiguousarray(act_offsets, dtype=np.int64)
+        e2 = np.ascontiguousarray(eps2, dtype=np.float64)
+        C = off.shape[0] - 1
+        self._chk(_lib.nbody_forces_batch(self._h, off.ctypes.data_as(_vp), C, e2.ctypes.data_as(_vp), _p(pos),
+                                          _p(vel), _p(mass), _p(active), aoff.ctypes.data_as(_vp), _p(acc),
+                                          _p(jerk), _p(pot)))
+        return acc, jerk, pot
+
+    # ---- Hermite --------------------------------------------------------------
+    def predict(self, pos, vel, acc, jerk, t_tick, t_next_tick, dt_min, pos_p, vel_p):
+        n = pos.shape[0]
+        self._chk(_lib.hermite_predict(self._h, _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), int(t_next_tick),
+                                       float(dt_min), n, _p(pos_p), _p(vel_p)))
+
+    def correct(self, active, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max,
+                max_level, clamp_dev=None):
+        self._chk(_lib.hermite_correct(self._h, _p(active), active.shape[0], _p(pos_p), _p(vel_p), _p(acc1),
+                                       _p(jerk1), _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), _p(dt_level),
+                                       float(eta), float(dt_max), int(max_level), _p(clamp_dev)))
+
+    def startup(self, acc, jerk, eta, dt_max, max_level, dt_level):
+        self._chk(_lib.hermite_startup(self._h, _p(acc), _p(jerk), acc.shape[0], float(eta), float(dt_max),
+                                       int(max_level), _p(dt_level)))
+
+    def schedule(self, t_tick, dt_level, max_level, active, sched):
+        self._chk(_lib.nb_schedule(self._h, _p(t_tick), _p(dt_level), t_tick.shape[0], int(max_level), _p(active),
+                                   _p(sched)))
+
+    def block_step(self, N, eps2, eta, dt_max, max_level, mass, pos, vel, acc, jerk, t_tick, dt_level, pos_p, vel_p,
+                   active, acc1, jerk1, pot1, sched):
+        self._chk(_lib.nb_block_step(self._h, int(N), float(eps2), float(eta), float(dt_max), int(max_level),
+                                     _p(mass), _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), _p(dt_level),
+                                     _p(pos_p), _p(vel_p), _p(active), _p(acc1), _p(jerk1), _p(pot1), _p(sched)))
+
+    def energy(self, pos, vel, mass, pot, out):
+        self._chk(_lib.nb_energy(self._h, _p(pos), _p(vel), _p(mass), _p(pot), mass.shape[0], _p(out)))
+        return out
+
+
+# Function-style aliases with the C names (the context is the first argument).
+def nbody_forces(ctx, pos, vel, mass, active_idx, eps2, acc=None, jerk=None, pot=None):
+    return ctx.forces(pos, vel, mass, active_idx, eps2, acc, jerk, pot)
+
+
+def nbody_forces_devcount(ctx, *a, **k):
+    return ctx.forces_devcount(*a, **k)
+
+
+def nbody_forces_batch(ctx, *a, **k):
+    return ctx.forces_batch(*a, **k)
+
+
+def hermite_predict(ctx, *a, **k):
+    return ctx.predict(*a, **k)
+
+
+def hermite_correct(ctx, *a, **k):
+    return ctx.correct(*a, **k)
+
+
+def hermite_startup(ctx, *a, **k):
+    return ctx.startup(*a, **k)
+
+
+def nb_schedule(ctx, *a, **k):
+    return ctx.schedule(*a, **k)
+
+
+def nb_block_step(ctx, *a, **k):
+    return ctx.block_step(*a, **k)
+
+
+def nb_energy(ctx, *a, **k):
+    return ctx.energy(*a, **k)
+
+
+def version():
+    return _lib.nb_version().decode()

@@ -1,0 +1,597 @@
+// C ABI of the library: argument checking, launch-configuration choice,
+// workspace management and the composite block step.  See include/nbody.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <new>
+
+#include "nb_internal.h"
+
+using nb::Launch;
+
+namespace {
+
+constexpr const char* kVersion = "nbody-mi355x 0.1 (gfx950)";
+
+int fail(nb_ctx* c, int code, const char* fmt, const char* detail = nullptr) {
+  if (c) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, fmt, detail ? detail : "");
+    c->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(nb_ctx* c, hipError_t e, const char* where) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
+  if (c) c->err = buf;
+  return NB_EDEVICE;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+  return st != hipStreamCaptureStatusNone;
+}
+
+// Grow the context workspace to at least `bytes` (never inside a capture).
+int ensure_ws(nb_ctx* c, size_t bytes) {
+  if (bytes <= c->ws_bytes) return NB_OK;
+  if (capturing(c->stream))
+    return fail(c, NB_ENOMEM, "workspace must grow but the stream is being captured; run the call once before capture%s");
+  if (c->ws) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(c->ws);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+  }
+  size_t b = bytes + bytes / 4;
+  if (hipMalloc(&c->ws, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NB_ENOMEM, "hipMalloc of the j-split workspace failed%s");
+  }
+  c->ws_bytes = b;
+  return NB_OK;
+}
+
+int ensure_sched(nb_ctx* c, int64_t n) {
+  const int nblk = nb::schedule_blocks(n);
+  const size_t need = (size_t)nblk;
+  if (need <= c->sched_cap && c->nact32) return NB_OK;
+  if (capturing(c->stream)) return fail(c, NB_ENOMEM, "scheduler scratch must grow during capture%s");
+  (void)hipStreamSynchronize(c->stream);
+  if (c->sched_tmp) (void)hipFree(c->sched_tmp);
+  if (c->sched_cnt) (void)hipFree(c->sched_cnt);
+  if (c->nact32) (void)hipFree(c->nact32);
+  c->sched_tmp = nullptr; c->sched_cnt = nullptr; c->nact32 = nullptr; c->sched_cap = 0;
+  if (hipMalloc(&c->sched_tmp, need * sizeof(int64_t)) != hipSuccess ||
+      hipMalloc(&c->sched_cnt, need * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&c->nact32, sizeof(int32_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NB_ENOMEM, "hipMalloc of scheduler scratch failed%s");
+  }
+  c->sched_cap = need;
+  return NB_OK;
+}
+
+int ensure_energy(nb_ctx* c, int64_t n) {
+  const size_t need = (size_t)nb::energy_blocks(n) * 8;
+  if (need <= c->energy_cap) return NB_OK;
+  if (capturing(c->stream)) return fail(c, NB_ENOMEM, "energy scratch must grow during capture%s");
+  (void)hipStreamSynchronize(c->stream);
+  if (c->energy_part) (void)hipFree(c->energy_part);
+  c->energy_part = nullptr; c->energy_cap = 0;
+  if (hipMalloc(&c->energy_part, need * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NB_ENOMEM, "hipMalloc of energy scratch failed%s");
+  }
+  c->energy_cap = need;
+  return NB_OK;
+}
+
+bool valid_K(int K) { return K == 1 || K == 2 || K == 4; }
+bool valid_L(int L) { return L >= 1 && L <= 256 && (L & (L - 1)) == 0; }
+
+int target_items(const nb_ctx* c) { return c->num_cus * 4; }
+
+// Built-in choice before any tuning: the i-parallel layout when the active
+// set alone fills the chip, more lanes per i-particle as it shrinks.
+Launch default_launch(int prec, int64_t n_act) {
+  (void)prec;
+  if (n_act >= 65536) return Launch{2, 1, 0};
+  if (n_act >= 8192) return Launch{1, 1, 0};
+  if (n_act >= 1024) return Launch{1, 4, 0};
+  if (n_act >= 128) return Launch{1, 16, 0};
+  return Launch{1, 64, 0};
+}
+
+Launch choose(const nb_ctx* c, int64_t n, int64_t n_act) {
+  Launch cfg;
+  bool found = false;
+  if (c->have_forced) {
+    cfg = c->forced;
+    found = true;
+  } else {
+    for (auto it = c->table.rbegin(); it != c->table.rend(); ++it) {
+      if (it->prec == c->prec && n >= it->n_min && n_act >= it->act_min && n_act <= it->act_max) {
+        cfg = it->cfg;
+        found = true;
+        break;
+      }
+    }
+  }
+  if (!found) cfg = default_launch(c->prec, n_act);
+  if (cfg.S <= 0) {
+    const int IB = (nb::kWG / cfg.L) * cfg.K;
+    cfg.S = nb::host_choose_S(n_act, IB, target_items(c), n);
+  }
+  const int64_t max_s = (n + nb::kTile - 1) / nb::kTile;
+  if (cfg.S > max_s) cfg.S = (int)max_s;
+  return cfg;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+bool kernel_mask(int prec, double eps2) {
+  return prec == NB_PREC_FP64 ? eps2 == 0.0 : (float)eps2 == 0.0f;
+}
+
+int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* vel, const double* mass, int64_t N,
+               const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot) {
+  nb::ForceArgs a{};
+  a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
+  a.active = active; a.n_active = n_active; a.n_active_dev = nullptr;
+  a.eps2 = eps2; a.S = cfg.S; a.target_items = target_items(c);
+  a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr;
+  const bool mask = kernel_mask(c->prec, eps2);
+  Launch eff = cfg;
+  if (mask) eff.K = 1;
+  if (cfg.S > 1) {
+    const size_t bytes = (size_t)cfg.S * 7 * (size_t)n_active * sizeof(double);
+    int rc = ensure_ws(c, bytes);
+    if (rc) return rc;
+    a.part = static_cast<double*>(c->ws);
+  }
+  hipError_t e = nb::launch_forces(c->prec, eff, mask, a, c->stream, 0);
+  if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
+  if (cfg.S > 1) {
+    const int IB = (nb::kWG / eff.L) * eff.K;
+    e = nb::launch_reduce_ib(c->prec, a, cfg.S, IB, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
+  }
+  return NB_OK;
+}
+
+int check_forces_args(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                      const void* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (n_active < 0) return fail(c, NB_EINVAL, "n_active must be >= 0%s");
+  if (!finite_nonneg(eps2)) return fail(c, NB_EINVAL, "eps2 must be finite and >= 0%s");
+  if (n_active > 0 && (!pos || !vel || !mass || !active || !acc || !jerk || !pot))
+    return fail(c, NB_EINVAL, "null pointer argument%s");
+  return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nb_version(void) { return kVersion; }
+
+int nb_create(nb_ctx** out, int device, int precision) {
+  if (!out) return NB_EINVAL;
+  *out = nullptr;
+  if (precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) return NB_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return NB_EDEVICE;
+  }
+  if (device < 0 || device >= ndev) return NB_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return NB_EDEVICE;
+  nb_ctx* c = new (std::nothrow) nb_ctx();
+  if (!c) return NB_ENOMEM;
+  c->device = device;
+  c->prec = precision;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) == hipSuccess && p.multiProcessorCount > 0) c->num_cus = p.multiProcessorCount;
+  *out = c;
+  return NB_OK;
+}
+
+int nb_destroy(nb_ctx* c) {
+  if (!c) return NB_OK;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->ws) (void)hipFree(c->ws);
+  if (c->sched_tmp) (void)hipFree(c->sched_tmp);
+  if (c->sched_cnt) (void)hipFree(c->sched_cnt);
+  if (c->nact32) (void)hipFree(c->nact32);
+  if (c->energy_part) (void)hipFree(c->energy_part);
+  if (c->batch_buf) (void)hipFree(c->batch_buf);
+  if (c->batch_host) (void)hipHostFree(c->batch_host);
+  if (c->batch_ev) (void)hipEventDestroy(c->batch_ev);
+  delete c;
+  return NB_OK;
+}
+
+int nb_set_stream(nb_ctx* c, void* s) {
+  if (!c) return NB_EINVAL;
+  c->stream = static_cast<hipStream_t>(s);
+  return NB_OK;
+}
+
+int nb_set_precision(nb_ctx* c, int precision) {
+  if (!c) return NB_EINVAL;
+  if (precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) return fail(c, NB_EINVAL, "unknown precision%s");
+  c->prec = precision;
+  return NB_OK;
+}
+
+int nb_get_precision(const nb_ctx* c) { return c ? c->prec : NB_EINVAL; }
+
+const char* nb_last_error(const nb_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int nb_set_launch(nb_ctx* c, int K, int L, int S) {
+  if (!c) return NB_EINVAL;
+  if (K == 0) {
+    c->have_forced = false;
+    return NB_OK;
+  }
+  if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
+  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
+  c->forced = Launch{K, L, S};
+  c->have_forced = true;
+  return NB_OK;
+}
+
+int nb_get_launch(nb_ctx* c, int64_t N, int64_t n_active, int* K, int* L, int* S) {
+  if (!c || !K || !L || !S || N < 1 || n_active < 0) return NB_EINVAL;
+  const Launch cfg = choose(c, N, n_active < 1 ? 1 : n_active);
+  *K = cfg.K; *L = cfg.L; *S = cfg.S;
+  return NB_OK;
+}
+
+int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_t act_max, int K, int L, int S) {
+  if (!c) return NB_EINVAL;
+  if ((precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) || !valid_K(K) || !valid_L(L) || S < 0 ||
+      act_min > act_max)
+    return fail(c, NB_EINVAL, "bad tune entry%s");
+  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
+  c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, Launch{K, L, S}});
+  return NB_OK;
+}
+
+int nb_tune_clear(nb_ctx* c) {
+  if (!c) return NB_EINVAL;
+  c->table.clear();
+  return NB_OK;
+}
+
+int nbody_forces(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                 const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot) {
+  int rc = check_forces_args(c, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (n_active == 0) return NB_OK;
+  const Launch cfg = choose(c, N, n_active);
+  return run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+}
+
+int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const double* vel, const double* mass,
+                   int64_t N, const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk,
+                   double* pot, int reps, double* ms) {
+  int rc = check_forces_args(c, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (!ms || reps < 1 || n_active < 1) return fail(c, NB_EINVAL, "reps >= 1, n_active >= 1 and ms required%s");
+  if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
+  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
+  Launch cfg{K, L, S};
+  if (cfg.S == 0) cfg.S = nb::host_choose_S(n_active, (nb::kWG / L) * K, target_items(c), N);
+  const int64_t max_s = (N + nb::kTile - 1) / nb::kTile;
+  if (cfg.S > max_s) cfg.S = (int)max_s;
+  rc = run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return hip_fail(c, hipGetLastError(), "hipEventCreate");
+  (void)hipEventRecord(e0, c->stream);
+  for (int r = 0; r < reps && rc == NB_OK; ++r)
+    rc = run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  (void)hipEventRecord(e1, c->stream);
+  hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (e != hipSuccess) return hip_fail(c, e, "timing");
+  *ms = (double)t / reps;
+  return NB_OK;
+}
+
+// Device-count variant: the active count lives in device memory, so the
+// launch configuration is fixed per regime of the count and each regime's
+// kernels return at once when the count is outside it.  Every regime's
+// workspace need is bounded on the host from max_active.
+int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                          const int32_t* active, const int32_t* n_active_dev, int64_t max_active, double eps2,
+                          double* acc, double* jerk, double* pot) {
+  int rc = check_forces_args(c, pos, vel, mass, N, active, max_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (!n_active_dev) return fail(c, NB_EINVAL, "n_active_dev is null%s");
+  if (max_active == 0) return NB_OK;
+  const bool mask = kernel_mask(c->prec, eps2);
+  // One fixed launch per regime; the count decides on the device which one works.
+  struct Regime {
+    int64_t lo, hi;
+  };
+  const Regime regimes[5] = {{0, 127}, {128, 1023}, {1024, 8191}, {8192, 65535}, {65536, INT64_MAX}};
+  size_t ws_need = 0;
+  for (const Regime& r : regimes) {
+    if (r.lo > max_active) break;
+    const int64_t top = r.hi < max_active ? r.hi : max_active;
+    Launch cfg = choose(c, N, top);
+    if (mask) cfg.K = 1;
+    const int IB = (nb::kWG / cfg.L) * cfg.K;
+    const int64_t n_iblk_max = (top + IB - 1) / IB;
+    const size_t rows = (size_t)(target_items(c) + n_iblk_max) * IB;
+    const size_t need = rows * 7 * sizeof(double);
+    if (need > ws_need) ws_need = need;
+  }
+  rc = ensure_ws(c, ws_need);
+  if (rc) return rc;
+  for (const Regime& r : regimes) {
+    if (r.lo > max_active) break;
+    const int64_t top = r.hi < max_active ? r.hi : max_active;
+    Launch cfg = choose(c, N, top);
+    if (mask) cfg.K = 1;
+    nb::ForceArgs a{};
+    a.last = 0;
+    a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
+    a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
+    a.act_lo = r.lo;
+    a.last = (top == max_active) ? 1 : 0;
+    a.eps2 = eps2; a.S = 1; a.target_items = target_items(c);
+    a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = nullptr;
+    const int IB = (nb::kWG / cfg.L) * cfg.K;
+    const int64_t n_iblk_max = (top + IB - 1) / IB;
+    int64_t grid = target_items(c) + n_iblk_max;
+    if (grid > 8 * c->num_cus * 4) grid = 8 * c->num_cus * 4;
+    hipError_t e = nb::launch_forces(c->prec, cfg, mask, a, c->stream, (int)grid);
+    if (e != hipSuccess) return hip_fail(c, e, "force kernel launch (device count)");
+    e = nb::launch_reduce_ib(c->prec, a, 1, IB, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch (device count)");
+  }
+  return NB_OK;
+}
+
+int hermite_predict(nb_ctx* c, const double* pos, const double* vel, const double* acc, const double* jerk,
+                    const int64_t* t_tick, int64_t t_next_tick, double dt_min, int64_t N, double* pos_p,
+                    double* vel_p) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (!pos || !vel || !acc || !jerk || !t_tick || !pos_p || !vel_p) return fail(c, NB_EINVAL, "null pointer%s");
+  if (!(dt_min > 0.0) || !std::isfinite(dt_min)) return fail(c, NB_EINVAL, "dt_min must be finite and > 0%s");
+  hipError_t e = nb::launch_predict(pos, vel, acc, jerk, t_tick, t_next_tick, nullptr, dt_min, N, pos_p, vel_p,
+                                    c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "predict launch");
+}
+
+static int check_levels(nb_ctx* c, double eta, double dt_max, int32_t max_level) {
+  if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be finite and > 0%s");
+  if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(c, NB_EINVAL, "dt_max must be finite and > 0%s");
+  if (max_level < 0 || max_level > 62) return fail(c, NB_EINVAL, "max_level must be in [0, 62]%s");
+  return NB_OK;
+}
+
+int hermite_correct(nb_ctx* c, const int32_t* active, int64_t n_active, const double* pos_p, const double* vel_p,
+                    const double* acc1, const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
+                    int64_t* t_tick, int32_t* dt_level, double eta, double dt_max, int32_t max_level,
+                    int64_t* clamp_count_dev) {
+  if (!c) return NB_EINVAL;
+  if (n_active < 0 || n_active >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "bad n_active%s");
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (n_active == 0) return NB_OK;
+  if (!active || !pos_p || !vel_p || !acc1 || !jerk1 || !pos || !vel || !acc || !jerk || !t_tick || !dt_level)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_correct(active, n_active, nullptr, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
+                                    t_tick, dt_level, eta, dt_max, max_level, clamp_count_dev, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
+}
+
+int hermite_startup(nb_ctx* c, const double* acc, const double* jerk, int64_t N, double eta, double dt_max,
+                    int32_t max_level, int32_t* dt_level) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (!acc || !jerk || !dt_level) return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_startup(acc, jerk, N, eta, dt_max, max_level, dt_level, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "startup launch");
+}
+
+int nb_schedule(nb_ctx* c, const int64_t* t_tick, const int32_t* dt_level, int64_t N, int32_t max_level,
+                int32_t* active, int64_t* sched) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (max_level < 0 || max_level > 62) return fail(c, NB_EINVAL, "max_level must be in [0, 62]%s");
+  if (!t_tick || !dt_level || !active || !sched) return fail(c, NB_EINVAL, "null pointer%s");
+  int rc = ensure_sched(c, N);
+  if (rc) return rc;
+  hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
+                                     c->nact32, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "schedule launch");
+}
+
+int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
+                  const double* mass, double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick,
+                  int32_t* dt_level, double* pos_p, double* vel_p, int32_t* active, double* acc1, double* jerk1,
+                  double* pot1, int64_t* sched) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (!finite_nonneg(eps2)) return fail(c, NB_EINVAL, "eps2 must be finite and >= 0%s");
+  if (!mass || !pos || !vel || !acc || !jerk || !t_tick || !dt_level || !pos_p || !vel_p || !active || !acc1 ||
+      !jerk1 || !pot1 || !sched)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  rc = ensure_sched(c, N);
+  if (rc) return rc;
+  const double dt_min = std::ldexp(dt_max, -max_level);
+  hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
+                                     c->nact32, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
+  e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "predict launch");
+  rc = nbody_forces_devcount(c, pos_p, vel_p, mass, N, active, c->nact32, N, eps2, acc1, jerk1, pot1);
+  if (rc) return rc;
+  e = nb::launch_correct_step(active, N, sched + 1, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level,
+                              eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
+}
+
+
+// Batched forces: the work list (system, i-block, j-chunk) is built on the
+// host, largest items first, staged through pinned memory and walked by one
+// launch.  Each system's j-range is cut into chunks of about the same
+// length J, chosen so the whole batch yields ~2 work items per CU slot.
+int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const double* eps2, const double* pos,
+                       const double* vel, const double* mass, const int32_t* active, const int64_t* act_offsets,
+                       double* acc, double* jerk, double* pot) {
+  if (!c) return NB_EINVAL;
+  if (C < 1 || C > (1 << 24) || !offsets || !eps2 || !act_offsets)
+    return fail(c, NB_EINVAL, "C >= 1 and host offsets/eps2/act_offsets required%s");
+  if (offsets[0] != 0 || act_offsets[0] != 0) return fail(c, NB_EINVAL, "offsets must start at 0%s");
+  int64_t n_total = offsets[C], a_total = act_offsets[C];
+  if (n_total < 1 || n_total >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "total rows must be in [1, 2^31)%s");
+  bool any_mask = false;
+  int64_t max_act = 0;
+  for (int64_t s = 0; s < C; ++s) {
+    if (offsets[s + 1] < offsets[s] || act_offsets[s + 1] < act_offsets[s])
+      return fail(c, NB_EINVAL, "offsets and act_offsets must be non-decreasing%s");
+    if (!finite_nonneg(eps2[s])) return fail(c, NB_EINVAL, "every eps2 must be finite and >= 0%s");
+    if (act_offsets[s + 1] > act_offsets[s] && offsets[s + 1] == offsets[s])
+      return fail(c, NB_EINVAL, "a system with active rows has no particles%s");
+    any_mask = any_mask || kernel_mask(c->prec, eps2[s]);
+    const int64_t na = act_offsets[s + 1] - act_offsets[s];
+    if (na > max_act) max_act = na;
+  }
+  if (a_total == 0) return NB_OK;
+  if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
+  // One kernel shape for the batch, from the typical active-set size.
+  Launch cfg = choose(c, n_total, (a_total + C - 1) / C);
+  if (any_mask) cfg.K = 1;
+  if (!nb::launch_supported(cfg) || (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64) ||
+      (cfg.K == 4) || (cfg.K == 2 && cfg.L == 64)) {
+    cfg.K = 1;
+    cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
+  }
+  const int IB = (nb::kWG / cfg.L) * cfg.K;
+  // total work in (i-slot x j) units and the chunk length that splits it
+  double work = 0.0;
+  for (int64_t s = 0; s < C; ++s) {
+    const int64_t na = act_offsets[s + 1] - act_offsets[s];
+    work += (double)((na + IB - 1) / IB) * IB * (double)(offsets[s + 1] - offsets[s]);
+  }
+  double jt = work / ((double)IB * 2.0 * target_items(c));
+  int64_t J = (int64_t)std::ceil(jt / nb::kTile) * nb::kTile;
+  if (J < nb::kTile) J = nb::kTile;
+  std::vector<nb::BatchSys> sys((size_t)C);
+  std::vector<int32_t> nch((size_t)C);
+  std::vector<nb::BatchItem> items;
+  int64_t part_rows = 0;
+  for (int64_t s = 0; s < C; ++s) {
+    const int64_t nj = offsets[s + 1] - offsets[s];
+    const int64_t na = act_offsets[s + 1] - act_offsets[s];
+    int64_t S = (nj + J - 1) / J;
+    const int64_t max_s = (nj + nb::kTile - 1) / nb::kTile;
+    if (S > max_s) S = max_s;
+    if (S < 1) S = 1;
+    nch[s] = (int32_t)S;
+    sys[s] = nb::BatchSys{offsets[s], offsets[s + 1], act_offsets[s], act_offsets[s + 1], eps2[s],
+                          S > 1 ? part_rows : 0};
+    if (S > 1) part_rows += S * na;
+    const int64_t nib = (na + IB - 1) / IB;
+    for (int64_t ch = 0; ch < S; ++ch)
+      for (int64_t b = 0; b < nib; ++b) items.push_back(nb::BatchItem{(int32_t)s, (int32_t)b, (int32_t)ch, (int32_t)S});
+  }
+  // largest items first (cost ~ chunk length)
+  std::stable_sort(items.begin(), items.end(), [&](const nb::BatchItem& x, const nb::BatchItem& y) {
+    const int64_t lx = (sys[x.sys].j1 - sys[x.sys].j0 + x.nchunk - 1) / x.nchunk;
+    const int64_t ly = (sys[y.sys].j1 - sys[y.sys].j0 + y.nchunk - 1) / y.nchunk;
+    return lx > ly;
+  });
+  if (items.size() > (size_t)INT32_MAX) return fail(c, NB_EINVAL, "work list too long%s");
+  const size_t b_items = items.size() * sizeof(nb::BatchItem);
+  const size_t b_sys = sys.size() * sizeof(nb::BatchSys);
+  const size_t b_nch = nch.size() * sizeof(int32_t);
+  const size_t off_sys = (b_items + 255) / 256 * 256;
+  const size_t off_nch = off_sys + (b_sys + 255) / 256 * 256;
+  const size_t total = off_nch + b_nch;
+  if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "nbody_forces_batch stages its work list with a copy; it cannot be captured%s");
+  if (total > c->batch_cap) {
+    (void)hipStreamSynchronize(c->stream);
+    if (c->batch_buf) (void)hipFree(c->batch_buf);
+    c->batch_buf = nullptr;
+    c->batch_cap = 0;
+    if (hipMalloc(&c->batch_buf, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, NB_ENOMEM, "hipMalloc of the batch work list failed%s");
+    }
+    c->batch_cap = total;
+  }
+  if (!c->batch_ev && hipEventCreateWithFlags(&c->batch_ev, hipEventDisableTiming) != hipSuccess)
+    return hip_fail(c, hipGetLastError(), "hipEventCreate");
+  if (hipEventSynchronize(c->batch_ev) != hipSuccess) return hip_fail(c, hipGetLastError(), "batch staging wait");
+  if (total > c->batch_host_cap) {
+    if (c->batch_host) (void)hipHostFree(c->batch_host);
+    c->batch_host = nullptr;
+    c->batch_host_cap = 0;
+    if (hipHostMalloc(&c->batch_host, total, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, NB_ENOMEM, "hipHostMalloc of the batch staging buffer failed%s");
+    }
+    c->batch_host_cap = total;
+  }
+  char* hb = static_cast<char*>(c->batch_host);
+  std::memcpy(hb, items.data(), b_items);
+  std::memcpy(hb + off_sys, sys.data(), b_sys);
+  std::memcpy(hb + off_nch, nch.data(), b_nch);
+  hipError_t e = hipMemcpyAsync(c->batch_buf, hb, total, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch work list copy");
+  e = hipEventRecord(c->batch_ev, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch event");
+  int rc = ensure_ws(c, (size_t)(part_rows > 0 ? part_rows : 1) * 7 * sizeof(double));
+  if (rc) return rc;
+  char* db = static_cast<char*>(c->batch_buf);
+  const nb::BatchItem* d_items = reinterpret_cast<const nb::BatchItem*>(db);
+  const nb::BatchSys* d_sys = reinterpret_cast<const nb::BatchSys*>(db + off_sys);
+  const int32_t* d_nch = reinterpret_cast<const int32_t*>(db + off_nch);
+  e = nb::launch_batch(c->prec, cfg, d_items, (int)items.size(), d_sys, pos, vel, mass, active, acc, jerk, pot,
+                       static_cast<double*>(c->ws), part_rows, any_mask, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
+  if (part_rows > 0) {
+    e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, a_total, acc, jerk, pot,
+                                static_cast<double*>(c->ws), c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "batch reduce launch");
+  }
+  return NB_OK;
+}
+
+int nb_energy(nb_ctx* c, const double* pos, const double* vel, const double* mass, const double* pot, int64_t N,
+              double* out) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (!pos || !vel || !mass || !pot || !out) return fail(c, NB_EINVAL, "null pointer%s");
+  int rc = ensure_energy(c, N);
+  if (rc) return rc;
+  hipError_t e = nb::launch_energy(pos, vel, mass, pot, N, c->energy_part, out, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "energy launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,577 @@
+// Direct-summation force kernels for gfx950 (CDNA4).
+//
+// Computes, for every i in the active set and every j of the j-set,
+//   r = x_j - x_i, u = v_j - v_i, s = |r|^2 + eps2, q = s^{-1/2}
+//   a += m_j q^3 r,   jdot += m_j q^3 (u - 3 (r.u) q^2 r),   phi -= m_j q
+// (the i-particle / j-particle split of the paper's section "Optimizations
+// for the GPU"; G = 1, Plummer softening).
+//
+// Mapping onto the chip (one family of kernels, three tiling axes):
+//  * j-tiles of kTile particles are read once per workgroup from the
+//    caller's row-major arrays with contiguous (coalesced) loads, converted
+//    to the kernel's layout and staged in LDS; the next tile is prefetched
+//    into registers while the current one is consumed.
+//  * K i-particles per lane: every LDS read of a j-particle feeds K pair
+//    evaluations, and the K independent chains hide VALU latency.
+//  * L lanes per i-particle: lane `sub` of a group takes j = sub, sub+L, ...
+//    of each tile; the L partial sums are combined by butterfly shuffles
+//    inside the wavefront and, for L > 64, through LDS across wavefronts.
+//  * S j-subsets: the j-range is cut into S chunks, one workgroup each; the
+//    partial sums go to a workspace and a second kernel adds them in a fixed
+//    order (the paper's two-kernel scheme).  Nothing uses float atomics, so
+//    every result is bitwise reproducible run to run.
+// The pair loop is VALU-bound (the pairwise reciprocal square root is not a
+// dense contraction), so the work is plain vector arithmetic, not MFMA.
+//
+// Precision policies
+//  * F64:   all pair arithmetic in double; per-tile double sums folded into a
+//           compensated (TwoSum) double-double accumulator.
+//  * Mixed: r = x_j - x_i formed in double and rounded to float, u, m and all
+//           pair arithmetic in float, per-tile float sums added into double
+//           accumulators (the paper's remedy for single precision: the
+//           largest error sits in the inter-particle distance, which is
+//           therefore formed in higher precision).
+// The self pair (j == i) is not skipped in the loop: with eps2 > 0 it adds
+// exactly zero to a and jdot and m_i q(eps2) to the potential sum, which is
+// removed afterwards using the identical value.  With eps2 == 0 the MASK
+// variant drops every pair with s == 0 instead.
+#include "nb_internal.h"
+
+namespace nb {
+namespace {
+
+// Reciprocal square root in double: hardware estimate refined by one
+// third-order Newton step, y <- y (1 + e/2 + 3 e^2/8) with e = 1 - s y^2.
+__device__ __forceinline__ double rsqrt_f64(double s) {
+  const double y = __builtin_amdgcn_rsq(s);
+  const double e = fma(-(s * y), y, 1.0);
+  return fma(y, e * fma(e, 0.375, 0.5), y);
+}
+
+__device__ __forceinline__ void two_sum_add(double& hi, double& lo, double x) {
+  const double s = hi + x;
+  const double bp = s - hi;
+  const double err = (hi - (s - bp)) + (x - bp);
+  hi = s;
+  lo += err;
+}
+
+// ------------------------------------------------------------------ F64 ----
+struct F64 {
+  using T = double;
+  struct JTile {
+    double2 xy[kTile];
+    double2 zm[kTile];
+    double2 vxy[kTile];
+    double vz[kTile];
+  };
+  struct JReg {
+    double x, y, z, vx, vy, vz, m;
+  };
+  struct IPart {
+    double x, y, z, vx, vy, vz;
+  };
+  struct Tot {
+    double hi[7], lo[7];
+  };
+  static __device__ __forceinline__ JReg load(const double* pos, const double* vel, const double* mass,
+                                              int64_t j, bool valid) {
+    JReg r;
+    if (valid) {
+      r.x = pos[3 * j]; r.y = pos[3 * j + 1]; r.z = pos[3 * j + 2];
+      r.vx = vel[3 * j]; r.vy = vel[3 * j + 1]; r.vz = vel[3 * j + 2];
+      r.m = mass[j];
+    } else {
+      r.x = r.y = r.z = r.vx = r.vy = r.vz = r.m = 0.0;
+    }
+    return r;
+  }
+  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+    t.xy[s] = make_double2(r.x, r.y);
+    t.zm[s] = make_double2(r.z, r.m);
+    t.vxy[s] = make_double2(r.vx, r.vy);
+    t.vz[s] = r.vz;
+  }
+  static __device__ __forceinline__ IPart load_i(const double* pos, const double* vel, int64_t i) {
+    IPart p;
+    p.x = pos[3 * i]; p.y = pos[3 * i + 1]; p.z = pos[3 * i + 2];
+    p.vx = vel[3 * i]; p.vy = vel[3 * i + 1]; p.vz = vel[3 * i + 2];
+    return p;
+  }
+  static __device__ __forceinline__ T eps(double eps2) { return eps2; }
+
+  template <bool MASK>
+  static __device__ __forceinline__ void pair(const IPart& I, const double2 xy, const double2 zm,
+                                              const double2 vxy, const double vz, const T e2, T* A) {
+    const double dx = xy.x - I.x, dy = xy.y - I.y, dz = zm.x - I.z;
+    const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, e2)));
+    double q = rsqrt_f64(s);
+    if (MASK) q = (s > 0.0) ? q : 0.0;
+    const double ux = vxy.x - I.vx, uy = vxy.y - I.vy, uz = vz - I.vz;
+    const double rv = fma(dz, uz, fma(dy, uy, dx * ux));
+    const double q2 = q * q;
+    const double mq = zm.y * q;
+    const double mq3 = mq * q2;
+    const double c = -3.0 * (rv * q2);
+    A[0] = fma(mq3, dx, A[0]);
+    A[1] = fma(mq3, dy, A[1]);
+    A[2] = fma(mq3, dz, A[2]);
+    A[3] = fma(mq3, fma(c, dx, ux), A[3]);
+    A[4] = fma(mq3, fma(c, dy, uy), A[4]);
+    A[5] = fma(mq3, fma(c, dz, uz), A[5]);
+    A[6] += mq;
+  }
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+                                                   int kcount) {
+    const double2 xy = t.xy[s];
+    const double2 zm = t.zm[s];
+    const double2 vxy = t.vxy[s];
+    const double vz = t.vz[s];
+#pragma unroll
+    for (int k = 0; k < kcount; ++k) pair<MASK>(I[k], xy, zm, vxy, vz, e2, A[k]);
+  }
+  static __device__ __forceinline__ void zero(Tot& t) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) t.hi[c] = t.lo[c] = 0.0;
+  }
+  static __device__ __forceinline__ void fold(Tot& t, T* A) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      two_sum_add(t.hi[c], t.lo[c], A[c]);
+      A[c] = 0.0;
+    }
+  }
+  static __device__ __forceinline__ double value(const Tot& t, int c) { return t.hi[c] + t.lo[c]; }
+  // The value the pair loop adds to the potential sum for the self pair.
+  static __device__ __forceinline__ double self_term(double m, double eps2) { return m * rsqrt_f64(eps2); }
+};
+
+// ---------------------------------------------------------------- Mixed ----
+struct Mixed {
+  using T = float;
+  struct JTile {
+    double2 xy[kTile];
+    double z[kTile];
+    float4 vm[kTile];
+  };
+  struct JReg {
+    double x, y, z;
+    float vx, vy, vz, m;
+  };
+  struct IPart {
+    double x, y, z;
+    float vx, vy, vz;
+  };
+  struct Tot {
+    double v[7];
+  };
+  static __device__ __forceinline__ JReg load(const double* pos, const double* vel, const double* mass,
+                                              int64_t j, bool valid) {
+    JReg r;
+    if (valid) {
+      r.x = pos[3 * j]; r.y = pos[3 * j + 1]; r.z = pos[3 * j + 2];
+      r.vx = (float)vel[3 * j]; r.vy = (float)vel[3 * j + 1]; r.vz = (float)vel[3 * j + 2];
+      r.m = (float)mass[j];
+    } else {
+      r.x = r.y = r.z = 0.0;
+      r.vx = r.vy = r.vz = r.m = 0.0f;
+    }
+    return r;
+  }
+  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+    t.xy[s] = make_double2(r.x, r.y);
+    t.z[s] = r.z;
+    t.vm[s] = make_float4(r.vx, r.vy, r.vz, r.m);
+  }
+  static __device__ __forceinline__ IPart load_i(const double* pos, const double* vel, int64_t i) {
+    IPart p;
+    p.x = pos[3 * i]; p.y = pos[3 * i + 1]; p.z = pos[3 * i + 2];
+    p.vx = (float)vel[3 * i]; p.vy = (float)vel[3 * i + 1]; p.vz = (float)vel[3 * i + 2];
+    return p;
+  }
+  static __device__ __forceinline__ T eps(double eps2) { return (float)eps2; }
+
+  template <bool MASK>
+  static __device__ __forceinline__ void pair(const IPart& I, const double2 xy, const double zj,
+                                              const float4 vm, const T e2, T* A) {
+    const float dx = (float)(xy.x - I.x);
+    const float dy = (float)(xy.y - I.y);
+    const float dz = (float)(zj - I.z);
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+    float q = __builtin_amdgcn_rsqf(s);
+    if (MASK) q = (s > 0.0f) ? q : 0.0f;
+    const float ux = vm.x - I.vx, uy = vm.y - I.vy, uz = vm.z - I.vz;
+    const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+    const float q2 = q * q;
+    const float mq = vm.w * q;
+    const float mq3 = mq * q2;
+    const float c = -3.0f * (rv * q2);
+    A[0] = fmaf(mq3, dx, A[0]);
+    A[1] = fmaf(mq3, dy, A[1]);
+    A[2] = fmaf(mq3, dz, A[2]);
+    A[3] = fmaf(mq3, fmaf(c, dx, ux), A[3]);
+    A[4] = fmaf(mq3, fmaf(c, dy, uy), A[4]);
+    A[5] = fmaf(mq3, fmaf(c, dz, uz), A[5]);
+    A[6] += mq;
+  }
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+                                                   int kcount) {
+    const double2 xy = t.xy[s];
+    const double z = t.z[s];
+    const float4 vm = t.vm[s];
+#pragma unroll
+    for (int k = 0; k < kcount; ++k) pair<MASK>(I[k], xy, z, vm, e2, A[k]);
+  }
+  static __device__ __forceinline__ void zero(Tot& t) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) t.v[c] = 0.0;
+  }
+  static __device__ __forceinline__ void fold(Tot& t, T* A) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      t.v[c] += (double)A[c];
+      A[c] = 0.0f;
+    }
+  }
+  static __device__ __forceinline__ double value(const Tot& t, int c) { return t.v[c]; }
+  static __device__ __forceinline__ double self_term(double m, double eps2) {
+    return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
+  }
+};
+
+// The j-split chosen on the device (device-count mode) and on the host
+// alike: enough work items to fill the chip, chunks of at least one tile.
+__host__ __device__ inline int choose_S(int64_t n_act, int IB, int target_items, int64_t n) {
+  const int64_t n_iblk = (n_act + IB - 1) / IB;
+  if (n_iblk <= 0) return 1;
+  int64_t s = (target_items + n_iblk - 1) / n_iblk;
+  const int64_t max_s = (n + kTile - 1) / kTile;
+  if (s > max_s) s = max_s;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+__host__ __device__ inline int64_t chunk_len(int64_t n, int S) {
+  const int64_t per = (n + S - 1) / S;
+  return ((per + kTile - 1) / kTile) * kTile;
+}
+
+// Shared body: one workgroup processes one (i-block, j-chunk) item.
+// Outputs: final rows (acc/jerk/pot at out_row0 + k) when `final_out`,
+// otherwise partial sums part[c * n_act + k] for c = 0..6.
+template <class P, int K, int L, bool MASK>
+__device__ __forceinline__ void process_item(typename P::JTile& tile, double* red, const double* __restrict__ pos,
+                                             const double* __restrict__ vel, const double* __restrict__ mass,
+                                             int64_t jbeg, int64_t jend, const int32_t* __restrict__ active,
+                                             int64_t n_act, int64_t k0, double eps2, bool final_out,
+                                             double* __restrict__ acc, double* __restrict__ jerk,
+                                             double* __restrict__ pot, double* __restrict__ part) {
+  constexpr int SLOTS = kWG / L;
+  const int t = threadIdx.x;
+  const int slot = t / L;
+  const int sub = t % L;
+
+  typename P::IPart I[K];
+  int64_t irow[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int64_t k = k0 + kk * SLOTS + slot;
+    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+  }
+  const typename P::T e2 = P::eps(eps2);
+
+  typename P::T A[K][7];
+  typename P::Tot Tt[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    P::zero(Tt[kk]);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) A[kk][c] = 0;
+  }
+
+  typename P::JReg nxt = P::load(pos, vel, mass, jbeg + t, jbeg + t < jend);
+  for (int64_t base = jbeg; base < jend; base += kTile) {
+    __syncthreads();  // every lane is done with the previous tile
+    P::store(tile, t, nxt);
+    __syncthreads();
+    const int64_t nb = base + kTile;
+    if (nb < jend) nxt = P::load(pos, vel, mass, nb + t, nb + t < jend);
+#pragma unroll 4
+    for (int jj = sub; jj < kTile; jj += L) P::template pair_tile<MASK>(tile, jj, I, e2, A, K);
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) P::fold(Tt[kk], A[kk]);
+  }
+
+  // Combine the L lanes of each i-particle, in a fixed order.
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    double v[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
+    if constexpr (L > 1) {
+      constexpr int LW = L < 64 ? L : 64;
+#pragma unroll
+      for (int o = LW / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] += __shfl_xor(v[c], o, 64);
+      }
+    }
+    if constexpr (L > 64) {
+      constexpr int NW = L / 64;  // wavefronts per i-particle
+      __syncthreads();
+      if ((t & 63) == 0) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) red[(t >> 6) * 7 + c] = v[c];
+      }
+      __syncthreads();
+      if (sub == 0) {
+        const int w0 = t >> 6;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          double s = red[w0 * 7 + c];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) s += red[(w0 + w) * 7 + c];
+          v[c] = s;
+        }
+      }
+    }
+    const int64_t k = k0 + kk * SLOTS + slot;
+    if (sub == 0 && k < n_act) {
+      if (final_out) {
+        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
+        jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
+        pot[k] = -(v[6] - self);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) part[c * n_act + k] = v[c];
+      }
+    }
+  }
+}
+
+template <class P, int L>
+struct Smem {
+  typename P::JTile tile;
+  double red[(L > 64 ? kWG / 64 : 1) * 7];
+};
+
+template <class P, int K, int L, bool MASK>
+__global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
+  __shared__ Smem<P, L> sm;
+  constexpr int IB = (kWG / L) * K;
+  int64_t n_act = a.n_active;
+  int S = a.S;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    if (d < a.act_lo || (d > a.n_active && !a.last)) return;  // another regime's launch
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    S = choose_S(n_act, IB, a.target_items, a.n);
+  }
+  const int64_t n_iblk = (n_act + IB - 1) / IB;
+  const int64_t items = n_iblk * S;
+  const int64_t clen = chunk_len(a.n, S);
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const int64_t chunk = w / n_iblk;
+    const int64_t iblk = w - chunk * n_iblk;
+    const int64_t jb = chunk * clen;
+    const int64_t je = jb + clen < a.n ? jb + clen : a.n;
+    process_item<P, K, L, MASK>(sm.tile, sm.red, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB,
+                                a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+  }
+}
+
+// Fixed-order sum of the S partial blocks, self-term removal, output.
+template <class P>
+__global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB) {
+  int64_t n_act = a.n_active;
+  int S = S_host;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    if (d < a.act_lo || (d > a.n_active && !a.last)) return;
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    S = choose_S(n_act, IB, a.target_items, a.n);
+  }
+  if (S <= 1) return;
+  const int64_t total = 7 * n_act;
+  const bool self_on = P::eps(a.eps2) > 0;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = idx / n_act;
+    const int64_t k = idx - c * n_act;
+    double s = 0.0;
+    for (int ch = 0; ch < S; ++ch) s += a.part[((int64_t)ch * 7 + c) * n_act + k];
+    if (c < 3) {
+      a.acc[3 * k + c] = s;
+    } else if (c < 6) {
+      a.jerk[3 * k + c - 3] = s;
+    } else {
+      const double self = self_on ? P::self_term(a.mass[a.active[k]], a.eps2) : 0.0;
+      a.pot[k] = -(s - self);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- batch ----
+template <class P, int K, int L, bool MASK>
+__global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restrict__ items, int n_items,
+                                                      const BatchSys* __restrict__ sys, const double* pos,
+                                                      const double* vel, const double* mass,
+                                                      const int32_t* active, double* acc, double* jerk,
+                                                      double* pot, double* part) {
+  __shared__ Smem<P, L> sm;
+  constexpr int IB = (kWG / L) * K;
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchSys sy = sys[it.sys];
+    const int64_t nj = sy.j1 - sy.j0;
+    const int64_t n_act = sy.a1 - sy.a0;
+    const int64_t clen = chunk_len(nj, it.nchunk);
+    const int64_t jb = sy.j0 + (int64_t)it.chunk * clen;
+    const int64_t je = jb + clen < sy.j1 ? jb + clen : sy.j1;
+    process_item<P, K, L, MASK>(sm.tile, sm.red, pos, vel, mass, jb, je, active + sy.a0, n_act,
+                                (int64_t)it.iblk * IB, sy.eps2, it.nchunk == 1, acc + 3 * sy.a0,
+                                jerk + 3 * sy.a0, pot + sy.a0,
+                                part + (sy.part_off + (int64_t)it.chunk * n_act) * 7);
+  }
+}
+
+// One workgroup per system with more than one chunk; fixed-order sums.
+template <class P>
+__global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict__ sys,
+                                                      const int32_t* __restrict__ nchunk, const double* mass,
+                                                      const int32_t* active, double* acc, double* jerk,
+                                                      double* pot, const double* part) {
+  const BatchSys sy = sys[blockIdx.x];
+  const int S = nchunk[blockIdx.x];
+  if (S <= 1) return;
+  const int64_t n_act = sy.a1 - sy.a0;
+  const double* pb = part + sy.part_off * 7;
+  const bool self_on = P::eps(sy.eps2) > 0;
+  for (int64_t idx = threadIdx.x; idx < 7 * n_act; idx += blockDim.x) {
+    const int64_t c = idx / n_act;
+    const int64_t k = idx - c * n_act;
+    double s = 0.0;
+    for (int ch = 0; ch < S; ++ch) s += pb[((int64_t)ch * 7 + c) * n_act + k];
+    const int64_t row = sy.a0 + k;
+    if (c < 3) {
+      acc[3 * row + c] = s;
+    } else if (c < 6) {
+      jerk[3 * row + c - 3] = s;
+    } else {
+      const double self = self_on ? P::self_term(mass[active[row]], sy.eps2) : 0.0;
+      pot[row] = -(s - self);
+    }
+  }
+}
+
+// ------------------------------------------------------------- dispatch ----
+using ForceFn = void (*)(ForceArgs);
+using BatchFn = void (*)(const BatchItem*, int, const BatchSys*, const double*, const double*, const double*,
+                         const int32_t*, double*, double*, double*, double*);
+
+template <class P, bool MASK>
+ForceFn pick_force(int K, int L) {
+#define NB_CASE(KK, LL) \
+  if (K == KK && L == LL) return k_forces<P, KK, LL, MASK>;
+  NB_CASE(1, 1) NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(1, 8) NB_CASE(1, 16) NB_CASE(1, 32) NB_CASE(1, 64)
+  NB_CASE(1, 128) NB_CASE(1, 256)
+  if constexpr (!MASK) {
+    NB_CASE(2, 1) NB_CASE(2, 2) NB_CASE(2, 4) NB_CASE(2, 8) NB_CASE(2, 16) NB_CASE(2, 32) NB_CASE(2, 64)
+    NB_CASE(4, 1) NB_CASE(4, 2) NB_CASE(4, 4) NB_CASE(4, 8) NB_CASE(4, 16)
+  }
+#undef NB_CASE
+  return nullptr;
+}
+
+template <class P, bool MASK>
+BatchFn pick_batch(int K, int L) {
+#define NB_CASE(KK, LL) \
+  if (K == KK && L == LL) return k_forces_batch<P, KK, LL, MASK>;
+  NB_CASE(1, 1) NB_CASE(1, 4) NB_CASE(1, 16) NB_CASE(1, 64)
+  if constexpr (!MASK) {
+    NB_CASE(2, 1) NB_CASE(2, 4) NB_CASE(2, 16)
+  }
+#undef NB_CASE
+  return nullptr;
+}
+
+}  // namespace
+
+bool launch_supported(const Launch& c) {
+  return pick_force<F64, false>(c.K, c.L) != nullptr && c.S >= 1;
+}
+
+int items_for(const Launch& c, int64_t n_active, int S) {
+  const int64_t IB = (int64_t)(kWG / c.L) * c.K;
+  return (int)(((n_active + IB - 1) / IB) * S);
+}
+
+hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
+                         int grid_override) {
+  const int K = mask ? 1 : cfg.K;
+  ForceFn fn = nullptr;
+  if (prec == NB_PREC_FP64)
+    fn = mask ? pick_force<F64, true>(K, cfg.L) : pick_force<F64, false>(K, cfg.L);
+  else
+    fn = mask ? pick_force<Mixed, true>(K, cfg.L) : pick_force<Mixed, false>(K, cfg.L);
+  if (!fn) return hipErrorInvalidValue;
+  int grid = grid_override > 0 ? grid_override : items_for(Launch{K, cfg.L, a.S}, a.n_active, a.S);
+  if (grid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st) {
+  if (!a.n_active_dev && S <= 1) return hipSuccess;
+  const int64_t total = 7 * a.n_active;
+  int grid = (int)((total + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  if (prec == NB_PREC_FP64)
+    hipLaunchKernelGGL(k_reduce<F64>, dim3(grid), dim3(256), 0, st, a, S, IB);
+  else
+    hipLaunchKernelGGL(k_reduce<Mixed>, dim3(grid), dim3(256), 0, st, a, S, IB);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const BatchSys* sys,
+                        const double* pos, const double* vel, const double* mass, const int32_t* active,
+                        double* acc, double* jerk, double* pot, double* part, int64_t part_rows, bool any_mask,
+                        hipStream_t st) {
+  (void)part_rows;
+  const int K = any_mask ? 1 : cfg.K;
+  BatchFn fn = nullptr;
+  if (prec == NB_PREC_FP64)
+    fn = any_mask ? pick_batch<F64, true>(K, cfg.L) : pick_batch<F64, false>(K, cfg.L);
+  else
+    fn = any_mask ? pick_batch<Mixed, true>(K, cfg.L) : pick_batch<Mixed, false>(K, cfg.L);
+  if (!fn) return hipErrorInvalidValue;
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fn, dim3(n_items), dim3(kWG), 0, st, items, n_items, sys, pos, vel, mass, active, acc, jerk,
+                     pot, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const int32_t* chunks_per_sys,
+                               const double* mass, const int32_t* active, int64_t n_act_total, double* acc,
+                               double* jerk, double* pot, const double* part, hipStream_t st) {
+  (void)n_act_total;
+  if (n_sys <= 0) return hipSuccess;
+  if (prec == NB_PREC_FP64)
+    hipLaunchKernelGGL(k_batch_reduce<F64>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
+                       jerk, pot, part);
+  else
+    hipLaunchKernelGGL(k_batch_reduce<Mixed>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active,
+                       acc, jerk, pot, part);
+  return hipGetLastError();
+}
+
+int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n) {
+  return choose_S(n_act, IB, target_items, n);
+}
+
+}  // namespace nb

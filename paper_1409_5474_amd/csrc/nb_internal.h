@@ -1,0 +1,134 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/nbody.h"
+
+namespace nb {
+
+constexpr int kWG = 256;    // threads per workgroup of every force kernel
+constexpr int kTile = 256;  // j-particles staged in LDS per tile
+
+// One launch configuration of the force kernel family.
+struct Launch {
+  int K = 1;  // i-particles per lane
+  int L = 1;  // lanes per i-particle
+  int S = 1;  // j-subsets (0 in a table entry: choose by the saturation rule)
+};
+
+struct TuneEntry {
+  int prec;
+  int64_t n_min, act_min, act_max;
+  Launch cfg;
+};
+
+// Arguments of one force launch.  j rows [0, n) of pos/vel/mass; i rows
+// active[0, n_active).  When n_active_dev is set the count is read on the
+// device and the j-split is chosen there.
+struct ForceArgs {
+  const double* pos;
+  const double* vel;
+  const double* mass;
+  int64_t n;
+  const int32_t* active;
+  int64_t n_active;             // host count (or the maximum, with n_active_dev)
+  const int32_t* n_active_dev;  // optional device count
+  double eps2;
+  int S;                        // j-subsets (host-chosen); ignored with n_active_dev
+  int target_items;             // device-chosen S aims at this many work items
+  double* acc;
+  double* jerk;
+  double* pot;
+  double* part;                 // [S][7][n_active] partial sums when S > 1
+  int* s_dev;                   // unused
+  int64_t act_lo;               // device-count mode: work only when count >= act_lo and
+  int last;                     // count <= n_active (or any larger count when `last`)
+};
+
+// Batched work list item: one (system, i-block, j-chunk) triple.
+struct BatchItem {
+  int32_t sys;      // system index
+  int32_t iblk;     // i-block inside the system's active list
+  int32_t chunk;    // j-chunk inside the system
+  int32_t nchunk;   // number of chunks of this system
+};
+
+struct BatchSys {
+  int64_t j0, j1;     // j rows of the system
+  int64_t a0, a1;     // rows of the active list / outputs
+  double eps2;
+  int64_t part_off;   // offset (in rows of 7 doubles) of its partials
+};
+
+// Kernel launchers (forces.hip).  Return hipSuccess or the launch error.
+hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
+                         int grid_override);
+hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st);
+int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n);
+bool launch_supported(const Launch& cfg);
+int items_for(const Launch& cfg, int64_t n_active, int S);
+hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items,
+                        const BatchSys* sys, const double* pos, const double* vel, const double* mass,
+                        const int32_t* active, double* acc, double* jerk, double* pot, double* part,
+                        int64_t part_rows, bool any_mask, hipStream_t st);
+hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const int32_t* chunks_per_sys,
+                               const double* mass, const int32_t* active, int64_t n_act_total,
+                               double* acc, double* jerk, double* pot, const double* part,
+                               hipStream_t st);
+
+// Hermite / schedule / energy launchers (hermite.hip).
+hipError_t launch_predict(const double* pos, const double* vel, const double* acc, const double* jerk,
+                          const int64_t* t_tick, int64_t t_next, const int64_t* t_next_dev, double dt_min,
+                          int64_t n, double* pos_p, double* vel_p, hipStream_t st);
+hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t* n_active_dev,
+                          const double* pos_p, const double* vel_p, const double* acc1, const double* jerk1,
+                          double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick,
+                          int32_t* level, double eta, double dt_max, int max_level, int64_t* clamp_dev,
+                          hipStream_t st);
+hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64_t* n_active_dev,
+                               const double* pos_p, const double* vel_p, const double* acc1, const double* jerk1,
+                               double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick, int32_t* level,
+                               double eta, double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev,
+                               hipStream_t st);
+hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, double eta, double dt_max,
+                          int max_level, int32_t* level, hipStream_t st);
+hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level,
+                           int32_t* active, int64_t* sched, int64_t* block_min, int32_t* block_cnt,
+                           int32_t* n_active32, hipStream_t st);
+int schedule_blocks(int64_t n);
+hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
+                         int64_t n, double* part, double* out, hipStream_t st);
+int energy_blocks(int64_t n);
+
+}  // namespace nb
+
+// The context behind the opaque handle of the C ABI.
+struct nb_ctx {
+  int device = 0;
+  int prec = NB_PREC_FP64;
+  int num_cus = 256;
+  hipStream_t stream = nullptr;
+  std::string err;
+  nb::Launch forced;            // K == 0: automatic
+  bool have_forced = false;
+  std::vector<nb::TuneEntry> table;
+  // device workspace (grown on demand)
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* s_dev = nullptr;         // device-chosen S of the last devcount launch
+  int64_t* sched_tmp = nullptr; // block minima for the scheduler
+  int32_t* sched_cnt = nullptr;
+  int32_t* nact32 = nullptr;    // int32 copy of the scheduled active count
+  size_t sched_cap = 0;
+  double* energy_part = nullptr;
+  size_t energy_cap = 0;
+  void* batch_buf = nullptr;    // device copy of the batch work list
+  size_t batch_cap = 0;
+  void* batch_host = nullptr;   // pinned staging buffer of the work list
+  size_t batch_host_cap = 0;
+  hipEvent_t batch_ev = nullptr;  // marks the end of the last staging copy
+};

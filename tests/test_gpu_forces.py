@@ -1,0 +1,209 @@
+"""GPU parity of the force kernels against the CPU oracle (extended
+precision), through the C ABI.  Gates:
+  FP64 : per particle |da_i| <= 1e-12 |a_i| + 64 eps64 A_i (A_i = sum_j |a_ij|)
+         and normwise ||da||/||a|| <= 1e-12, for acc, jerk and pot
+  mixed: RMS_i |da_i|/|a_i| <= 1e-6 for acc; jerk <= 1e-5; pot <= 1e-6
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from errors import all_errs
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def nb():
+    import paper_1409_5474_amd as nbm
+    return nbm
+
+
+@pytest.fixture(scope="module")
+def ctx(nb):
+    c = nb.Context(0, "fp64")
+    yield c
+    c.close()
+
+
+def _dev(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def run_gpu(ctx, prec, p, eps2, active, launch=None):
+    import torch
+    ctx.set_precision(prec)
+    if launch:
+        ctx.set_launch(*launch)
+    else:
+        ctx.set_launch(0)
+    acc, jerk, pot = ctx.forces(_dev(p.pos), _dev(p.vel), _dev(p.mass), _dev(active.astype(np.int32)), eps2)
+    torch.cuda.synchronize()
+    ctx.set_launch(0)
+    return acc.cpu().numpy(), jerk.cpu().numpy(), pot.cpu().numpy()
+
+
+def check_fp64(res, ref, normwise=1e-12, rel=1e-12, cond=64 * EPS64):
+    for name, got in zip(("acc", "jerk", "pot"), res):
+        r = ref[name]
+        a = ref["abs_" + name]
+        d = np.asarray(got) - r
+        dn = np.linalg.norm(d, axis=1) if d.ndim == 2 else np.abs(d)
+        rn = np.linalg.norm(r, axis=1) if r.ndim == 2 else np.abs(r)
+        bound = rel * rn + cond * a
+        worst = int(np.argmax(dn - bound))
+        assert np.all(dn <= bound), (name, worst, dn[worst], bound[worst])
+        assert np.linalg.norm(d) <= normwise * np.linalg.norm(r), name
+
+
+def check_mixed(res, ref, acc_rms=1e-6, jerk_rms=1e-5, pot_rms=1e-6):
+    e = all_errs(*res, ref)
+    assert e["acc"]["rms"] <= acc_rms, e
+    assert e["jerk"]["rms"] <= jerk_rms, e
+    assert e["pot"]["rms"] <= pot_rms, e
+    return e
+
+
+def _case(n, seed):
+    return synth.plummer(n, seed)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_small_plummer_all_active(ctx, prec):
+    # Plummer N = 1024, eps = 0.01, every particle active.
+    p = _case(1024, 1)
+    eps2 = synth.plummer_eps2_c1()
+    act = np.arange(1024, dtype=np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, eps2, act)
+    res = run_gpu(ctx, prec, p, eps2, act)
+    if prec == "fp64":
+        check_fp64(res, ref)
+    else:
+        check_mixed(res, ref)
+
+
+LAUNCHES = [(1, 1, 1), (2, 1, 1), (4, 1, 1), (1, 1, 3), (2, 1, 5), (1, 2, 1), (1, 4, 2), (2, 8, 3), (4, 16, 1),
+            (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("launch", LAUNCHES)
+def test_every_launch_shape_ragged(ctx, prec, launch):
+    # N not a multiple of the tile, an active set not a multiple of the i-block.
+    n = 3001
+    p = _case(n, 7)
+    eps2 = 1e-3
+    rng = np.random.default_rng(3)
+    act = np.sort(rng.choice(n, 777, replace=False)).astype(np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, eps2, act)
+    res = run_gpu(ctx, prec, p, eps2, act, launch)
+    if prec == "fp64":
+        check_fp64(res, ref)
+    else:
+        check_mixed(res, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("n_act", [1, 7, 63, 64, 65, 1000, 4096])
+def test_active_set_sizes(ctx, prec, n_act):
+    n = 4096
+    p = _case(n, 9)
+    eps2 = 2.0 ** -16
+    rng = np.random.default_rng(n_act)
+    act = np.sort(rng.choice(n, n_act, replace=False)).astype(np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, eps2, act)
+    res = run_gpu(ctx, prec, p, eps2, act)
+    if prec == "fp64":
+        check_fp64(res, ref)
+    else:
+        check_mixed(res, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_duplicates_and_unsorted(ctx, prec):
+    p = _case(500, 4)
+    act = np.array([499, 3, 3, 250, 0, 3, 499], dtype=np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, 1e-3, act)
+    res = run_gpu(ctx, prec, p, 1e-3, act)
+    (check_fp64 if prec == "fp64" else check_mixed)(res, ref)
+    # duplicated rows are bitwise equal
+    for arr in res:
+        assert np.array_equal(arr[1], arr[2]) and np.array_equal(arr[1], arr[5])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tiny_systems(ctx, prec):
+    # N = 1: no other particle -> zeros; N = 2: the two-body closed form.
+    import types
+    one = types.SimpleNamespace(pos=np.zeros((1, 3)), vel=np.zeros((1, 3)), mass=np.ones(1))
+    res = run_gpu(ctx, prec, one, 0.01, np.array([0], np.int32))
+    for arr in res:
+        assert np.all(arr == 0.0)
+    two = types.SimpleNamespace(pos=np.array([[0.0, 0, 0], [1.5, 0, 0]]), vel=np.zeros((2, 3)),
+                                mass=np.array([0.3, 0.7]))
+    res = run_gpu(ctx, prec, two, 0.04, np.array([0, 1], np.int32))
+    tol = 1e-15 if prec == "fp64" else 1e-6
+    s32 = (1.5 ** 2 + 0.04) ** 1.5
+    assert res[0][0, 0] == pytest.approx(0.7 * 1.5 / s32, rel=tol)
+    assert res[0][1, 0] == pytest.approx(-0.3 * 1.5 / s32, rel=tol)
+    assert res[2][0] == pytest.approx(-0.7 / np.sqrt(1.5 ** 2 + 0.04), rel=tol)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_zero_softening_masks_coincident_pairs(ctx, prec):
+    # eps2 = 0: the self pair and a coincident twin contribute nothing.
+    p = _case(300, 5)
+    pos = p.pos.copy()
+    pos[10] = pos[20]
+    import types
+    q = types.SimpleNamespace(pos=pos, vel=p.vel, mass=p.mass)
+    act = np.arange(300, dtype=np.int32)
+    ref = oracle.forces_ld(pos, p.vel, p.mass, 0.0, act)
+    assert ref["skipped"] == 2
+    res = run_gpu(ctx, prec, q, 0.0, act)
+    for arr in res:
+        assert np.all(np.isfinite(arr))
+    if prec == "fp64":
+        check_fp64(res, ref)
+    else:
+        check_mixed(res, ref, acc_rms=1e-5, jerk_rms=1e-4, pot_rms=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_bitwise_deterministic(ctx, prec):
+    p = _case(5000, 6)
+    act = np.arange(0, 5000, 3, dtype=np.int32)
+    r1 = run_gpu(ctx, prec, p, 1e-3, act, (1, 4, 3))
+    r2 = run_gpu(ctx, prec, p, 1e-3, act, (1, 4, 3))
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_size_sampled(ctx, prec):
+    # Plummer N = 262144, eps = 1/256, all active in the launch the benchmark
+    # uses; 512 sampled rows checked against the oracle one by one.
+    n = 262144
+    p = _case(n, 3)
+    eps2 = 2.0 ** -16
+    act = np.arange(n, dtype=np.int32)
+    res = run_gpu(ctx, prec, p, eps2, act)
+    rows = np.sort(np.random.default_rng(11).choice(n, 512, replace=False)).astype(np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, eps2, rows)
+    sub = tuple(a[rows] for a in res)
+    if prec == "fp64":
+        check_fp64(sub, ref)
+    else:
+        check_mixed(sub, ref)
+    # Newton's third law over the whole system (exact in exact arithmetic)
+    a = res[0]
+    fa = np.linalg.norm((p.mass[:, None] * a).sum(0))
+    scale = (p.mass * np.linalg.norm(a, axis=1)).sum()
+    assert fa <= (1e-13 if prec == "fp64" else 1e-6) * scale
