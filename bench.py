@@ -1,0 +1,186 @@
+"""Benchmark: direct-summation acc+jerk(+pot) throughput on one MI355X.
+
+Workload: Plummer sphere, N = 262144 (2^18), equal masses, eps = 1/256,
+mixed precision (double-precision separations, float pair arithmetic,
+double accumulation), every particle active.  One step = one Hermite block
+step through the library's block-step entry point: schedule, predict all
+N particles, forces on the active set (all N), correct.  The run uses one
+step level, so every block step has all N particles active (a
+shared-time-step Hermite step); N^2 pair interactions per step.
+
+Printed: one JSON line with the metric (G-interactions/s of the whole step,
+mixed precision), the FP64 figure and the mixed/FP64 speedup on the same
+GPU, the roofline of the force kernel (VALU-bound; nominal 43 flops per
+interaction against the FP32 vector peak), and the CPU oracle's rate on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOPS_PER_INTERACTION = 43          # nominal count for acc + jerk + pot
+FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X, vendor figure
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=262144)
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1409_5474_amd as nb
+    import synth
+
+    dev = torch.device("cuda", 0)
+    n = args.n
+    eps2 = 2.0 ** -16
+    p = synth.plummer(n, 3)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    mass = t(p.mass)
+    stream = torch.cuda.current_stream(dev)
+
+    def make_state():
+        st = dict(pos=t(p.pos), vel=t(p.vel))
+        st["acc"] = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        st["jerk"] = torch.empty_like(st["acc"])
+        st["t_tick"] = torch.zeros(n, dtype=torch.int64, device=dev)
+        st["level"] = torch.zeros(n, dtype=torch.int32, device=dev)
+        st["pos_p"] = torch.empty_like(st["acc"])
+        st["vel_p"] = torch.empty_like(st["acc"])
+        st["active"] = torch.empty(n, dtype=torch.int32, device=dev)
+        st["acc1"] = torch.empty_like(st["acc"])
+        st["jerk1"] = torch.empty_like(st["acc"])
+        st["pot1"] = torch.empty(n, dtype=torch.float64, device=dev)
+        st["sched"] = torch.zeros(4, dtype=torch.int64, device=dev)
+        return st
+
+    dt_max, max_level, eta = 2.0 ** -12, 0, 0.01
+
+    def run(prec):
+        ctx = nb.Context(0, prec)
+        st = make_state()
+        act = torch.arange(n, dtype=torch.int32, device=dev)
+        # start-up forces at t = 0 for every particle
+        ctx.forces(st["pos"], st["vel"], mass, act, eps2, st["acc"], st["jerk"], st["pot1"])
+
+        def step():
+            ctx.block_step(n, eps2, eta, dt_max, max_level, mass, st["pos"], st["vel"], st["acc"], st["jerk"],
+                           st["t_tick"], st["level"], st["pos_p"], st["vel_p"], st["active"], st["acc1"],
+                           st["jerk1"], st["pot1"], st["sched"])
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_step = e0.elapsed_time(e1) / args.steps
+        sched = st["sched"].cpu().tolist()
+        assert sched[1] == n, f"block step was not all-active: {sched}"
+        # the force kernel alone, same inputs and launch, HIP events on its stream
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty_like(acc)
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        ctx.forces(st["pos_p"], st["vel_p"], mass, act, eps2, acc, jerk, pot)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            ctx.forces(st["pos_p"], st["vel_p"], mass, act, eps2, acc, jerk, pot)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_force = e0.elapsed_time(e1) / args.steps
+        launch = ctx.get_launch(n, n)
+        finite = bool(torch.isfinite(st["pos"]).all().item())
+        ctx.close()
+        return dict(ms_step=ms_step, wall_s=wall, ms_force=ms_force, launch=launch, sched=sched, finite=finite)
+
+    res = {args.prec: run(args.prec)}
+    other = "fp64" if args.prec == "mixed" else "mixed"
+    res[other] = run(other)
+    main_r = res[args.prec]
+    inter = float(n) * float(n)
+    value = inter / (main_r["ms_step"] * 1e-3) / 1e9
+    fp64_gint = inter / (res["fp64"]["ms_step"] * 1e-3) / 1e9
+    mixed_gint = inter / (res["mixed"]["ms_step"] * 1e-3) / 1e9
+    achieved = FLOPS_PER_INTERACTION * inter / (main_r["ms_force"] * 1e-3) / 1e12
+    peak = FP32_VECTOR_PEAK_TFLOPS if args.prec == "mixed" else FP64_VECTOR_PEAK_TFLOPS
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        probe = np.arange(0, n, n // 256, dtype=np.int32)[:256]
+        t0 = time.perf_counter()
+        oracle.forces_f64(p.pos, p.vel, p.mass, eps2, probe, nthreads=threads)
+        rate = 256 * n / (time.perf_counter() - t0)
+        rows = int(min(n, max(256, args.cpu_seconds * rate / n)))
+        sample = np.linspace(0, n - 1, rows).astype(np.int32)
+        t0 = time.perf_counter()
+        oracle.forces_f64(p.pos, p.vel, p.mass, eps2, sample, nthreads=threads)
+        dt = time.perf_counter() - t0
+        cpu = {"value": rows * n / dt / 1e9, "unit": "G-interactions/s", "cores": threads, "kind": "oracle",
+               "sample": f"{rows} evenly spaced i-rows of the N={n} Plummer workload against all {n} j "
+                         f"(FP64 oracle, {dt:.1f} s)"}
+
+    line = {
+        "metric": "G-interactions/s (acc+jerk) and % vector peak at N=262144; mixed vs FP64",
+        "value": round(value, 2),
+        "unit": "G-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_r["ms_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair / f64 separation+accumulation" if args.prec == "mixed" else "f64",
+        "data": "synthetic (seeded Plummer sphere)",
+        "config": {"workload": f"Plummer N={n}, eps=1/256, all particles active, shared-step Hermite block step "
+                               f"({args.prec})", "n": n, "eps2": eps2, "launch_KLS": main_r["launch"]},
+        "fp64": {"value": round(fp64_gint, 2), "ms_per_step": round(res["fp64"]["ms_step"], 4),
+                 "ms_force_kernel": round(res["fp64"]["ms_force"], 4),
+                 "pct_fp64_vector_peak": round(100 * FLOPS_PER_INTERACTION * inter /
+                                               (res["fp64"]["ms_force"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS, 2)},
+        "mixed": {"value": round(mixed_gint, 2), "ms_per_step": round(res["mixed"]["ms_step"], 4),
+                  "ms_force_kernel": round(res["mixed"]["ms_force"], 4),
+                  "pct_fp32_vector_peak": round(100 * FLOPS_PER_INTERACTION * inter /
+                                                (res["mixed"]["ms_force"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 2)},
+        "mixed_vs_fp64_speedup": round(res["fp64"]["ms_step"] / res["mixed"]["ms_step"], 3),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": f"force kernel ({args.prec}), {FLOPS_PER_INTERACTION} flops x N^2 per launch",
+                     "ms_per_launch": round(main_r["ms_force"], 4)},
+        "cpu_baseline": cpu,
+        "finite": all(r["finite"] for r in res.values()),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,123 @@
+"""The oracle's pins must catch plausible mistakes.  Each case plants one
+mistake in a copy of the oracle (on the CPU only) -- a dropped term, a
+wrong sign, power, constant or index -- and runs the pin tests against the
+copy, which must fail."""
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "forces.c")
+
+# (name, regex, replacement): applied to every match, i.e. to both the
+# double and the extended-precision evaluation.
+FORCE_MUTANTS = [
+    ("jerk factor 3 -> 2", r"3\.0L? \* ru", "2.0 * ru"),
+    ("jerk sign", r"\(ux - c \* rx\)", "(ux + c * rx)"),
+    ("acc power s^-1 instead of s^-3/2", r"\* inv_sqrt_s \* inv_s;", "* inv_s;"),
+    ("potential sign", r"ph -= ", "ph += "),
+    ("softening dropped", r" \+ \(long double\)eps2;| \+ eps2;", ";"),
+    ("y/z component swap", r"pos\[3 \* j \+ 1\] - yi", "pos[3 * j + 2] - yi"),
+    ("self pair not excluded", r"if \(j == i\) continue;", ""),
+    ("relative velocity uses i twice", r"vel\[3 \* j\] - vxi", "vel[3 * i] - vxi"),
+    ("jerk uses acc direction only", r"\(uz - c \* rz\)", "(uz - c * rx)"),
+]
+
+
+def _build_mutant(tmp_path, name, pat, rep):
+    src = open(SRC).read()
+    mut, n = re.subn(pat, rep, src)
+    assert n > 0, f"mutation {name!r} did not apply"
+    c = tmp_path / "forces_mut.c"
+    c.write_text(mut)
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", str(c), "-o", str(so),
+                    "-lm"], check=True)
+    return so
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,pat,rep", FORCE_MUTANTS, ids=[m[0] for m in FORCE_MUTANTS])
+def test_force_pins_catch_mutant(tmp_path, name, pat, rep):
+    so = _build_mutant(tmp_path, name, pat, rep)
+    env = dict(os.environ, NB_ORACLE_LIB=str(so), PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_forces.py")],
+                       env=env, capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode == 1, f"mutant {name!r} survived:\n{r.stdout[-2000:]}"
+
+
+# Hermite mutants: patch one function of oracle.hermite and run a pin.
+def _hermite_pins():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_oracle_hermite as T
+    return [T.test_predictor_exact_for_constant_jerk, T.test_corrector_exact_for_cubic_acceleration,
+            T.test_aarseth_hand_value, T.test_level_rules, T.test_block_step_invariants]
+
+
+def _mut_predict(x, v, a, j, d):
+    d = np.asarray(d, dtype=np.float64)
+    d = d[:, None] if d.ndim == 1 else d
+    return x + v * d + a * (d * d / 2.0) + j * (d * d * d / 2.0), v + a * d + j * (d * d / 2.0)
+
+
+def _mut_interpolate(a0, j0, a1, j1, dt):
+    dt = np.asarray(dt, dtype=np.float64)
+    dt = dt[:, None] if dt.ndim == 1 else dt
+    a2 = (-6.0 * (a0 - a1) - dt * (4.0 * j1 + 2.0 * j0)) / (dt * dt)   # j0/j1 transposed
+    a3 = (12.0 * (a0 - a1) + 6.0 * dt * (j0 + j1)) / (dt * dt * dt)
+    return a2, a3
+
+
+def _mut_correct(xp, vp, a2, a3, dt):
+    dt = np.asarray(dt, dtype=np.float64)
+    dt = dt[:, None] if dt.ndim == 1 else dt
+    return xp + a2 * dt ** 4 / 24.0 + a3 * dt ** 5 / 24.0, vp + a2 * dt ** 3 / 6.0 + a3 * dt ** 4 / 24.0
+
+
+def _mut_aarseth(a1, j1, a2, a3, dt, eta, dt_max):
+    from oracle import hermite as H
+    n = lambda u: np.sqrt((u * u).sum(-1))
+    num = n(a1) * n(a2) + n(j1) ** 2            # a2 at the start instead of the end of the step
+    den = n(j1) * n(a3) + n(a2) ** 2
+    return np.where(den > 0, np.sqrt(eta * num / np.where(den > 0, den, 1)), dt_max)
+
+
+def _mut_new_level(level, dt_star, t_new, dt_max, max_level):
+    level = np.array(level, dtype=np.int64)
+    out = level.copy()
+    for k in range(level.size):
+        L = int(level.flat[k]); ds = float(np.asarray(dt_star).flat[k]); dt = dt_max * 2.0 ** -L
+        if ds < dt:
+            while dt > ds and L < max_level:
+                L += 1; dt = dt_max * 2.0 ** -L
+        elif ds >= 2.0 * dt and L > 0:
+            L -= 1                               # doubles without the commensurability check
+        out.flat[k] = L
+    return out, np.zeros(level.shape, dtype=bool)
+
+
+HERMITE_MUTANTS = [("predictor jerk coefficient", "predict", _mut_predict),
+                   ("interpolation j0/j1 transposed", "interpolate", _mut_interpolate),
+                   ("corrector a3 coefficient", "correct", _mut_correct),
+                   ("Aarseth uses start-of-step a2", "aarseth_dt", _mut_aarseth),
+                   ("level doubling not commensurate", "new_level", _mut_new_level)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,attr,fn", HERMITE_MUTANTS, ids=[m[0] for m in HERMITE_MUTANTS])
+def test_hermite_pins_catch_mutant(monkeypatch, name, attr, fn):
+    from oracle import hermite as H
+    monkeypatch.setattr(H, attr, fn)
+    caught = False
+    for pin in _hermite_pins():
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived every Hermite pin"
