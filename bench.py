@@ -34,14 +34,135 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=262144)
-    ap.add_argument("--prec", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--prec", default="mixed", choices=["mixed", "mixed_ds", "fp64"])
+    ap.add_argument("--force-only", action="store_true",
+                    help="profiling target: only the all-active force launch, --steps times")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
+                         "(calibrates the HBM byte counters)")
+    ap.add_argument("--workload", default="", choices=["", "plummer1k", "hermite65k", "hermite262k", "batch128",
+                                                        "merger"],
+                    help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
+def workloads(args):
+    """Measurements of the other workloads (one JSON line each).
+
+    plummer1k   Plummer N=1024, eps=0.01, FP64, one all-active evaluation
+    hermite65k  Plummer N=65536, eps=1/256, FP64 Hermite block steps (eta=0.01,
+                dt_max=1/16) to t=1/8, graph-replayed; energy drift, steps
+    hermite262k Plummer N=262144, eps=1/256, block steps to t=1/8 in FP64 and
+                in mixed precision: drift of each and the time of each
+    batch128    128 Plummer clusters, N log-uniform in [128, 16384],
+                eps_c = 0.05 N_c^-1/3, mixed, block steps to t=1/16, one
+                graph replay per 8 steps vs eager launches
+    merger      11 Hernquist galaxies (2^17 stars + a point mass each): the
+                i-set near the point masses against all 1,441,803 bodies,
+                FP64 and mixed
+    """
+    import numpy as np
+    import torch
+
+    import paper_1409_5474_amd as nb
+    import synth
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+
+    dev = torch.device("cuda", 0)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    out = {"workload": args.workload, "data": "synthetic (seeded)"}
+    if args.workload == "plummer1k":
+        p = synth.plummer(1024, 1)
+        ctx = nb.Context(0, "fp64")
+        act = torch.arange(1024, dtype=torch.int32, device=dev)
+        P, V, M = t(p.pos), t(p.vel), t(p.mass)
+        ctx.forces(P, V, M, act, 1e-4)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.forces(P, V, M, act, 1e-4)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out.update(n=1024, prec="fp64", ms_per_eval=round(ms, 5), gint=round(1024 * 1024 / ms / 1e6, 3))
+    elif args.workload in ("hermite65k", "hermite262k"):
+        n, seed = (65536, 2) if args.workload == "hermite65k" else (262144, 3)
+        p = synth.plummer(n, seed)
+        precs = ("fp64",) if n == 65536 else ("fp64", "mixed")
+        for prec in precs:
+            ctx = nb.Context(0, prec)
+            bi = BlockIntegrator(ctx, t(p.pos), t(p.vel), t(p.mass), 2.0 ** -16, 0.01, 1.0 / 16, 30)
+            E0 = bi.energy()["E"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bi.run_until(0.125, graph_steps=32)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            E1 = bi.energy()
+            evals = None
+            out[prec] = dict(n=n, steps=bi.steps, clamps=bi.clamps, wall_s=round(wall, 3),
+                             E0=E0, E1=E1["E"], drift=abs(E1["E"] - E0) / abs(E0),
+                             level_histogram=np.bincount(bi.level.cpu().numpy(), minlength=31).tolist())
+            if n == 65536:
+                out[prec]["pos_sample"] = bi.pos.cpu().numpy()[::4096].tolist()
+            ctx.close()
+    elif args.workload == "batch128":
+        b = synth.cluster_batch(seed=4, n_clusters=128)
+        ctx = nb.Context(0, "mixed")
+        res = {}
+        for mode in ("graph", "eager"):
+            bi = BlockIntegrator(ctx, t(b.pos), t(b.vel), t(b.mass), b.eps2, 0.01, 1.0 / 16, 30, offsets=b.offsets)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bi.run_until(0.0625, graph_steps=8, use_graph=(mode == "graph"))
+            torch.cuda.synchronize()
+            res[mode] = dict(wall_s=round(time.perf_counter() - t0, 3), steps=bi.steps)
+        # one all-active batched evaluation: interactions = sum N_c^2
+        n = int(b.offsets[-1])
+        act = torch.arange(n, dtype=torch.int32, device=dev)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        jerk, pot = torch.empty_like(acc), torch.empty(n, dtype=torch.float64, device=dev)
+        P, V, M = t(b.pos), t(b.vel), t(b.mass)
+        ctx.forces_batch(b.offsets, b.eps2, P, V, M, act, b.offsets, acc, jerk, pot)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.forces_batch(b.offsets, b.eps2, P, V, M, act, b.offsets, acc, jerk, pot)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        inter = float((b.sizes.astype(np.float64) ** 2).sum())
+        out.update(clusters=128, bodies=n, interactions_all_active=inter, ms_all_active=round(ms, 4),
+                   gint_all_active=round(inter / ms / 1e6, 2), block_steps_to_t_1_16=res,
+                   graph_speedup=round(res["eager"]["wall_s"] / res["graph"]["wall_s"], 3))
+    elif args.workload == "merger":
+        m = synth.hernquist_merger()
+        P, V, M = t(m.pos), t(m.vel), t(m.mass)
+        act = t(m.active)
+        for prec in ("fp64", "mixed"):
+            ctx = nb.Context(0, prec)
+            ctx.forces(P, V, M, act, m.eps2)
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(args.steps):
+                ctx.forces(P, V, M, act, m.eps2)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            na, nj = int(m.active.size), int(m.mass.size)
+            out[prec] = dict(n_i=na, n_j=nj, ms=round(ms, 4), gint=round(na * nj / ms / 1e6, 2),
+                             launch=ctx.get_launch(nj, na))
+            ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload:
+        return workloads(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}), flush=True)
@@ -53,6 +174,28 @@ def main():
     import synth
 
     dev = torch.device("cuda", 0)
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup + args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 8, "launches": args.warmup + args.steps}), flush=True)
+        return
+    if args.force_only:
+        p = synth.plummer(args.n, 3)
+        t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+        ctx = nb.Context(0, args.prec)
+        P, V, M = t(p.pos), t(p.vel), t(p.mass)
+        act = torch.arange(args.n, dtype=torch.int32, device=dev)
+        acc = torch.empty((args.n, 3), dtype=torch.float64, device=dev)
+        jerk, pot = torch.empty_like(acc), torch.empty(args.n, dtype=torch.float64, device=dev)
+        for _ in range(args.warmup + args.steps):
+            ctx.forces(P, V, M, act, 2.0 ** -16, acc, jerk, pot)
+        torch.cuda.synchronize()
+        print(json.dumps({"force_only": args.prec, "n": args.n, "launches": args.warmup + args.steps,
+                          "launch_KLS": ctx.get_launch(args.n, args.n)}), flush=True)
+        return
     n = args.n
     eps2 = 2.0 ** -16
     p = synth.plummer(n, 3)

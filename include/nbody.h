@@ -61,9 +61,13 @@ enum nb_status {
 
 enum nb_precision {
     NB_PREC_FP64 = 0,  /* every pair in IEEE double */
-    NB_PREC_MIXED = 1  /* r formed in double and rounded to float; the pair
+    NB_PREC_MIXED = 1, /* r formed in double and rounded to float; the pair
                           arithmetic in float; per-tile float sums folded
                           into a double-precision accumulator */
+    NB_PREC_MIXED_DS = 2 /* as NB_PREC_MIXED, but r formed in emulated double
+                          precision on float hardware: positions split into
+                          hi + lo floats, r = (hi_j - hi_i) + (lo_j - lo_i)
+                          (the paper's remedy for single-precision devices) */
 };
 
 /* ---- context ------------------------------------------------------------ */
@@ -94,11 +98,14 @@ const char *nb_version(void);
 int nb_set_launch(nb_ctx *ctx, int K, int L, int S);
 int nb_get_launch(nb_ctx *ctx, int64_t N, int64_t n_active, int *K, int *L, int *S);
 /* Install one entry of the automatic table: for this precision, N >= n_min
- * and n_active in [act_min, act_max], use (K, L, S); S = 0 means "choose S
- * by the saturation rule".  Later entries take precedence.  Used by the
- * autotuner front end to load its cache. */
+ * and n_active in [act_min, act_max], use K and L, and choose S by the
+ * saturation rule aiming at `items` work items (i-blocks x j-subsets;
+ * 0 = 4 per compute unit).  The same entry drives host-count and
+ * device-count launches, so both split the work identically.  Later
+ * entries take precedence on their range.  Used by the autotuner front end
+ * to load its cache. */
 int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int64_t act_max,
-                int K, int L, int S);
+                int K, int L, int items);
 int nb_tune_clear(nb_ctx *ctx);
 /* Time the force kernel for one configuration on the caller's arrays:
  * `reps` launches after one warm-up, on the context stream, with HIP
@@ -202,12 +209,30 @@ int nb_schedule(nb_ctx *ctx, const int64_t *t_tick, const int32_t *dt_level, int
  * count) -> correct.  State arrays as above; work arrays supplied by the
  * caller: pos_p, vel_p [N][3]; active_idx [N]; acc1, jerk1 [N][3]; pot1 [N];
  * sched (device int64 [4]): after the call sched[0] = t_next,
- * sched[1] = n_active, sched[2] += 1 (steps), sched[3] += clamps. */
+ * sched[1] = n_active, sched[2] += 1 (steps taken), sched[3] += clamps.
+ * A step whose t_next exceeds t_stop_tick is empty (n_active = 0, nothing
+ * changes), so a graph of several steps can be replayed up to a stop time
+ * without the host reading the state in between (INT64_MAX: no stop). */
 int nb_block_step(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
                   const double *mass, double *pos, double *vel, double *acc, double *jerk,
                   int64_t *t_tick, int32_t *dt_level,
                   double *pos_p, double *vel_p, int32_t *active_idx,
-                  double *acc1, double *jerk1, double *pot1, int64_t *sched);
+                  double *acc1, double *jerk1, double *pot1, int64_t *sched, int64_t t_stop_tick);
+
+/* One block step over a batch of C independent systems stored back to back
+ * (system s owns rows offsets[s] .. offsets[s+1]-1; host arrays offsets
+ * [C+1] and eps2 [C]); pairs across systems never interact.  The block step
+ * is global: t_next is the minimum over every system.  The work list
+ * (system, i-block, j-chunk) is built on the device from the scheduled
+ * active set, so the call makes no host-device transfer once the system
+ * table has been uploaded (first call, or when offsets/eps2 change -- not
+ * allowed during a stream capture) and a graph can replay it.  State, work
+ * arrays and sched as for nb_block_step, over all offsets[C] rows. */
+int nb_block_step_batch(nb_ctx *ctx, const int64_t *offsets, int64_t C, const double *eps2, double eta,
+                        double dt_max, int32_t max_level, const double *mass, double *pos, double *vel,
+                        double *acc, double *jerk, int64_t *t_tick, int32_t *dt_level,
+                        double *pos_p, double *vel_p, int32_t *active_idx,
+                        double *acc1, double *jerk1, double *pot1, int64_t *sched, int64_t t_stop_tick);
 
 /* Energy and momenta of a synchronised system, summed in double in a fixed
  * order: out (device double [8]) = K, W, Px, Py, Pz, Lx, Ly, Lz with

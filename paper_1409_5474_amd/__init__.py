@@ -14,13 +14,14 @@ import os
 
 import torch
 
-__all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "lib_path", "library",
+__all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", "lib_path", "library",
            "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
            "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy"]
 
 PREC_FP64 = 0
 PREC_MIXED = 1
-_PREC_NAMES = {"fp64": PREC_FP64, "f64": PREC_FP64, "mixed": PREC_MIXED}
+PREC_MIXED_DS = 2
+_PREC_NAMES = {"fp64": PREC_FP64, "f64": PREC_FP64, "mixed": PREC_MIXED, "mixed_ds": PREC_MIXED_DS}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libnbody.so")
@@ -66,10 +67,11 @@ _sig("hermite_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, 
 _sig("hermite_startup", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
 _sig("nb_schedule", _vp, _vp, _vp, _i64, _i32, _vp, _vp)
 _sig("nb_block_step", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-     _vp, _vp, _vp, _vp)
+     _vp, _vp, _vp, _vp, _i64)
 _sig("nb_energy", _vp, _vp, _vp, _vp, _vp, _i64, _vp)
-if hasattr(_lib, "nbody_forces_batch"):
-    _sig("nbody_forces_batch", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nbody_forces_batch", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
+_sig("nb_block_step_batch", _vp, _vp, _i64, _vp, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+     _vp, _vp, _vp, _vp, _vp, _i64)
 
 
 def library():
@@ -104,7 +106,9 @@ def _check_1d(t, n, name, dtype, dev):
 class Context:
     """One library context on one GPU (``nb_create``)."""
 
-    def __init__(self, device=0, precision="fp64", stream=None):
+    def __init__(self, device=0, precision="fp64", stream=None, load_tuning=True):
+        """load_tuning: install the autotuner's saved table for this GPU
+        (``tuning_gfx950.json`` next to this file) when it exists."""
         prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
         h = ctypes.c_void_p()
         rc = _lib.nb_create(ctypes.byref(h), int(device), prec)
@@ -113,6 +117,10 @@ class Context:
         self._h = h
         self.device = torch.device("cuda", int(device))
         self.set_stream(stream)
+        if load_tuning:
+            from . import autotune
+            if os.path.exists(autotune.DEFAULT_TABLE):
+                autotune.load(self, autotune.DEFAULT_TABLE)
 
     def _chk(self, rc):
         if rc != 0:
@@ -231,10 +239,23 @@ class Context:
                                    _p(sched)))
 
     def block_step(self, N, eps2, eta, dt_max, max_level, mass, pos, vel, acc, jerk, t_tick, dt_level, pos_p, vel_p,
-                   active, acc1, jerk1, pot1, sched):
+                   active, acc1, jerk1, pot1, sched, t_stop_tick=2 ** 63 - 1):
         self._chk(_lib.nb_block_step(self._h, int(N), float(eps2), float(eta), float(dt_max), int(max_level),
                                      _p(mass), _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), _p(dt_level),
-                                     _p(pos_p), _p(vel_p), _p(active), _p(acc1), _p(jerk1), _p(pot1), _p(sched)))
+                                     _p(pos_p), _p(vel_p), _p(active), _p(acc1), _p(jerk1), _p(pot1), _p(sched),
+                                     int(t_stop_tick)))
+
+    def block_step_batch(self, offsets, eps2, eta, dt_max, max_level, mass, pos, vel, acc, jerk, t_tick, dt_level,
+                         pos_p, vel_p, active, acc1, jerk1, pot1, sched, t_stop_tick=2 ** 63 - 1):
+        """offsets (C+1) and eps2 (C): host int64/float64 arrays (kept alive by the caller)."""
+        import numpy as np
+        off = np.ascontiguousarray(offsets, dtype=np.int64)
+        e2 = np.ascontiguousarray(eps2, dtype=np.float64)
+        self._chk(_lib.nb_block_step_batch(self._h, off.ctypes.data_as(_vp), off.shape[0] - 1,
+                                           e2.ctypes.data_as(_vp), float(eta), float(dt_max), int(max_level),
+                                           _p(mass), _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), _p(dt_level),
+                                           _p(pos_p), _p(vel_p), _p(active), _p(acc1), _p(jerk1), _p(pot1),
+                                           _p(sched), int(t_stop_tick)))
 
     def energy(self, pos, vel, mass, pot, out):
         self._chk(_lib.nb_energy(self._h, _p(pos), _p(vel), _p(mass), _p(pot), mass.shape[0], _p(out)))

@@ -1,0 +1,126 @@
+"""Autotuner for the force kernel's launch shape.
+
+For each precision and each active-set bucket it times every built
+(K, L) shape over a range of j-subset counts S with ``nb_time_forces`` (HIP
+events on the context stream) and keeps the fastest.  The winner is stored
+as a table entry (K, L, work-item target = S x i-blocks) covering the active
+counts between the geometric midpoints of neighbouring buckets; the library
+derives S from that target with the paper's saturation rule, identically for
+host-count and device-count launches.
+
+    python -m paper_1409_5474_amd.autotune --n 65536 262144 --out tuning.json
+
+``load(ctx, path)`` installs a saved table into a context.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+# (K, L); L = 0 is the scalar j-path (i-parallel, j-records through the scalar cache)
+SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (1, 256), (2, 1), (2, 4), (2, 16), (4, 1), (4, 4), (1, 0), (2, 0), (4, 0)]
+BUCKETS = [1, 8, 64, 256, 1024, 4096, 16384, 65536, 262144]
+DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
+TILE, WG = 256, 256
+
+
+def _s_candidates(n, n_act, K, L, num_cus):
+    ib = (WG // max(L, 1)) * K
+    n_iblk = -(-n_act // ib)
+    max_s = -(-n // TILE)
+    out = {0}
+    s = 1
+    while s <= max_s and n_iblk * s <= 32 * num_cus:
+        out.add(s)
+        s *= 2
+    return sorted(out), n_iblk
+
+
+def _midpoints(buckets):
+    lo = [0]
+    for a, b in zip(buckets[:-1], buckets[1:]):
+        lo.append(int(math.floor(math.sqrt(a * b))) + 1)
+    hi = [x - 1 for x in lo[1:]] + [2 ** 31 - 1]
+    return list(zip(lo, hi))
+
+
+def tune(ctx, n, precisions=("fp64", "mixed", "mixed_ds"), buckets=BUCKETS, seed=2, reps=3, log=print):
+    import synth
+    dev = ctx.device
+    p = synth.plummer(n, seed)
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    P, V, M = t(p.pos), t(p.vel), t(p.mass)
+    eps2 = 2.0 ** -16
+    num_cus = torch.cuda.get_device_properties(dev).multi_processor_count
+    bks = [b for b in buckets if b <= n]
+    ranges = _midpoints(bks)
+    entries = []
+    for prec in precisions:
+        ctx.set_precision(prec)
+        for b, (lo, hi) in zip(bks, ranges):
+            act = torch.from_numpy(np.linspace(0, n - 1, b).astype(np.int32)).to(dev)
+            acc = torch.empty((b, 3), dtype=torch.float64, device=dev)
+            jerk = torch.empty_like(acc)
+            pot = torch.empty(b, dtype=torch.float64, device=dev)
+            best = None
+            for K, L in SHAPES:
+                if K > 1 and b < 64 * K:
+                    continue
+                svals, n_iblk = _s_candidates(n, b, K, L, num_cus)
+                for S in svals:
+                    r = reps if b * n < 2 ** 32 else max(1, reps - 1)
+                    ms = ctx.time_forces(K, L, S, P, V, M, act, eps2, acc, jerk, pot, reps=r)
+                    if best is None or ms < best[0]:
+                        best = (ms, K, L, S, n_iblk)
+            ms, K, L, S, n_iblk = best
+            items = S * n_iblk if S else 0
+            e = dict(prec=prec, n_min=n, act_min=lo, act_max=hi, K=K, L=L, items=items, ms=round(ms, 5),
+                     rep_n_active=b, gint=round(b * n / ms / 1e6, 2))
+            entries.append(e)
+            log(json.dumps(e))
+    return entries
+
+
+def save(entries, path, meta=None):
+    doc = {"format": 1, "meta": meta or {}, "entries": entries}
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+
+
+def load(ctx, path=DEFAULT_TABLE):
+    """Install a saved table into a context (entries in file order)."""
+    with open(path) as f:
+        doc = json.load(f)
+    for e in sorted(doc["entries"], key=lambda e: e["n_min"]):
+        ctx.tune_add(e["prec"], e["n_min"], e["act_min"], e["act_max"], e["K"], e["L"], e["items"])
+    return len(doc["entries"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, nargs="+", default=[65536, 262144])
+    ap.add_argument("--prec", nargs="+", default=["fp64", "mixed", "mixed_ds"])
+    ap.add_argument("--out", default="tuning.json")
+    ap.add_argument("--reps", type=int, default=3)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_1409_5474_amd as nb
+    ctx = nb.Context(0, "fp64", load_tuning=False)
+    t0 = time.time()
+    entries = []
+    for n in sorted(args.n):
+        entries += tune(ctx, n, args.prec, reps=args.reps)
+        print(f"# N={n} done after {time.time() - t0:.0f} s", flush=True)
+    props = torch.cuda.get_device_properties(0)
+    save(entries, args.out, meta={"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+                                  "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1)})
+    print(f"wrote {args.out} ({len(entries)} entries)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

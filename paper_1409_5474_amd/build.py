@@ -11,13 +11,14 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-OUT = os.path.join(HERE, "libnbody.so")
-OBJ = os.path.join(HERE, "_build")
+OUT = os.environ.get("NB_LIB_OUT") or os.path.join(HERE, "libnbody.so")
+OBJ = os.path.join(os.path.dirname(OUT), "_build")
 SOURCES = ["forces.hip", "hermite.hip", "api.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+EXTRA = os.environ.get("NB_HIPCC_EXTRA", "").split()
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", *EXTRA,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
 

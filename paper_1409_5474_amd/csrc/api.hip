@@ -56,6 +56,23 @@ int ensure_ws(nb_ctx* c, size_t bytes) {
   return NB_OK;
 }
 
+// The j-record mirror of the scalar j-path (L = 0), grown on demand.
+int ensure_mirror(nb_ctx* c, int64_t n) {
+  const size_t bytes = nb::mirror_bytes(c->prec, n);
+  if (bytes <= c->mirror_bytes) return NB_OK;
+  if (capturing(c->stream)) return fail(c, NB_ENOMEM, "j-record mirror must grow during capture%s");
+  (void)hipStreamSynchronize(c->stream);
+  if (c->mirror) (void)hipFree(c->mirror);
+  c->mirror = nullptr;
+  c->mirror_bytes = 0;
+  if (hipMalloc(&c->mirror, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, NB_ENOMEM, "hipMalloc of the j-record mirror failed%s");
+  }
+  c->mirror_bytes = bytes;
+  return NB_OK;
+}
+
 int ensure_sched(nb_ctx* c, int64_t n) {
   const int nblk = nb::schedule_blocks(n);
   const size_t need = (size_t)nblk;
@@ -91,42 +108,71 @@ int ensure_energy(nb_ctx* c, int64_t n) {
   return NB_OK;
 }
 
+bool valid_prec(int p) { return p == NB_PREC_FP64 || p == NB_PREC_MIXED || p == NB_PREC_MIXED_DS; }
+
 bool valid_K(int K) { return K == 1 || K == 2 || K == 4; }
-bool valid_L(int L) { return L >= 1 && L <= 256 && (L & (L - 1)) == 0; }
+// L = 0 selects the scalar j-path (i-parallel, j-records through the scalar cache)
+bool valid_L(int L) { return L == 0 || (L >= 1 && L <= 256 && (L & (L - 1)) == 0); }
 
 int target_items(const nb_ctx* c) { return c->num_cus * 4; }
 
-// Built-in choice before any tuning: the i-parallel layout when the active
-// set alone fills the chip, more lanes per i-particle as it shrinks.
-Launch default_launch(int prec, int64_t n_act) {
-  (void)prec;
-  if (n_act >= 65536) return Launch{2, 1, 0};
-  if (n_act >= 8192) return Launch{1, 1, 0};
-  if (n_act >= 1024) return Launch{1, 4, 0};
-  if (n_act >= 128) return Launch{1, 16, 0};
-  return Launch{1, 64, 0};
+// Workgroups the whole chip holds at once for this kernel shape.
+int resident_grid(const nb_ctx* c, const Launch& cfg, bool mask) {
+  return c->num_cus * nb::resident_wgs(c->prec, cfg, mask);
 }
 
+// Default work-item target: four items per resident workgroup, so a
+// persistent grid of resident workgroups walks equal shares of the work.
+int default_items(const nb_ctx* c, const Launch& cfg) { return 4 * resident_grid(c, cfg, false); }
+
+// Built-in choice before any tuning: the i-parallel layout when the active
+// set alone fills the chip, more lanes per i-particle as it shrinks.
+struct Regime {
+  int64_t lo, hi;
+  Launch cfg;
+};
+const Regime kDefaultRegimes[5] = {{0, 127, Launch{1, 64, 0, 0}},
+                                   {128, 1023, Launch{1, 16, 0, 0}},
+                                   {1024, 8191, Launch{1, 4, 0, 0}},
+                                   {8192, 65535, Launch{1, 1, 0, 0}},
+                                   {65536, INT64_MAX, Launch{2, 1, 0, 0}}};
+
+// The active-count regimes of this context and precision: the tuned table
+// entries that apply to N (later entries override earlier ones on their
+// range), else the built-in breakpoints.  Regimes tile [0, inf).
+std::vector<Regime> regimes(const nb_ctx* c, int64_t n) {
+  std::vector<Regime> r(std::begin(kDefaultRegimes), std::end(kDefaultRegimes));
+  for (const nb::TuneEntry& e : c->table) {
+    if (e.prec != c->prec || n < e.n_min) continue;
+    std::vector<Regime> out;
+    for (const Regime& g : r) {
+      if (g.hi < e.act_min || g.lo > e.act_max) {
+        out.push_back(g);
+        continue;
+      }
+      if (g.lo < e.act_min) out.push_back(Regime{g.lo, e.act_min - 1, g.cfg});
+      if (g.hi > e.act_max) out.push_back(Regime{e.act_max + 1, g.hi, g.cfg});
+    }
+    out.push_back(Regime{e.act_min, e.act_max, e.cfg});
+    std::sort(out.begin(), out.end(), [](const Regime& a, const Regime& b) { return a.lo < b.lo; });
+    r.swap(out);
+  }
+  return r;
+}
+
+// Resolve K, L and the work-item target for an active count; S is then the
+// saturation rule unless a forced configuration fixes it.
 Launch choose(const nb_ctx* c, int64_t n, int64_t n_act) {
   Launch cfg;
-  bool found = false;
   if (c->have_forced) {
     cfg = c->forced;
-    found = true;
   } else {
-    for (auto it = c->table.rbegin(); it != c->table.rend(); ++it) {
-      if (it->prec == c->prec && n >= it->n_min && n_act >= it->act_min && n_act <= it->act_max) {
-        cfg = it->cfg;
-        found = true;
-        break;
-      }
-    }
+    for (const Regime& g : regimes(c, n))
+      if (n_act >= g.lo && n_act <= g.hi) cfg = g.cfg;
   }
-  if (!found) cfg = default_launch(c->prec, n_act);
-  if (cfg.S <= 0) {
-    const int IB = (nb::kWG / cfg.L) * cfg.K;
-    cfg.S = nb::host_choose_S(n_act, IB, target_items(c), n);
-  }
+  if (cfg.items <= 0) cfg.items = default_items(c, cfg);
+  const int IB = nb::ib_of(cfg);
+  if (cfg.S <= 0) cfg.S = nb::host_choose_S(n_act, IB, cfg.items, n);
   const int64_t max_s = (n + nb::kTile - 1) / nb::kTile;
   if (cfg.S > max_s) cfg.S = (int)max_s;
   return cfg;
@@ -143,21 +189,27 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
   nb::ForceArgs a{};
   a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
   a.active = active; a.n_active = n_active; a.n_active_dev = nullptr;
-  a.eps2 = eps2; a.S = cfg.S; a.target_items = target_items(c);
+  a.eps2 = eps2; a.S = cfg.S; a.target_items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
   a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr;
   const bool mask = kernel_mask(c->prec, eps2);
   Launch eff = cfg;
   if (mask) eff.K = 1;
+  const int max_grid = resident_grid(c, eff, mask);
+  if (eff.L == 0) {
+    int rc = ensure_mirror(c, N);
+    if (rc) return rc;
+    a.rec = c->mirror;
+  }
   if (cfg.S > 1) {
     const size_t bytes = (size_t)cfg.S * 7 * (size_t)n_active * sizeof(double);
     int rc = ensure_ws(c, bytes);
     if (rc) return rc;
     a.part = static_cast<double*>(c->ws);
   }
-  hipError_t e = nb::launch_forces(c->prec, eff, mask, a, c->stream, 0);
+  hipError_t e = nb::launch_forces(c->prec, eff, mask, a, c->stream, 0, max_grid);
   if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
   if (cfg.S > 1) {
-    const int IB = (nb::kWG / eff.L) * eff.K;
+    const int IB = nb::ib_of(eff);
     e = nb::launch_reduce_ib(c->prec, a, cfg.S, IB, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch");
   }
@@ -184,7 +236,7 @@ const char* nb_version(void) { return kVersion; }
 int nb_create(nb_ctx** out, int device, int precision) {
   if (!out) return NB_EINVAL;
   *out = nullptr;
-  if (precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) return NB_EINVAL;
+  if (!valid_prec(precision)) return NB_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
     (void)hipGetLastError();
@@ -208,6 +260,7 @@ int nb_destroy(nb_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   if (c->ws) (void)hipFree(c->ws);
+  if (c->mirror) (void)hipFree(c->mirror);
   if (c->sched_tmp) (void)hipFree(c->sched_tmp);
   if (c->sched_cnt) (void)hipFree(c->sched_cnt);
   if (c->nact32) (void)hipFree(c->nact32);
@@ -215,6 +268,7 @@ int nb_destroy(nb_ctx* c) {
   if (c->batch_buf) (void)hipFree(c->batch_buf);
   if (c->batch_host) (void)hipHostFree(c->batch_host);
   if (c->batch_ev) (void)hipEventDestroy(c->batch_ev);
+  if (c->bp_buf) (void)hipFree(c->bp_buf);
   delete c;
   return NB_OK;
 }
@@ -227,7 +281,7 @@ int nb_set_stream(nb_ctx* c, void* s) {
 
 int nb_set_precision(nb_ctx* c, int precision) {
   if (!c) return NB_EINVAL;
-  if (precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) return fail(c, NB_EINVAL, "unknown precision%s");
+  if (!valid_prec(precision)) return fail(c, NB_EINVAL, "unknown precision%s");
   c->prec = precision;
   return NB_OK;
 }
@@ -244,7 +298,7 @@ int nb_set_launch(nb_ctx* c, int K, int L, int S) {
   }
   if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
   if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  c->forced = Launch{K, L, S};
+  c->forced = Launch{K, L, S, 0};
   c->have_forced = true;
   return NB_OK;
 }
@@ -256,13 +310,13 @@ int nb_get_launch(nb_ctx* c, int64_t N, int64_t n_active, int* K, int* L, int* S
   return NB_OK;
 }
 
-int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_t act_max, int K, int L, int S) {
+int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_t act_max, int K, int L, int S) {  // S: work-item target
   if (!c) return NB_EINVAL;
-  if ((precision != NB_PREC_FP64 && precision != NB_PREC_MIXED) || !valid_K(K) || !valid_L(L) || S < 0 ||
+  if (!valid_prec(precision) || !valid_K(K) || !valid_L(L) || S < 0 ||
       act_min > act_max)
     return fail(c, NB_EINVAL, "bad tune entry%s");
   if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, Launch{K, L, S}});
+  c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, Launch{K, L, 0, S}});
   return NB_OK;
 }
 
@@ -289,8 +343,9 @@ int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const doub
   if (!ms || reps < 1 || n_active < 1) return fail(c, NB_EINVAL, "reps >= 1, n_active >= 1 and ms required%s");
   if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
   if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  Launch cfg{K, L, S};
-  if (cfg.S == 0) cfg.S = nb::host_choose_S(n_active, (nb::kWG / L) * K, target_items(c), N);
+  Launch cfg{K, L, S, 0};
+  cfg.items = default_items(c, cfg);
+  if (cfg.S == 0) cfg.S = nb::host_choose_S(n_active, nb::ib_of(cfg), cfg.items, N);
   const int64_t max_s = (N + nb::kTile - 1) / nb::kTile;
   if (cfg.S > max_s) cfg.S = (int)max_s;
   rc = run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
@@ -326,42 +381,50 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   if (max_active == 0) return NB_OK;
   const bool mask = kernel_mask(c->prec, eps2);
   // One fixed launch per regime; the count decides on the device which one works.
-  struct Regime {
-    int64_t lo, hi;
-  };
-  const Regime regimes[5] = {{0, 127}, {128, 1023}, {1024, 8191}, {8192, 65535}, {65536, INT64_MAX}};
+  const std::vector<Regime> regs = regimes(c, N);
   size_t ws_need = 0;
-  for (const Regime& r : regimes) {
+  for (const Regime& r : regs) {
     if (r.lo > max_active) break;
     const int64_t top = r.hi < max_active ? r.hi : max_active;
-    Launch cfg = choose(c, N, top);
+    Launch cfg = c->have_forced ? c->forced : r.cfg;
     if (mask) cfg.K = 1;
-    const int IB = (nb::kWG / cfg.L) * cfg.K;
+    const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
+    const int IB = nb::ib_of(cfg);
     const int64_t n_iblk_max = (top + IB - 1) / IB;
-    const size_t rows = (size_t)(target_items(c) + n_iblk_max) * IB;
+    const size_t rows = (size_t)(items + n_iblk_max) * IB;
     const size_t need = rows * 7 * sizeof(double);
     if (need > ws_need) ws_need = need;
   }
   rc = ensure_ws(c, ws_need);
   if (rc) return rc;
-  for (const Regime& r : regimes) {
+  bool need_mirror = false;
+  for (const Regime& r : regs)
+    if (r.lo <= max_active && (c->have_forced ? c->forced.L : r.cfg.L) == 0) need_mirror = true;
+  if (need_mirror) {
+    rc = ensure_mirror(c, N);
+    if (rc) return rc;
+  }
+  for (const Regime& r : regs) {
     if (r.lo > max_active) break;
     const int64_t top = r.hi < max_active ? r.hi : max_active;
-    Launch cfg = choose(c, N, top);
+    Launch cfg = c->have_forced ? c->forced : r.cfg;
     if (mask) cfg.K = 1;
+    const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
     nb::ForceArgs a{};
-    a.last = 0;
     a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
     a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
     a.act_lo = r.lo;
     a.last = (top == max_active) ? 1 : 0;
-    a.eps2 = eps2; a.S = 1; a.target_items = target_items(c);
+    a.eps2 = eps2; a.S = 1; a.target_items = items;
     a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = nullptr;
-    const int IB = (nb::kWG / cfg.L) * cfg.K;
+    a.rec = c->mirror;
+    const int IB = nb::ib_of(cfg);
     const int64_t n_iblk_max = (top + IB - 1) / IB;
-    int64_t grid = target_items(c) + n_iblk_max;
-    if (grid > 8 * c->num_cus * 4) grid = 8 * c->num_cus * 4;
-    hipError_t e = nb::launch_forces(c->prec, cfg, mask, a, c->stream, (int)grid);
+    // persistent: at most one round of resident workgroups walks the items
+    int64_t grid = items + n_iblk_max;
+    const int64_t rg = resident_grid(c, cfg, mask);
+    if (grid > rg) grid = rg;
+    hipError_t e = nb::launch_forces(c->prec, cfg, mask, a, c->stream, (int)grid, 0);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch (device count)");
     e = nb::launch_reduce_ib(c->prec, a, 1, IB, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch (device count)");
@@ -424,14 +487,14 @@ int nb_schedule(nb_ctx* c, const int64_t* t_tick, const int32_t* dt_level, int64
   int rc = ensure_sched(c, N);
   if (rc) return rc;
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, c->stream);
+                                     c->nact32, INT64_MAX, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "schedule launch");
 }
 
 int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
                   const double* mass, double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick,
                   int32_t* dt_level, double* pos_p, double* vel_p, int32_t* active, double* acc1, double* jerk1,
-                  double* pot1, int64_t* sched) {
+                  double* pot1, int64_t* sched, int64_t t_stop_tick) {
   if (!c) return NB_EINVAL;
   if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
   int rc = check_levels(c, eta, dt_max, max_level);
@@ -444,7 +507,7 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, c->stream);
+                                     c->nact32, t_stop_tick, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "predict launch");
@@ -491,7 +554,7 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
     cfg.K = 1;
     cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
   }
-  const int IB = (nb::kWG / cfg.L) * cfg.K;
+  const int IB = nb::ib_of(cfg);
   // total work in (i-slot x j) units and the chunk length that splits it
   double work = 0.0;
   for (int64_t s = 0; s < C; ++s) {
@@ -572,8 +635,8 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   const nb::BatchItem* d_items = reinterpret_cast<const nb::BatchItem*>(db);
   const nb::BatchSys* d_sys = reinterpret_cast<const nb::BatchSys*>(db + off_sys);
   const int32_t* d_nch = reinterpret_cast<const int32_t*>(db + off_nch);
-  e = nb::launch_batch(c->prec, cfg, d_items, (int)items.size(), d_sys, pos, vel, mass, active, acc, jerk, pot,
-                       static_cast<double*>(c->ws), part_rows, any_mask, c->stream);
+  e = nb::launch_batch(c->prec, cfg, d_items, (int)items.size(), nullptr, d_sys, pos, vel, mass, active, acc, jerk,
+                       pot, static_cast<double*>(c->ws), part_rows, any_mask, 0, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
   if (part_rows > 0) {
     e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, a_total, acc, jerk, pot,
@@ -581,6 +644,104 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
     if (e != hipSuccess) return hip_fail(c, e, "batch reduce launch");
   }
   return NB_OK;
+}
+
+// Block step over a batch of independent systems, planned on the device.
+// The system table (offsets, softenings) is uploaded on the first call and
+// whenever it changes (never during a capture); after that a step makes no
+// host-device transfer and can be replayed from a graph.
+extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const double* eps2, double eta, double dt_max,
+                        int32_t max_level, const double* mass, double* pos, double* vel, double* acc, double* jerk,
+                        int64_t* t_tick, int32_t* dt_level, double* pos_p, double* vel_p, int32_t* active,
+                        double* acc1, double* jerk1, double* pot1, int64_t* sched, int64_t t_stop_tick) {
+  if (!c) return NB_EINVAL;
+  if (C < 1 || C > (1 << 20) || !offsets || !eps2) return fail(c, NB_EINVAL, "C in [1, 2^20] and host offsets/eps2 required%s");
+  if (offsets[0] != 0) return fail(c, NB_EINVAL, "offsets must start at 0%s");
+  const int64_t N = offsets[C];
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "total rows must be in [1, 2^31)%s");
+  bool any_mask = false;
+  for (int64_t s = 0; s < C; ++s) {
+    if (offsets[s + 1] < offsets[s]) return fail(c, NB_EINVAL, "offsets must be non-decreasing%s");
+    if (!finite_nonneg(eps2[s])) return fail(c, NB_EINVAL, "every eps2 must be finite and >= 0%s");
+    any_mask = any_mask || kernel_mask(c->prec, eps2[s]);
+  }
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (!mass || !pos || !vel || !acc || !jerk || !t_tick || !dt_level || !pos_p || !vel_p || !active || !acc1 ||
+      !jerk1 || !pot1 || !sched)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  rc = ensure_sched(c, N);
+  if (rc) return rc;
+  // one kernel shape for the batch, from the typical system size
+  Launch cfg = choose(c, N, (N + C - 1) / C);
+  if (any_mask) cfg.K = 1;
+  if (cfg.K == 4 || (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64) || (cfg.K == 2 && cfg.L == 64)) {
+    cfg.K = 1;
+    cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
+  }
+  const int IB = nb::ib_of(cfg);
+  const int rgrid = resident_grid(c, cfg, any_mask);
+  const int target = 2 * rgrid;
+  const int max_items = target + (int)((N + IB - 1) / IB) + (int)C + 64;
+  const int64_t part_cap = (int64_t)IB * target + N;
+  // device system table and work list
+  const size_t o_off = 0;
+  const size_t o_eps = o_off + ((size_t)(C + 1) * 8 + 255) / 256 * 256;
+  const size_t o_sys = o_eps + ((size_t)C * 8 + 255) / 256 * 256;
+  const size_t o_nch = o_sys + ((size_t)C * sizeof(nb::BatchSys) + 255) / 256 * 256;
+  const size_t o_items = o_nch + ((size_t)C * 4 + 255) / 256 * 256;
+  const size_t o_nit = o_items + ((size_t)max_items * sizeof(nb::BatchItem) + 255) / 256 * 256;
+  const size_t total = o_nit + 256;
+  const bool same = c->bp_buf && c->bp_off.size() == (size_t)C + 1 &&
+                    std::equal(c->bp_off.begin(), c->bp_off.end(), offsets) &&
+                    std::equal(c->bp_eps2.begin(), c->bp_eps2.end(), eps2) && total <= c->bp_cap;
+  if (!same) {
+    if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "the batch table changed during a capture; run one step first%s");
+    (void)hipStreamSynchronize(c->stream);
+    if (total > c->bp_cap) {
+      if (c->bp_buf) (void)hipFree(c->bp_buf);
+      c->bp_buf = nullptr;
+      c->bp_cap = 0;
+      if (hipMalloc(&c->bp_buf, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, NB_ENOMEM, "hipMalloc of the batch plan failed%s");
+      }
+      c->bp_cap = total;
+    }
+    char* b = static_cast<char*>(c->bp_buf);
+    if (hipMemcpy(b + o_off, offsets, (size_t)(C + 1) * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b + o_eps, eps2, (size_t)C * 8, hipMemcpyHostToDevice) != hipSuccess)
+      return hip_fail(c, hipGetLastError(), "batch table upload");
+    c->bp_off.assign(offsets, offsets + C + 1);
+    c->bp_eps2.assign(eps2, eps2 + C);
+  }
+  rc = ensure_ws(c, (size_t)part_cap * 7 * sizeof(double));
+  if (rc) return rc;
+  char* b = static_cast<char*>(c->bp_buf);
+  const int64_t* d_off = reinterpret_cast<const int64_t*>(b + o_off);
+  const double* d_eps = reinterpret_cast<const double*>(b + o_eps);
+  nb::BatchSys* d_sys = reinterpret_cast<nb::BatchSys*>(b + o_sys);
+  int32_t* d_nch = reinterpret_cast<int32_t*>(b + o_nch);
+  nb::BatchItem* d_items = reinterpret_cast<nb::BatchItem*>(b + o_items);
+  int* d_nit = reinterpret_cast<int*>(b + o_nit);
+  const double dt_min = std::ldexp(dt_max, -max_level);
+  hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
+                                     c->nact32, t_stop_tick, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
+  e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "predict launch");
+  e = nb::launch_batch_plan(d_off, d_eps, (int)C, active, sched + 1, IB, target, d_sys, d_nch, d_items, max_items,
+                            d_nit, part_cap, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch plan launch");
+  e = nb::launch_batch(c->prec, cfg, d_items, max_items, d_nit, d_sys, pos_p, vel_p, mass, active, acc1, jerk1, pot1,
+                       static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
+  e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, N, acc1, jerk1, pot1,
+                              static_cast<double*>(c->ws), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "batch reduce launch");
+  e = nb::launch_correct_step(active, N, sched + 1, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level,
+                              eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
 }
 
 int nb_energy(nb_ctx* c, const double* pos, const double* vel, const double* mass, const double* pot, int64_t N,

@@ -35,6 +35,16 @@
 // exactly zero to a and jdot and m_i q(eps2) to the potential sum, which is
 // removed afterwards using the identical value.  With eps2 == 0 the MASK
 // variant drops every pair with s == 0 instead.
+#include <map>
+#include <mutex>
+
+// Unroll factor of the pair loop over a staged tile: more unrolling gives
+// the scheduler more independent LDS reads, fewer leaves VGPRs for more
+// resident waves (which the dual VALU issue of gfx950 needs).
+#ifndef NB_JJ_UNROLL
+#define NB_JJ_UNROLL 4
+#endif
+
 #include "nb_internal.h"
 
 namespace nb {
@@ -145,6 +155,13 @@ struct F64 {
   static __device__ __forceinline__ double value(const Tot& t, int c) { return t.hi[c] + t.lo[c]; }
   // The value the pair loop adds to the potential sum for the self pair.
   static __device__ __forceinline__ double self_term(double m, double eps2) { return m * rsqrt_f64(eps2); }
+  // The pair from a j-record held in (scalar) registers.
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_reg(const JReg& r, const IPart* I, T e2, T (*A)[7], int kcount) {
+#pragma unroll
+    for (int k = 0; k < kcount; ++k)
+      pair<MASK>(I[k], make_double2(r.x, r.y), make_double2(r.z, r.m), make_double2(r.vx, r.vy), r.vz, e2, A[k]);
+  }
 };
 
 // ---------------------------------------------------------------- Mixed ----
@@ -239,6 +256,127 @@ struct Mixed {
   static __device__ __forceinline__ double self_term(double m, double eps2) {
     return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
   }
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_reg(const JReg& r, const IPart* I, T e2, T (*A)[7], int kcount) {
+#pragma unroll
+    for (int k = 0; k < kcount; ++k)
+      pair<MASK>(I[k], make_double2(r.x, r.y), r.z, make_float4(r.vx, r.vy, r.vz, r.m), e2, A[k]);
+  }
+};
+
+// ------------------------------------------------------------- MixedDS -----
+// As Mixed, but the separation is formed in emulated double precision on
+// float hardware (the paper's remedy for single-precision devices): every
+// position is split once, at staging, into x = hi + lo (two floats), and
+//   r = (x_j,hi - x_i,hi) + (x_j,lo - x_i,lo)
+// costs three float operations instead of a double subtraction and a
+// conversion.  The error of r stays within a few float ulps of |r|.
+struct MixedDS {
+  using T = float;
+  struct JTile {
+    float4 hm[kTile];   // x_hi, y_hi, z_hi, m
+    float4 lv[kTile];   // x_lo, y_lo, z_lo, vx
+    float2 vyz[kTile];  // vy, vz
+  };
+  struct JReg {
+    float4 hm, lv;
+    float2 vyz;
+  };
+  struct IPart {
+    float xh, yh, zh, xl, yl, zl, vx, vy, vz;
+  };
+  struct Tot {
+    double v[7];
+  };
+  static __device__ __forceinline__ void split(double x, float& hi, float& lo) {
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+  }
+  static __device__ __forceinline__ JReg load(const double* pos, const double* vel, const double* mass,
+                                              int64_t j, bool valid) {
+    JReg r;
+    if (valid) {
+      float xh, xl, yh, yl, zh, zl;
+      split(pos[3 * j], xh, xl);
+      split(pos[3 * j + 1], yh, yl);
+      split(pos[3 * j + 2], zh, zl);
+      r.hm = make_float4(xh, yh, zh, (float)mass[j]);
+      r.lv = make_float4(xl, yl, zl, (float)vel[3 * j]);
+      r.vyz = make_float2((float)vel[3 * j + 1], (float)vel[3 * j + 2]);
+    } else {
+      r.hm = make_float4(0.f, 0.f, 0.f, 0.f);
+      r.lv = make_float4(0.f, 0.f, 0.f, 0.f);
+      r.vyz = make_float2(0.f, 0.f);
+    }
+    return r;
+  }
+  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+    t.hm[s] = r.hm;
+    t.lv[s] = r.lv;
+    t.vyz[s] = r.vyz;
+  }
+  static __device__ __forceinline__ IPart load_i(const double* pos, const double* vel, int64_t i) {
+    IPart p;
+    split(pos[3 * i], p.xh, p.xl);
+    split(pos[3 * i + 1], p.yh, p.yl);
+    split(pos[3 * i + 2], p.zh, p.zl);
+    p.vx = (float)vel[3 * i]; p.vy = (float)vel[3 * i + 1]; p.vz = (float)vel[3 * i + 2];
+    return p;
+  }
+  static __device__ __forceinline__ T eps(double eps2) { return (float)eps2; }
+
+  template <bool MASK>
+  static __device__ __forceinline__ void pair(const IPart& I, const float4 hm, const float4 lv, const float2 vyz,
+                                              const T e2, T* A) {
+    const float dx = (hm.x - I.xh) + (lv.x - I.xl);
+    const float dy = (hm.y - I.yh) + (lv.y - I.yl);
+    const float dz = (hm.z - I.zh) + (lv.z - I.zl);
+    const float s = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, e2)));
+    float q = __builtin_amdgcn_rsqf(s);
+    if (MASK) q = (s > 0.0f) ? q : 0.0f;
+    const float ux = lv.w - I.vx, uy = vyz.x - I.vy, uz = vyz.y - I.vz;
+    const float rv = fmaf(dz, uz, fmaf(dy, uy, dx * ux));
+    const float q2 = q * q;
+    const float mq = hm.w * q;
+    const float mq3 = mq * q2;
+    const float c = -3.0f * (rv * q2);
+    A[0] = fmaf(mq3, dx, A[0]);
+    A[1] = fmaf(mq3, dy, A[1]);
+    A[2] = fmaf(mq3, dz, A[2]);
+    A[3] = fmaf(mq3, fmaf(c, dx, ux), A[3]);
+    A[4] = fmaf(mq3, fmaf(c, dy, uy), A[4]);
+    A[5] = fmaf(mq3, fmaf(c, dz, uz), A[5]);
+    A[6] += mq;
+  }
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+                                                   int kcount) {
+    const float4 hm = t.hm[s];
+    const float4 lv = t.lv[s];
+    const float2 vyz = t.vyz[s];
+#pragma unroll
+    for (int k = 0; k < kcount; ++k) pair<MASK>(I[k], hm, lv, vyz, e2, A[k]);
+  }
+  static __device__ __forceinline__ void zero(Tot& t) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) t.v[c] = 0.0;
+  }
+  static __device__ __forceinline__ void fold(Tot& t, T* A) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      t.v[c] += (double)A[c];
+      A[c] = 0.0f;
+    }
+  }
+  static __device__ __forceinline__ double value(const Tot& t, int c) { return t.v[c]; }
+  static __device__ __forceinline__ double self_term(double m, double eps2) {
+    return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
+  }
+  template <bool MASK>
+  static __device__ __forceinline__ void pair_reg(const JReg& r, const IPart* I, T e2, T (*A)[7], int kcount) {
+#pragma unroll
+    for (int k = 0; k < kcount; ++k) pair<MASK>(I[k], r.hm, r.lv, r.vyz, e2, A[k]);
+  }
 };
 
 // The j-split chosen on the device (device-count mode) and on the host
@@ -299,7 +437,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
     __syncthreads();
     const int64_t nb = base + kTile;
     if (nb < jend) nxt = P::load(pos, vel, mass, nb + t, nb + t < jend);
-#pragma unroll 4
+#pragma unroll NB_JJ_UNROLL
     for (int jj = sub; jj < kTile; jj += L) P::template pair_tile<MASK>(tile, jj, I, e2, A, K);
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) P::fold(Tt[kk], A[kk]);
@@ -415,15 +553,128 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
   }
 }
 
+
+// ------------------------------------------------------- scalar j-path -----
+// Variant of the i-parallel layout (L = 1) without LDS: the j-records are
+// first converted once per call into the kernel's layout (a mirror array),
+// and every wavefront then walks them with a wave-uniform index, so the
+// compiler reads them through the scalar data cache into SGPRs (one-ahead
+// prefetch).  No barriers, no LDS, no VGPRs for j-data; the VALU
+// instructions take their j operand from an SGPR.
+template <class P>
+__global__ __launch_bounds__(256) void k_mirror(const double* __restrict__ pos, const double* __restrict__ vel,
+                                                const double* __restrict__ mass, int64_t n,
+                                                typename P::JReg* __restrict__ rec) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
+    rec[j] = P::load(pos, vel, mass, j, true);
+}
+
+template <class P, int K, bool MASK>
+__device__ __forceinline__ void process_item_sj(const typename P::JReg* __restrict__ rec,
+                                                const double* __restrict__ pos, const double* __restrict__ vel,
+                                                const double* __restrict__ mass, int64_t jbeg, int64_t jend,
+                                                const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
+                                                double eps2, bool final_out, double* __restrict__ acc,
+                                                double* __restrict__ jerk, double* __restrict__ pot,
+                                                double* __restrict__ part) {
+  const int t = threadIdx.x;
+  typename P::IPart I[K];
+  int64_t irow[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int64_t k = k0 + kk * kWG + t;
+    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+  }
+  const typename P::T e2 = P::eps(eps2);
+  typename P::T A[K][7];
+  typename P::Tot Tt[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    P::zero(Tt[kk]);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) A[kk][c] = 0;
+  }
+  if (jbeg < jend) {
+    typename P::JReg nxt = rec[jbeg];
+    for (int64_t base = jbeg; base < jend; base += kTile) {
+      if (base + kTile <= jend) {
+#pragma unroll NB_JJ_UNROLL
+        for (int jj = 0; jj < kTile; ++jj) {
+          const typename P::JReg r = nxt;
+          const int64_t jn = base + jj + 1;
+          nxt = rec[jn < jend ? jn : jbeg];
+          P::template pair_reg<MASK>(r, I, e2, A, K);
+        }
+      } else {
+        for (int64_t j = base; j < jend; ++j) {
+          const typename P::JReg r = nxt;
+          nxt = rec[j + 1 < jend ? j + 1 : jbeg];
+          P::template pair_reg<MASK>(r, I, e2, A, K);
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < K; ++kk) P::fold(Tt[kk], A[kk]);
+    }
+  }
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int64_t k = k0 + kk * kWG + t;
+    if (k < n_act) {
+      double v[7];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
+      if (final_out) {
+        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
+        jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
+        pot[k] = -(v[6] - self);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) part[c * n_act + k] = v[c];
+      }
+    }
+  }
+}
+
+template <class P, int K, bool MASK>
+__global__ __launch_bounds__(kWG) void k_forces_sj(ForceArgs a, const typename P::JReg* __restrict__ rec) {
+  constexpr int IB = kWG * K;
+  int64_t n_act = a.n_active;
+  int S = a.S;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    if (d < a.act_lo || (d > a.n_active && !a.last)) return;
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    S = choose_S(n_act, IB, a.target_items, a.n);
+  }
+  const int64_t n_iblk = (n_act + IB - 1) / IB;
+  const int64_t items = n_iblk * S;
+  const int64_t clen = chunk_len(a.n, S);
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const int64_t chunk = w / n_iblk;
+    const int64_t iblk = w - chunk * n_iblk;
+    const int64_t jb = chunk * clen;
+    const int64_t je = jb + clen < a.n ? jb + clen : a.n;
+    process_item_sj<P, K, MASK>(rec, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
+                                a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+  }
+}
+
 // ---------------------------------------------------------------- batch ----
 template <class P, int K, int L, bool MASK>
 __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restrict__ items, int n_items,
+                                                      const int* __restrict__ n_items_dev,
                                                       const BatchSys* __restrict__ sys, const double* pos,
                                                       const double* vel, const double* mass,
                                                       const int32_t* active, double* acc, double* jerk,
                                                       double* pot, double* part) {
   __shared__ Smem<P, L> sm;
   constexpr int IB = (kWG / L) * K;
+  if (n_items_dev) {
+    const int d = *n_items_dev;
+    n_items = d < n_items ? (d < 0 ? 0 : d) : n_items;
+  }
   for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
     const BatchItem it = items[w];
     const BatchSys sy = sys[it.sys];
@@ -468,10 +719,147 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict
   }
 }
 
+
+// ------------------------------------------------------------ batch plan ---
+// One workgroup turns the scheduled active set of a batch of independent
+// systems into the work list of the batched force kernel, entirely on the
+// device (so a block step over the batch can be captured in a graph):
+//   per system: its rows of the (ascending) active list by binary search,
+//   n_iblk = ceil(n_act / IB); a common chunk length J chosen so the whole
+//   batch yields about `target` items; S_c = ceil(nj / J) chunks (at least
+//   one tile each); items (system, i-block, chunk) and partial-sum offsets
+//   by exclusive scans over the systems.
+constexpr int kPlanThreads = 1024;
+
+__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int64_t key) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)a[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__device__ int64_t block_sum_i64(int64_t v, int64_t* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const int64_t r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// exclusive scan of one value per thread (thread order); returns the total
+__device__ int64_t block_exscan_i64(int64_t v, int64_t* red, int64_t* excl) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 1; o < kPlanThreads; o <<= 1) {
+    const int64_t t = (int)threadIdx.x >= o ? red[threadIdx.x - o] : 0;
+    __syncthreads();
+    red[threadIdx.x] += t;
+    __syncthreads();
+  }
+  *excl = red[threadIdx.x] - v;
+  const int64_t total = red[kPlanThreads - 1];
+  __syncthreads();
+  return total;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __restrict__ off,
+                                                            const double* __restrict__ eps2, int C,
+                                                            const int32_t* __restrict__ active,
+                                                            const int64_t* __restrict__ n_act_dev, int IB, int target,
+                                                            BatchSys* __restrict__ sys, int32_t* __restrict__ nchunk,
+                                                            BatchItem* __restrict__ items, int max_items,
+                                                            int* __restrict__ n_items_dev, int64_t part_cap_rows) {
+  __shared__ int64_t red[kPlanThreads];
+  __shared__ int64_t J_s;
+  int64_t n_act = *n_act_dev;
+  if (n_act < 0) n_act = 0;
+  const int per = (C + kPlanThreads - 1) / kPlanThreads;
+  const int c0 = threadIdx.x * per;
+  const int c1 = c0 + per < C ? c0 + per : C;
+  // 1. active rows per system and the total work (i-slots x j)
+  int64_t work = 0;
+  for (int c = c0; c < c1; ++c) {
+    const int64_t a0 = lower_bound_i32(active, n_act, off[c]);
+    const int64_t a1 = lower_bound_i32(active, n_act, off[c + 1]);
+    const int64_t nib = (a1 - a0 + IB - 1) / IB;
+    work += nib * IB * (off[c + 1] - off[c]);
+    sys[c].j0 = off[c];
+    sys[c].j1 = off[c + 1];
+    sys[c].a0 = a0;
+    sys[c].a1 = a1;
+    sys[c].eps2 = eps2[c];
+  }
+  const int64_t W = block_sum_i64(work, red);
+  if (threadIdx.x == 0) {
+    int64_t J = (W + (int64_t)IB * target - 1) / ((int64_t)IB * target);
+    J = (J + kTile - 1) / kTile * kTile;
+    J_s = J < kTile ? kTile : J;
+  }
+  __syncthreads();
+  const int64_t J = J_s;
+  // 2. chunks, items and partial rows per system
+  int64_t my_items = 0, my_parts = 0;
+  for (int c = c0; c < c1; ++c) {
+    const int64_t nj = sys[c].j1 - sys[c].j0;
+    const int64_t na = sys[c].a1 - sys[c].a0;
+    int64_t S = (nj + J - 1) / J;
+    const int64_t max_s = (nj + kTile - 1) / kTile;
+    if (S > max_s) S = max_s;
+    if (S < 1) S = 1;
+    nchunk[c] = (int32_t)S;
+    my_items += ((na + IB - 1) / IB) * S;
+    if (S > 1) my_parts += S * na;
+  }
+  int64_t item_base, part_base;
+  const int64_t total_items = block_exscan_i64(my_items, red, &item_base);
+  const int64_t total_parts = block_exscan_i64(my_parts, red, &part_base);
+  const bool fits = total_items <= max_items && total_parts <= part_cap_rows;
+  // 3. the work list, system by system
+  for (int c = c0; c < c1; ++c) {
+    const int64_t na = sys[c].a1 - sys[c].a0;
+    const int32_t S = fits ? nchunk[c] : 1;
+    if (!fits) nchunk[c] = 1;
+    const int64_t nib = (na + IB - 1) / IB;
+    sys[c].part_off = (S > 1) ? part_base : 0;
+    if (S > 1) part_base += (int64_t)S * na;
+    if (fits) {
+      for (int32_t ch = 0; ch < S; ++ch)
+        for (int64_t b = 0; b < nib; ++b)
+          items[item_base + (int64_t)ch * nib + b] = BatchItem{(int32_t)c, (int32_t)b, ch, S};
+      item_base += nib * S;
+    }
+  }
+  if (!fits) {
+    // The bounds of the host sizing make this unreachable; fall back to one
+    // chunk per system (no partials), written in a second ordered pass.
+    __syncthreads();
+    int64_t mine = 0;
+    for (int c = c0; c < c1; ++c) mine += (sys[c].a1 - sys[c].a0 + IB - 1) / IB;
+    int64_t base;
+    const int64_t tot = block_exscan_i64(mine, red, &base);
+    for (int c = c0; c < c1; ++c) {
+      const int64_t nib = (sys[c].a1 - sys[c].a0 + IB - 1) / IB;
+      for (int64_t b = 0; b < nib; ++b)
+        if (base + b < max_items) items[base + b] = BatchItem{(int32_t)c, (int32_t)b, 0, 1};
+      base += nib;
+    }
+    if (threadIdx.x == 0) *n_items_dev = (int)(tot < max_items ? tot : max_items);
+  } else if (threadIdx.x == 0) {
+    *n_items_dev = (int)total_items;
+  }
+}
+
 // ------------------------------------------------------------- dispatch ----
 using ForceFn = void (*)(ForceArgs);
-using BatchFn = void (*)(const BatchItem*, int, const BatchSys*, const double*, const double*, const double*,
-                         const int32_t*, double*, double*, double*, double*);
+using BatchFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const double*, const double*,
+                         const double*, const int32_t*, double*, double*, double*, double*);
 
 template <class P, bool MASK>
 ForceFn pick_force(int K, int L) {
@@ -485,6 +873,34 @@ ForceFn pick_force(int K, int L) {
   }
 #undef NB_CASE
   return nullptr;
+}
+
+template <class P, bool MASK>
+using SjFn = void (*)(ForceArgs, const typename P::JReg*);
+
+template <class P, bool MASK>
+SjFn<P, MASK> pick_sj(int K) {
+  if (K == 1) return k_forces_sj<P, 1, MASK>;
+  if constexpr (!MASK) {
+    if (K == 2) return k_forces_sj<P, 2, MASK>;
+    if (K == 4) return k_forces_sj<P, 4, MASK>;
+  }
+  return nullptr;
+}
+
+template <class P, bool MASK>
+hipError_t launch_sj_p(int K, const ForceArgs& a, hipStream_t st, int grid_override, int max_grid) {
+  SjFn<P, MASK> fn = pick_sj<P, MASK>(K);
+  if (!fn || !a.rec) return hipErrorInvalidValue;
+  typename P::JReg* rec = static_cast<typename P::JReg*>(a.rec);
+  int64_t mg = (a.n + 255) / 256;
+  if (mg > 8192) mg = 8192;
+  hipLaunchKernelGGL(k_mirror<P>, dim3((int)mg), dim3(256), 0, st, a.pos, a.vel, a.mass, a.n, rec);
+  int grid = grid_override > 0 ? grid_override : items_for(Launch{K, 1, a.S}, a.n_active, a.S);
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
+  if (grid <= 0) return hipGetLastError();
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a, rec);
+  return hipGetLastError();
 }
 
 template <class P, bool MASK>
@@ -502,27 +918,82 @@ BatchFn pick_batch(int K, int L) {
 }  // namespace
 
 bool launch_supported(const Launch& c) {
+  if (c.L == 0) return pick_sj<F64, false>(c.K) != nullptr && c.S >= 1;
   return pick_force<F64, false>(c.K, c.L) != nullptr && c.S >= 1;
 }
 
+size_t mirror_bytes(int prec, int64_t n) {
+  const size_t rec = prec == NB_PREC_FP64 ? sizeof(F64::JReg)
+                     : prec == NB_PREC_MIXED_DS ? sizeof(MixedDS::JReg) : sizeof(Mixed::JReg);
+  return rec * (size_t)(n > 0 ? n : 1);
+}
+
 int items_for(const Launch& c, int64_t n_active, int S) {
-  const int64_t IB = (int64_t)(kWG / c.L) * c.K;
+  const int64_t IB = ib_of(c);
   return (int)(((n_active + IB - 1) / IB) * S);
 }
 
 hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
-                         int grid_override) {
+                         int grid_override, int max_grid) {
   const int K = mask ? 1 : cfg.K;
+  if (cfg.L == 0) {
+    if (prec == NB_PREC_FP64)
+      return mask ? launch_sj_p<F64, true>(K, a, st, grid_override, max_grid)
+                  : launch_sj_p<F64, false>(K, a, st, grid_override, max_grid);
+    if (prec == NB_PREC_MIXED_DS)
+      return mask ? launch_sj_p<MixedDS, true>(K, a, st, grid_override, max_grid)
+                  : launch_sj_p<MixedDS, false>(K, a, st, grid_override, max_grid);
+    return mask ? launch_sj_p<Mixed, true>(K, a, st, grid_override, max_grid)
+                : launch_sj_p<Mixed, false>(K, a, st, grid_override, max_grid);
+  }
   ForceFn fn = nullptr;
   if (prec == NB_PREC_FP64)
     fn = mask ? pick_force<F64, true>(K, cfg.L) : pick_force<F64, false>(K, cfg.L);
+  else if (prec == NB_PREC_MIXED_DS)
+    fn = mask ? pick_force<MixedDS, true>(K, cfg.L) : pick_force<MixedDS, false>(K, cfg.L);
   else
     fn = mask ? pick_force<Mixed, true>(K, cfg.L) : pick_force<Mixed, false>(K, cfg.L);
   if (!fn) return hipErrorInvalidValue;
   int grid = grid_override > 0 ? grid_override : items_for(Launch{K, cfg.L, a.S}, a.n_active, a.S);
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
   if (grid <= 0) return hipSuccess;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a);
   return hipGetLastError();
+}
+
+// Workgroups of this kernel that one compute unit holds at once (from the
+// occupancy calculator, cached per kernel).  A grid of num_CUs times this
+// runs as one round, with no tail of lightly loaded SIMDs.
+int resident_wgs(int prec, const Launch& cfg, bool mask) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  const int K = mask ? 1 : cfg.K;
+  const void* fn = nullptr;
+  if (cfg.L == 0) {
+    if (prec == NB_PREC_FP64)
+      fn = mask ? (const void*)pick_sj<F64, true>(K) : (const void*)pick_sj<F64, false>(K);
+    else if (prec == NB_PREC_MIXED_DS)
+      fn = mask ? (const void*)pick_sj<MixedDS, true>(K) : (const void*)pick_sj<MixedDS, false>(K);
+    else
+      fn = mask ? (const void*)pick_sj<Mixed, true>(K) : (const void*)pick_sj<Mixed, false>(K);
+  } else if (prec == NB_PREC_FP64) {
+    fn = mask ? (const void*)pick_force<F64, true>(K, cfg.L) : (const void*)pick_force<F64, false>(K, cfg.L);
+  } else if (prec == NB_PREC_MIXED_DS) {
+    fn = mask ? (const void*)pick_force<MixedDS, true>(K, cfg.L) : (const void*)pick_force<MixedDS, false>(K, cfg.L);
+  } else {
+    fn = mask ? (const void*)pick_force<Mixed, true>(K, cfg.L) : (const void*)pick_force<Mixed, false>(K, cfg.L);
+  }
+  if (!fn) return 1;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(reinterpret_cast<const void*>(fn));
+  if (it != cache.end()) return it->second;
+  int nblk = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, kWG, 0) != hipSuccess || nblk < 1) {
+    (void)hipGetLastError();
+    nblk = 1;
+  }
+  cache[reinterpret_cast<const void*>(fn)] = nblk;
+  return nblk;
 }
 
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st) {
@@ -533,26 +1004,32 @@ hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStre
   if (grid < 1) grid = 1;
   if (prec == NB_PREC_FP64)
     hipLaunchKernelGGL(k_reduce<F64>, dim3(grid), dim3(256), 0, st, a, S, IB);
+  else if (prec == NB_PREC_MIXED_DS)
+    hipLaunchKernelGGL(k_reduce<MixedDS>, dim3(grid), dim3(256), 0, st, a, S, IB);
   else
     hipLaunchKernelGGL(k_reduce<Mixed>, dim3(grid), dim3(256), 0, st, a, S, IB);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const BatchSys* sys,
-                        const double* pos, const double* vel, const double* mass, const int32_t* active,
-                        double* acc, double* jerk, double* pot, double* part, int64_t part_rows, bool any_mask,
-                        hipStream_t st) {
+hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
+                        const BatchSys* sys, const double* pos, const double* vel, const double* mass,
+                        const int32_t* active, double* acc, double* jerk, double* pot, double* part,
+                        int64_t part_rows, bool any_mask, int max_grid, hipStream_t st) {
   (void)part_rows;
   const int K = any_mask ? 1 : cfg.K;
   BatchFn fn = nullptr;
   if (prec == NB_PREC_FP64)
     fn = any_mask ? pick_batch<F64, true>(K, cfg.L) : pick_batch<F64, false>(K, cfg.L);
+  else if (prec == NB_PREC_MIXED_DS)
+    fn = any_mask ? pick_batch<MixedDS, true>(K, cfg.L) : pick_batch<MixedDS, false>(K, cfg.L);
   else
     fn = any_mask ? pick_batch<Mixed, true>(K, cfg.L) : pick_batch<Mixed, false>(K, cfg.L);
   if (!fn) return hipErrorInvalidValue;
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fn, dim3(n_items), dim3(kWG), 0, st, items, n_items, sys, pos, vel, mass, active, acc, jerk,
-                     pot, part);
+  int grid = n_items;
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, items, n_items, n_items_dev, sys, pos, vel, mass, active, acc,
+                     jerk, pot, part);
   return hipGetLastError();
 }
 
@@ -564,9 +1041,21 @@ hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const i
   if (prec == NB_PREC_FP64)
     hipLaunchKernelGGL(k_batch_reduce<F64>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
                        jerk, pot, part);
+  else if (prec == NB_PREC_MIXED_DS)
+    hipLaunchKernelGGL(k_batch_reduce<MixedDS>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active,
+                       acc, jerk, pot, part);
   else
     hipLaunchKernelGGL(k_batch_reduce<Mixed>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active,
                        acc, jerk, pot, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, const int32_t* active,
+                             const int64_t* n_act_dev, int IB, int target, BatchSys* sys, int32_t* nchunk,
+                             BatchItem* items, int max_items, int* n_items_dev, int64_t part_cap_rows,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_plan, dim3(1), dim3(kPlanThreads), 0, st, off, eps2, C, active, n_act_dev, IB, target,
+                     sys, nchunk, items, max_items, n_items_dev, part_cap_rows);
   return hipGetLastError();
 }
 

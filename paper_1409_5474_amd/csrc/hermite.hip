@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kB) void k_correct(const int32_t* __restrict__ acti
     const int64_t d = *n_active_dev;
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
   }
-  if (step_dev && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(step_dev, 1ull);
+  if (step_dev && n_act > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(step_dev, 1ull);
   for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * kB) {
     const int64_t i = active[k];
     const int L = level[i];
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ block_cnt, int nblk,
                                                     const int64_t* sched_in,
                                                     int32_t* __restrict__ active, int64_t* sched,
-                                                    int32_t* __restrict__ n_active32) {
+                                                    int32_t* __restrict__ n_active32, int64_t t_stop) {
   __shared__ int sc[kB];
   __shared__ int64_t off_s;
   const int64_t t_next = sched_in[0];
@@ -232,8 +232,10 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
     off += sc[kB - 1];
   }
   if (blockIdx.x == (unsigned)(nblk - 1) && threadIdx.x == 0) {
-    sched[1] = off;
-    if (n_active32) *n_active32 = (int32_t)off;
+    // past the stop time the step is empty: every later kernel does nothing
+    const int64_t cnt = t_next <= t_stop ? off : 0;
+    sched[1] = cnt;
+    if (n_active32) *n_active32 = (int32_t)cnt;
   }
 }
 
@@ -335,13 +337,13 @@ int schedule_blocks(int64_t n) { return (int)((n + kSchedBlock - 1) / kSchedBloc
 
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level, int32_t* active,
                            int64_t* sched, int64_t* block_min, int32_t* block_cnt, int32_t* n_active32,
-                           hipStream_t st) {
+                           int64_t t_stop, hipStream_t st) {
   const int nblk = schedule_blocks(n);
   hipLaunchKernelGGL(k_sched_min, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min);
   hipLaunchKernelGGL(k_sched_count, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min, nblk,
                      block_cnt, sched);
   hipLaunchKernelGGL(k_sched_write, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_cnt, nblk,
-                     sched, active, sched, n_active32);
+                     sched, active, sched, n_active32, t_stop);
   return hipGetLastError();
 }
 

@@ -15,10 +15,15 @@ constexpr int kTile = 256;  // j-particles staged in LDS per tile
 
 // One launch configuration of the force kernel family.
 struct Launch {
-  int K = 1;  // i-particles per lane
-  int L = 1;  // lanes per i-particle
-  int S = 1;  // j-subsets (0 in a table entry: choose by the saturation rule)
+  int K = 1;      // i-particles per lane
+  int L = 1;      // lanes per i-particle
+  int S = 1;      // j-subsets (0: choose by the saturation rule)
+  int items = 0;  // work-item target of the saturation rule (0: 4 per CU)
 };
+
+// i-particles per workgroup of a launch shape (L = 0: the scalar j-path,
+// one i-slot per lane like L = 1).
+inline int ib_of(const Launch& c) { return (kWG / (c.L > 0 ? c.L : 1)) * c.K; }
 
 struct TuneEntry {
   int prec;
@@ -47,6 +52,7 @@ struct ForceArgs {
   int* s_dev;                   // unused
   int64_t act_lo;               // device-count mode: work only when count >= act_lo and
   int last;                     // count <= n_active (or any larger count when `last`)
+  void* rec;                    // scalar j-path: mirror of n j-records (context-owned)
 };
 
 // Batched work list item: one (system, i-block, j-chunk) triple.
@@ -66,15 +72,21 @@ struct BatchSys {
 
 // Kernel launchers (forces.hip).  Return hipSuccess or the launch error.
 hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
-                         int grid_override);
+                         int grid_override, int max_grid);
+int resident_wgs(int prec, const Launch& cfg, bool mask);
+size_t mirror_bytes(int prec, int64_t n);  // j-record mirror of the scalar j-path
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st);
 int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n);
 bool launch_supported(const Launch& cfg);
 int items_for(const Launch& cfg, int64_t n_active, int S);
-hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items,
+hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
                         const BatchSys* sys, const double* pos, const double* vel, const double* mass,
                         const int32_t* active, double* acc, double* jerk, double* pot, double* part,
-                        int64_t part_rows, bool any_mask, hipStream_t st);
+                        int64_t part_rows, bool any_mask, int max_grid, hipStream_t st);
+hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, const int32_t* active,
+                             const int64_t* n_act_dev, int IB, int target, BatchSys* sys, int32_t* nchunk,
+                             BatchItem* items, int max_items, int* n_items_dev, int64_t part_cap_rows,
+                             hipStream_t st);
 hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const int32_t* chunks_per_sys,
                                const double* mass, const int32_t* active, int64_t n_act_total,
                                double* acc, double* jerk, double* pot, const double* part,
@@ -98,7 +110,7 @@ hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, doub
                           int max_level, int32_t* level, hipStream_t st);
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level,
                            int32_t* active, int64_t* sched, int64_t* block_min, int32_t* block_cnt,
-                           int32_t* n_active32, hipStream_t st);
+                           int32_t* n_active32, int64_t t_stop, hipStream_t st);
 int schedule_blocks(int64_t n);
 hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
                          int64_t n, double* part, double* out, hipStream_t st);
@@ -119,6 +131,8 @@ struct nb_ctx {
   // device workspace (grown on demand)
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  void* mirror = nullptr;       // j-records of the scalar j-path
+  size_t mirror_bytes = 0;
   int* s_dev = nullptr;         // device-chosen S of the last devcount launch
   int64_t* sched_tmp = nullptr; // block minima for the scheduler
   int32_t* sched_cnt = nullptr;
@@ -131,4 +145,10 @@ struct nb_ctx {
   void* batch_host = nullptr;   // pinned staging buffer of the work list
   size_t batch_host_cap = 0;
   hipEvent_t batch_ev = nullptr;  // marks the end of the last staging copy
+  // device-planned batch block steps: system table and work list
+  std::vector<int64_t> bp_off;    // host copy of the uploaded offsets
+  std::vector<double> bp_eps2;    // host copy of the uploaded softenings
+  void* bp_buf = nullptr;         // offsets, eps2, sys, nchunk, items, n_items
+  size_t bp_cap = 0;
+  int bp_max_items = 0;
 };

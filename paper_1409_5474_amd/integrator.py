@@ -1,0 +1,140 @@
+"""Hermite block-step integrator driver (device-resident state, HIP graphs).
+
+The state lives in torch tensors on the GPU; every step runs through the C
+ABI's ``nb_block_step`` (schedule -> predict -> forces -> correct, no host
+synchronisation).  ``run_until`` captures ``graph_steps`` consecutive block
+steps into one HIP graph and replays it; a step beyond the stop time is
+empty, so the host reads the schedule once per replay to decide whether to
+go on.
+
+Time is kept in integer ticks of dt_max 2^-max_level (see nbody.h).
+"""
+import torch
+
+from . import Context
+
+INT64_MAX = 2 ** 63 - 1
+
+
+class BlockIntegrator:
+    """Block-step integration of one system, or of a batch of independent
+    systems stored back to back (``offsets`` of length C+1 and one softening
+    per system in ``eps2``; the block step is then global over the batch)."""
+
+    def __init__(self, ctx: Context, pos, vel, mass, eps2, eta=0.01, dt_max=1.0 / 16, max_level=30,
+                 offsets=None):
+        import numpy as np
+        dev = ctx.device
+        n = mass.shape[0]
+        self.ctx, self.n, self.dev = ctx, n, dev
+        self.batch = offsets is not None
+        if self.batch:
+            self.offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+            self.eps2_sys = np.ascontiguousarray(eps2, dtype=np.float64)
+            if self.offsets[-1] != n or self.eps2_sys.shape[0] != self.offsets.shape[0] - 1:
+                raise ValueError("offsets must end at N and eps2 must have one value per system")
+            self.eps2 = None
+        else:
+            self.eps2 = float(eps2)
+        self.eta, self.dt_max, self.max_level = float(eta), float(dt_max), int(max_level)
+        self.tick = self.dt_max * 2.0 ** -self.max_level
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.mass = mass.to(**f64).contiguous()
+        self.pos = pos.to(**f64).contiguous().clone()
+        self.vel = vel.to(**f64).contiguous().clone()
+        self.acc = torch.empty((n, 3), **f64)
+        self.jerk = torch.empty((n, 3), **f64)
+        self.pos_p = torch.empty((n, 3), **f64)
+        self.vel_p = torch.empty((n, 3), **f64)
+        self.acc1 = torch.empty((n, 3), **f64)
+        self.jerk1 = torch.empty((n, 3), **f64)
+        self.pot1 = torch.empty(n, **f64)
+        self.active = torch.empty(n, dtype=torch.int32, device=dev)
+        self.t_tick = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.level = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.sched = torch.zeros(4, dtype=torch.int64, device=dev)   # t_next, n_active, steps, clamps
+        self.all_idx = torch.arange(n, dtype=torch.int32, device=dev)
+        self._graphs = {}
+        # start-up: forces on every particle at t = 0 and the first levels
+        self._all_forces(self.pos, self.vel, self.acc, self.jerk, self.pot1)
+        ctx.startup(self.acc, self.jerk, self.eta, self.dt_max, self.max_level, self.level)
+
+    def _all_forces(self, pos, vel, acc, jerk, pot):
+        if self.batch:
+            self.ctx.forces_batch(self.offsets, self.eps2_sys, pos, vel, self.mass, self.all_idx, self.offsets,
+                                  acc, jerk, pot)
+        else:
+            self.ctx.forces(pos, vel, self.mass, self.all_idx, self.eps2, acc, jerk, pot)
+
+    # ---- stepping ---------------------------------------------------------
+    def step(self, t_stop_tick=INT64_MAX):
+        """One block step, launched eagerly on the context stream."""
+        if self.batch:
+            self.ctx.block_step_batch(self.offsets, self.eps2_sys, self.eta, self.dt_max, self.max_level, self.mass,
+                                      self.pos, self.vel, self.acc, self.jerk, self.t_tick, self.level, self.pos_p,
+                                      self.vel_p, self.active, self.acc1, self.jerk1, self.pot1, self.sched,
+                                      t_stop_tick)
+        else:
+            self.ctx.block_step(self.n, self.eps2, self.eta, self.dt_max, self.max_level, self.mass, self.pos,
+                                self.vel, self.acc, self.jerk, self.t_tick, self.level, self.pos_p, self.vel_p,
+                                self.active, self.acc1, self.jerk1, self.pot1, self.sched, t_stop_tick)
+
+    def _graph(self, steps, t_stop_tick):
+        key = (steps, t_stop_tick)
+        g = self._graphs.get(key)
+        if g is None:
+            stream = torch.cuda.Stream(self.dev)
+            self.ctx.set_stream(stream)
+            try:
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=stream):
+                    for _ in range(steps):
+                        self.step(t_stop_tick)
+            finally:
+                self.ctx.set_stream(None)
+            self._graphs[key] = g
+        return g
+
+    def run_until(self, t_end, graph_steps=32, use_graph=True):
+        """Integrate until every particle reaches t_end (a multiple of dt_max)."""
+        end = int(round(t_end / self.tick))
+        if end * self.tick != t_end:
+            raise ValueError("t_end must be a whole number of ticks")
+        if end % (1 << self.max_level):
+            raise ValueError("t_end must be a multiple of dt_max (a synchronisation time)")
+        # one eager step sizes every workspace before a graph is captured
+        self.step(end)
+        while int(self.t_tick.min().item()) < end:
+            if use_graph:
+                g = self._graph(graph_steps, end)
+                torch.cuda.synchronize(self.dev)
+                g.replay()
+                torch.cuda.synchronize(self.dev)
+            else:
+                for _ in range(graph_steps):
+                    self.step(end)
+        return self
+
+    # ---- diagnostics ------------------------------------------------------
+    @property
+    def steps(self):
+        return int(self.sched[2].item())
+
+    @property
+    def clamps(self):
+        return int(self.sched[3].item())
+
+    @property
+    def time(self):
+        return int(self.t_tick.min().item()) * self.tick
+
+    def energy(self):
+        """K, W, E, P, L of the current (synchronised) state, summed over every system."""
+        acc = torch.empty_like(self.acc)
+        jerk = torch.empty_like(self.jerk)
+        pot = torch.empty_like(self.pot1)
+        self._all_forces(self.pos, self.vel, acc, jerk, pot)
+        out = torch.zeros(8, dtype=torch.float64, device=self.dev)
+        self.ctx.energy(self.pos, self.vel, self.mass, pot, out)
+        o = out.cpu().tolist()
+        return dict(K=o[0], W=o[1], E=o[0] + o[1], P=o[2:5], L=o[5:8])

@@ -14,6 +14,7 @@ from errors import all_errs
 pytestmark = pytest.mark.gpu
 
 EPS64 = 2.0 ** -53
+PRECS = ["fp64", "mixed", "mixed_ds"]
 
 
 @pytest.fixture(scope="module")
@@ -75,7 +76,7 @@ def _case(n, seed):
     return synth.plummer(n, seed)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_small_plummer_all_active(ctx, prec):
     # Plummer N = 1024, eps = 0.01, every particle active.
     p = _case(1024, 1)
@@ -89,11 +90,13 @@ def test_small_plummer_all_active(ctx, prec):
         check_mixed(res, ref)
 
 
+# (K, L, S); L = 0 is the scalar j-path
 LAUNCHES = [(1, 1, 1), (2, 1, 1), (4, 1, 1), (1, 1, 3), (2, 1, 5), (1, 2, 1), (1, 4, 2), (2, 8, 3), (4, 16, 1),
-            (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2)]
+            (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2), (1, 0, 1), (2, 0, 3),
+            (4, 0, 1), (2, 0, 1)]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("launch", LAUNCHES)
 def test_every_launch_shape_ragged(ctx, prec, launch):
     # N not a multiple of the tile, an active set not a multiple of the i-block.
@@ -110,7 +113,7 @@ def test_every_launch_shape_ragged(ctx, prec, launch):
         check_mixed(res, ref)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("n_act", [1, 7, 63, 64, 65, 1000, 4096])
 def test_active_set_sizes(ctx, prec, n_act):
     n = 4096
@@ -156,8 +159,9 @@ def test_tiny_systems(ctx, prec):
     assert res[2][0] == pytest.approx(-0.7 / np.sqrt(1.5 ** 2 + 0.04), rel=tol)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_zero_softening_masks_coincident_pairs(ctx, prec):
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("L", [1, 0])
+def test_zero_softening_masks_coincident_pairs(ctx, prec, L):
     # eps2 = 0: the self pair and a coincident twin contribute nothing.
     p = _case(300, 5)
     pos = p.pos.copy()
@@ -167,7 +171,7 @@ def test_zero_softening_masks_coincident_pairs(ctx, prec):
     act = np.arange(300, dtype=np.int32)
     ref = oracle.forces_ld(pos, p.vel, p.mass, 0.0, act)
     assert ref["skipped"] == 2
-    res = run_gpu(ctx, prec, q, 0.0, act)
+    res = run_gpu(ctx, prec, q, 0.0, act, (1, L, 2))
     for arr in res:
         assert np.all(np.isfinite(arr))
     if prec == "fp64":
@@ -176,17 +180,18 @@ def test_zero_softening_masks_coincident_pairs(ctx, prec):
         check_mixed(res, ref, acc_rms=1e-5, jerk_rms=1e-4, pot_rms=1e-5)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_bitwise_deterministic(ctx, prec):
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("launch", [(1, 4, 3), (2, 0, 2)])
+def test_bitwise_deterministic(ctx, prec, launch):
     p = _case(5000, 6)
     act = np.arange(0, 5000, 3, dtype=np.int32)
-    r1 = run_gpu(ctx, prec, p, 1e-3, act, (1, 4, 3))
-    r2 = run_gpu(ctx, prec, p, 1e-3, act, (1, 4, 3))
+    r1 = run_gpu(ctx, prec, p, 1e-3, act, launch)
+    r2 = run_gpu(ctx, prec, p, 1e-3, act, launch)
     for a, b in zip(r1, r2):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_full_size_sampled(ctx, prec):
     # Plummer N = 262144, eps = 1/256, all active in the launch the benchmark
     # uses; 512 sampled rows checked against the oracle one by one.

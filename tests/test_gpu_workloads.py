@@ -1,0 +1,97 @@
+"""Parity at the workloads' full sizes:
+  * Plummer N = 65536 Hermite block steps to t = 1/8 (FP64, graph-replayed)
+    against the CPU oracle's run stored in tests/golden (written by
+    tests/golden/make_hermite_reference.py from oracle/ only);
+  * the 128-cluster batch, all active, sampled rows against the oracle;
+  * the Hernquist merger direct part (i-set near the point masses against
+    all 1,441,803 bodies), sampled rows against the oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from errors import all_errs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hermite_plummer_N65536.json")
+
+
+def T(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def test_hermite_65536_matches_cpu_reference():
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    ref = json.load(open(GOLDEN))
+    w = ref["workload"]
+    p = synth.plummer(w["n"], w["seed"])
+    ctx = nb.Context(0, "fp64")
+    bi = BlockIntegrator(ctx, T(p.pos), T(p.vel), T(p.mass), w["eps2"], w["eta"], w["dt_max"], w["max_level"])
+    E0 = bi.energy()["E"]
+    assert E0 == pytest.approx(ref["E0"], rel=1e-12)
+    bi.run_until(w["t_end"], graph_steps=32)
+    E1 = bi.energy()["E"]
+    drift = abs(E1 - E0) / abs(E0)
+    print(f"steps gpu {bi.steps} cpu {ref['steps']}; drift gpu {drift:.4e} cpu {ref['drift']:.4e}")
+    # block-level decisions are discrete: equal step counts mean no level flips
+    assert abs(bi.steps - ref["steps"]) <= max(2, ref["steps"] // 100)
+    assert abs(drift - ref["drift"]) <= 0.1 * ref["drift"]
+    rows = np.array(ref["sample_rows"])
+    lev = bi.level.cpu().numpy()[rows]
+    same = lev == np.array(ref["sample_level"])
+    assert same.mean() > 0.95
+    dx = np.abs(bi.pos.cpu().numpy()[rows] - np.array(ref["sample_pos"]))
+    assert dx[same].max() < 1e-9, dx[same].max()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cluster_batch_128_sampled(prec):
+    import torch
+    import paper_1409_5474_amd as nb
+    b = synth.cluster_batch(seed=4, n_clusters=128)
+    n = int(b.offsets[-1])
+    ctx = nb.Context(0, prec)
+    act = torch.arange(n, dtype=torch.int32, device="cuda")
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    jerk, pot = torch.empty_like(acc), torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.forces_batch(b.offsets, b.eps2, T(b.pos), T(b.vel), T(b.mass), act, b.offsets, acc, jerk, pot)
+    A, J, P = acc.cpu().numpy(), jerk.cpu().numpy(), pot.cpu().numpy()
+    rng = np.random.default_rng(0)
+    for c in list(np.argsort(b.sizes)[[0, 1, 64, 126, 127]]) + [17]:
+        lo, hi = int(b.offsets[c]), int(b.offsets[c + 1])
+        rows = np.sort(rng.choice(hi - lo, min(64, hi - lo), replace=False)).astype(np.int32)
+        ref = oracle.forces_ld(b.pos[lo:hi], b.vel[lo:hi], b.mass[lo:hi], b.eps2[c], rows)
+        e = all_errs(A[lo + rows], J[lo + rows], P[lo + rows], ref)
+        if prec == "fp64":
+            assert e["acc"]["max"] < 1e-12 and e["jerk"]["cond_max"] < 1e-13 and e["pot"]["max"] < 1e-13, (c, e)
+        else:
+            assert e["acc"]["rms"] < 1e-6 and e["jerk"]["rms"] < 1e-5 and e["pot"]["rms"] < 1e-6, (c, e)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_merger_direct_part_sampled(prec):
+    import paper_1409_5474_amd as nb
+    m = synth.hernquist_merger()
+    ctx = nb.Context(0, prec)
+    acc, jerk, pot = ctx.forces(T(m.pos), T(m.vel), T(m.mass), T(m.active), m.eps2)
+    A, J, P = acc.cpu().numpy(), jerk.cpu().numpy(), pot.cpu().numpy()
+    # every point mass plus 53 sampled stars of the i-set
+    bh_rows = np.searchsorted(m.active, m.bh_index)
+    rest = np.setdiff1d(np.arange(m.active.size), bh_rows)
+    rows = np.sort(np.concatenate([bh_rows, np.random.default_rng(1).choice(rest, 53, replace=False)]))
+    ref = oracle.forces_ld(m.pos, m.vel, m.mass, m.eps2, m.active[rows])
+    e = all_errs(A[rows], J[rows], P[rows], ref)
+    print(prec, json.dumps(e))
+    if prec == "fp64":
+        assert e["acc"]["max"] < 1e-12 and e["pot"]["max"] < 1e-13, e
+        assert e["jerk"]["cond_max"] < 1e-13, e
+    else:
+        assert e["acc"]["rms"] < 1e-6 and e["pot"]["rms"] < 1e-6 and e["jerk"]["rms"] < 1e-5, e
+    ctx.close()
