@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOPS_PER_INTERACTION = 43          # nominal count for acc + jerk + pot
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_hbm_traffic.md")
+FORCE_SRC = os.path.join(ROOT, "paper_1409_5474_amd", "csrc", "forces.hip")
 FP32_VECTOR_PEAK_TFLOPS = 157.3     # MI355X, vendor figure
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
@@ -46,6 +48,24 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
+
+
+def measured_traffic(prec):
+    """HBM bytes per launch of the all-active force kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel source
+    has changed since those counters were taken (or none were taken)."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+        src = hashlib.sha256(open(FORCE_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for ln in lines:
+        if ln.startswith("traffic-json:"):
+            d = json.loads(ln.split(":", 1)[1])
+            if d.get("forces_hip_sha256") == src and d.get("prec") == prec:
+                return d.get("hbm_bytes_per_launch")
+    return None
 
 
 def workloads(args):
@@ -316,7 +336,7 @@ def main():
                                                 (res["mixed"]["ms_force"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 2)},
         "mixed_vs_fp64_speedup": round(res["fp64"]["ms_step"] / res["mixed"]["ms_step"], 3),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.prec),
                      "kernel": f"force kernel ({args.prec}), {FLOPS_PER_INTERACTION} flops x N^2 per launch",
                      "ms_per_launch": round(main_r["ms_force"], 4)},
         "cpu_baseline": cpu,

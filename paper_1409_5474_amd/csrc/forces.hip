@@ -42,7 +42,7 @@
 // the scheduler more independent LDS reads, fewer leaves VGPRs for more
 // resident waves (which the dual VALU issue of gfx950 needs).
 #ifndef NB_JJ_UNROLL
-#define NB_JJ_UNROLL 4
+#define NB_JJ_UNROLL 2
 #endif
 
 #include "nb_internal.h"
