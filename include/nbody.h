@@ -86,12 +86,17 @@ const char *nb_last_error(const nb_ctx *ctx);
 const char *nb_version(void);
 
 /* ---- launch configuration (the j-split of the paper) --------------------
- * K = i-particles per lane (1, 2, 4); L = lanes sharing one i-particle, each
- * taking every L-th j of a tile, combined by cross-lane and cross-wave
- * reduction (1, 2, 4, ..., 256); S = j-subsets, one workgroup each, whose
- * partial sums a second kernel adds in fixed order (>= 1).  The paper's rule
- * is that the device is saturated once N_i times the number of j-subsets
- * exceeds the number of threads.
+ * K = i-particles per lane (1, 2, 4; 3 for L <= 0); L = lanes sharing one
+ * i-particle, each taking every L-th j of a tile staged in LDS, combined by
+ * cross-lane and cross-wave reduction (1, 2, 4, ..., 256); L = 0 selects the
+ * scalar j-path (one lane per i-particle, j-records converted once per call
+ * into a mirror and read with a wave-uniform index through the scalar
+ * cache); L = -1 the hybrid path (mixed precision only, else as L = 0:
+ * positions through the scalar cache, velocities and masses through LDS).
+ * S = j-subsets, one work item each per i-block, whose partial sums a second
+ * kernel adds in fixed order (>= 1).  The paper's rule is that the device is
+ * saturated once N_i times the number of j-subsets exceeds the number of
+ * threads.
  * nb_set_launch forces one configuration for every later force call
  * (K = 0 returns to automatic choice); nb_get_launch reports the
  * configuration the context would use for (N, n_active). */

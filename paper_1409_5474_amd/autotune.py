@@ -23,7 +23,7 @@ import numpy as np
 import torch
 
 # (K, L); L = 0 is the scalar j-path (i-parallel, j-records through the scalar cache)
-SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (1, 256), (2, 1), (2, 4), (2, 16), (4, 1), (4, 4), (1, 0), (2, 0), (4, 0)]
+SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (1, 256), (2, 1), (2, 4), (2, 16), (4, 1), (4, 4), (1, 0), (2, 0), (3, 0), (4, 0)]
 BUCKETS = [1, 8, 64, 256, 1024, 4096, 16384, 65536, 262144]
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 TILE, WG = 256, 256

@@ -110,9 +110,11 @@ int ensure_energy(nb_ctx* c, int64_t n) {
 
 bool valid_prec(int p) { return p == NB_PREC_FP64 || p == NB_PREC_MIXED || p == NB_PREC_MIXED_DS; }
 
-bool valid_K(int K) { return K == 1 || K == 2 || K == 4; }
-// L = 0 selects the scalar j-path (i-parallel, j-records through the scalar cache)
-bool valid_L(int L) { return L == 0 || (L >= 1 && L <= 256 && (L & (L - 1)) == 0); }
+bool valid_K(int K) { return K >= 1 && K <= 4; }  // K = 3 exists for the scalar j-path only
+// L = 0 selects the scalar j-path (i-parallel, j-records through the scalar
+// cache); L = -1 the hybrid path (positions through the scalar cache,
+// velocities and masses through LDS; mixed precision, else as L = 0)
+bool valid_L(int L) { return L == 0 || L == -1 || (L >= 1 && L <= 256 && (L & (L - 1)) == 0); }
 
 int target_items(const nb_ctx* c) { return c->num_cus * 4; }
 
@@ -195,7 +197,7 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
   Launch eff = cfg;
   if (mask) eff.K = 1;
   const int max_grid = resident_grid(c, eff, mask);
-  if (eff.L == 0) {
+  if (eff.L <= 0) {
     int rc = ensure_mirror(c, N);
     if (rc) return rc;
     a.rec = c->mirror;
@@ -399,7 +401,7 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   if (rc) return rc;
   bool need_mirror = false;
   for (const Regime& r : regs)
-    if (r.lo <= max_active && (c->have_forced ? c->forced.L : r.cfg.L) == 0) need_mirror = true;
+    if (r.lo <= max_active && (c->have_forced ? c->forced.L : r.cfg.L) <= 0) need_mirror = true;
   if (need_mirror) {
     rc = ensure_mirror(c, N);
     if (rc) return rc;

@@ -58,6 +58,25 @@ __device__ __forceinline__ double rsqrt_f64(double s) {
   return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
+// A wave-uniform value copied into a VGPR.  gfx950 pairs two independent
+// VALU instructions of a wave per issue cycle only when neither reads an
+// SGPR, so a loop-invariant operand such as eps2 is kept in a VGPR.
+__device__ __forceinline__ float in_vgpr(float x) {
+  float r;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+__device__ __forceinline__ double in_vgpr(double x) {
+  double r;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(r) : "s"(x));
+  return r;
+}
+
+__device__ __forceinline__ float add_nocontract(float a, float b) {
+#pragma clang fp contract(off)
+  return a + b;
+}
+
 __device__ __forceinline__ void two_sum_add(double& hi, double& lo, double x) {
   const double s = hi + x;
   const double bp = s - hi;
@@ -230,7 +249,10 @@ struct Mixed {
     A[3] = fmaf(mq3, fmaf(c, dx, ux), A[3]);
     A[4] = fmaf(mq3, fmaf(c, dy, uy), A[4]);
     A[5] = fmaf(mq3, fmaf(c, dz, uz), A[5]);
-    A[6] += mq;
+    // a separate add (no contraction): fused into an FMA the mass, often an
+    // SGPR, would be read twice per pair, and SGPR-operand instructions never
+    // dual-issue
+    A[6] = add_nocontract(A[6], mq);
   }
   template <bool MASK>
   static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
@@ -346,7 +368,7 @@ struct MixedDS {
     A[3] = fmaf(mq3, fmaf(c, dx, ux), A[3]);
     A[4] = fmaf(mq3, fmaf(c, dy, uy), A[4]);
     A[5] = fmaf(mq3, fmaf(c, dz, uz), A[5]);
-    A[6] += mq;
+    A[6] = add_nocontract(A[6], mq);
   }
   template <bool MASK>
   static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
@@ -419,7 +441,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
     irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
     I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
   }
-  const typename P::T e2 = P::eps(eps2);
+  const typename P::T e2 = in_vgpr(P::eps(eps2));
 
   typename P::T A[K][7];
   typename P::Tot Tt[K];
@@ -565,8 +587,10 @@ template <class P>
 __global__ __launch_bounds__(256) void k_mirror(const double* __restrict__ pos, const double* __restrict__ vel,
                                                 const double* __restrict__ mass, int64_t n,
                                                 typename P::JReg* __restrict__ rec) {
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256)
-    rec[j] = P::load(pos, vel, mass, j, true);
+  // records 0..n-1 and one zero padding record at n (read by the prefetch
+  // of the last pair, never used)
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j <= n; j += (int64_t)gridDim.x * 256)
+    rec[j] = P::load(pos, vel, mass, j, j < n);
 }
 
 template <class P, int K, bool MASK>
@@ -586,7 +610,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
     irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
     I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
   }
-  const typename P::T e2 = P::eps(eps2);
+  const typename P::T e2 = in_vgpr(P::eps(eps2));
   typename P::T A[K][7];
   typename P::Tot Tt[K];
 #pragma unroll
@@ -599,11 +623,15 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
     typename P::JReg nxt = rec[jbeg];
     for (int64_t base = jbeg; base < jend; base += kTile) {
       if (base + kTile <= jend) {
+        // the prefetch of the tile's last pair wraps to jbeg on the last tile;
+        // the test is kept on 32-bit uniform values so it stays on the scalar
+        // unit (an unclamped index made the compiler hoist loads further ahead
+        // at a cost of 14 VGPRs, one resident wave per SIMD, for K = 2)
+        const bool last = base + kTile >= jend;
 #pragma unroll NB_JJ_UNROLL
         for (int jj = 0; jj < kTile; ++jj) {
           const typename P::JReg r = nxt;
-          const int64_t jn = base + jj + 1;
-          nxt = rec[jn < jend ? jn : jbeg];
+          nxt = rec[(jj + 1 < kTile || !last) ? base + jj + 1 : jbeg];
           P::template pair_reg<MASK>(r, I, e2, A, K);
         }
       } else {
@@ -637,8 +665,18 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
   }
 }
 
+// Waves per SIMD the scalar j-path asks the register allocator for: with
+// two i-particles per lane the float kernels then fit five waves (86
+// VGPRs), measured 12% faster than four waves (110 VGPRs) with a deeper
+// scalar-load pipeline.
+template <class P, int K>
+struct SjWaves {
+  static constexpr int value = (K == 2 && sizeof(typename P::T) == 4) ? 5 : 1;
+};
+
 template <class P, int K, bool MASK>
-__global__ __launch_bounds__(kWG) void k_forces_sj(ForceArgs a, const typename P::JReg* __restrict__ rec) {
+__global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(ForceArgs a,
+                                                                        const typename P::JReg* __restrict__ rec) {
   constexpr int IB = kWG * K;
   int64_t n_act = a.n_active;
   int S = a.S;
@@ -658,6 +696,122 @@ __global__ __launch_bounds__(kWG) void k_forces_sj(ForceArgs a, const typename P
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
     process_item_sj<P, K, MASK>(rec, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                                 a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+  }
+}
+
+
+// Hybrid of the two j-paths for the mixed policy (launch shape L = -1):
+// positions come through the scalar cache (they feed double subtractions,
+// which never dual-issue anyway) while velocities and masses are staged per
+// tile into LDS, so the velocity differences and m q read VGPR operands and
+// can pair with their neighbours.
+template <int K>
+__device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ rec, float4* vm_tile,
+                                                const double* __restrict__ pos, const double* __restrict__ vel,
+                                                const double* __restrict__ mass, int64_t jbeg, int64_t jend,
+                                                const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
+                                                double eps2, bool final_out, double* __restrict__ acc,
+                                                double* __restrict__ jerk, double* __restrict__ pot,
+                                                double* __restrict__ part) {
+  using P = Mixed;
+  const int t = threadIdx.x;
+  P::IPart I[K];
+  int64_t irow[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int64_t k = k0 + kk * kWG + t;
+    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+  }
+  const float e2 = in_vgpr(P::eps(eps2));
+  float A[K][7];
+  P::Tot Tt[K];
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    P::zero(Tt[kk]);
+#pragma unroll
+    for (int c = 0; c < 7; ++c) A[kk][c] = 0;
+  }
+  for (int64_t base = jbeg; base < jend; base += kTile) {
+    __syncthreads();  // every lane is done with the previous tile
+    {
+      const int64_t j = base + t;
+      const P::JReg r = rec[j < jend ? j : jend];  // record jend exists (padding)
+      vm_tile[t] = make_float4(r.vx, r.vy, r.vz, j < jend ? r.m : 0.0f);
+    }
+    __syncthreads();
+    double2 nxy = make_double2(rec[base].x, rec[base].y);
+    double nz = rec[base].z;
+    if (base + kTile <= jend) {
+#pragma unroll NB_JJ_UNROLL
+      for (int jj = 0; jj < kTile; ++jj) {
+        const double2 xy = nxy;
+        const double z = nz;
+        const int64_t jn = base + jj + 1 < jend ? base + jj + 1 : jbeg;
+        nxy = make_double2(rec[jn].x, rec[jn].y);
+        nz = rec[jn].z;
+        const float4 vm = vm_tile[jj];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) P::pair<false>(I[kk], xy, z, vm, e2, A[kk]);
+      }
+    } else {
+      const int cnt = (int)(jend - base);
+      for (int jj = 0; jj < cnt; ++jj) {
+        const double2 xy = nxy;
+        const double z = nz;
+        const int64_t jn = base + jj + 1 < jend ? base + jj + 1 : jbeg;
+        nxy = make_double2(rec[jn].x, rec[jn].y);
+        nz = rec[jn].z;
+        const float4 vm = vm_tile[jj];
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) P::pair<false>(I[kk], xy, z, vm, e2, A[kk]);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) P::fold(Tt[kk], A[kk]);
+  }
+#pragma unroll
+  for (int kk = 0; kk < K; ++kk) {
+    const int64_t k = k0 + kk * kWG + t;
+    if (k < n_act) {
+      double v[7];
+#pragma unroll
+      for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
+      if (final_out) {
+        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
+        jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
+        pot[k] = -(v[6] - self);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) part[c * n_act + k] = v[c];
+      }
+    }
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a, const Mixed::JReg* __restrict__ rec) {
+  __shared__ float4 vm_tile[kTile];
+  constexpr int IB = kWG * K;
+  int64_t n_act = a.n_active;
+  int S = a.S;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    if (d < a.act_lo || (d > a.n_active && !a.last)) return;
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    S = choose_S(n_act, IB, a.target_items, a.n);
+  }
+  const int64_t n_iblk = (n_act + IB - 1) / IB;
+  const int64_t items = n_iblk * S;
+  const int64_t clen = chunk_len(a.n, S);
+  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+    const int64_t chunk = w / n_iblk;
+    const int64_t iblk = w - chunk * n_iblk;
+    const int64_t jb = chunk * clen;
+    const int64_t je = jb + clen < a.n ? jb + clen : a.n;
+    process_item_hy<K>(rec, vm_tile, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
+                       a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
   }
 }
 
@@ -883,6 +1037,7 @@ SjFn<P, MASK> pick_sj(int K) {
   if (K == 1) return k_forces_sj<P, 1, MASK>;
   if constexpr (!MASK) {
     if (K == 2) return k_forces_sj<P, 2, MASK>;
+    if (K == 3) return k_forces_sj<P, 3, MASK>;
     if (K == 4) return k_forces_sj<P, 4, MASK>;
   }
   return nullptr;
@@ -903,6 +1058,15 @@ hipError_t launch_sj_p(int K, const ForceArgs& a, hipStream_t st, int grid_overr
   return hipGetLastError();
 }
 
+using HyFn = void (*)(ForceArgs, const Mixed::JReg*);
+HyFn pick_hy(int K) {
+  if (K == 1) return k_forces_hy<1>;
+  if (K == 2) return k_forces_hy<2>;
+  if (K == 3) return k_forces_hy<3>;
+  if (K == 4) return k_forces_hy<4>;
+  return nullptr;
+}
+
 template <class P, bool MASK>
 BatchFn pick_batch(int K, int L) {
 #define NB_CASE(KK, LL) \
@@ -918,6 +1082,7 @@ BatchFn pick_batch(int K, int L) {
 }  // namespace
 
 bool launch_supported(const Launch& c) {
+  if (c.L < 0) return pick_hy(c.K) != nullptr && c.S >= 1;
   if (c.L == 0) return pick_sj<F64, false>(c.K) != nullptr && c.S >= 1;
   return pick_force<F64, false>(c.K, c.L) != nullptr && c.S >= 1;
 }
@@ -925,7 +1090,7 @@ bool launch_supported(const Launch& c) {
 size_t mirror_bytes(int prec, int64_t n) {
   const size_t rec = prec == NB_PREC_FP64 ? sizeof(F64::JReg)
                      : prec == NB_PREC_MIXED_DS ? sizeof(MixedDS::JReg) : sizeof(Mixed::JReg);
-  return rec * (size_t)(n > 0 ? n : 1);
+  return rec * (size_t)((n > 0 ? n : 1) + 1);  // one padding record
 }
 
 int items_for(const Launch& c, int64_t n_active, int S) {
@@ -936,6 +1101,25 @@ int items_for(const Launch& c, int64_t n_active, int S) {
 hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
                          int grid_override, int max_grid) {
   const int K = mask ? 1 : cfg.K;
+  if (cfg.L < 0) {
+    // hybrid path: mixed precision with eps2 > 0 only (otherwise the scalar j-path)
+    if (prec != NB_PREC_MIXED || mask) {
+      Launch c2 = cfg;
+      c2.L = 0;
+      return launch_forces(prec, c2, mask, a, st, grid_override, max_grid);
+    }
+    HyFn fn = pick_hy(K);
+    if (!fn || !a.rec) return hipErrorInvalidValue;
+    Mixed::JReg* rec = static_cast<Mixed::JReg*>(a.rec);
+    int64_t mg = (a.n + 256) / 256;
+    if (mg > 8192) mg = 8192;
+    hipLaunchKernelGGL(k_mirror<Mixed>, dim3((int)mg), dim3(256), 0, st, a.pos, a.vel, a.mass, a.n, rec);
+    int grid = grid_override > 0 ? grid_override : items_for(Launch{K, 1, a.S}, a.n_active, a.S);
+    if (max_grid > 0 && grid > max_grid) grid = max_grid;
+    if (grid <= 0) return hipGetLastError();
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a, rec);
+    return hipGetLastError();
+  }
   if (cfg.L == 0) {
     if (prec == NB_PREC_FP64)
       return mask ? launch_sj_p<F64, true>(K, a, st, grid_override, max_grid)
@@ -969,7 +1153,9 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
   static std::map<const void*, int> cache;
   const int K = mask ? 1 : cfg.K;
   const void* fn = nullptr;
-  if (cfg.L == 0) {
+  if (cfg.L < 0 && prec == NB_PREC_MIXED && !mask) {
+    fn = (const void*)pick_hy(K);
+  } else if (cfg.L <= 0) {
     if (prec == NB_PREC_FP64)
       fn = mask ? (const void*)pick_sj<F64, true>(K) : (const void*)pick_sj<F64, false>(K);
     else if (prec == NB_PREC_MIXED_DS)

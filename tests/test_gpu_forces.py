@@ -92,7 +92,7 @@ def test_small_plummer_all_active(ctx, prec):
 
 # (K, L, S); L = 0 is the scalar j-path
 LAUNCHES = [(1, 1, 1), (2, 1, 1), (4, 1, 1), (1, 1, 3), (2, 1, 5), (1, 2, 1), (1, 4, 2), (2, 8, 3), (4, 16, 1),
-            (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2), (1, 0, 1), (2, 0, 3),
+            (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2), (1, 0, 1), (2, 0, 3), (3, 0, 2), (1, -1, 1), (2, -1, 3), (3, -1, 2),
             (4, 0, 1), (2, 0, 1)]
 
 
