@@ -38,7 +38,10 @@
  *    stated (device-resident indices cannot be checked without a copy).
  *  - The context owns only its launch table, a workspace for j-split
  *    partial sums (grown on demand with hipMalloc outside any stream capture)
- *    and a few bytes of device scratch.
+ *    and a few bytes of device scratch.  If the environment variable
+ *    NB_MAX_WORKSPACE_BYTES holds a decimal byte count, a call whose j-split
+ *    (or scalar-path mirror) workspace would exceed it fails with NB_ENOMEM
+ *    before anything is launched, leaving every output untouched.
  */
 #ifndef NBODY_H
 #define NBODY_H
@@ -54,7 +57,7 @@ typedef struct nb_ctx nb_ctx;
 enum nb_status {
     NB_OK = 0,
     NB_EINVAL = -1,    /* bad argument (size, null pointer, range, NaN eps2 ...) */
-    NB_ENOMEM = -2,    /* device allocation failed */
+    NB_ENOMEM = -2,    /* device allocation failed or over NB_MAX_WORKSPACE_BYTES */
     NB_EDEVICE = -3,   /* HIP runtime error (launch, stream, device) */
     NB_ENOTSUP = -6    /* combination not supported by this build */
 };

@@ -1,7 +1,9 @@
 // C ABI of the library: argument checking, launch-configuration choice,
 // workspace management and the composite block step.  See include/nbody.h.
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <new>
@@ -36,9 +38,22 @@ bool capturing(hipStream_t s) {
   return st != hipStreamCaptureStatusNone;
 }
 
+// Optional cap on the j-split workspace and on the j-record mirror
+// (environment NB_MAX_WORKSPACE_BYTES): a request above it fails with
+// NB_ENOMEM instead of allocating.
+size_t workspace_cap() {
+  const char* v = std::getenv("NB_MAX_WORKSPACE_BYTES");
+  if (!v || !*v) return SIZE_MAX;
+  char* end = nullptr;
+  const unsigned long long x = std::strtoull(v, &end, 10);
+  return (end && *end == '\0') ? (size_t)x : SIZE_MAX;
+}
+
 // Grow the context workspace to at least `bytes` (never inside a capture).
 int ensure_ws(nb_ctx* c, size_t bytes) {
   if (bytes <= c->ws_bytes) return NB_OK;
+  if (bytes > workspace_cap())
+    return fail(c, NB_ENOMEM, "j-split workspace request exceeds NB_MAX_WORKSPACE_BYTES%s");
   if (capturing(c->stream))
     return fail(c, NB_ENOMEM, "workspace must grow but the stream is being captured; run the call once before capture%s");
   if (c->ws) {
@@ -60,6 +75,8 @@ int ensure_ws(nb_ctx* c, size_t bytes) {
 int ensure_mirror(nb_ctx* c, int64_t n) {
   const size_t bytes = nb::mirror_bytes(c->prec, n);
   if (bytes <= c->mirror_bytes) return NB_OK;
+  if (bytes > workspace_cap())
+    return fail(c, NB_ENOMEM, "j-record mirror exceeds NB_MAX_WORKSPACE_BYTES%s");
   if (capturing(c->stream)) return fail(c, NB_ENOMEM, "j-record mirror must grow during capture%s");
   (void)hipStreamSynchronize(c->stream);
   if (c->mirror) (void)hipFree(c->mirror);

@@ -27,8 +27,9 @@
 //  * F64:   all pair arithmetic in double; per-tile double sums folded into a
 //           compensated (TwoSum) double-double accumulator.
 //  * Mixed: r = x_j - x_i formed in double and rounded to float, u, m and all
-//           pair arithmetic in float, per-tile float sums added into double
-//           accumulators (the paper's remedy for single precision: the
+//           pair arithmetic in float, float sums over runs of NB_FP32_RUN
+//           pairs (acceleration, potential) or one tile (jerk) added into
+//           double accumulators (the paper's remedy for single precision: the
 //           largest error sits in the inter-particle distance, which is
 //           therefore formed in higher precision).
 // The self pair (j == i) is not skipped in the loop: with eps2 > 0 it adds
@@ -43,6 +44,19 @@
 // resident waves (which the dual VALU issue of gfx950 needs).
 #ifndef NB_JJ_UNROLL
 #define NB_JJ_UNROLL 2
+#endif
+
+// Length of the float runs of the mixed policies: every NB_FP32_RUN pairs
+// a lane adds its float sums of acceleration and potential into the double
+// accumulators.  A float sum that already holds one dominant term (a
+// heavy neighbour, or the self pair m_i/eps) rounds every later small term
+// to its own ulp, with an error that has a sign bias and so grows linearly
+// with the run length; 32 keeps it near the float rounding of one pair for
+// mass ratios of 1e3 at a cost of two instructions per component per run.
+// The jerk error is set by the float velocity differences instead and is
+// folded once per tile.
+#ifndef NB_FP32_RUN
+#define NB_FP32_RUN 32
 #endif
 
 #include "nb_internal.h"
@@ -171,6 +185,9 @@ struct F64 {
       A[c] = 0.0;
     }
   }
+  // Double tile sums are folded once per tile only.
+  static constexpr int kRun = kTile;
+  static __device__ __forceinline__ void fold_run(Tot&, T*) {}
   static __device__ __forceinline__ double value(const Tot& t, int c) { return t.hi[c] + t.lo[c]; }
   // The value the pair loop adds to the potential sum for the self pair.
   static __device__ __forceinline__ double self_term(double m, double eps2) { return m * rsqrt_f64(eps2); }
@@ -270,6 +287,17 @@ struct Mixed {
   static __device__ __forceinline__ void fold(Tot& t, T* A) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
+      t.v[c] += (double)A[c];
+      A[c] = 0.0f;
+    }
+  }
+  // Acceleration and potential leave their float sums every kRun pairs.
+  static constexpr int kRun = NB_FP32_RUN;
+  static_assert(kRun > 0 && (kRun & (kRun - 1)) == 0 && kTile % kRun == 0, "float run must divide the tile");
+  static __device__ __forceinline__ void fold_run(Tot& t, T* A) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      if (c >= 3 && c < 6) continue;
       t.v[c] += (double)A[c];
       A[c] = 0.0f;
     }
@@ -390,6 +418,17 @@ struct MixedDS {
       A[c] = 0.0f;
     }
   }
+  // Acceleration and potential leave their float sums every kRun pairs.
+  static constexpr int kRun = NB_FP32_RUN;
+  static_assert(kRun > 0 && (kRun & (kRun - 1)) == 0 && kTile % kRun == 0, "float run must divide the tile");
+  static __device__ __forceinline__ void fold_run(Tot& t, T* A) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      if (c >= 3 && c < 6) continue;
+      t.v[c] += (double)A[c];
+      A[c] = 0.0f;
+    }
+  }
   static __device__ __forceinline__ double value(const Tot& t, int c) { return t.v[c]; }
   static __device__ __forceinline__ double self_term(double m, double eps2) {
     return (double)((float)m * __builtin_amdgcn_rsqf((float)eps2));
@@ -429,6 +468,8 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
                                              double* __restrict__ acc, double* __restrict__ jerk,
                                              double* __restrict__ pot, double* __restrict__ part) {
   constexpr int SLOTS = kWG / L;
+  constexpr int PER = kTile / L;                          // pairs per lane and tile
+  constexpr int RUN = P::kRun < PER ? P::kRun : PER;      // pairs per float run
   const int t = threadIdx.x;
   const int slot = t / L;
   const int sub = t % L;
@@ -459,8 +500,17 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
     __syncthreads();
     const int64_t nb = base + kTile;
     if (nb < jend) nxt = P::load(pos, vel, mass, nb + t, nb + t < jend);
+#pragma unroll 1
+    for (int jb = 0; jb < kTile; jb += RUN * L) {
 #pragma unroll NB_JJ_UNROLL
-    for (int jj = sub; jj < kTile; jj += L) P::template pair_tile<MASK>(tile, jj, I, e2, A, K);
+      for (int jj = jb + sub; jj < jb + RUN * L; jj += L) P::template pair_tile<MASK>(tile, jj, I, e2, A, K);
+      if constexpr (RUN < PER) {
+        if (jb + RUN * L < kTile) {
+#pragma unroll
+          for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
+        }
+      }
+    }
 #pragma unroll
     for (int kk = 0; kk < K; ++kk) P::fold(Tt[kk], A[kk]);
   }
@@ -601,6 +651,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
                                                 double eps2, bool final_out, double* __restrict__ acc,
                                                 double* __restrict__ jerk, double* __restrict__ pot,
                                                 double* __restrict__ part) {
+  constexpr int RUN = P::kRun;  // pairs per float run
   const int t = threadIdx.x;
   typename P::IPart I[K];
   int64_t irow[K];
@@ -628,17 +679,33 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
         // unit (an unclamped index made the compiler hoist loads further ahead
         // at a cost of 14 VGPRs, one resident wave per SIMD, for K = 2)
         const bool last = base + kTile >= jend;
+#pragma unroll 1
+        for (int jb = 0; jb < kTile; jb += RUN) {
 #pragma unroll NB_JJ_UNROLL
-        for (int jj = 0; jj < kTile; ++jj) {
-          const typename P::JReg r = nxt;
-          nxt = rec[(jj + 1 < kTile || !last) ? base + jj + 1 : jbeg];
-          P::template pair_reg<MASK>(r, I, e2, A, K);
+          for (int jj = jb; jj < jb + RUN; ++jj) {
+            const typename P::JReg r = nxt;
+            nxt = rec[(jj + 1 < kTile || !last) ? base + jj + 1 : jbeg];
+            P::template pair_reg<MASK>(r, I, e2, A, K);
+          }
+          if constexpr (RUN < kTile) {
+            if (jb + RUN < kTile) {
+#pragma unroll
+              for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
+            }
+          }
         }
       } else {
-        for (int64_t j = base; j < jend; ++j) {
+        const int cnt = (int)(jend - base);
+        for (int o = 0; o < cnt; ++o) {
           const typename P::JReg r = nxt;
-          nxt = rec[j + 1 < jend ? j + 1 : jbeg];
+          nxt = rec[o + 1 < cnt ? base + o + 1 : jbeg];
           P::template pair_reg<MASK>(r, I, e2, A, K);
+          if constexpr (RUN < kTile) {
+            if ((o & (RUN - 1)) == RUN - 1) {
+#pragma unroll
+              for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
+            }
+          }
         }
       }
 #pragma unroll
@@ -714,6 +781,7 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
                                                 double* __restrict__ jerk, double* __restrict__ pot,
                                                 double* __restrict__ part) {
   using P = Mixed;
+  constexpr int RUN = P::kRun;  // pairs per float run
   const int t = threadIdx.x;
   P::IPart I[K];
   int64_t irow[K];
@@ -743,16 +811,25 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
     double2 nxy = make_double2(rec[base].x, rec[base].y);
     double nz = rec[base].z;
     if (base + kTile <= jend) {
+#pragma unroll 1
+      for (int jb = 0; jb < kTile; jb += RUN) {
 #pragma unroll NB_JJ_UNROLL
-      for (int jj = 0; jj < kTile; ++jj) {
-        const double2 xy = nxy;
-        const double z = nz;
-        const int64_t jn = base + jj + 1 < jend ? base + jj + 1 : jbeg;
-        nxy = make_double2(rec[jn].x, rec[jn].y);
-        nz = rec[jn].z;
-        const float4 vm = vm_tile[jj];
+        for (int jj = jb; jj < jb + RUN; ++jj) {
+          const double2 xy = nxy;
+          const double z = nz;
+          const int64_t jn = base + jj + 1 < jend ? base + jj + 1 : jbeg;
+          nxy = make_double2(rec[jn].x, rec[jn].y);
+          nz = rec[jn].z;
+          const float4 vm = vm_tile[jj];
 #pragma unroll
-        for (int kk = 0; kk < K; ++kk) P::pair<false>(I[kk], xy, z, vm, e2, A[kk]);
+          for (int kk = 0; kk < K; ++kk) P::pair<false>(I[kk], xy, z, vm, e2, A[kk]);
+        }
+        if constexpr (RUN < kTile) {
+          if (jb + RUN < kTile) {
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
+          }
+        }
       }
     } else {
       const int cnt = (int)(jend - base);
@@ -765,6 +842,12 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
         const float4 vm = vm_tile[jj];
 #pragma unroll
         for (int kk = 0; kk < K; ++kk) P::pair<false>(I[kk], xy, z, vm, e2, A[kk]);
+        if constexpr (RUN < kTile) {
+          if ((jj & (RUN - 1)) == RUN - 1) {
+#pragma unroll
+            for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
+          }
+        }
       }
     }
 #pragma unroll

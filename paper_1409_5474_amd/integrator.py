@@ -115,6 +115,59 @@ class BlockIntegrator:
                     self.step(end)
         return self
 
+    # ---- checkpoint / resume ----------------------------------------------
+    _STATE = ("pos", "vel", "acc", "jerk", "t_tick", "level", "sched")
+
+    def checkpoint(self, path):
+        """Write the integration state to an .npz file (host copies).  The
+        kernels are deterministic, so resuming continues bit for bit."""
+        import numpy as np
+        torch.cuda.synchronize(self.dev)
+        arrays = {k: getattr(self, k).cpu().numpy() for k in self._STATE}
+        arrays["mass"] = self.mass.cpu().numpy()
+        meta = np.array([self.eta, self.dt_max, float(self.max_level), float(self.batch)], dtype=np.float64)
+        arrays["meta"] = meta
+        if self.batch:
+            arrays["offsets"] = self.offsets
+            arrays["eps2_sys"] = self.eps2_sys
+        else:
+            arrays["eps2"] = np.array([self.eps2], dtype=np.float64)
+        np.savez(path, **arrays)
+
+    @classmethod
+    def restore(cls, ctx: Context, path):
+        """Rebuild an integrator from ``checkpoint`` output."""
+        import numpy as np
+        d = np.load(path, allow_pickle=False)
+        eta, dt_max, max_level, batch = d["meta"].tolist()
+        dev = ctx.device
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        self = cls.__new__(cls)
+        self.ctx, self.n, self.dev = ctx, int(d["mass"].shape[0]), dev
+        self.batch = bool(batch)
+        if self.batch:
+            self.offsets = d["offsets"].astype(np.int64)
+            self.eps2_sys = d["eps2_sys"].astype(np.float64)
+            self.eps2 = None
+        else:
+            self.eps2 = float(d["eps2"][0])
+        self.eta, self.dt_max, self.max_level = float(eta), float(dt_max), int(max_level)
+        self.tick = self.dt_max * 2.0 ** -self.max_level
+        self.mass = t(d["mass"])
+        for k in self._STATE:
+            setattr(self, k, t(d[k]))
+        n = self.n
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.pos_p = torch.empty((n, 3), **f64)
+        self.vel_p = torch.empty((n, 3), **f64)
+        self.acc1 = torch.empty((n, 3), **f64)
+        self.jerk1 = torch.empty((n, 3), **f64)
+        self.pot1 = torch.empty(n, **f64)
+        self.active = torch.empty(n, dtype=torch.int32, device=dev)
+        self.all_idx = torch.arange(n, dtype=torch.int32, device=dev)
+        self._graphs = {}
+        return self
+
     # ---- diagnostics ------------------------------------------------------
     @property
     def steps(self):

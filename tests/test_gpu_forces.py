@@ -212,3 +212,32 @@ def test_full_size_sampled(ctx, prec):
     fa = np.linalg.norm((p.mass[:, None] * a).sum(0))
     scale = (p.mass * np.linalg.norm(a, axis=1)).sum()
     assert fa <= (1e-13 if prec == "fp64" else 1e-6) * scale
+
+
+def test_workspace_cap_reports_enomem_without_writing(ctx):
+    # A j-split needs a workspace; a cap below its size must fail with
+    # NB_ENOMEM (-2) before anything is launched, and leave outputs untouched.
+    import os
+    import subprocess
+    import sys
+    code = r'''
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+import paper_1409_5474_amd as nb, synth
+p = synth.plummer(4096, 3)
+ctx = nb.Context(0, "fp64", load_tuning=False)
+ctx.set_launch(1, 64, 32)
+t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+acc = torch.full((16, 3), 7.0, dtype=torch.float64, device="cuda")
+jerk = torch.full((16, 3), 7.0, dtype=torch.float64, device="cuda")
+pot = torch.full((16,), 7.0, dtype=torch.float64, device="cuda")
+try:
+    ctx.forces(t(p.pos), t(p.vel), t(p.mass), torch.arange(16, dtype=torch.int32, device="cuda"), 1e-4, acc, jerk, pot)
+    print("NO-ERROR")
+except nb.NbodyError as e:
+    torch.cuda.synchronize()
+    print("CODE", e.code, bool((acc == 7.0).all() and (pot == 7.0).all()))
+''' % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, NB_MAX_WORKSPACE_BYTES="1024")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert "CODE -2 True" in r.stdout, (r.stdout, r.stderr[-2000:])

@@ -73,3 +73,26 @@ def test_batch_block_steps_follow_per_system_oracle(ctx):
     # block count is at least the largest per-system count
     assert bi.steps >= 1
     assert int(bi.t_tick.min().item()) * bi.tick == t_end
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_checkpoint_resume_is_bitwise(ctx, tmp_path, batch):
+    import torch
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    eta, dt_max, ML = 0.02, 1.0 / 16, 30
+    if batch:
+        b = synth.cluster_batch(seed=4, n_clusters=6, n_min=64, n_max=900)
+        args = (T(b.pos), T(b.vel), T(b.mass), b.eps2)
+        kw = dict(offsets=b.offsets)
+    else:
+        p = synth.plummer(1500, 13)
+        args = (T(p.pos), T(p.vel), T(p.mass), 1e-4)
+        kw = {}
+    straight = BlockIntegrator(ctx, *args, eta, dt_max, ML, **kw).run_until(0.125, graph_steps=8)
+    half = BlockIntegrator(ctx, *args, eta, dt_max, ML, **kw).run_until(0.0625, graph_steps=8)
+    path = tmp_path / "state.npz"
+    half.checkpoint(str(path))
+    resumed = BlockIntegrator.restore(ctx, str(path)).run_until(0.125, graph_steps=8)
+    for k in ("pos", "vel", "acc", "jerk", "t_tick", "level"):
+        assert torch.equal(getattr(straight, k), getattr(resumed, k)), k
+    assert straight.steps == resumed.steps
