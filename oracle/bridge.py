@@ -1,0 +1,151 @@
+"""Second-order Hamiltonian split ("bridge") of a collisional subsystem and
+a field subsystem -- TEST INFRASTRUCTURE ONLY.
+
+Section "The multi-scale approach" writes the Hamiltonian of the whole system
+as H = H_A + H_B, where H_A = W_gc is the potential energy between the galaxy
+particles (g) and the stars in the sphere of influence of the central black
+holes (c), and H_B = (K_g + W_g) + (K_c + W_c) = H_g + H_c.  The evolution over
+dt is taken to second order as e^{dt/2 A} e^{dt B} e^{dt/2 A} (A and B the
+Poisson-bracket operators of H_A and H_B); e^{dt B} factors into separate
+evolutions of g and c because H_B has no cross term.  Written out
+(kick-drift-kick):
+
+  kick(h)    every particle of c: v += h a_{c<-g}(x); every particle of g:
+             v += h a_{g<-c}(x).  H_A depends on positions only, so the
+             positions stay.
+  drift(dt)  c advances under H_c alone with the block-step Hermite scheme
+             (oracle.hermite).  The kick changed its velocities, so every
+             drift restarts it: new a and jdot, start-up levels.  Its dt_max
+             is the bridge step, so each drift ends on a synchronisation time.
+             g advances under H_g alone with n_sub shared-step leapfrog
+             substeps (kick-drift-kick) of h = dt/n_sub with its own forces.
+             The paper advances g with a tree code; a direct sum stands in for
+             it here (the field solver is not part of the split).
+
+Softening: eps2_g inside g, eps2_c inside c, eps2_gc across.  Arithmetic of
+the elementwise updates, in this order and without fused multiply-adds:
+v + (h/2) a, then x + h v.
+
+The force sums are the oracle's own direct sums (``forces_f64``); the field
+of g on the particles of c (and the reverse) is that sum over the
+concatenated set [g | c] with the receiving subsystem's masses set to zero,
+so only the other subsystem exerts (the i-set/j-set split of the paper's
+section on GPU optimisations).
+"""
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import forces_f64
+from . import hermite
+
+
+def cross_forces(x_i, v_i, x_j, v_j, m_j, eps2):
+    """Acceleration, jerk and potential on every particle of i in the field of j.
+
+    Returns (acc [Ni,3], jerk [Ni,3], pot [Ni])."""
+    x_i, v_i = np.asarray(x_i, dtype=np.float64), np.asarray(v_i, dtype=np.float64)
+    nj = np.asarray(m_j).shape[0]
+    ni = x_i.shape[0]
+    pos = np.concatenate([x_j, x_i])
+    vel = np.concatenate([v_j, v_i])
+    mass = np.concatenate([np.asarray(m_j, dtype=np.float64), np.zeros(ni)])
+    act = np.arange(nj, nj + ni, dtype=np.int32)
+    a, j, p, _ = forces_f64(pos, vel, mass, eps2, act)
+    return a, j, p
+
+
+def self_forces(eps2):
+    """Force routine in the form oracle.hermite expects: (x, v, m, act) -> (a, j, pot)."""
+    def f(x, v, m, act):
+        a, j, p, _ = forces_f64(x, v, m, eps2, act)
+        return a, j, p
+    return f
+
+
+@dataclass
+class BridgeState:
+    xg: np.ndarray
+    vg: np.ndarray
+    mg: np.ndarray
+    ag: np.ndarray                 # self acceleration of g at xg
+    cluster: hermite.BlockState    # c, with dt_max = the bridge step
+    eps2_g: float
+    eps2_c: float
+    eps2_gc: float
+    dt: float
+    n_sub: int
+    steps: int = 0
+
+    @property
+    def time(self):
+        return self.steps * self.dt
+
+
+def initialise(xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt, n_sub=1, eta=0.01, max_level=30):
+    xg = np.array(xg, dtype=np.float64)
+    vg = np.array(vg, dtype=np.float64)
+    mg = np.array(mg, dtype=np.float64)
+    if mg.shape[0]:
+        ag = self_forces(eps2_g)(xg, vg, mg, np.arange(mg.shape[0], dtype=np.int32))[0]
+    else:
+        ag = np.zeros((0, 3))
+    cl = hermite.initialise(np.asarray(xc, dtype=np.float64), np.asarray(vc, dtype=np.float64),
+                            np.asarray(mc, dtype=np.float64), eps2_c, eta, dt, max_level, self_forces(eps2_c))
+    return BridgeState(xg, vg, mg, ag, cl, float(eps2_g), float(eps2_c), float(eps2_gc), float(dt), int(n_sub))
+
+
+def kick(st: BridgeState, h):
+    """e^{h A}: both subsystems take the other's field at the current positions."""
+    c = st.cluster
+    a_cg = cross_forces(c.x, c.v, st.xg, st.vg, st.mg, st.eps2_gc)[0]
+    a_gc = cross_forces(st.xg, st.vg, c.x, c.v, c.m, st.eps2_gc)[0]
+    c.v = c.v + h * a_cg
+    st.vg = st.vg + h * a_gc
+
+
+def drift_cluster(st: BridgeState):
+    """c under H_c for one bridge step: restart, then block steps to the next synchronisation time."""
+    c = st.cluster
+    n = c.m.shape[0]
+    c.a, c.j, _ = self_forces(st.eps2_c)(c.x, c.v, c.m, np.arange(n, dtype=np.int32))
+    lev, cl = hermite.startup_level(c.a, c.j, c.eta, c.dt_max, c.max_level)
+    c.level = lev
+    c.clamps += int(cl.sum())
+    c.force_evals += n
+    hermite.run_until(c, (st.steps + 1) * st.dt, self_forces(st.eps2_c))
+
+
+def drift_galaxy(st: BridgeState):
+    """g under H_g for one bridge step: n_sub leapfrog substeps (kick-drift-kick)."""
+    h = st.dt / st.n_sub
+    f = self_forces(st.eps2_g)
+    act = np.arange(st.mg.shape[0], dtype=np.int32)
+    for _ in range(st.n_sub):
+        st.vg = st.vg + (0.5 * h) * st.ag
+        st.xg = st.xg + h * st.vg
+        st.ag = f(st.xg, st.vg, st.mg, act)[0]
+        st.vg = st.vg + (0.5 * h) * st.ag
+
+
+def step(st: BridgeState):
+    """One bridge step: half kick, both drifts, half kick."""
+    kick(st, 0.5 * st.dt)
+    drift_cluster(st)
+    if st.mg.shape[0]:
+        drift_galaxy(st)
+    kick(st, 0.5 * st.dt)
+    st.steps += 1
+    return st
+
+
+def energy(st: BridgeState):
+    """K_g + W_g + K_c + W_c + W_gc, each potential with its own softening."""
+    c = st.cluster
+    ng, nc = st.mg.shape[0], c.m.shape[0]
+    Kg = 0.5 * float((st.mg * (st.vg * st.vg).sum(1)).sum())
+    Kc = 0.5 * float((c.m * (c.v * c.v).sum(1)).sum())
+    Wg = 0.5 * float((st.mg * self_forces(st.eps2_g)(st.xg, st.vg, st.mg, np.arange(ng, dtype=np.int32))[2]).sum())
+    Wc = 0.5 * float((c.m * self_forces(st.eps2_c)(c.x, c.v, c.m, np.arange(nc, dtype=np.int32))[2]).sum())
+    Wgc = float((c.m * cross_forces(c.x, c.v, st.xg, st.vg, st.mg, st.eps2_gc)[2]).sum())
+    return dict(Kg=Kg, Wg=Wg, Kc=Kc, Wc=Wc, Wgc=Wgc, E=Kg + Wg + Kc + Wc + Wgc)

@@ -121,3 +121,81 @@ def test_hermite_pins_catch_mutant(monkeypatch, name, attr, fn):
             caught = True
             break
     assert caught, f"mutant {name!r} survived every Hermite pin"
+
+
+# Bridge mutants: patch one function of oracle.bridge and run its pins.
+def _bridge_pins():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_oracle_bridge as T
+    return [T.test_cross_field_adds_up_to_the_whole, T.test_kicks_conserve_total_momentum_and_keep_positions,
+            T.test_two_body_split_is_the_textbook_leapfrog, T.test_two_body_split_converges_at_second_order,
+            T.test_massless_cluster_leaves_the_galaxy_a_plain_leapfrog,
+            T.test_cluster_in_galaxy_converges_at_second_order_in_the_bridge_step]
+
+
+def _mut_step_first_order(st):
+    from oracle import bridge as B
+    B.kick(st, st.dt)                      # the whole kick before the drifts
+    B.drift_cluster(st)
+    if st.mg.shape[0]:
+        B.drift_galaxy(st)
+    st.steps += 1
+    return st
+
+
+def _mut_cross_sign(x_i, v_i, x_j, v_j, m_j, eps2):
+    from oracle import forces_f64
+    nj, ni = np.asarray(m_j).shape[0], np.asarray(x_i).shape[0]
+    a, j, p, _ = forces_f64(np.concatenate([x_j, x_i]), np.concatenate([v_j, v_i]),
+                            np.concatenate([m_j, np.zeros(ni)]), eps2, np.arange(nj, nj + ni, dtype=np.int32))
+    return -a, -j, p
+
+
+def _mut_kick_c_only(st, h):
+    from oracle import bridge as B
+    c = st.cluster
+    c.v = c.v + h * B.cross_forces(c.x, c.v, st.xg, st.vg, st.mg, st.eps2_gc)[0]
+
+
+def _mut_galaxy_drift_first(st):
+    from oracle import bridge as B
+    h = st.dt / st.n_sub
+    f = B.self_forces(st.eps2_g)
+    act = np.arange(st.mg.shape[0], dtype=np.int32)
+    for _ in range(st.n_sub):
+        st.xg = st.xg + h * st.vg          # drift before the half kick
+        st.vg = st.vg + (0.5 * h) * st.ag
+        st.ag = f(st.xg, st.vg, st.mg, act)[0]
+        st.vg = st.vg + (0.5 * h) * st.ag
+
+
+def _mut_cross_includes_receivers(x_i, v_i, x_j, v_j, m_j, eps2):
+    from oracle import forces_f64
+    nj, ni = np.asarray(m_j).shape[0], np.asarray(x_i).shape[0]
+    # receivers keep a mass: they pull on each other too
+    mass = np.concatenate([m_j, np.full(ni, float(np.mean(m_j)) if nj else 0.0)])
+    a, j, p, _ = forces_f64(np.concatenate([x_j, x_i]), np.concatenate([v_j, v_i]), mass, eps2,
+                            np.arange(nj, nj + ni, dtype=np.int32))
+    return a, j, p
+
+
+BRIDGE_MUTANTS = [("whole kick first (first-order split)", "step", _mut_step_first_order),
+                  ("cross field sign", "cross_forces", _mut_cross_sign),
+                  ("g never kicked", "kick", _mut_kick_c_only),
+                  ("galaxy drifts before its half kick", "drift_galaxy", _mut_galaxy_drift_first),
+                  ("receivers exert forces", "cross_forces", _mut_cross_includes_receivers)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,attr,fn", BRIDGE_MUTANTS, ids=[m[0] for m in BRIDGE_MUTANTS])
+def test_bridge_pins_catch_mutant(monkeypatch, name, attr, fn):
+    from oracle import bridge as B
+    monkeypatch.setattr(B, attr, fn)
+    caught = False
+    for pin in _bridge_pins():
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived every bridge pin"
