@@ -43,7 +43,7 @@ def parse():
                     help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="", choices=["", "plummer1k", "hermite65k", "hermite262k", "batch128",
-                                                        "merger"],
+                                                        "merger", "bridge"],
                     help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -82,6 +82,12 @@ def workloads(args):
     merger      11 Hernquist galaxies (2^17 stars + a point mass each): the
                 i-set near the point masses against all 1,441,803 bodies,
                 FP64 and mixed
+    bridge      the same bodies under the kick-drift-kick split: c = the
+                point masses and the stars near them (FP64 Hermite block
+                steps, eta=0.01), g = every other star (mixed-precision
+                leapfrog with direct forces), cross field in mixed
+                precision; bridge step 1/128; --steps bridge steps after one
+                warm-up step, each part timed
     """
     import numpy as np
     import torch
@@ -176,6 +182,49 @@ def workloads(args):
             out[prec] = dict(n_i=na, n_j=nj, ms=round(ms, 4), gint=round(na * nj / ms / 1e6, 2),
                              launch=ctx.get_launch(nj, na))
             ctx.close()
+    elif args.workload == "bridge":
+        from paper_1409_5474_amd.bridge import Bridge
+        m = synth.hernquist_merger()
+        is_c = np.zeros(m.mass.size, dtype=bool)
+        is_c[m.active] = True
+        c, g = np.nonzero(is_c)[0], np.nonzero(~is_c)[0]
+        dt = 1.0 / 128
+        c64, cmx = nb.Context(0, "fp64"), nb.Context(0, "mixed")
+        br = Bridge(c64, cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]), t(m.vel[c]), t(m.mass[c]),
+                    m.eps2, m.eps2, m.eps2, dt, n_sub=1, eta=0.01, max_level=30)
+        E0 = br.energy()
+        parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
+        block_steps = 0
+
+        def timed(key, fn):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            parts[key] += time.perf_counter() - t0
+
+        for k in range(args.steps + 1):
+            if k == 1:                      # the first step is the warm-up
+                parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
+                block_steps = br.block_steps
+            timed("kick", lambda: br.kick(0.5 * dt))
+            timed("cluster", br.drift_cluster)
+            timed("galaxy", br.drift_galaxy)
+            timed("kick", lambda: br.kick(0.5 * dt))
+            br.steps += 1
+        E1 = br.energy()
+        nsteps = args.steps
+        ng, nc = int(g.size), int(c.size)
+        wall = sum(parts.values())
+        cross = 4.0 * ng * nc                # two kicks, both directions
+        out.update(n_g=ng, n_c=nc, bridge_dt=dt, bridge_steps=nsteps,
+                   ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
+                   ms_per_part={k: round(1e3 * v / nsteps, 2) for k, v in parts.items()},
+                   cross_field_gint=round(cross * nsteps / parts["kick"] / 1e9, 1),
+                   galaxy_gint=round(float(ng) * ng * nsteps / parts["galaxy"] / 1e9, 1),
+                   cluster_block_steps_per_bridge_step=round((br.block_steps - block_steps) / nsteps, 1),
+                   energy_drift=abs(E1["E"] - E0["E"]) / abs(E0["E"]), time=br.time)
+        c64.close(); cmx.close()
     print(json.dumps(out), flush=True)
 
 

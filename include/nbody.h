@@ -144,6 +144,21 @@ int nbody_forces(nb_ctx *ctx, const double *pos, const double *vel, const double
                  const int32_t *active_idx, int64_t n_active, double eps2,
                  double *acc, double *jerk, double *pot);
 
+/* Forces on particles that are not part of the j-set (the paper's section
+ * on GPU optimisations lets the i-set be a different set of particles from
+ * the j-set; the coupling kicks of a Hamiltonian split need exactly this):
+ * acceleration, jerk and potential of the rows active_idx[0..n_active) of
+ * pos_i/vel_i ([N_i][3]) in the field of the N_j particles pos_j/vel_j/mass_j.
+ * Every (i, j) pair contributes -- no pair is taken to be a self pair -- and
+ * with eps2 == 0 a pair at zero distance contributes nothing.  Outputs as
+ * nbody_forces.  Errors as nbody_forces (with N_j for N), plus NB_EINVAL for
+ * N_i outside [0, 2^31) or empty or null i arrays when n_active > 0.
+ * active_idx entries must lie in [0, N_i) (not range-checked). */
+int nbody_forces_ij(nb_ctx *ctx, const double *pos_j, const double *vel_j, const double *mass_j, int64_t N_j,
+                    const double *pos_i, const double *vel_i, int64_t N_i,
+                    const int32_t *active_idx, int64_t n_active, double eps2,
+                    double *acc, double *jerk, double *pot);
+
 /* Same, with the active count read from device memory (*n_active_dev) when
  * the kernels run, so a captured graph can replay it for any count.
  * max_active bounds *n_active_dev and sizes the launch; the launch
@@ -166,6 +181,25 @@ int nbody_forces_batch(nb_ctx *ctx, const int64_t *offsets, int64_t C, const dou
                        const double *pos, const double *vel, const double *mass,
                        const int32_t *active_idx, const int64_t *act_offsets,
                        double *acc, double *jerk, double *pot);
+
+/* ---- Hamiltonian split (bridge) ------------------------------------------
+ * Section "The multi-scale approach" evolves a collisional subsystem c and a
+ * field subsystem g together by splitting H = H_A + H_B with H_A = W_gc (the
+ * potential energy between them) and H_B = H_g + H_c, to second order as
+ * e^{dt/2 A} e^{dt B} e^{dt/2 A}: a half kick by the cross field
+ * (nbody_forces_ij both ways, then nb_kick), each subsystem on its own for
+ * dt, another half kick.  These two passes are the element-wise parts.
+ *
+ * nb_kick:       vel[i] = vel[i] + h acc[i]
+ * nb_kick_drift: vel[i] = vel[i] + h_kick acc[i]; pos[i] = pos[i] + h_drift vel[i]
+ *                (the new velocity), i.e. the first half of a leapfrog step.
+ * Arrays are [N][3] doubles and must not overlap; each update is a rounded
+ * multiply followed by a rounded add (no fused multiply-add).  Errors:
+ * NB_EINVAL for N outside [0, 2^31), a non-finite step, or a null pointer
+ * when N > 0; N == 0 does nothing. */
+int nb_kick(nb_ctx *ctx, double *vel, const double *acc, int64_t N, double h);
+int nb_kick_drift(nb_ctx *ctx, double *pos, double *vel, const double *acc, int64_t N, double h_kick,
+                  double h_drift);
 
 /* ---- Hermite block steps --------------------------------------------------
  * Time is kept in int64 ticks of dt_min = dt_max 2^-max_level; particle i

@@ -16,7 +16,8 @@ import torch
 
 __all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", "lib_path", "library",
            "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
-           "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy"]
+           "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy",
+           "nbody_forces_ij", "nb_kick", "nb_kick_drift"]
 
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -62,6 +63,9 @@ _sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _d
      ctypes.POINTER(_dbl))
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_devcount", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("nbody_forces_ij", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("nb_kick", _vp, _vp, _vp, _i64, _dbl)
+_sig("nb_kick_drift", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl)
 _sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
 _sig("hermite_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp)
 _sig("hermite_startup", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
@@ -192,6 +196,43 @@ class Context:
                                     _p(acc), _p(jerk), _p(pot)))
         return acc, jerk, pot
 
+    def forces_ij(self, pos_j, vel_j, mass_j, pos_i, vel_i, active, eps2, acc=None, jerk=None, pot=None):
+        """Forces on rows ``active`` of pos_i/vel_i from the separate j-set (``nbody_forces_ij``)."""
+        nj, ni, na = mass_j.shape[0], pos_i.shape[0], active.shape[0]
+        _check_vec(pos_j, nj, "pos_j", self.device)
+        _check_vec(vel_j, nj, "vel_j", self.device)
+        _check_1d(mass_j, nj, "mass_j", torch.float64, self.device)
+        _check_vec(pos_i, ni, "pos_i", self.device)
+        _check_vec(vel_i, ni, "vel_i", self.device)
+        _check_1d(active, na, "active_idx", torch.int32, self.device)
+        if acc is None:
+            acc = torch.empty((na, 3), dtype=torch.float64, device=self.device)
+        if jerk is None:
+            jerk = torch.empty((na, 3), dtype=torch.float64, device=self.device)
+        if pot is None:
+            pot = torch.empty((na,), dtype=torch.float64, device=self.device)
+        _check_vec(acc, na, "acc", self.device)
+        _check_vec(jerk, na, "jerk", self.device)
+        _check_1d(pot, na, "pot", torch.float64, self.device)
+        self._chk(_lib.nbody_forces_ij(self._h, _p(pos_j), _p(vel_j), _p(mass_j), nj, _p(pos_i), _p(vel_i), ni,
+                                       _p(active), na, float(eps2), _p(acc), _p(jerk), _p(pot)))
+        return acc, jerk, pot
+
+    def kick(self, vel, acc, h):
+        """vel += h acc (``nb_kick``)."""
+        n = vel.shape[0]
+        _check_vec(vel, n, "vel", self.device)
+        _check_vec(acc, n, "acc", self.device)
+        self._chk(_lib.nb_kick(self._h, _p(vel), _p(acc), n, float(h)))
+
+    def kick_drift(self, pos, vel, acc, h_kick, h_drift):
+        """vel += h_kick acc, then pos += h_drift vel (``nb_kick_drift``)."""
+        n = vel.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        _check_vec(vel, n, "vel", self.device)
+        _check_vec(acc, n, "acc", self.device)
+        self._chk(_lib.nb_kick_drift(self._h, _p(pos), _p(vel), _p(acc), n, float(h_kick), float(h_drift)))
+
     def forces_devcount(self, pos, vel, mass, active, n_active_dev, max_active, eps2, acc, jerk, pot):
         n = mass.shape[0]
         _check_1d(n_active_dev, 1, "n_active_dev", torch.int32, self.device)
@@ -301,3 +342,15 @@ def nb_energy(ctx, *a, **k):
 
 def version():
     return _lib.nb_version().decode()
+
+
+def nbody_forces_ij(ctx, *a, **k):
+    return ctx.forces_ij(*a, **k)
+
+
+def nb_kick(ctx, *a, **k):
+    return ctx.kick(*a, **k)
+
+
+def nb_kick_drift(ctx, *a, **k):
+    return ctx.kick_drift(*a, **k)

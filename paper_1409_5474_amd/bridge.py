@@ -1,0 +1,144 @@
+"""Second-order Hamiltonian split of a collisional subsystem and a field
+subsystem, on the GPU (section "The multi-scale approach").
+
+H = H_A + H_B with H_A = W_gc, the potential energy between the field
+particles g and the collisional particles c (the stars in the sphere of
+influence of the central black holes), and H_B = H_g + H_c.  One step of
+length dt is e^{dt/2 A} e^{dt B} e^{dt/2 A}:
+
+  kick(dt/2)  both subsystems take the other's field at the current
+              positions: ``nbody_forces_ij`` both ways, then ``nb_kick``;
+  drift(dt)   c: the Hermite block-step integrator (``BlockIntegrator``),
+              restarted -- new forces and start-up levels -- since the kick
+              changed its velocities, with dt_max = dt, so each drift ends on
+              a synchronisation time;
+              g: n_sub shared-step leapfrog substeps of dt/n_sub with its own
+              direct forces (``nb_kick_drift``, ``nbody_forces``, ``nb_kick``)
+              -- a direct sum standing in for the paper's tree code;
+  kick(dt/2).
+
+Every arithmetic step runs in the library's kernels; this module only
+sequences the calls on the contexts' streams.  The subsystems may use
+different contexts (and so precisions): ``ctx_c`` for c, ``ctx_g`` for g's
+own forces, ``ctx_x`` for the cross field (default ``ctx_g``).  All contexts
+must be on the same device and use the same stream (torch's current one by
+default).
+"""
+import torch
+
+from . import Context
+from .integrator import BlockIntegrator
+
+
+class Bridge:
+    def __init__(self, ctx_c: Context, ctx_g: Context, xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt,
+                 n_sub=1, eta=0.01, max_level=30, ctx_x: Context = None):
+        self.ctx_c, self.ctx_g = ctx_c, ctx_g
+        self.ctx_x = ctx_x if ctx_x is not None else ctx_g
+        dev = ctx_c.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.eps2_g, self.eps2_c, self.eps2_gc = float(eps2_g), float(eps2_c), float(eps2_gc)
+        self.dt, self.n_sub, self.steps = float(dt), int(n_sub), 0
+        self.xg = xg.to(**f64).contiguous().clone()
+        self.vg = vg.to(**f64).contiguous().clone()
+        self.mg = mg.to(**f64).contiguous()
+        self.ng = self.mg.shape[0]
+        self.cluster = BlockIntegrator(ctx_c, xc, vc, mc, eps2_c, eta, self.dt, max_level)
+        self.nc = self.cluster.n
+        self.idx_g = torch.arange(self.ng, dtype=torch.int32, device=dev)
+        self.idx_c = torch.arange(self.nc, dtype=torch.int32, device=dev)
+        self.ag = torch.zeros((self.ng, 3), **f64)
+        self._jg = torch.empty((self.ng, 3), **f64)
+        self._pg = torch.empty(self.ng, **f64)
+        self.a_cg = torch.empty((self.nc, 3), **f64)
+        self._j_cg = torch.empty((self.nc, 3), **f64)
+        self._p_cg = torch.empty(self.nc, **f64)
+        self.a_gc = torch.empty((self.ng, 3), **f64)
+        self._j_gc = torch.empty((self.ng, 3), **f64)
+        self._p_gc = torch.empty(self.ng, **f64)
+        if self.ng:
+            self._galaxy_forces()
+        self.block_steps = 0
+
+    # ---- pieces of the split ----------------------------------------------
+    def _galaxy_forces(self):
+        self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, self.ag, self._jg, self._pg)
+
+    def cross_field(self):
+        """Field of g on every particle of c and of c on every particle of g."""
+        c = self.cluster
+        if self.ng and self.nc:
+            self.ctx_x.forces_ij(self.xg, self.vg, self.mg, c.pos, c.vel, self.idx_c, self.eps2_gc,
+                                 self.a_cg, self._j_cg, self._p_cg)
+            self.ctx_x.forces_ij(c.pos, c.vel, c.mass, self.xg, self.vg, self.idx_g, self.eps2_gc,
+                                 self.a_gc, self._j_gc, self._p_gc)
+        else:
+            self.a_cg.zero_()
+            self.a_gc.zero_()
+
+    def kick(self, h):
+        """e^{h A}: velocities of both subsystems move in the other's field."""
+        self.cross_field()
+        self.ctx_x.kick(self.cluster.vel, self.a_cg, h)
+        self.ctx_x.kick(self.vg, self.a_gc, h)
+
+    def drift_cluster(self, use_graph=False):
+        c = self.cluster
+        before = c.steps
+        c.restart()
+        c.run_to_tick((self.steps + 1) << c.max_level, use_graph=use_graph)
+        self.block_steps += c.steps - before
+
+    def drift_galaxy(self):
+        h = self.dt / self.n_sub
+        for _ in range(self.n_sub):
+            self.ctx_g.kick_drift(self.xg, self.vg, self.ag, 0.5 * h, h)
+            self._galaxy_forces()
+            self.ctx_g.kick(self.vg, self.ag, 0.5 * h)
+
+    def step(self, use_graph=False):
+        """One bridge step: half kick, both drifts, half kick."""
+        self.kick(0.5 * self.dt)
+        self.drift_cluster(use_graph)
+        if self.ng:
+            self.drift_galaxy()
+        self.kick(0.5 * self.dt)
+        self.steps += 1
+        return self
+
+    def run(self, n_steps, use_graph=False):
+        for _ in range(n_steps):
+            self.step(use_graph)
+        return self
+
+    @property
+    def time(self):
+        return self.steps * self.dt
+
+    # ---- diagnostics ------------------------------------------------------
+    def energy(self):
+        """K_g + W_g + K_c + W_c + W_gc, each potential with its own softening."""
+        c = self.cluster
+        dev = c.dev
+        out = torch.zeros(8, dtype=torch.float64, device=dev)
+        parts = {}
+        if self.ng:
+            pot = torch.empty(self.ng, dtype=torch.float64, device=dev)
+            self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, None, None, pot)
+            o = self.ctx_g.energy(self.xg, self.vg, self.mg, pot, out).cpu().tolist()
+            parts["Kg"], parts["Wg"] = o[0], o[1]
+        else:
+            parts["Kg"] = parts["Wg"] = 0.0
+        pot = torch.empty(self.nc, dtype=torch.float64, device=dev)
+        self.ctx_c.forces(c.pos, c.vel, c.mass, self.idx_c, self.eps2_c, None, None, pot)
+        o = self.ctx_c.energy(c.pos, c.vel, c.mass, pot, out.zero_()).cpu().tolist()
+        parts["Kc"], parts["Wc"] = o[0], o[1]
+        if self.ng:
+            pot = torch.empty(self.nc, dtype=torch.float64, device=dev)
+            self.ctx_x.forces_ij(self.xg, self.vg, self.mg, c.pos, c.vel, self.idx_c, self.eps2_gc, None, None, pot)
+            o = self.ctx_x.energy(c.pos, c.vel, c.mass, pot, out.zero_()).cpu().tolist()
+            parts["Wgc"] = 2.0 * o[1]     # nb_energy halves the pair sum
+        else:
+            parts["Wgc"] = 0.0
+        parts["E"] = parts["Kg"] + parts["Wg"] + parts["Kc"] + parts["Wc"] + parts["Wgc"]
+        return parts

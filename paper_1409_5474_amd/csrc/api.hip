@@ -204,9 +204,11 @@ bool kernel_mask(int prec, double eps2) {
 }
 
 int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* vel, const double* mass, int64_t N,
-               const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot) {
+               const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot,
+               const double* ipos = nullptr, const double* ivel = nullptr, bool no_self = false) {
   nb::ForceArgs a{};
   a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
+  a.ipos = ipos; a.ivel = ivel; a.no_self = no_self ? 1 : 0;
   a.active = active; a.n_active = n_active; a.n_active_dev = nullptr;
   a.eps2 = eps2; a.S = cfg.S; a.target_items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
   a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr;
@@ -354,6 +356,19 @@ int nbody_forces(nb_ctx* c, const double* pos, const double* vel, const double* 
   return run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
 }
 
+int nbody_forces_ij(nb_ctx* c, const double* pos_j, const double* vel_j, const double* mass_j, int64_t N_j,
+                    const double* pos_i, const double* vel_i, int64_t N_i, const int32_t* active, int64_t n_active,
+                    double eps2, double* acc, double* jerk, double* pot) {
+  int rc = check_forces_args(c, pos_j, vel_j, mass_j, N_j, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (N_i < 0 || N_i >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N_i must be in [0, 2^31)%s");
+  if (n_active > 0 && (N_i < 1 || !pos_i || !vel_i))
+    return fail(c, NB_EINVAL, "i-particle arrays are empty or null%s");
+  if (n_active == 0) return NB_OK;
+  const Launch cfg = choose(c, N_j, n_active);
+  return run_forces(c, cfg, pos_j, vel_j, mass_j, N_j, active, n_active, eps2, acc, jerk, pot, pos_i, vel_i, true);
+}
+
 int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const double* vel, const double* mass,
                    int64_t N, const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk,
                    double* pot, int reps, double* ms) {
@@ -461,6 +476,26 @@ int hermite_predict(nb_ctx* c, const double* pos, const double* vel, const doubl
   hipError_t e = nb::launch_predict(pos, vel, acc, jerk, t_tick, t_next_tick, nullptr, dt_min, N, pos_p, vel_p,
                                     c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "predict launch");
+}
+
+int nb_kick(nb_ctx* c, double* vel, const double* acc, int64_t N, double h) {
+  if (!c) return NB_EINVAL;
+  if (N < 0 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [0, 2^31)%s");
+  if (!std::isfinite(h)) return fail(c, NB_EINVAL, "h must be finite%s");
+  if (N == 0) return NB_OK;
+  if (!vel || !acc) return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_kick(vel, acc, h, N, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "kick launch");
+}
+
+int nb_kick_drift(nb_ctx* c, double* pos, double* vel, const double* acc, int64_t N, double h_kick, double h_drift) {
+  if (!c) return NB_EINVAL;
+  if (N < 0 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [0, 2^31)%s");
+  if (!std::isfinite(h_kick) || !std::isfinite(h_drift)) return fail(c, NB_EINVAL, "h must be finite%s");
+  if (N == 0) return NB_OK;
+  if (!pos || !vel || !acc) return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_kick_drift(pos, vel, acc, h_kick, h_drift, N, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "kick-drift launch");
 }
 
 static int check_levels(nb_ctx* c, double eta, double dt_max, int32_t max_level) {

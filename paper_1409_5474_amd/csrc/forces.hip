@@ -463,6 +463,8 @@ __host__ __device__ inline int64_t chunk_len(int64_t n, int S) {
 template <class P, int K, int L, bool MASK>
 __device__ __forceinline__ void process_item(typename P::JTile& tile, double* red, const double* __restrict__ pos,
                                              const double* __restrict__ vel, const double* __restrict__ mass,
+                                             const double* __restrict__ ipos, const double* __restrict__ ivel,
+                                             const double* __restrict__ smass,
                                              int64_t jbeg, int64_t jend, const int32_t* __restrict__ active,
                                              int64_t n_act, int64_t k0, double eps2, bool final_out,
                                              double* __restrict__ acc, double* __restrict__ jerk,
@@ -480,7 +482,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * SLOTS + slot;
     irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
-    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+    I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const typename P::T e2 = in_vgpr(P::eps(eps2));
 
@@ -551,7 +553,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
     const int64_t k = k0 + kk * SLOTS + slot;
     if (sub == 0 && k < n_act) {
       if (final_out) {
-        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        const double self = (e2 > 0 && smass) ? P::self_term(smass[irow[kk]], eps2) : 0.0;
         acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
         jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
         pot[k] = -(v[6] - self);
@@ -589,7 +591,8 @@ __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item<P, K, L, MASK>(sm.tile, sm.red, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB,
+    process_item<P, K, L, MASK>(sm.tile, sm.red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
+                                a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
                                 a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
   }
 }
@@ -619,7 +622,7 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
     } else if (c < 6) {
       a.jerk[3 * k + c - 3] = s;
     } else {
-      const double self = self_on ? P::self_term(a.mass[a.active[k]], a.eps2) : 0.0;
+      const double self = (self_on && !a.no_self) ? P::self_term(a.mass[a.active[k]], a.eps2) : 0.0;
       a.pot[k] = -(s - self);
     }
   }
@@ -645,8 +648,8 @@ __global__ __launch_bounds__(256) void k_mirror(const double* __restrict__ pos, 
 
 template <class P, int K, bool MASK>
 __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restrict__ rec,
-                                                const double* __restrict__ pos, const double* __restrict__ vel,
-                                                const double* __restrict__ mass, int64_t jbeg, int64_t jend,
+                                                const double* __restrict__ ipos, const double* __restrict__ ivel,
+                                                const double* __restrict__ smass, int64_t jbeg, int64_t jend,
                                                 const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
                                                 double eps2, bool final_out, double* __restrict__ acc,
                                                 double* __restrict__ jerk, double* __restrict__ pot,
@@ -659,7 +662,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
     irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
-    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+    I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const typename P::T e2 = in_vgpr(P::eps(eps2));
   typename P::T A[K][7];
@@ -720,7 +723,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
       if (final_out) {
-        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        const double self = (e2 > 0 && smass) ? P::self_term(smass[irow[kk]], eps2) : 0.0;
         acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
         jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
         pot[k] = -(v[6] - self);
@@ -761,7 +764,8 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item_sj<P, K, MASK>(rec, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
+    process_item_sj<P, K, MASK>(rec, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass,
+                                jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                                 a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
   }
 }
@@ -774,8 +778,8 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
 // can pair with their neighbours.
 template <int K>
 __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ rec, float4* vm_tile,
-                                                const double* __restrict__ pos, const double* __restrict__ vel,
-                                                const double* __restrict__ mass, int64_t jbeg, int64_t jend,
+                                                const double* __restrict__ ipos, const double* __restrict__ ivel,
+                                                const double* __restrict__ smass, int64_t jbeg, int64_t jend,
                                                 const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
                                                 double eps2, bool final_out, double* __restrict__ acc,
                                                 double* __restrict__ jerk, double* __restrict__ pot,
@@ -789,7 +793,7 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
     irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
-    I[kk] = P::load_i(pos, vel, irow[kk] >= 0 ? irow[kk] : 0);
+    I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const float e2 = in_vgpr(P::eps(eps2));
   float A[K][7];
@@ -861,7 +865,7 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
       if (final_out) {
-        const double self = (e2 > 0) ? P::self_term(mass[irow[kk]], eps2) : 0.0;
+        const double self = (e2 > 0 && smass) ? P::self_term(smass[irow[kk]], eps2) : 0.0;
         acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
         jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
         pot[k] = -(v[6] - self);
@@ -893,7 +897,8 @@ __global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item_hy<K>(rec, vm_tile, a.pos, a.vel, a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
+    process_item_hy<K>(rec, vm_tile, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel,
+                       a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                        a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
   }
 }
@@ -920,7 +925,7 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
     const int64_t clen = chunk_len(nj, it.nchunk);
     const int64_t jb = sy.j0 + (int64_t)it.chunk * clen;
     const int64_t je = jb + clen < sy.j1 ? jb + clen : sy.j1;
-    process_item<P, K, L, MASK>(sm.tile, sm.red, pos, vel, mass, jb, je, active + sy.a0, n_act,
+    process_item<P, K, L, MASK>(sm.tile, sm.red, pos, vel, mass, pos, vel, mass, jb, je, active + sy.a0, n_act,
                                 (int64_t)it.iblk * IB, sy.eps2, it.nchunk == 1, acc + 3 * sy.a0,
                                 jerk + 3 * sy.a0, pot + sy.a0,
                                 part + (sy.part_off + (int64_t)it.chunk * n_act) * 7);

@@ -53,6 +53,12 @@ struct ForceArgs {
   int64_t act_lo;               // device-count mode: work only when count >= act_lo and
   int last;                     // count <= n_active (or any larger count when `last`)
   void* rec;                    // scalar j-path: mirror of n j-records (context-owned)
+  // Receiving particles given apart from the j-set: `active` then indexes
+  // ipos/ivel (null: the j arrays) and, with no_self set, no self pair is
+  // removed from the potential (the i-set is not part of the j-set).
+  const double* ipos;
+  const double* ivel;
+  int no_self;
 };
 
 // Batched work list item: one (system, i-block, j-chunk) triple.
@@ -115,6 +121,11 @@ int schedule_blocks(int64_t n);
 hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
                          int64_t n, double* part, double* out, hipStream_t st);
 int energy_blocks(int64_t n);
+
+// Kick / kick-drift passes of the Hamiltonian split (bridge.hip).
+hipError_t launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t st);
+hipError_t launch_kick_drift(double* pos, double* vel, const double* acc, double h_kick, double h_drift, int64_t n,
+                             hipStream_t st);
 
 }  // namespace nb
 

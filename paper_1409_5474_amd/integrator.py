@@ -100,6 +100,18 @@ class BlockIntegrator:
         end = int(round(t_end / self.tick))
         if end * self.tick != t_end:
             raise ValueError("t_end must be a whole number of ticks")
+        return self.run_to_tick(end, graph_steps, use_graph)
+
+    def restart(self):
+        """Start afresh from the current (synchronised) state: forces on every
+        particle and start-up levels, as at t = 0 (after an outside change of
+        the velocities, e.g. a kick, the stored jerks are stale)."""
+        self._all_forces(self.pos, self.vel, self.acc, self.jerk, self.pot1)
+        self.ctx.startup(self.acc, self.jerk, self.eta, self.dt_max, self.max_level, self.level)
+
+    def run_to_tick(self, end, graph_steps=32, use_graph=True):
+        """Integrate until every particle reaches tick ``end`` (a multiple of 2^max_level)."""
+        end = int(end)
         if end % (1 << self.max_level):
             raise ValueError("t_end must be a multiple of dt_max (a synchronisation time)")
         # one eager step sizes every workspace before a graph is captured

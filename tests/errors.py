@@ -33,3 +33,27 @@ def all_errs(acc, jerk, pot, ref):
     return dict(acc=vec_err(acc, ref["acc"], ref["abs_acc"]),
                 jerk=vec_err(jerk, ref["jerk"], ref["abs_jerk"]),
                 pot=vec_err(pot, ref["pot"], ref["abs_pot"]))
+
+
+# The parity gates.  FP64: per particle |da_i| <= rel |a_i| + cond A_i (A_i
+# from the extended-precision oracle) and normwise <= 1e-12.  Mixed: RMS of
+# the per-particle relative errors.
+def check_fp64(res, ref, normwise=1e-12, rel=1e-12, cond=64 * 2.0 ** -53):
+    for name, got in zip(("acc", "jerk", "pot"), res):
+        r = ref[name]
+        a = ref["abs_" + name]
+        d = np.asarray(got) - r
+        dn = np.linalg.norm(d, axis=1) if d.ndim == 2 else np.abs(d)
+        rn = np.linalg.norm(r, axis=1) if r.ndim == 2 else np.abs(r)
+        bound = rel * rn + cond * a
+        worst = int(np.argmax(dn - bound))
+        assert np.all(dn <= bound), (name, worst, dn[worst], bound[worst])
+        assert np.linalg.norm(d) <= normwise * np.linalg.norm(r), name
+
+
+def check_mixed(res, ref, acc_rms=1e-6, jerk_rms=1e-5, pot_rms=1e-6):
+    e = all_errs(*res, ref)
+    assert e["acc"]["rms"] <= acc_rms, e
+    assert e["jerk"]["rms"] <= jerk_rms, e
+    assert e["pot"]["rms"] <= pot_rms, e
+    return e

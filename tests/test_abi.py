@@ -22,7 +22,8 @@ def test_header_declares_the_entry_points():
     names = declared_functions()
     for need in ("nbody_forces", "hermite_predict", "hermite_correct", "nb_create", "nb_destroy",
                  "nbody_forces_batch", "nb_block_step", "nb_schedule", "nb_energy", "hermite_startup",
-                 "nbody_forces_devcount", "nb_time_forces", "nb_tune_add"):
+                 "nbody_forces_devcount", "nb_time_forces", "nb_tune_add", "nbody_forces_ij", "nb_kick",
+                 "nb_kick_drift"):
         assert need in names
 
 

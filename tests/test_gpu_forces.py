@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import synth
-from errors import all_errs
+from errors import all_errs, check_fp64, check_mixed
 
 pytestmark = pytest.mark.gpu
 
@@ -49,27 +49,6 @@ def run_gpu(ctx, prec, p, eps2, active, launch=None):
     torch.cuda.synchronize()
     ctx.set_launch(0)
     return acc.cpu().numpy(), jerk.cpu().numpy(), pot.cpu().numpy()
-
-
-def check_fp64(res, ref, normwise=1e-12, rel=1e-12, cond=64 * EPS64):
-    for name, got in zip(("acc", "jerk", "pot"), res):
-        r = ref[name]
-        a = ref["abs_" + name]
-        d = np.asarray(got) - r
-        dn = np.linalg.norm(d, axis=1) if d.ndim == 2 else np.abs(d)
-        rn = np.linalg.norm(r, axis=1) if r.ndim == 2 else np.abs(r)
-        bound = rel * rn + cond * a
-        worst = int(np.argmax(dn - bound))
-        assert np.all(dn <= bound), (name, worst, dn[worst], bound[worst])
-        assert np.linalg.norm(d) <= normwise * np.linalg.norm(r), name
-
-
-def check_mixed(res, ref, acc_rms=1e-6, jerk_rms=1e-5, pot_rms=1e-6):
-    e = all_errs(*res, ref)
-    assert e["acc"]["rms"] <= acc_rms, e
-    assert e["jerk"]["rms"] <= jerk_rms, e
-    assert e["pot"]["rms"] <= pot_rms, e
-    return e
 
 
 def _case(n, seed):
