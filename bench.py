@@ -46,7 +46,7 @@ def parse():
                                                         "merger", "bridge"],
                     help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     return ap.parse_args()
 
 
