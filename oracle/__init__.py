@@ -8,7 +8,10 @@ generators, which hold none of the method's arithmetic).
 Contents
   forces_f64 / forces_ld   plain O(N^2) sums (C, ``forces.c``)
   pair_potential_energy    W as a sum over pairs i<j (C)
+  snap_ld                  acceleration, jerk, snap and potential (C, ``snap.c``)
   hermite                  4th-order Hermite block-step integrator (numpy)
+  hermite6                 6th-order Hermite block-step integrator (numpy)
+  bridge                   kick-drift-kick split of two subsystems (numpy)
 """
 import ctypes
 import os
@@ -96,3 +99,48 @@ def pair_potential_energy(pos, mass, eps2):
     pos = np.ascontiguousarray(pos, dtype=np.float64)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
     return float(_lib().oracle_pair_potential_energy(_d(pos), _d(mass), mass.shape[0], float(eps2)))
+
+
+_SNAP = None
+
+
+def _snap_lib():
+    global _SNAP
+    if _SNAP is None:
+        # NB_ORACLE_SNAP_LIB lets the mutation tests load a deliberately broken build
+        path = os.environ.get("NB_ORACLE_SNAP_LIB") or os.path.join(_HERE, "liboracle_snap.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        lib.oracle_snap_ld.restype = ctypes.c_int64
+        lib.oracle_snap_ld.argtypes = [dp, dp, dp, dp, ctypes.c_int64, ip, ctypes.c_int64, ctypes.c_double,
+                                       dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int]
+        _SNAP = lib
+    return _SNAP
+
+
+def snap_ld(pos, vel, acc_j, mass, eps2, active=None, nthreads=0):
+    """Acceleration, jerk, snap and potential in extended precision, each
+    particle moving with its own acceleration ``acc_j`` [N,3] at the instant.
+
+    Returns a dict with acc, jerk, snap, pot, the magnitude sums abs_acc,
+    abs_jerk, abs_snap, abs_pot and the count of skipped coincident pairs."""
+    pos, vel, mass, active = _prep(pos, vel, mass, active)
+    acc_j = np.ascontiguousarray(acc_j, dtype=np.float64)
+    if acc_j.shape != pos.shape:
+        raise ValueError("acc_j must be (N,3)")
+    na = active.shape[0]
+    out = {k: np.zeros((na, 3)) for k in ("acc", "jerk", "snap")}
+    out["pot"] = np.zeros(na)
+    ab = {k: np.zeros(na) for k in ("abs_acc", "abs_jerk", "abs_snap", "abs_pot")}
+    sk = _snap_lib().oracle_snap_ld(_d(pos), _d(vel), _d(acc_j), _d(mass), mass.shape[0],
+                                    active.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), na, float(eps2),
+                                    _d(out["acc"]), _d(out["jerk"]), _d(out["snap"]), _d(out["pot"]),
+                                    _d(ab["abs_acc"]), _d(ab["abs_jerk"]), _d(ab["abs_snap"]), _d(ab["abs_pot"]),
+                                    int(nthreads))
+    out.update(ab)
+    out["skipped"] = int(sk)
+    return out

@@ -199,3 +199,99 @@ def test_bridge_pins_catch_mutant(monkeypatch, name, attr, fn):
             caught = True
             break
     assert caught, f"mutant {name!r} survived every bridge pin"
+
+
+# Snap mutants: planted in a copy of oracle/snap.c, run against its pins.
+SNAP_SRC = os.path.join(ROOT, "oracle", "snap.c")
+SNAP_MUTANTS = [
+    ("snap u-term factor 6 -> 3", r"6\.0L \* ru \* u\[c\]", "3.0L * ru * u[c]"),
+    ("snap last-term factor 15 -> 5", r"15\.0L \* ru \* ru", "5.0L * ru * ru"),
+    ("snap r.w term dropped", r"\(uu \+ rw\)", "(uu)"),
+    ("snap relative acceleration sign", r"\(long double\)accj\[3 \* j \+ c\] - \(long double\)accj\[3 \* i \+ c\]",
+     "(long double)accj[3 * i + c] - (long double)accj[3 * j + c]"),
+    ("snap power s^-5/2 -> s^-3/2 in the r-term", r"\(uu \+ rw\) \* r\[c\] / s52", "(uu + rw) * r[c] / s32"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,pat,rep", SNAP_MUTANTS, ids=[m[0] for m in SNAP_MUTANTS])
+def test_snap_pins_catch_mutant(tmp_path, name, pat, rep):
+    src = open(SNAP_SRC).read()
+    mut, n = re.subn(pat, rep, src)
+    assert n > 0, f"mutation {name!r} did not apply"
+    c = tmp_path / "snap_mut.c"
+    c.write_text(mut)
+    so = tmp_path / "liboracle_snap_mut.so"
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off", str(c), "-o", str(so),
+                    "-lm"], check=True)
+    env = dict(os.environ, NB_ORACLE_SNAP_LIB=str(so), PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_hermite6.py")],
+                       env=env, capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode == 1, f"mutant {name!r} survived:\n{r.stdout[-2000:]}"
+
+
+# 6th-order Hermite mutants: patch one function of oracle.hermite6.
+def _hermite6_pins():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_oracle_hermite6 as T
+    return [T.test_interpolation_recovers_a_quintic, T.test_corrector_exact_for_quintic_acceleration,
+            T.test_predictor_exact_for_constant_crackle, T.test_step_criterion_hand_values,
+            T.test_kepler_sixth_order_convergence, T.test_block_step_invariants_and_energy]
+
+
+def _m6_predict(x, v, a, j, s, c, d):
+    d = np.asarray(d, dtype=np.float64)
+    d = d[:, None] if d.ndim == 1 else d
+    return (x + v * d + a * d ** 2 / 2 + j * d ** 3 / 6 + s * d ** 4 / 24 + c * d ** 5 / 24,   # crackle /24
+            v + a * d + j * d ** 2 / 2 + s * d ** 3 / 6 + c * d ** 4 / 24,
+            a + j * d + s * d ** 2 / 2 + c * d ** 3 / 6)
+
+
+def _m6_interpolate(a0, j0, s0, a1, j1, s1, dt):
+    from oracle import hermite6 as H6
+    return H6.__dict__["_orig_interpolate"](a0, s0, j0, a1, j1, s1, dt)       # j0/s0 swapped
+
+
+def _m6_correct(x0, v0, a0, j0, s0, c0, p0, q0, dt):
+    dt = np.asarray(dt, dtype=np.float64)
+    dt = dt[:, None] if dt.ndim == 1 else dt
+    v1 = v0 + a0 * dt + j0 * dt ** 2 / 2 + s0 * dt ** 3 / 6 + c0 * dt ** 4 / 24 + p0 * dt ** 5 / 120
+    x1 = x0 + v0 * dt + a0 * dt ** 2 / 2 + j0 * dt ** 3 / 6 + s0 * dt ** 4 / 24 + c0 * dt ** 5 / 120 \
+        + p0 * dt ** 6 / 720                                                   # q0 terms dropped
+    return x1, v1, c0 + p0 * dt + q0 * dt ** 2 / 2, p0 + q0 * dt
+
+
+def _m6_new_dt(a1, j1, s1, c1, p1, q, eta, dt_max):
+    n = lambda u: np.sqrt((u * u).sum(-1))
+    num = np.sqrt(n(a1) * n(s1)) + n(j1)
+    den = np.sqrt(n(c1) * n(q)) + n(p1)
+    return np.where(den > 0, eta * np.sqrt(num / np.where(den > 0, den, 1)), dt_max)   # exponent 1/2
+
+
+def _m6_startup(a, j, s, eta_s, dt_max, max_level):
+    from oracle import hermite as H
+    return H.startup_level(a, j, eta_s, dt_max, max_level)                     # snap term ignored
+
+
+HERMITE6_MUTANTS = [("predictor crackle coefficient", "predict", _m6_predict),
+                    ("interpolation j0/s0 swapped", "interpolate", _m6_interpolate),
+                    ("corrector drops the fifth derivative", "correct", _m6_correct),
+                    ("step criterion exponent 1/2", "new_dt", _m6_new_dt),
+                    ("start-up ignores the snap", "startup_level", _m6_startup)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,attr,fn", HERMITE6_MUTANTS, ids=[m[0] for m in HERMITE6_MUTANTS])
+def test_hermite6_pins_catch_mutant(monkeypatch, name, attr, fn):
+    from oracle import hermite6 as H6
+    monkeypatch.setitem(H6.__dict__, "_orig_interpolate", H6.interpolate)
+    monkeypatch.setattr(H6, attr, fn)
+    caught = False
+    for pin in _hermite6_pins():
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived every 6th-order pin"
