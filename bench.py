@@ -43,7 +43,7 @@ def parse():
                     help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="", choices=["", "plummer1k", "hermite65k", "hermite262k", "batch128",
-                                                        "merger", "bridge"],
+                                                        "merger", "bridge", "hermite6"],
                     help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -82,6 +82,11 @@ def workloads(args):
     merger      11 Hernquist galaxies (2^17 stars + a point mass each): the
                 i-set near the point masses against all 1,441,803 bodies,
                 FP64 and mixed
+    hermite6    sixth-order Hermite: the snap kernel on Plummer N=262144 all
+                active (FP64), and block steps of Plummer N=65536, eps=1/256,
+                to t=1/8 (eta=0.4, eta_s=0.02, graph-replayed) beside the
+                fourth-order run of the same model (eta=0.01): steps, time
+                and energy drift of each
     bridge      the same bodies under the kick-drift-kick split: c = the
                 point masses and the stars near them (FP64 Hermite block
                 steps, eta=0.01), g = every other star (mixed-precision
@@ -182,6 +187,43 @@ def workloads(args):
             out[prec] = dict(n_i=na, n_j=nj, ms=round(ms, 4), gint=round(na * nj / ms / 1e6, 2),
                              launch=ctx.get_launch(nj, na))
             ctx.close()
+    elif args.workload == "hermite6":
+        from paper_1409_5474_amd.integrator import BlockIntegrator6
+        ctx = nb.Context(0, "fp64")
+        n = 262144
+        p = synth.plummer(n, 3)
+        P, V, M = t(p.pos), t(p.vel), t(p.mass)
+        act = torch.arange(n, dtype=torch.int32, device=dev)
+        A, J, _ = ctx.forces(P, V, M, act, 2.0 ** -16)
+        outs = [torch.empty((n, 3), dtype=torch.float64, device=dev) for _ in range(3)]
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        ctx.forces6(P, V, A, M, act, 2.0 ** -16, *outs, pot)
+        e0, e1 = ev(), ev()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.forces6(P, V, A, M, act, 2.0 ** -16, *outs, pot)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        out["snap_kernel"] = dict(n=n, prec="fp64", ms=round(ms, 3), gint=round(float(n) * n / ms / 1e6, 1))
+        n2 = 65536
+        p2 = synth.plummer(n2, 2)
+        runs = {}
+        for order in (4, 6):
+            if order == 4:
+                bi = BlockIntegrator(ctx, t(p2.pos), t(p2.vel), t(p2.mass), 2.0 ** -16, 0.01, 1.0 / 16, 30)
+            else:
+                bi = BlockIntegrator6(ctx, t(p2.pos), t(p2.vel), t(p2.mass), 2.0 ** -16, 0.4, 1.0 / 16, 30, 0.02)
+            E0 = bi.energy()["E"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bi.run_until(0.125, graph_steps=32)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            E1 = bi.energy()["E"]
+            runs[f"order{order}"] = dict(steps=bi.steps, wall_s=round(wall, 3), drift=abs(E1 - E0) / abs(E0))
+        out["plummer65k_to_t_1_8"] = runs
+        ctx.close()
     elif args.workload == "bridge":
         from paper_1409_5474_amd.bridge import Bridge
         m = synth.hernquist_merger()

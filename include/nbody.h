@@ -182,6 +182,66 @@ int nbody_forces_batch(nb_ctx *ctx, const int64_t *offsets, int64_t C, const dou
                        const int32_t *active_idx, const int64_t *act_offsets,
                        double *acc, double *jerk, double *pot);
 
+/* ---- sixth-order Hermite ------------------------------------------------
+ * A higher-order Hermite scheme (the paper cites Hermite integrators of order
+ * above four for its direct method, section "Simulating Collisional systems
+ * with direct force evaluation methods", and writes none down).  Every
+ * particle carries x, v, a, jdot, snap s and crackle c; time and levels are
+ * kept as for the fourth-order calls above.
+ *
+ * nbody_forces6: acceleration, jerk, snap and potential of the i-set
+ * active_idx[0..n_active), every particle moving with its own pos, vel and
+ * acceleration acc_j ([N][3], e.g. the predicted ones).  For r = x_j - x_i,
+ * u = v_j - v_i, w = a_j - a_i, s = |r|^2 + eps2:
+ *   snap_i = sum_{j != i} m_j [w s^-3/2 - 6 (r.u) u s^-5/2 - 3 (u.u + r.w) r s^-5/2
+ *                              + 15 (r.u)^2 r s^-7/2]
+ * and acc, jerk, pot as nbody_forces.  Double precision throughout (the
+ * context's precision does not apply).  Outputs [n_active][3] (pot
+ * [n_active]); errors as nbody_forces. */
+int nbody_forces6(nb_ctx *ctx, const double *pos, const double *vel, const double *acc_j, const double *mass,
+                  int64_t N, const int32_t *active_idx, int64_t n_active, double eps2,
+                  double *acc, double *jerk, double *snap, double *pot);
+
+/* Predict every particle to t_next (d = (t_next_tick - t_tick[i]) dt_min):
+ *   pos_p = x + v d + a d^2/2 + j d^3/6 + s d^4/24 + c d^5/120
+ *   vel_p = v + a d + j d^2/2 + s d^3/6 + c d^4/24
+ *   acc_p = a + j d + s d^2/2 + c d^3/6 */
+int hermite6_predict(nb_ctx *ctx, const double *pos, const double *vel, const double *acc, const double *jerk,
+                     const double *snap, const double *crackle, const int64_t *t_tick, int64_t t_next_tick,
+                     double dt_min, int64_t N, double *pos_p, double *vel_p, double *acc_p);
+
+/* Correct the active particles after their new acc1/jerk1/snap1 (compact
+ * [n_active][3]).  With h = the particle's step, the quintic a(t) through
+ * (a, jdot, snap) at both ends gives crackle c0, pop p0 and the fifth
+ * derivative q0 at the start; x and v become the exact integrals of that
+ * quintic; a, jdot, snap take the new values, crackle the end-of-step
+ * c1 = c0 + p0 h + q0 h^2/2; t_tick advances by the step; the new level
+ * comes from dt* = eta ((sqrt(|a1||s1|) + |j1|)/(sqrt(|c1||q0|) + |p1|))^(1/3),
+ * p1 = p0 + q0 h (dt_max when the denominator is 0), with the level rules of
+ * hermite_correct (clamps counted in *clamp_count_dev, may be NULL).
+ * active_idx must not repeat an index. */
+int hermite6_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active, const double *acc1,
+                     const double *jerk1, const double *snap1, double *pos, double *vel, double *acc, double *jerk,
+                     double *snap, double *crackle, int64_t *t_tick, int32_t *dt_level, double eta, double dt_max,
+                     int32_t max_level, int64_t *clamp_count_dev);
+
+/* Start-up levels: dt* = eta_s min(|a|/|j|, sqrt(|a|/|s|)) over the terms
+ * with a non-zero denominator (dt_max if none); level = smallest k >= 0 with
+ * dt_max 2^-k <= dt*. */
+int hermite6_startup(nb_ctx *ctx, const double *acc, const double *jerk, const double *snap, int64_t N,
+                     double eta_s, double dt_max, int32_t max_level, int32_t *dt_level);
+
+/* One sixth-order block step with no host synchronisation: schedule (as
+ * nb_block_step), predict all particles, forces6 on the scheduled active
+ * set (count read on the device), correct.  Scratch arrays pos_p, vel_p,
+ * acc_p [N][3], active [N], acc1, jerk1, snap1 [N][3], pot1 [N]; sched[4]
+ * as nb_block_step. */
+int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
+                   const double *mass, double *pos, double *vel, double *acc, double *jerk, double *snap,
+                   double *crackle, int64_t *t_tick, int32_t *dt_level, double *pos_p, double *vel_p,
+                   double *acc_p, int32_t *active, double *acc1, double *jerk1, double *snap1, double *pot1,
+                   int64_t *sched, int64_t t_stop_tick);
+
 /* ---- Hamiltonian split (bridge) ------------------------------------------
  * Section "The multi-scale approach" evolves a collisional subsystem c and a
  * field subsystem g together by splitting H = H_A + H_B with H_A = W_gc (the

@@ -17,7 +17,8 @@ import torch
 __all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", "lib_path", "library",
            "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
            "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy",
-           "nbody_forces_ij", "nb_kick", "nb_kick_drift"]
+           "nbody_forces_ij", "nb_kick", "nb_kick_drift", "nbody_forces6", "hermite6_predict",
+           "hermite6_correct", "hermite6_startup", "nb_block_step6"]
 
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -64,6 +65,13 @@ _sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _d
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_devcount", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_ij", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("nbody_forces6", _vp, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _vp)
+_sig("hermite6_predict", _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp, _vp)
+_sig("hermite6_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32,
+     _vp)
+_sig("hermite6_startup", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
+_sig("nb_block_step6", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+     _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64)
 _sig("nb_kick", _vp, _vp, _vp, _i64, _dbl)
 _sig("nb_kick_drift", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl)
 _sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
@@ -218,6 +226,49 @@ class Context:
                                        _p(active), na, float(eps2), _p(acc), _p(jerk), _p(pot)))
         return acc, jerk, pot
 
+    # ---- sixth-order Hermite -------------------------------------------------
+    def forces6(self, pos, vel, acc_j, mass, active, eps2, acc=None, jerk=None, snap=None, pot=None):
+        """Acceleration, jerk, snap, potential of ``active`` (``nbody_forces6``)."""
+        n, na = mass.shape[0], active.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        _check_vec(vel, n, "vel", self.device)
+        _check_vec(acc_j, n, "acc_j", self.device)
+        _check_1d(mass, n, "mass", torch.float64, self.device)
+        _check_1d(active, na, "active_idx", torch.int32, self.device)
+        new = lambda: torch.empty((na, 3), dtype=torch.float64, device=self.device)
+        acc = new() if acc is None else acc
+        jerk = new() if jerk is None else jerk
+        snap = new() if snap is None else snap
+        pot = torch.empty((na,), dtype=torch.float64, device=self.device) if pot is None else pot
+        for t, nm in ((acc, "acc"), (jerk, "jerk"), (snap, "snap")):
+            _check_vec(t, na, nm, self.device)
+        _check_1d(pot, na, "pot", torch.float64, self.device)
+        self._chk(_lib.nbody_forces6(self._h, _p(pos), _p(vel), _p(acc_j), _p(mass), n, _p(active), na,
+                                     float(eps2), _p(acc), _p(jerk), _p(snap), _p(pot)))
+        return acc, jerk, snap, pot
+
+    def predict6(self, pos, vel, acc, jerk, snap, crackle, t_tick, t_next_tick, dt_min, pos_p, vel_p, acc_p):
+        self._chk(_lib.hermite6_predict(self._h, _p(pos), _p(vel), _p(acc), _p(jerk), _p(snap), _p(crackle),
+                                        _p(t_tick), int(t_next_tick), float(dt_min), pos.shape[0], _p(pos_p),
+                                        _p(vel_p), _p(acc_p)))
+
+    def correct6(self, active, acc1, jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick, dt_level, eta, dt_max,
+                 max_level, clamp_count=None):
+        self._chk(_lib.hermite6_correct(self._h, _p(active), active.shape[0], _p(acc1), _p(jerk1), _p(snap1),
+                                        _p(pos), _p(vel), _p(acc), _p(jerk), _p(snap), _p(crackle), _p(t_tick),
+                                        _p(dt_level), float(eta), float(dt_max), int(max_level), _p(clamp_count)))
+
+    def startup6(self, acc, jerk, snap, eta_s, dt_max, max_level, dt_level):
+        self._chk(_lib.hermite6_startup(self._h, _p(acc), _p(jerk), _p(snap), acc.shape[0], float(eta_s),
+                                        float(dt_max), int(max_level), _p(dt_level)))
+
+    def block_step6(self, N, eps2, eta, dt_max, max_level, mass, pos, vel, acc, jerk, snap, crackle, t_tick,
+                    dt_level, pos_p, vel_p, acc_p, active, acc1, jerk1, snap1, pot1, sched, t_stop_tick=2 ** 63 - 1):
+        self._chk(_lib.nb_block_step6(self._h, int(N), float(eps2), float(eta), float(dt_max), int(max_level),
+                                      _p(mass), _p(pos), _p(vel), _p(acc), _p(jerk), _p(snap), _p(crackle),
+                                      _p(t_tick), _p(dt_level), _p(pos_p), _p(vel_p), _p(acc_p), _p(active),
+                                      _p(acc1), _p(jerk1), _p(snap1), _p(pot1), _p(sched), int(t_stop_tick)))
+
     def kick(self, vel, acc, h):
         """vel += h acc (``nb_kick``)."""
         n = vel.shape[0]
@@ -354,3 +405,23 @@ def nb_kick(ctx, *a, **k):
 
 def nb_kick_drift(ctx, *a, **k):
     return ctx.kick_drift(*a, **k)
+
+
+def nbody_forces6(ctx, *a, **k):
+    return ctx.forces6(*a, **k)
+
+
+def hermite6_predict(ctx, *a, **k):
+    return ctx.predict6(*a, **k)
+
+
+def hermite6_correct(ctx, *a, **k):
+    return ctx.correct6(*a, **k)
+
+
+def hermite6_startup(ctx, *a, **k):
+    return ctx.startup6(*a, **k)
+
+
+def nb_block_step6(ctx, *a, **k):
+    return ctx.block_step6(*a, **k)

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.environ.get("NB_LIB_OUT") or os.path.join(HERE, "libnbody.so")
 OBJ = os.path.join(os.path.dirname(OUT), "_build")
-SOURCES = ["forces.hip", "hermite.hip", "bridge.hip", "api.hip"]
+SOURCES = ["forces.hip", "forces6.hip", "hermite.hip", "hermite6.hip", "bridge.hip", "api.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -34,7 +34,7 @@ def _compile(src):
     return obj, noise
 
 
-def build(verbose: bool = False, jobs: int = 3) -> str:
+def build(verbose: bool = False, jobs: int = 6) -> str:
     os.makedirs(OBJ, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         results = list(ex.map(_compile, SOURCES))

@@ -478,6 +478,112 @@ int hermite_predict(nb_ctx* c, const double* pos, const double* vel, const doubl
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "predict launch");
 }
 
+// ---- sixth-order Hermite ---------------------------------------------------
+static int run_forces6(nb_ctx* c, const double* pos, const double* vel, const double* accj, const double* mass,
+                       int64_t N, const int32_t* active, int64_t n_max, const int32_t* n_active_dev, double eps2,
+                       double* acc, double* jerk, double* snap, double* pot) {
+  const bool mask = eps2 == 0.0;
+  const int grid = c->num_cus * nb::forces6_resident_wgs(mask);
+  const int target = 4 * grid;
+  nb::Force6Args a{};
+  a.pos = pos; a.vel = vel; a.accj = accj; a.mass = mass; a.n = N;
+  a.active = active; a.n_active = n_max; a.n_active_dev = n_active_dev; a.eps2 = eps2;
+  a.target_items = target;
+  a.S = nb::forces6_split(n_max, target, N);
+  a.acc = acc; a.jerk = jerk; a.snap = snap; a.pot = pot;
+  const int64_t rows = n_active_dev ? nb::forces6_workspace_rows(n_max, target, N) : (int64_t)a.S * n_max;
+  if (n_active_dev || a.S > 1) {
+    int rc = ensure_ws(c, (size_t)rows * 10 * sizeof(double));
+    if (rc) return rc;
+    a.part = static_cast<double*>(c->ws);
+  }
+  hipError_t e = nb::launch_forces6(a, mask, grid, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order force launch");
+}
+
+int nbody_forces6(nb_ctx* c, const double* pos, const double* vel, const double* acc_j, const double* mass, int64_t N,
+                  const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* snap,
+                  double* pot) {
+  int rc = check_forces_args(c, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (n_active > 0 && (!acc_j || !snap)) return fail(c, NB_EINVAL, "null pointer argument%s");
+  if (n_active == 0) return NB_OK;
+  return run_forces6(c, pos, vel, acc_j, mass, N, active, n_active, nullptr, eps2, acc, jerk, snap, pot);
+}
+
+int hermite6_predict(nb_ctx* c, const double* pos, const double* vel, const double* acc, const double* jerk,
+                     const double* snap, const double* crackle, const int64_t* t_tick, int64_t t_next_tick,
+                     double dt_min, int64_t N, double* pos_p, double* vel_p, double* acc_p) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (!pos || !vel || !acc || !jerk || !snap || !crackle || !t_tick || !pos_p || !vel_p || !acc_p)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  if (!(dt_min > 0.0) || !std::isfinite(dt_min)) return fail(c, NB_EINVAL, "dt_min must be finite and > 0%s");
+  hipError_t e = nb::launch_predict6(pos, vel, acc, jerk, snap, crackle, t_tick, t_next_tick, nullptr, dt_min, N,
+                                     pos_p, vel_p, acc_p, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order predict launch");
+}
+
+static int check_levels(nb_ctx* c, double eta, double dt_max, int32_t max_level);
+
+int hermite6_correct(nb_ctx* c, const int32_t* active, int64_t n_active, const double* acc1, const double* jerk1,
+                     const double* snap1, double* pos, double* vel, double* acc, double* jerk, double* snap,
+                     double* crackle, int64_t* t_tick, int32_t* dt_level, double eta, double dt_max,
+                     int32_t max_level, int64_t* clamp_count_dev) {
+  if (!c) return NB_EINVAL;
+  if (n_active < 0 || n_active >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "n_active must be in [0, 2^31)%s");
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (n_active == 0) return NB_OK;
+  if (!active || !acc1 || !jerk1 || !snap1 || !pos || !vel || !acc || !jerk || !snap || !crackle || !t_tick ||
+      !dt_level)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_correct6(active, n_active, nullptr, acc1, jerk1, snap1, pos, vel, acc, jerk, snap,
+                                     crackle, t_tick, dt_level, eta, dt_max, max_level, clamp_count_dev, nullptr,
+                                     c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
+}
+
+int hermite6_startup(nb_ctx* c, const double* acc, const double* jerk, const double* snap, int64_t N, double eta_s,
+                     double dt_max, int32_t max_level, int32_t* dt_level) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  int rc = check_levels(c, eta_s, dt_max, max_level);
+  if (rc) return rc;
+  if (!acc || !jerk || !snap || !dt_level) return fail(c, NB_EINVAL, "null pointer%s");
+  hipError_t e = nb::launch_startup6(acc, jerk, snap, N, eta_s, dt_max, max_level, dt_level, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order startup launch");
+}
+
+int nb_block_step6(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, int32_t max_level,
+                   const double* mass, double* pos, double* vel, double* acc, double* jerk, double* snap,
+                   double* crackle, int64_t* t_tick, int32_t* dt_level, double* pos_p, double* vel_p, double* acc_p,
+                   int32_t* active, double* acc1, double* jerk1, double* snap1, double* pot1, int64_t* sched,
+                   int64_t t_stop_tick) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  int rc = check_levels(c, eta, dt_max, max_level);
+  if (rc) return rc;
+  if (!finite_nonneg(eps2)) return fail(c, NB_EINVAL, "eps2 must be finite and >= 0%s");
+  if (!mass || !pos || !vel || !acc || !jerk || !snap || !crackle || !t_tick || !dt_level || !pos_p || !vel_p ||
+      !acc_p || !active || !acc1 || !jerk1 || !snap1 || !pot1 || !sched)
+    return fail(c, NB_EINVAL, "null pointer%s");
+  rc = ensure_sched(c, N);
+  if (rc) return rc;
+  const double dt_min = std::ldexp(dt_max, -max_level);
+  hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
+                                     c->nact32, t_stop_tick, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
+  e = nb::launch_predict6(pos, vel, acc, jerk, snap, crackle, t_tick, 0, sched, dt_min, N, pos_p, vel_p, acc_p,
+                          c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sixth-order predict launch");
+  rc = run_forces6(c, pos_p, vel_p, acc_p, mass, N, active, N, c->nact32, eps2, acc1, jerk1, snap1, pot1);
+  if (rc) return rc;
+  e = nb::launch_correct6(active, N, sched + 1, acc1, jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick,
+                          dt_level, eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
+}
+
 int nb_kick(nb_ctx* c, double* vel, const double* acc, int64_t N, double h) {
   if (!c) return NB_EINVAL;
   if (N < 0 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [0, 2^31)%s");

@@ -61,6 +61,28 @@ struct ForceArgs {
   int no_self;
 };
 
+// Arguments of the sixth-order force kernel (forces6.hip): acceleration,
+// jerk, snap and potential of the active rows, every particle moving with
+// its own position, velocity and (predicted) acceleration accj.
+struct Force6Args {
+  const double* pos;
+  const double* vel;
+  const double* accj;
+  const double* mass;
+  int64_t n;
+  const int32_t* active;
+  int64_t n_active;             // host count (or the maximum, with n_active_dev)
+  const int32_t* n_active_dev;  // optional device count
+  double eps2;
+  int S;                        // j-chunks (host count only)
+  int target_items;             // device count: chunks chosen for this many items
+  double* acc;
+  double* jerk;
+  double* snap;
+  double* pot;
+  double* part;                 // [S][10][n_active] partial sums when S > 1
+};
+
 // Batched work list item: one (system, i-block, j-chunk) triple.
 struct BatchItem {
   int32_t sys;      // system index
@@ -121,6 +143,24 @@ int schedule_blocks(int64_t n);
 hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
                          int64_t n, double* part, double* out, hipStream_t st);
 int energy_blocks(int64_t n);
+
+// Sixth-order force kernel (forces6.hip).
+int forces6_resident_wgs(bool mask);
+int forces6_split(int64_t n_act, int target_items, int64_t n);
+int64_t forces6_workspace_rows(int64_t n_max, int target_items, int64_t n);
+hipError_t launch_forces6(const Force6Args& a, bool mask, int grid, hipStream_t st);
+
+// Sixth-order Hermite passes (hermite6.hip).
+hipError_t launch_predict6(const double* pos, const double* vel, const double* acc, const double* jerk,
+                           const double* snap, const double* crackle, const int64_t* t_tick, int64_t t_next,
+                           const int64_t* t_next_dev, double dt_min, int64_t n, double* pos_p, double* vel_p,
+                           double* acc_p, hipStream_t st);
+hipError_t launch_correct6(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, const double* acc1,
+                           const double* jerk1, const double* snap1, double* pos, double* vel, double* acc,
+                           double* jerk, double* snap, double* crackle, int64_t* t_tick, int32_t* level, double eta,
+                           double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev, hipStream_t st);
+hipError_t launch_startup6(const double* acc, const double* jerk, const double* snap, int64_t n, double eta_s,
+                           double dt_max, int max_level, int32_t* level, hipStream_t st);
 
 // Kick / kick-drift passes of the Hamiltonian split (bridge.hip).
 hipError_t launch_kick(double* vel, const double* acc, double h, int64_t n, hipStream_t st);

@@ -44,20 +44,24 @@ class BlockIntegrator:
         self.vel = vel.to(**f64).contiguous().clone()
         self.acc = torch.empty((n, 3), **f64)
         self.jerk = torch.empty((n, 3), **f64)
+        self.t_tick = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.level = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.sched = torch.zeros(4, dtype=torch.int64, device=dev)   # t_next, n_active, steps, clamps
+        self._alloc_scratch()
+        # start-up: forces on every particle at t = 0 and the first levels
+        self.restart()
+
+    def _alloc_scratch(self):
+        n, dev = self.n, self.dev
+        f64 = dict(dtype=torch.float64, device=dev)
         self.pos_p = torch.empty((n, 3), **f64)
         self.vel_p = torch.empty((n, 3), **f64)
         self.acc1 = torch.empty((n, 3), **f64)
         self.jerk1 = torch.empty((n, 3), **f64)
         self.pot1 = torch.empty(n, **f64)
         self.active = torch.empty(n, dtype=torch.int32, device=dev)
-        self.t_tick = torch.zeros(n, dtype=torch.int64, device=dev)
-        self.level = torch.zeros(n, dtype=torch.int32, device=dev)
-        self.sched = torch.zeros(4, dtype=torch.int64, device=dev)   # t_next, n_active, steps, clamps
         self.all_idx = torch.arange(n, dtype=torch.int32, device=dev)
         self._graphs = {}
-        # start-up: forces on every particle at t = 0 and the first levels
-        self._all_forces(self.pos, self.vel, self.acc, self.jerk, self.pot1)
-        ctx.startup(self.acc, self.jerk, self.eta, self.dt_max, self.max_level, self.level)
 
     def _all_forces(self, pos, vel, acc, jerk, pot):
         if self.batch:
@@ -168,17 +172,13 @@ class BlockIntegrator:
         self.mass = t(d["mass"])
         for k in self._STATE:
             setattr(self, k, t(d[k]))
-        n = self.n
-        f64 = dict(dtype=torch.float64, device=dev)
-        self.pos_p = torch.empty((n, 3), **f64)
-        self.vel_p = torch.empty((n, 3), **f64)
-        self.acc1 = torch.empty((n, 3), **f64)
-        self.jerk1 = torch.empty((n, 3), **f64)
-        self.pot1 = torch.empty(n, **f64)
-        self.active = torch.empty(n, dtype=torch.int32, device=dev)
-        self.all_idx = torch.arange(n, dtype=torch.int32, device=dev)
-        self._graphs = {}
+        for k, v in self._restore_extra(d).items():
+            setattr(self, k, v)
+        self._alloc_scratch()
         return self
+
+    def _restore_extra(self, d):
+        return {}
 
     # ---- diagnostics ------------------------------------------------------
     @property
@@ -203,3 +203,57 @@ class BlockIntegrator:
         self.ctx.energy(self.pos, self.vel, self.mass, pot, out)
         o = out.cpu().tolist()
         return dict(K=o[0], W=o[1], E=o[0] + o[1], P=o[2:5], L=o[5:8])
+
+
+class BlockIntegrator6(BlockIntegrator):
+    """Sixth-order Hermite block steps (``nb_block_step6``) of one system.
+
+    Every particle carries a, jdot, snap and crackle; start-up evaluates a and
+    jdot, then the snap with those accelerations, sets the crackle to zero and
+    takes its levels from dt* = eta_s min(|a|/|j|, sqrt(|a|/|s|)).  ``eta``
+    scales the order-six step criterion (typical values 0.1-0.3).  Time,
+    levels, graphs, energy and checkpoints work as in ``BlockIntegrator``."""
+
+    _STATE = BlockIntegrator._STATE + ("snap", "crackle")
+
+    def __init__(self, ctx: Context, pos, vel, mass, eps2, eta=0.15, dt_max=1.0 / 16, max_level=30, eta_s=0.01):
+        self.eta_s = float(eta_s)
+        dev = ctx.device
+        n = mass.shape[0]
+        self.snap = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        self.crackle = torch.zeros((n, 3), dtype=torch.float64, device=dev)
+        super().__init__(ctx, pos, vel, mass, eps2, eta, dt_max, max_level)
+
+    def _alloc_scratch(self):
+        super()._alloc_scratch()
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        self.acc_p = torch.empty((self.n, 3), **f64)
+        self.snap1 = torch.empty((self.n, 3), **f64)
+
+    def restart(self):
+        """Forces and start-up levels from the current (synchronised) state; crackle = 0."""
+        zero = torch.zeros_like(self.acc)
+        self.ctx.forces6(self.pos, self.vel, zero, self.mass, self.all_idx, self.eps2, self.acc, self.jerk,
+                         self.snap1, self.pot1)
+        self.ctx.forces6(self.pos, self.vel, self.acc, self.mass, self.all_idx, self.eps2, self.acc1, self.jerk,
+                         self.snap, self.pot1)
+        self.acc.copy_(self.acc1)
+        self.crackle.zero_()
+        self.ctx.startup6(self.acc, self.jerk, self.snap, self.eta_s, self.dt_max, self.max_level, self.level)
+
+    def step(self, t_stop_tick=INT64_MAX):
+        self.ctx.block_step6(self.n, self.eps2, self.eta, self.dt_max, self.max_level, self.mass, self.pos, self.vel,
+                             self.acc, self.jerk, self.snap, self.crackle, self.t_tick, self.level, self.pos_p,
+                             self.vel_p, self.acc_p, self.active, self.acc1, self.jerk1, self.snap1, self.pot1,
+                             self.sched, t_stop_tick)
+
+    def checkpoint(self, path):
+        import numpy as np
+        super().checkpoint(path)
+        d = dict(np.load(path, allow_pickle=False))
+        d["eta_s"] = np.array([self.eta_s])
+        np.savez(path, **d)
+
+    def _restore_extra(self, d):
+        self.eta_s = float(d["eta_s"][0])
+        return {}

@@ -38,8 +38,8 @@ def all_errs(acc, jerk, pot, ref):
 # The parity gates.  FP64: per particle |da_i| <= rel |a_i| + cond A_i (A_i
 # from the extended-precision oracle) and normwise <= 1e-12.  Mixed: RMS of
 # the per-particle relative errors.
-def check_fp64(res, ref, normwise=1e-12, rel=1e-12, cond=64 * 2.0 ** -53):
-    for name, got in zip(("acc", "jerk", "pot"), res):
+def check_fp64(res, ref, normwise=1e-12, rel=1e-12, cond=64 * 2.0 ** -53, names=("acc", "jerk", "pot")):
+    for name, got in zip(names, res):
         r = ref[name]
         a = ref["abs_" + name]
         d = np.asarray(got) - r
