@@ -295,3 +295,74 @@ def test_hermite6_pins_catch_mutant(monkeypatch, name, attr, fn):
             caught = True
             break
     assert caught, f"mutant {name!r} survived every 6th-order pin"
+
+
+# Tree-code mutants: patch one function of oracle.tree and run its pins.
+def _tree_pins():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_oracle_tree as T
+    return [lambda: T.test_hilbert_keys_are_a_bijection_along_unit_steps(3), T.test_hilbert_prefixes_are_aligned_cubes,
+            T.test_tree_leaves_partition_and_cubes_contain, T.test_moments_definitions_and_parallel_axis,
+            T.test_multipole_far_field_error_falls_as_the_fifth_power,
+            T.test_opening_criterion_never_accepts_a_cell_touching_its_group, T.test_groups_are_contiguous_and_small,
+            T.test_theta_zero_is_the_direct_sum]
+
+
+def _mt_keys_no_gray(ijk, bits=21):
+    from oracle import tree as TR
+    # the keys of the axes themselves (a Morton order): loses the unit steps
+    key = np.zeros(ijk.shape[0], dtype=np.int64)
+    for b in range(bits - 1, -1, -1):
+        for k in range(3):
+            key = (key << 1) | ((ijk[:, k].astype(np.int64) >> b) & 1)
+    return key
+
+
+def _mt_accept(cell, glo, ghi, theta):
+    gap = np.maximum(np.maximum(cell.corner - ghi, glo - (cell.corner + cell.side)), 0.0)
+    return theta * float(gap @ gap) > cell.side * cell.side                # theta not squared
+
+
+def _mt_field(M, X, Q, x, eps2):
+    y = x - X
+    s = (y * y).sum(1) + eps2
+    Qy = y @ Q.T
+    yQy = (y * Qy).sum(1)
+    a = -M * y * s[:, None] ** -1.5 - Qy * s[:, None] ** -2.5 + 2.5 * (yQy * s ** -3.5)[:, None] * y   # sign
+    return a, -M * s ** -0.5 - 0.5 * yQy * s ** -2.5
+
+
+def _mt_moments(x, m, centre):
+    M = float(m.sum())
+    X = (m[:, None] * x).sum(0) / M if M > 0 else centre
+    d = x - X
+    dd = (d * d).sum(1)
+    Q = (m[:, None, None] * (2.0 * (d[:, :, None] * d[:, None, :]) - dd[:, None, None] * np.eye(3))).sum(0)
+    return M, X, Q                                                          # factor 3 -> 2
+
+
+def _mt_groups(tree, g_max, size=64):
+    n = tree.mass.shape[0]
+    return [(b, min(n, b + size)) for b in range(0, n, size)]            # never split
+
+
+TREE_MUTANTS = [("Morton keys instead of Hilbert", "hilbert_keys", _mt_keys_no_gray),
+                ("opening criterion without theta squared", "_accept", _mt_accept),
+                ("quadrupole force sign", "cell_field", _mt_field),
+                ("quadrupole factor 3 -> 2", "moments", _mt_moments),
+                ("groups never split", "groups", _mt_groups)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,attr,fn", TREE_MUTANTS, ids=[m[0] for m in TREE_MUTANTS])
+def test_tree_pins_catch_mutant(monkeypatch, name, attr, fn):
+    from oracle import tree as TR
+    monkeypatch.setattr(TR, attr, fn)
+    caught = False
+    for pin in _tree_pins():
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived every tree pin"
