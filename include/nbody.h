@@ -242,6 +242,42 @@ int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_ma
                    double *acc_p, int32_t *active, double *acc1, double *jerk1, double *snap1, double *pot1,
                    int64_t *sched, int64_t t_stop_tick);
 
+/* ---- tree code -------------------------------------------------------------
+ * Barnes-Hut forces of every particle (the paper's collisionless method,
+ * section "Simulating collisionless systems with hierarchical
+ * domain-decomposition methods" and its "Implementation"), entirely on the
+ * device:
+ *  - box: lo = per-dimension minimum of pos, side = the power of two 2^e
+ *    >= (1 + 2^-10) x the largest extent (1 if all positions coincide),
+ *    h = side 2^-21, integer coordinates floor((x - lo)/h) clamped to
+ *    [0, 2^21 - 1];
+ *  - particles sorted along the 63-bit Peano-Hilbert curve (Skilling's
+ *    construction), ties by index;
+ *  - cells: the particles sharing a key prefix; a cell holding more than
+ *    n_crit particles is split into its non-empty children (down to prefix
+ *    level 21); each cell's cube, mass, centre of mass X and traceless
+ *    quadrupole Q = sum m (3 d d^T - |d|^2 I), d = x - X;
+ *  - groups: curve-consecutive runs of 64 particles, halved while a group's
+ *    bounding box is wider than g_frac x side in some dimension (g_frac <= 0:
+ *    never);
+ *  - walk: a cell other than the root is accepted for a group when
+ *    theta^2 d^2 > side_cell^2, d the distance between the group's bounding
+ *    box and the cell's cube; other leaves are opened;
+ *  - forces: an accepted cell gives a = -M y s^-3/2 + Q y s^-5/2 -
+ *    (5/2)(y.Qy) y s^-7/2 and phi = -M s^-1/2 - (1/2)(y.Qy) s^-5/2 with
+ *    y = x - X, s = |y|^2 + eps2; an opened leaf's particles j != i the
+ *    softened pair terms (a pair at zero distance with eps2 = 0 is dropped).
+ * theta = 0 opens every leaf: the direct sum.  pos [N][3], mass [N] in,
+ * acc [N][3], pot [N] out, all in the caller's order (device pointers).
+ * stats (host array of 5, may be NULL): cells, groups, accepted (group, cell)
+ * pairs, opened (group, leaf) pairs, depth.  The call synchronises the stream
+ * (the host reads one count per tree level) and cannot be captured in a
+ * graph (NB_ENOTSUP).  Errors: NB_EINVAL for N outside [1, 2^31), negative
+ * or non-finite eps2 or theta, n_crit < 1, non-finite g_frac, null
+ * pointers; NB_ENOMEM when the interaction lists would exceed 2^31 entries. */
+int nb_tree_forces(nb_ctx *ctx, const double *pos, const double *mass, int64_t N, double eps2, double theta,
+                   int32_t n_crit, double g_frac, double *acc, double *pot, int64_t *stats);
+
 /* ---- Hamiltonian split (bridge) ------------------------------------------
  * Section "The multi-scale approach" evolves a collisional subsystem c and a
  * field subsystem g together by splitting H = H_A + H_B with H_A = W_gc (the

@@ -251,7 +251,7 @@ def forces(pos, mass, eps2, theta, n_crit=16, g_max=None, tree=None):
     """Tree acceleration and potential of every particle (original order).
 
     Returns (acc [N,3], pot [N], stats) with stats the per-group counts of
-    accepted cells and directly summed particles."""
+    accepted cells, opened leaves and directly summed particles."""
     pos = np.asarray(pos, dtype=np.float64)
     n = pos.shape[0]
     t = tree if tree is not None else build(pos, mass, n_crit)
@@ -285,7 +285,7 @@ def forces(pos, mass, eps2, theta, n_crit=16, g_max=None, tree=None):
             nd += c.end - c.begin
         acc_s[b:e] = a
         pot_s[b:e] = p
-        stats.append((len(ci), nd))
+        stats.append((len(ci), len(li), nd))
     acc = np.empty_like(acc_s)
     pot = np.empty_like(pot_s)
     acc[t.order] = acc_s

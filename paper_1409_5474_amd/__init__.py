@@ -18,7 +18,7 @@ __all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", 
            "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
            "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy",
            "nbody_forces_ij", "nb_kick", "nb_kick_drift", "nbody_forces6", "hermite6_predict",
-           "hermite6_correct", "hermite6_startup", "nb_block_step6"]
+           "hermite6_correct", "hermite6_startup", "nb_block_step6", "nb_tree_forces"]
 
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -72,6 +72,7 @@ _sig("hermite6_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
 _sig("hermite6_startup", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
 _sig("nb_block_step6", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64)
+_sig("nb_tree_forces", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _dbl, _vp, _vp, _vp)
 _sig("nb_kick", _vp, _vp, _vp, _i64, _dbl)
 _sig("nb_kick_drift", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl)
 _sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
@@ -269,6 +270,25 @@ class Context:
                                       _p(t_tick), _p(dt_level), _p(pos_p), _p(vel_p), _p(acc_p), _p(active),
                                       _p(acc1), _p(jerk1), _p(snap1), _p(pot1), _p(sched), int(t_stop_tick)))
 
+    # ---- tree code --------------------------------------------------------------
+    def tree_forces(self, pos, mass, eps2, theta=0.5, n_crit=16, g_frac=1.0 / 16, acc=None, pot=None):
+        """Barnes-Hut acceleration and potential of every particle (``nb_tree_forces``).
+
+        Returns (acc, pot, stats) with stats the numbers of cells, groups,
+        accepted (group, cell) pairs, opened (group, leaf) pairs and the depth."""
+        n = mass.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        _check_1d(mass, n, "mass", torch.float64, self.device)
+        acc = torch.empty((n, 3), dtype=torch.float64, device=self.device) if acc is None else acc
+        pot = torch.empty((n,), dtype=torch.float64, device=self.device) if pot is None else pot
+        _check_vec(acc, n, "acc", self.device)
+        _check_1d(pot, n, "pot", torch.float64, self.device)
+        st = (ctypes.c_int64 * 5)()
+        self._chk(_lib.nb_tree_forces(self._h, _p(pos), _p(mass), n, float(eps2), float(theta), int(n_crit),
+                                      float(g_frac), _p(acc), _p(pot), st))
+        stats = dict(zip(("cells", "groups", "accepted", "opened_leaves", "depth"), list(st)))
+        return acc, pot, stats
+
     def kick(self, vel, acc, h):
         """vel += h acc (``nb_kick``)."""
         n = vel.shape[0]
@@ -425,3 +445,7 @@ def hermite6_startup(ctx, *a, **k):
 
 def nb_block_step6(ctx, *a, **k):
     return ctx.block_step6(*a, **k)
+
+
+def nb_tree_forces(ctx, *a, **k):
+    return ctx.tree_forces(*a, **k)

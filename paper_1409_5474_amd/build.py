@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.environ.get("NB_LIB_OUT") or os.path.join(HERE, "libnbody.so")
 OBJ = os.path.join(os.path.dirname(OUT), "_build")
-SOURCES = ["forces.hip", "forces6.hip", "hermite.hip", "hermite6.hip", "bridge.hip", "api.hip"]
+SOURCES = ["forces.hip", "forces6.hip", "hermite.hip", "hermite6.hip", "bridge.hip", "tree.hip", "api.hip"]
 ARCH = os.environ.get("NB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

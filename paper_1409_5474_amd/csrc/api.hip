@@ -290,6 +290,7 @@ int nb_destroy(nb_ctx* c) {
   if (c->batch_host) (void)hipHostFree(c->batch_host);
   if (c->batch_ev) (void)hipEventDestroy(c->batch_ev);
   if (c->bp_buf) (void)hipFree(c->bp_buf);
+  nb::tree_scratch_free(c->tree);
   delete c;
   return NB_OK;
 }
@@ -582,6 +583,33 @@ int nb_block_step6(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max,
   e = nb::launch_correct6(active, N, sched + 1, acc1, jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick,
                           dt_level, eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
+}
+
+// ---- tree code -------------------------------------------------------------
+int nb_tree_forces(nb_ctx* c, const double* pos, const double* mass, int64_t N, double eps2, double theta,
+                   int32_t n_crit, double g_frac, double* acc, double* pot, int64_t* stats) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (!finite_nonneg(eps2)) return fail(c, NB_EINVAL, "eps2 must be finite and >= 0%s");
+  if (!finite_nonneg(theta)) return fail(c, NB_EINVAL, "theta must be finite and >= 0%s");
+  if (n_crit < 1) return fail(c, NB_EINVAL, "n_crit must be >= 1%s");
+  if (!std::isfinite(g_frac)) return fail(c, NB_EINVAL, "g_frac must be finite%s");
+  if (!pos || !mass || !acc || !pot) return fail(c, NB_EINVAL, "null pointer%s");
+  if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "the tree code reads counts on the host: no stream capture%s");
+  const char* msg = "";
+  nb::TreeStats st{};
+  hipError_t e = nb::tree_forces_run(c->tree, c->stream, pos, mass, (int32_t)N, eps2, theta, n_crit, g_frac, acc,
+                                     pot, &st, &msg);
+  if (e == hipErrorInvalidValue) return fail(c, NB_ENOMEM, "%s", msg);
+  if (e != hipSuccess) return hip_fail(c, e, msg);
+  if (stats) {
+    stats[0] = st.cells;
+    stats[1] = st.groups;
+    stats[2] = st.accepted;
+    stats[3] = st.opened_leaves;
+    stats[4] = st.depth;
+  }
+  return NB_OK;
 }
 
 int nb_kick(nb_ctx* c, double* vel, const double* acc, int64_t N, double h) {

@@ -144,6 +144,31 @@ hipError_t launch_energy(const double* pos, const double* vel, const double* mas
                          int64_t n, double* part, double* out, hipStream_t st);
 int energy_blocks(int64_t n);
 
+// Tree code (tree.hip).
+struct TreeCell {
+  int32_t begin, end;      // range of the cell's particles along the curve
+  int32_t child0, nchild;  // children are contiguous; nchild == 0 for a leaf
+  int32_t level, pad;
+  double corner[3];        // cube corner and side
+  double side;
+  double M;                // mass, centre of mass, traceless quadrupole
+  double X[3];
+  double Q[6];             // xx, yy, zz, xy, xz, yz
+};
+struct TreeStats {
+  int64_t cells, groups, accepted, opened_leaves;
+  int depth;
+};
+// Device buffers of the tree code, grown on demand and kept between calls.
+struct TreeScratch {
+  std::vector<std::pair<void*, size_t>> slots;
+  void* host = nullptr;    // pinned, for the per-level counts
+};
+hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
+                           double eps2, double theta, int n_crit, double g_frac, double* acc, double* pot,
+                           TreeStats* stats, const char** msg);
+void tree_scratch_free(TreeScratch& s);
+
 // Sixth-order force kernel (forces6.hip).
 int forces6_resident_wgs(bool mask);
 int forces6_split(int64_t n_act, int target_items, int64_t n);
@@ -199,6 +224,7 @@ struct nb_ctx {
   // device-planned batch block steps: system table and work list
   std::vector<int64_t> bp_off;    // host copy of the uploaded offsets
   std::vector<double> bp_eps2;    // host copy of the uploaded softenings
+  nb::TreeScratch tree;           // buffers of the tree code
   void* bp_buf = nullptr;         // offsets, eps2, sys, nchunk, items, n_items
   size_t bp_cap = 0;
   int bp_max_items = 0;

@@ -1,0 +1,870 @@
+// Barnes-Hut tree code on the GPU (the paper's collisionless method: section
+// "Simulating collisionless systems with hierarchical domain-decomposition
+// methods", subsection "Implementation"): every part runs on the device --
+// Peano-Hilbert keys and the sort along the curve, an octree whose cells cut
+// the curve into distinct pieces until a cell holds at most n_crit
+// particles, monopole and quadrupole moments, groups of up to 64
+// curve-consecutive particles (split while wider than g_max), the walk with
+// a geometric opening criterion, and the force evaluation.
+//
+// Readings shared with the documentation of nb_tree_forces (nbody.h):
+//  * box: lo = per-dimension minimum, side = 2^e >= (1 + 2^-10) * largest
+//    extent, h = side 2^-21, integer coordinates floor((x - lo)/h) clamped
+//  * keys: 63-bit Peano-Hilbert index (Skilling's construction), particles
+//    sorted by (key, index) with a stable radix sort
+//  * cell (l, p): the particles with key prefix p of 3l bits; split while it
+//    holds more than n_crit particles (l < 21); cube corner from the first
+//    particle's coordinates with the low 21-l bits cleared, side 2^(21-l) h
+//  * a cell other than the root is accepted for a group when
+//    theta^2 d^2 > side^2, d the distance between the group's bounding box
+//    and the cube; an opened leaf's particles interact directly
+//  * accepted cell: a = -M y s^-3/2 + Q y s^-5/2 - (5/2)(y.Qy) y s^-7/2,
+//    phi = -M s^-1/2 - (y.Qy)/2 s^-5/2 with y = x - X, s = |y|^2 + eps2,
+//    Q = sum m (3 d d^T - |d|^2 I) about the centre of mass X
+//
+// Structure on the chip: the build and the walk are level-synchronous and
+// data-parallel -- one thread per cell or per (group, cell) pair, with
+// stable scans (hipCUB) placing the outputs, so every list keeps curve
+// order and the results are reproducible run to run; the host reads one
+// count per level to size the next launch.  The force kernel runs one
+// wavefront per group: its 64 lanes are the group's particles, accepted
+// cells are staged 64 at a time in LDS and opened leaves are read with
+// wave-uniform loads.  Everything is double precision.  The opening test and
+// the cube geometry are computed without fused multiply-adds, in the order
+// stated above, so they match any implementation that rounds each operation.
+#include <hipcub/hipcub.hpp>
+
+#include <string>
+#include <vector>
+
+#include "nb_internal.h"
+
+namespace nb {
+namespace {
+
+constexpr int kBits = 21;
+constexpr int kTB = 256;   // threads per block of the element-wise kernels
+constexpr int kGS = 64;    // particles per group (one wavefront)
+
+inline int blocks_for(int64_t n, int cap = 65535) {
+  int64_t g = (n + kTB - 1) / kTB;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+struct Box {
+  double lo[3];
+  double side;
+  double h;
+};
+
+// ---------------------------------------------------------------- box -----
+__global__ __launch_bounds__(kTB) void k_bbox_partial(const double* __restrict__ pos, int64_t n,
+                                                      double* __restrict__ part) {
+  __shared__ double red[6][kTB];
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB)
+    for (int c = 0; c < 3; ++c) {
+      const double x = pos[3 * i + c];
+      mn[c] = fmin(mn[c], x);
+      mx[c] = fmax(mx[c], x);
+    }
+  for (int c = 0; c < 3; ++c) {
+    red[c][threadIdx.x] = mn[c];
+    red[3 + c][threadIdx.x] = mx[c];
+  }
+  __syncthreads();
+  for (int o = kTB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) {
+        red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + o]);
+        red[3 + c][threadIdx.x] = fmax(red[3 + c][threadIdx.x], red[3 + c][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bbox_final(const double* __restrict__ part, int nblk, Box* __restrict__ box) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int b = 0; b < nblk; ++b)
+    for (int c = 0; c < 3; ++c) {
+      mn[c] = fmin(mn[c], part[6 * b + c]);
+      mx[c] = fmax(mx[c], part[6 * b + 3 + c]);
+    }
+  double ext = 0.0;
+  for (int c = 0; c < 3; ++c) ext = fmax(ext, mx[c] - mn[c]);
+  double side = 1.0;
+  if (ext > 0.0) {
+    int e = 0;
+    (void)frexp(ext * (1.0 + 0x1p-10), &e);
+    side = ldexp(1.0, e);
+  }
+  Box b;
+  for (int c = 0; c < 3; ++c) b.lo[c] = mn[c];
+  b.side = side;
+  b.h = ldexp(side, -kBits);
+  *box = b;
+}
+
+// --------------------------------------------------------------- keys -----
+__device__ __forceinline__ void grid_of(const double* x, const Box& b, int32_t* q) {
+  for (int c = 0; c < 3; ++c) {
+    double v = floor((x[c] - b.lo[c]) / b.h);
+    v = v < 0.0 ? 0.0 : (v > (double)((1 << kBits) - 1) ? (double)((1 << kBits) - 1) : v);
+    q[c] = (int32_t)v;
+  }
+}
+
+// Peano-Hilbert index of three 21-bit coordinates: plane by plane from the
+// top, an axis whose bit is set flips the lower bits of axis 0, otherwise
+// the two trade their lower bits; then Gray coding along the axes and the
+// parity mask of the last axis; finally the bits interleaved from the top.
+__device__ __forceinline__ uint64_t hilbert63(uint32_t a0, uint32_t a1, uint32_t a2) {
+  uint32_t w[3] = {a0, a1, a2};
+  for (uint32_t plane = 1u << (kBits - 1); plane > 1u; plane >>= 1) {
+    const uint32_t low = plane - 1u;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if (w[k] & plane) {
+        w[0] ^= low;
+      } else {
+        const uint32_t d = (w[0] ^ w[k]) & low;
+        w[0] ^= d;
+        w[k] ^= d;
+      }
+    }
+  }
+  w[1] ^= w[0];
+  w[2] ^= w[1];
+  uint32_t mask = 0;
+  for (uint32_t plane = 1u << (kBits - 1); plane > 1u; plane >>= 1)
+    if (w[2] & plane) mask ^= plane - 1u;
+  w[0] ^= mask; w[1] ^= mask; w[2] ^= mask;
+  uint64_t key = 0;
+  for (int b = kBits - 1; b >= 0; --b)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) key = (key << 1) | ((w[k] >> b) & 1u);
+  return key;
+}
+
+__global__ __launch_bounds__(kTB) void k_keys(const double* __restrict__ pos, int64_t n, const Box* __restrict__ box,
+                                              uint64_t* __restrict__ keys, int32_t* __restrict__ idx) {
+  const Box b = *box;
+  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kTB) {
+    int32_t q[3];
+    grid_of(pos + 3 * i, b, q);
+    keys[i] = hilbert63((uint32_t)q[0], (uint32_t)q[1], (uint32_t)q[2]);
+    idx[i] = (int32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_gather(const double* __restrict__ pos, const double* __restrict__ mass,
+                                                const int32_t* __restrict__ idx, int64_t n,
+                                                const Box* __restrict__ box, double* __restrict__ pos_s,
+                                                double* __restrict__ mass_s, int32_t* __restrict__ ijk_s) {
+  const Box b = *box;
+  for (int64_t k = (int64_t)blockIdx.x * kTB + threadIdx.x; k < n; k += (int64_t)gridDim.x * kTB) {
+    const int64_t i = idx[k];
+    for (int c = 0; c < 3; ++c) pos_s[3 * k + c] = pos[3 * i + c];
+    mass_s[k] = mass[i];
+    grid_of(pos + 3 * i, b, ijk_s + 3 * k);
+  }
+}
+
+// --------------------------------------------------------------- tree -----
+__device__ __forceinline__ void set_geometry(TreeCell& c, const int32_t* ijk_s, const Box& b) {
+#pragma clang fp contract(off)
+  const int shift = kBits - c.level;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t ci = ((int64_t)ijk_s[3 * c.begin + k] >> shift) << shift;
+    c.corner[k] = b.lo[k] + (double)ci * b.h;
+  }
+  c.side = ldexp(b.h, shift);
+}
+
+__global__ void k_root(TreeCell* __restrict__ cells, int32_t n, const int32_t* __restrict__ ijk_s,
+                       const Box* __restrict__ box) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  TreeCell c{};
+  c.begin = 0; c.end = n; c.child0 = -1; c.nchild = 0; c.level = 0;
+  set_geometry(c, ijk_s, *box);
+  cells[0] = c;
+}
+
+// first position in [lo, hi) whose key is >= bound
+__device__ __forceinline__ int32_t lower_bound_key(const uint64_t* keys, int32_t lo, int32_t hi, uint64_t bound) {
+  while (lo < hi) {
+    const int32_t mid = lo + (hi - lo) / 2;
+    if (keys[mid] < bound) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Child k of a cell at level l covers keys [(p<<3|k) << s, (p<<3|k)+1 << s)
+// with s = 3(20 - l); the last child ends with its parent.
+__device__ __forceinline__ void child_ranges(const TreeCell& c, const uint64_t* keys, int32_t* ends) {
+  const int s = 3 * (kBits - c.level - 1);
+  const uint64_t prefix = keys[c.begin] >> (s + 3);
+  int32_t b = c.begin;
+  for (int k = 0; k < 7; ++k) {
+    const uint64_t bound = ((prefix << 3) | (uint64_t)(k + 1)) << s;
+    b = lower_bound_key(keys, b, c.end, bound);
+    ends[k] = b;
+  }
+  ends[7] = c.end;
+}
+
+__global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restrict__ cells, int32_t ncell,
+                                                        const uint64_t* __restrict__ keys, int n_crit,
+                                                        int32_t* __restrict__ cnt) {
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
+    const TreeCell c = cells[i];
+    int32_t m = 0;
+    if (c.end - c.begin > n_crit && c.level < kBits) {
+      int32_t ends[8];
+      child_ranges(c, keys, ends);
+      int32_t b = c.begin;
+      for (int k = 0; k < 8; ++k) {
+        m += ends[k] > b;
+        b = ends[k];
+      }
+    }
+    cnt[i] = m;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
+                                                        const uint64_t* __restrict__ keys,
+                                                        const int32_t* __restrict__ ijk_s,
+                                                        const Box* __restrict__ box, int n_crit,
+                                                        const int32_t* __restrict__ off, int32_t next) {
+  const Box bx = *box;
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
+    TreeCell& c = cells[first + i];
+    if (!(c.end - c.begin > n_crit && c.level < kBits)) {
+      c.child0 = -1;
+      c.nchild = 0;
+      continue;
+    }
+    int32_t ends[8];
+    child_ranges(c, keys, ends);
+    const int32_t base = next + off[i];
+    int32_t b = c.begin, m = 0;
+    for (int k = 0; k < 8; ++k) {
+      if (ends[k] > b) {
+        TreeCell ch{};
+        ch.begin = b; ch.end = ends[k]; ch.child0 = -1; ch.nchild = 0; ch.level = c.level + 1;
+        set_geometry(ch, ijk_s, bx);
+        cells[base + m] = ch;
+        ++m;
+      }
+      b = ends[k];
+    }
+    c.child0 = base;
+    c.nchild = m;
+  }
+}
+
+// Moments: leaves from their particles, internal cells from their children.
+__global__ __launch_bounds__(kTB) void k_moments(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
+                                                 const double* __restrict__ pos_s, const double* __restrict__ mass_s) {
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
+    TreeCell& c = cells[first + i];
+    double M = 0.0, S[3] = {0.0, 0.0, 0.0}, Q[6] = {0, 0, 0, 0, 0, 0}, X[3];
+    if (c.nchild == 0) {
+      for (int32_t j = c.begin; j < c.end; ++j) {
+        const double m = mass_s[j];
+        M += m;
+        for (int k = 0; k < 3; ++k) S[k] += m * pos_s[3 * j + k];
+      }
+      for (int k = 0; k < 3; ++k) X[k] = M > 0.0 ? S[k] / M : c.corner[k] + 0.5 * c.side;
+      for (int32_t j = c.begin; j < c.end; ++j) {
+        const double m = mass_s[j];
+        const double d0 = pos_s[3 * j] - X[0], d1 = pos_s[3 * j + 1] - X[1], d2 = pos_s[3 * j + 2] - X[2];
+        const double dd = d0 * d0 + d1 * d1 + d2 * d2;
+        Q[0] += m * (3.0 * (d0 * d0) - dd);
+        Q[1] += m * (3.0 * (d1 * d1) - dd);
+        Q[2] += m * (3.0 * (d2 * d2) - dd);
+        Q[3] += m * (3.0 * (d0 * d1));
+        Q[4] += m * (3.0 * (d0 * d2));
+        Q[5] += m * (3.0 * (d1 * d2));
+      }
+    } else {
+      for (int32_t k = 0; k < c.nchild; ++k) {
+        const TreeCell& ch = cells[c.child0 + k];
+        M += ch.M;
+        for (int q = 0; q < 3; ++q) S[q] += ch.M * ch.X[q];
+      }
+      for (int k = 0; k < 3; ++k) X[k] = M > 0.0 ? S[k] / M : c.corner[k] + 0.5 * c.side;
+      for (int32_t k = 0; k < c.nchild; ++k) {
+        const TreeCell& ch = cells[c.child0 + k];
+        const double e0 = ch.X[0] - X[0], e1 = ch.X[1] - X[1], e2 = ch.X[2] - X[2];
+        const double ee = e0 * e0 + e1 * e1 + e2 * e2;
+        const double m = ch.M;
+        Q[0] += ch.Q[0] + m * (3.0 * (e0 * e0) - ee);
+        Q[1] += ch.Q[1] + m * (3.0 * (e1 * e1) - ee);
+        Q[2] += ch.Q[2] + m * (3.0 * (e2 * e2) - ee);
+        Q[3] += ch.Q[3] + m * (3.0 * (e0 * e1));
+        Q[4] += ch.Q[4] + m * (3.0 * (e0 * e2));
+        Q[5] += ch.Q[5] + m * (3.0 * (e1 * e2));
+      }
+    }
+    c.M = M;
+    for (int k = 0; k < 3; ++k) c.X[k] = X[k];
+    for (int k = 0; k < 6; ++k) c.Q[k] = Q[k];
+  }
+}
+
+// ------------------------------------------------------------- groups -----
+__device__ __forceinline__ double extent(const double* pos_s, int32_t b, int32_t e) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int32_t j = b; j < e; ++j)
+    for (int k = 0; k < 3; ++k) {
+      mn[k] = fmin(mn[k], pos_s[3 * j + k]);
+      mx[k] = fmax(mx[k], pos_s[3 * j + k]);
+    }
+  return fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
+}
+
+__global__ __launch_bounds__(kTB) void k_groups_init(int32_t n, int32_t* __restrict__ gb, int32_t* __restrict__ ge,
+                                                     int32_t cap, int32_t* __restrict__ ng) {
+  const int32_t g0 = (n + kGS - 1) / kGS;
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < cap; i += gridDim.x * kTB) {
+    gb[i] = i < g0 ? i * kGS : 0;
+    ge[i] = i < g0 ? (i * kGS + kGS < n ? i * kGS + kGS : n) : 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ng = g0;
+}
+
+__global__ __launch_bounds__(kTB) void k_groups_count(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
+                                                      const int32_t* __restrict__ ng, int32_t cap,
+                                                      const double* __restrict__ pos_s, const Box* __restrict__ box,
+                                                      double g_frac, int32_t* __restrict__ cnt) {
+  const int32_t m = *ng;
+  const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < cap; i += gridDim.x * kTB) {
+    int32_t c = 0;
+    if (i < m) c = (ge[i] - gb[i] > 1 && extent(pos_s, gb[i], ge[i]) > g_max) ? 2 : 1;
+    cnt[i] = c;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_groups_write(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
+                                                      const int32_t* __restrict__ ng, int32_t cap,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const int32_t* __restrict__ off, int32_t* __restrict__ gb2,
+                                                      int32_t* __restrict__ ge2, int32_t* __restrict__ ng2) {
+  const int32_t m = *ng;
+  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < m; i += gridDim.x * kTB) {
+    const int32_t o = off[i];
+    if (cnt[i] == 2) {
+      const int32_t mid = gb[i] + (ge[i] - gb[i] + 1) / 2;
+      gb2[o] = gb[i]; ge2[o] = mid;
+      gb2[o + 1] = mid; ge2[o + 1] = ge[i];
+    } else {
+      gb2[o] = gb[i]; ge2[o] = ge[i];
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ng2 = m > 0 ? off[m - 1] + cnt[m - 1] : 0;
+  (void)cap;
+}
+
+__global__ __launch_bounds__(kTB) void k_group_box(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
+                                                   int32_t ng, const double* __restrict__ pos_s,
+                                                   double* __restrict__ gbox) {
+  for (int32_t g = blockIdx.x * kTB + threadIdx.x; g < ng; g += gridDim.x * kTB) {
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t j = gb[g]; j < ge[g]; ++j)
+      for (int k = 0; k < 3; ++k) {
+        mn[k] = fmin(mn[k], pos_s[3 * j + k]);
+        mx[k] = fmax(mx[k], pos_s[3 * j + k]);
+      }
+    for (int k = 0; k < 3; ++k) {
+      gbox[6 * g + k] = mn[k];
+      gbox[6 * g + 3 + k] = mx[k];
+    }
+  }
+}
+
+// --------------------------------------------------------------- walk -----
+__device__ __forceinline__ bool accepted(const TreeCell& c, const double* gbox, double theta) {
+#pragma clang fp contract(off)
+  double d2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double a = c.corner[k] - gbox[3 + k];
+    const double b = gbox[k] - (c.corner[k] + c.side);
+    double gap = a > b ? a : b;
+    gap = gap > 0.0 ? gap : 0.0;
+    d2 = k == 0 ? gap * gap : d2 + gap * gap;
+  }
+  return theta * theta * d2 > c.side * c.side;
+}
+
+// kind per pair: 0 accepted, 1 opened leaf, 2 opened internal cell
+__global__ __launch_bounds__(kTB) void k_walk_count(const int32_t* __restrict__ fg, const int32_t* __restrict__ fc,
+                                                    int64_t nf, const TreeCell* __restrict__ cells,
+                                                    const double* __restrict__ gbox, double theta,
+                                                    int64_t* __restrict__ ca, int64_t* __restrict__ cl,
+                                                    int64_t* __restrict__ cf) {
+  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < nf; i += (int64_t)gridDim.x * kTB) {
+    const TreeCell& c = cells[fc[i]];
+    const bool acc = fc[i] != 0 && accepted(c, gbox + 6 * fg[i], theta);
+    ca[i] = acc ? 1 : 0;
+    cl[i] = (!acc && c.nchild == 0) ? 1 : 0;
+    cf[i] = (!acc && c.nchild > 0) ? c.nchild : 0;
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_walk_write(const int32_t* __restrict__ fg, const int32_t* __restrict__ fc,
+                                                    int64_t nf, const TreeCell* __restrict__ cells,
+                                                    const int64_t* __restrict__ ca, const int64_t* __restrict__ cl,
+                                                    const int64_t* __restrict__ cf, const int64_t* __restrict__ oa,
+                                                    const int64_t* __restrict__ ol, const int64_t* __restrict__ of,
+                                                    int64_t base_a, int64_t base_l, int32_t* __restrict__ ag,
+                                                    int32_t* __restrict__ ac, int32_t* __restrict__ lg,
+                                                    int32_t* __restrict__ lc, int32_t* __restrict__ ng_,
+                                                    int32_t* __restrict__ nc_) {
+  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < nf; i += (int64_t)gridDim.x * kTB) {
+    const int32_t g = fg[i], ci = fc[i];
+    if (ca[i]) {
+      ag[base_a + oa[i]] = g;
+      ac[base_a + oa[i]] = ci;
+    } else if (cl[i]) {
+      lg[base_l + ol[i]] = g;
+      lc[base_l + ol[i]] = ci;
+    } else if (cf[i]) {
+      const TreeCell& c = cells[ci];
+      for (int32_t k = 0; k < c.nchild; ++k) {
+        ng_[of[i] + k] = g;
+        nc_[of[i] + k] = c.child0 + k;
+      }
+    }
+  }
+}
+
+// first index in [0, n) whose group is >= g (lists are sorted by group)
+__device__ __forceinline__ int64_t lower_bound_group(const int32_t* a, int64_t n, int32_t g) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < g) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// -------------------------------------------------------------- forces ----
+struct CellLite {
+  double M, X[3], Q[6];
+};
+
+__global__ __launch_bounds__(kGS) void k_tree_forces(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
+                                                     int32_t ngroups, const TreeCell* __restrict__ cells,
+                                                     const int32_t* __restrict__ ag, const int32_t* __restrict__ ac,
+                                                     int64_t na, const int32_t* __restrict__ lg,
+                                                     const int32_t* __restrict__ lc, int64_t nl,
+                                                     const double* __restrict__ pos_s,
+                                                     const double* __restrict__ mass_s, double eps2,
+                                                     const int32_t* __restrict__ idx_s, double* __restrict__ acc,
+                                                     double* __restrict__ pot) {
+  __shared__ CellLite tile[kGS];
+  const int32_t g = blockIdx.x;
+  if (g >= ngroups) return;
+  const int lane = threadIdx.x;
+  const int32_t b = gb[g], e = ge[g];
+  const int32_t i = b + lane;
+  const bool valid = i < e;
+  const int32_t ir = valid ? i : b;
+  const double x0 = pos_s[3 * ir], x1 = pos_s[3 * ir + 1], x2 = pos_s[3 * ir + 2];
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, ph = 0.0;
+
+  // accepted cells, 64 at a time through LDS
+  const int64_t ab = lower_bound_group(ag, na, g), ae = lower_bound_group(ag, na, g + 1);
+  for (int64_t base = ab; base < ae; base += kGS) {
+    const int64_t k = base + lane;
+    if (k < ae) {
+      const TreeCell& c = cells[ac[k]];
+      CellLite cl;
+      cl.M = c.M;
+      for (int q = 0; q < 3; ++q) cl.X[q] = c.X[q];
+      for (int q = 0; q < 6; ++q) cl.Q[q] = c.Q[q];
+      tile[lane] = cl;
+    }
+    __syncthreads();
+    const int cnt = (int)(ae - base < kGS ? ae - base : kGS);
+    for (int t = 0; t < cnt; ++t) {
+      const CellLite& c = tile[t];
+      const double y0 = x0 - c.X[0], y1 = x1 - c.X[1], y2 = x2 - c.X[2];
+      const double s = y0 * y0 + y1 * y1 + y2 * y2 + eps2;
+      const double q = 1.0 / sqrt(s);
+      const double q2 = q * q;
+      const double q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+      const double Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
+      const double Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
+      const double Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
+      const double yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
+      const double f = -c.M * q3 - 2.5 * yQy * q7;
+      a0 += f * y0 + Qy0 * q5;
+      a1 += f * y1 + Qy1 * q5;
+      a2 += f * y2 + Qy2 * q5;
+      ph += -c.M * q - 0.5 * yQy * q5;
+    }
+    __syncthreads();
+  }
+
+  // opened leaves: their particles, wave-uniform loads
+  const int64_t lb = lower_bound_group(lg, nl, g), le = lower_bound_group(lg, nl, g + 1);
+  for (int64_t k = lb; k < le; ++k) {
+    const TreeCell& c = cells[lc[k]];
+    for (int32_t j = c.begin; j < c.end; ++j) {
+      const double r0 = pos_s[3 * j] - x0, r1 = pos_s[3 * j + 1] - x1, r2 = pos_s[3 * j + 2] - x2;
+      const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
+      const bool keep = j != i && s > 0.0;
+      const double q = keep ? 1.0 / sqrt(s) : 0.0;
+      const double mq = mass_s[j] * q;
+      const double mq3 = mq * q * q;
+      a0 += mq3 * r0;
+      a1 += mq3 * r1;
+      a2 += mq3 * r2;
+      ph -= mq;
+    }
+  }
+  if (valid) {
+    const int32_t o = idx_s[i];
+    acc[3 * o] = a0;
+    acc[3 * o + 1] = a1;
+    acc[3 * o + 2] = a2;
+    pot[o] = ph;
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_root_pairs(int32_t ng, const TreeCell* __restrict__ cells, int32_t* __restrict__ fg,
+                             int32_t* __restrict__ fc) {
+  // the root is never accepted: each group starts from the root's children
+  // (or from the root itself when it is a leaf)
+  const TreeCell root = cells[0];
+  const int32_t per = root.nchild > 0 ? root.nchild : 1;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)ng * per;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    fg[t] = (int32_t)(t / per);
+    fc[t] = root.nchild > 0 ? root.child0 + (int32_t)(t % per) : 0;
+  }
+}
+
+// ------------------------------------------------------- host helpers -----
+struct Alloc {
+  TreeScratch& s;
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+  template <class T>
+  T* get(int slot, int64_t count) {
+    if (err != hipSuccess) return nullptr;
+    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    if ((int)s.slots.size() <= slot) s.slots.resize(slot + 1, {nullptr, 0});
+    auto& sl = s.slots[slot];
+    if (sl.second < bytes) {
+      if (sl.first) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(sl.first);
+        sl.first = nullptr;
+        sl.second = 0;
+      }
+      const size_t cap = bytes + bytes / 4;
+      err = hipMalloc(&sl.first, cap);
+      if (err != hipSuccess) return nullptr;
+      sl.second = cap;
+    }
+    return static_cast<T*>(sl.first);
+  }
+};
+
+enum Slot {
+  S_BOXPART, S_BOX, S_KEYS, S_KEYS2, S_IDX, S_IDX2, S_POS, S_MASS, S_IJK, S_CELLS, S_CNT, S_OFF, S_TMP,
+  S_GB, S_GE, S_GB2, S_GE2, S_GN, S_GBOX, S_FG, S_FC, S_FG2, S_FC2, S_CA, S_CL, S_CF, S_OA, S_OL, S_OF,
+  S_AG, S_AC, S_LG, S_LC, S_AG2, S_AC2, S_LG2, S_LC2
+};
+
+template <class T>
+hipError_t exclusive_sum(Alloc& al, const T* in, T* out, int64_t n) {
+  size_t bytes = 0;
+  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n, al.st);
+  if (e != hipSuccess) return e;
+  void* tmp = al.get<char>(S_TMP, (int64_t)bytes);
+  if (!tmp) return al.err;
+  return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, n, al.st);
+}
+
+template <class K, class V>
+hipError_t sort_pairs(Alloc& al, const K* kin, K* kout, const V* vin, V* vout, int64_t n, int end_bit) {
+  size_t bytes = 0;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, n, 0, end_bit, al.st);
+  if (e != hipSuccess) return e;
+  void* tmp = al.get<char>(S_TMP, (int64_t)bytes);
+  if (!tmp) return al.err;
+  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, n, 0, end_bit, al.st);
+}
+
+// last exclusive-sum entry + last count, read to the host (synchronises)
+template <class T>
+hipError_t read_total(TreeScratch& s, hipStream_t st, const T* off, const T* cnt, int64_t n, int64_t* total) {
+  if (n <= 0) {
+    *total = 0;
+    return hipSuccess;
+  }
+  T* h = static_cast<T*>(s.host);
+  hipError_t e = hipMemcpyAsync(h, off + n - 1, sizeof(T), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h + 1, cnt + n - 1, sizeof(T), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) *total = (int64_t)h[0] + (int64_t)h[1];
+  return e;
+}
+
+}  // namespace
+
+#define NB_TRY(x)                 \
+  do {                            \
+    hipError_t e_ = (x);          \
+    if (e_ != hipSuccess) {       \
+      *msg = #x;                  \
+      return e_;                  \
+    }                             \
+  } while (0)
+
+hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
+                           double eps2, double theta, int n_crit, double g_frac, double* acc, double* pot,
+                           TreeStats* stats, const char** msg) {
+  *msg = "";
+  if (!s.host) NB_TRY(hipHostMalloc(&s.host, 64 * sizeof(int64_t), hipHostMallocDefault));
+  Alloc al{s, st};
+  auto need = [&](void* p) -> hipError_t { return p ? hipSuccess : (al.err != hipSuccess ? al.err : hipErrorOutOfMemory); };
+
+  // box, keys, sort along the curve
+  const int nbb = blocks_for(n, 1024);
+  double* part = al.get<double>(S_BOXPART, 6 * nbb);
+  Box* box = al.get<Box>(S_BOX, 1);
+  uint64_t* keys = al.get<uint64_t>(S_KEYS, n);
+  uint64_t* keys_s = al.get<uint64_t>(S_KEYS2, n);
+  int32_t* idx = al.get<int32_t>(S_IDX, n);
+  int32_t* idx_s = al.get<int32_t>(S_IDX2, n);
+  double* pos_s = al.get<double>(S_POS, 3 * (int64_t)n);
+  double* mass_s = al.get<double>(S_MASS, n);
+  int32_t* ijk_s = al.get<int32_t>(S_IJK, 3 * (int64_t)n);
+  NB_TRY(need(ijk_s));
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kTB), 0, st, pos, (int64_t)n, part);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, nbb, box);
+  hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kTB), 0, st, pos, (int64_t)n, box, keys, idx);
+  NB_TRY(hipGetLastError());
+  NB_TRY(sort_pairs(al, keys, keys_s, idx, idx_s, n, 3 * kBits));
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kTB), 0, st, pos, mass, idx_s, (int64_t)n, box, pos_s,
+                     mass_s, ijk_s);
+  NB_TRY(hipGetLastError());
+
+  // cells, level by level; cells of level l are [lvl[l], lvl[l + 1])
+  TreeCell* cells = al.get<TreeCell>(S_CELLS, 2 * (int64_t)n / (n_crit > 0 ? n_crit : 1) + 64);
+  NB_TRY(need(cells));
+  int64_t cap_cells = (int64_t)(s.slots[S_CELLS].second / sizeof(TreeCell));
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, st, cells, n, ijk_s, box);
+  std::vector<int64_t> lvl = {0, 1};
+  for (int l = 0; l < kBits; ++l) {
+    const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
+    int32_t* cntc = al.get<int32_t>(S_CNT, cnt);
+    int32_t* offc = al.get<int32_t>(S_OFF, cnt);
+    NB_TRY(need(offc));
+    hipLaunchKernelGGL(k_count_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells + first, (int32_t)cnt,
+                       keys_s, n_crit, cntc);
+    NB_TRY(hipGetLastError());
+    NB_TRY(exclusive_sum(al, cntc, offc, cnt));
+    int64_t total = 0;
+    NB_TRY(read_total(s, st, offc, cntc, cnt, &total));
+    if (total == 0) break;
+    const int64_t next = lvl[l + 1];
+    if (next + total > cap_cells) {
+      // grow, keeping the cells built so far
+      TreeCell* old = cells;
+      const int64_t newcap = 2 * (next + total);
+      TreeCell* fresh = nullptr;
+      NB_TRY(hipMalloc(&fresh, (size_t)newcap * sizeof(TreeCell)));
+      NB_TRY(hipMemcpyAsync(fresh, old, (size_t)next * sizeof(TreeCell), hipMemcpyDeviceToDevice, st));
+      NB_TRY(hipStreamSynchronize(st));
+      (void)hipFree(s.slots[S_CELLS].first);
+      s.slots[S_CELLS] = {fresh, (size_t)newcap * sizeof(TreeCell)};
+      cells = fresh;
+      cap_cells = newcap;
+    }
+    hipLaunchKernelGGL(k_write_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells, (int32_t)first,
+                       (int32_t)cnt, keys_s, ijk_s, box, n_crit, offc, (int32_t)next);
+    NB_TRY(hipGetLastError());
+    lvl.push_back(next + total);
+  }
+  // cells are created as leaves (no children); the last level visited made none
+  const int depth = (int)lvl.size() - 2;
+  for (int l = depth; l >= 0; --l) {
+    const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
+    hipLaunchKernelGGL(k_moments, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells, (int32_t)first, (int32_t)cnt,
+                       pos_s, mass_s);
+  }
+  NB_TRY(hipGetLastError());
+  const int64_t ncells = lvl[depth + 1];
+
+  // groups: chunks of 64, halved while wider than g_max
+  const int32_t gcap = n;
+  int32_t* gb = al.get<int32_t>(S_GB, gcap);
+  int32_t* ge = al.get<int32_t>(S_GE, gcap);
+  int32_t* gb2 = al.get<int32_t>(S_GB2, gcap);
+  int32_t* ge2 = al.get<int32_t>(S_GE2, gcap);
+  int32_t* gn = al.get<int32_t>(S_GN, 2);
+  int32_t* gcnt = al.get<int32_t>(S_CNT, gcap);
+  int32_t* goff = al.get<int32_t>(S_OFF, gcap);
+  NB_TRY(need(goff));
+  hipLaunchKernelGGL(k_groups_init, dim3(blocks_for(gcap)), dim3(kTB), 0, st, n, gb, ge, gcap, gn);
+  for (int round = 0; round < 7; ++round) {
+    hipLaunchKernelGGL(k_groups_count, dim3(blocks_for(gcap)), dim3(kTB), 0, st, gb, ge, gn, gcap, pos_s, box,
+                       g_frac, gcnt);
+    NB_TRY(exclusive_sum(al, gcnt, goff, gcap));
+    hipLaunchKernelGGL(k_groups_write, dim3(blocks_for(gcap)), dim3(kTB), 0, st, gb, ge, gn, gcap, gcnt, goff,
+                       gb2, ge2, gn + 1);
+    NB_TRY(hipGetLastError());
+    std::swap(gb, gb2);
+    std::swap(ge, ge2);
+    NB_TRY(hipMemcpyAsync(gn, gn + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  }
+  int32_t ngroups = 0;
+  {
+    int32_t* h = static_cast<int32_t*>(s.host);
+    NB_TRY(hipMemcpyAsync(h, gn, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    NB_TRY(hipStreamSynchronize(st));
+    ngroups = h[0];
+  }
+  double* gbox = al.get<double>(S_GBOX, 6 * (int64_t)ngroups);
+  NB_TRY(need(gbox));
+  hipLaunchKernelGGL(k_group_box, dim3(blocks_for(ngroups)), dim3(kTB), 0, st, gb, ge, ngroups, pos_s, gbox);
+
+  // walk, level-synchronous over (group, cell) pairs
+  int32_t root_nchild = 0;
+  {
+    int32_t* h = static_cast<int32_t*>(s.host);
+    NB_TRY(hipMemcpyAsync(h, &cells[0].nchild, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    NB_TRY(hipStreamSynchronize(st));
+    root_nchild = h[0];
+  }
+  int64_t nf = (int64_t)ngroups * (root_nchild > 0 ? root_nchild : 1);
+  int32_t* fg = al.get<int32_t>(S_FG, nf);
+  int32_t* fc = al.get<int32_t>(S_FC, nf);
+  NB_TRY(need(fc));
+  hipLaunchKernelGGL(k_root_pairs, dim3(blocks_for(nf)), dim3(kTB), 0, st, ngroups, cells, fg, fc);
+  NB_TRY(hipGetLastError());
+  int64_t na = 0, nl = 0, cap_a = 0, cap_l = 0;
+  int32_t *ag = nullptr, *acl = nullptr, *lg = nullptr, *lcl = nullptr;
+  int fslot = 0;
+  while (nf > 0) {
+    int64_t* ca = al.get<int64_t>(S_CA, nf);
+    int64_t* cl = al.get<int64_t>(S_CL, nf);
+    int64_t* cf = al.get<int64_t>(S_CF, nf);
+    int64_t* oa = al.get<int64_t>(S_OA, nf);
+    int64_t* ol = al.get<int64_t>(S_OL, nf);
+    int64_t* of = al.get<int64_t>(S_OF, nf);
+    NB_TRY(need(of));
+    hipLaunchKernelGGL(k_walk_count, dim3(blocks_for(nf)), dim3(kTB), 0, st, fg, fc, nf, cells, gbox, theta, ca, cl,
+                       cf);
+    NB_TRY(hipGetLastError());
+    NB_TRY(exclusive_sum(al, ca, oa, nf));
+    NB_TRY(exclusive_sum(al, cl, ol, nf));
+    NB_TRY(exclusive_sum(al, cf, of, nf));
+    int64_t ta = 0, tl = 0, tf = 0;
+    NB_TRY(read_total(s, st, oa, ca, nf, &ta));
+    NB_TRY(read_total(s, st, ol, cl, nf, &tl));
+    NB_TRY(read_total(s, st, of, cf, nf, &tf));
+    if (na + ta > ((int64_t)1 << 31) - 1 || nl + tl > ((int64_t)1 << 31) - 1 || tf > ((int64_t)1 << 31) - 1) {
+      *msg = "interaction lists exceed 2^31 entries (raise theta or n_crit)";
+      return hipErrorInvalidValue;
+    }
+    // grow the accumulated lists, keeping their contents
+    auto grow = [&](int slot_g, int slot_c, int32_t*& pg, int32_t*& pc, int64_t& cap, int64_t used,
+                    int64_t want) -> hipError_t {
+      if (used + want <= cap) return hipSuccess;
+      const int64_t nc = 2 * (used + want) + 1024;
+      int32_t *ng_ = nullptr, *nc_ = nullptr;
+      hipError_t e = hipMalloc(&ng_, (size_t)nc * sizeof(int32_t));
+      if (e == hipSuccess) e = hipMalloc(&nc_, (size_t)nc * sizeof(int32_t));
+      if (e != hipSuccess) return e;
+      if (used > 0) {
+        e = hipMemcpyAsync(ng_, pg, (size_t)used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(nc_, pc, (size_t)used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+      }
+      if ((int)s.slots.size() <= slot_c) s.slots.resize(slot_c + 1, {nullptr, 0});
+      if (s.slots[slot_g].first) (void)hipFree(s.slots[slot_g].first);
+      if (s.slots[slot_c].first) (void)hipFree(s.slots[slot_c].first);
+      s.slots[slot_g] = {ng_, (size_t)nc * sizeof(int32_t)};
+      s.slots[slot_c] = {nc_, (size_t)nc * sizeof(int32_t)};
+      pg = ng_;
+      pc = nc_;
+      cap = nc;
+      return hipSuccess;
+    };
+    if (!ag) {
+      ag = al.get<int32_t>(S_AG, 1024); acl = al.get<int32_t>(S_AC, 1024);
+      lg = al.get<int32_t>(S_LG, 1024); lcl = al.get<int32_t>(S_LC, 1024);
+      NB_TRY(need(lcl));
+      cap_a = (int64_t)(s.slots[S_AG].second < s.slots[S_AC].second ? s.slots[S_AG].second : s.slots[S_AC].second) /
+              (int64_t)sizeof(int32_t);
+      cap_l = (int64_t)(s.slots[S_LG].second < s.slots[S_LC].second ? s.slots[S_LG].second : s.slots[S_LC].second) /
+              (int64_t)sizeof(int32_t);
+    }
+    NB_TRY(grow(S_AG, S_AC, ag, acl, cap_a, na, ta));
+    NB_TRY(grow(S_LG, S_LC, lg, lcl, cap_l, nl, tl));
+    const int nslot_g = fslot ? S_FG : S_FG2, nslot_c = fslot ? S_FC : S_FC2;
+    int32_t* ng_ = al.get<int32_t>(nslot_g, tf);
+    int32_t* nc_ = al.get<int32_t>(nslot_c, tf);
+    NB_TRY(need(nc_));
+    hipLaunchKernelGGL(k_walk_write, dim3(blocks_for(nf)), dim3(kTB), 0, st, fg, fc, nf, cells, ca, cl, cf, oa, ol,
+                       of, na, nl, ag, acl, lg, lcl, ng_, nc_);
+    NB_TRY(hipGetLastError());
+    na += ta;
+    nl += tl;
+    fg = ng_;
+    fc = nc_;
+    nf = tf;
+    fslot ^= 1;
+  }
+
+  // lists grouped by group (stable: curve and level order kept inside a group)
+  int32_t* ag2 = al.get<int32_t>(S_AG2, na);
+  int32_t* ac2 = al.get<int32_t>(S_AC2, na);
+  int32_t* lg2 = al.get<int32_t>(S_LG2, nl);
+  int32_t* lc2 = al.get<int32_t>(S_LC2, nl);
+  NB_TRY(need(lc2));
+  int end_bit = 1;
+  while (end_bit < 31 && ((int64_t)1 << end_bit) <= ngroups) ++end_bit;
+  if (na > 0) NB_TRY(sort_pairs(al, ag, ag2, acl, ac2, na, end_bit));
+  if (nl > 0) NB_TRY(sort_pairs(al, lg, lg2, lcl, lc2, nl, end_bit));
+
+  hipLaunchKernelGGL(k_tree_forces, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na, lg2, lc2,
+                     nl, pos_s, mass_s, eps2, idx_s, acc, pot);
+  NB_TRY(hipGetLastError());
+  if (stats) {
+    stats->cells = ncells;
+    stats->groups = ngroups;
+    stats->accepted = na;
+    stats->opened_leaves = nl;
+    stats->depth = depth;
+  }
+  return hipSuccess;
+}
+
+void tree_scratch_free(TreeScratch& s) {
+  for (auto& sl : s.slots)
+    if (sl.first) (void)hipFree(sl.first);
+  s.slots.clear();
+  if (s.host) (void)hipHostFree(s.host);
+  s.host = nullptr;
+}
+
+}  // namespace nb

@@ -1,0 +1,143 @@
+"""GPU parity of the tree code against the CPU oracle, through the C ABI:
+identical interaction sets (accepted cells and opened leaves per group) and
+forces within rounding of the oracle's, theta = 0 reproducing the direct
+sum, edge cases (one particle, coincident particles, two distant clusters,
+unsoftened), repeatability and argument errors."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tree as TR
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def T(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1409_5474_amd as nb
+    c = nb.Context(0, "fp64")
+    yield c
+    c.close()
+
+
+def _gpu(ctx, pos, mass, eps2, theta, n_crit=16, g_frac=1.0 / 16):
+    import torch
+    acc, pot, st = ctx.tree_forces(T(pos), T(mass), eps2, theta, n_crit, g_frac)
+    torch.cuda.synchronize()
+    return acc.cpu().numpy(), pot.cpu().numpy(), st
+
+
+def _oracle(pos, mass, eps2, theta, n_crit=16, g_frac=1.0 / 16):
+    t = TR.build(pos, mass, n_crit)
+    acc, pot, st = TR.forces(pos, mass, eps2, theta, n_crit, g_max=g_frac * t.side, tree=t)
+    return acc, pot, st, t
+
+
+def _close(got, ref, tol):
+    a, p = got
+    ra, rp = ref
+    assert np.linalg.norm(a - ra) <= tol * np.linalg.norm(ra)
+    assert np.linalg.norm(p - rp) <= tol * np.linalg.norm(rp)
+    rel = np.linalg.norm(a - ra, axis=1) / np.maximum(np.linalg.norm(ra, axis=1), 1e-300)
+    assert rel.max() <= 1e3 * tol, rel.max()
+
+
+@pytest.mark.parametrize("n,theta,n_crit,seed", [(3000, 0.5, 16, 1), (5000, 0.3, 8, 2), (4096, 0.8, 16, 3),
+                                                 (2500, 0.6, 32, 4), (700, 0.5, 16, 5)])
+def test_tree_matches_oracle(ctx, n, theta, n_crit, seed):
+    p = synth.plummer(n, seed)
+    eps2 = 1e-4
+    acc, pot, st = _gpu(ctx, p.pos, p.mass, eps2, theta, n_crit)
+    ra, rp, rst, t = _oracle(p.pos, p.mass, eps2, theta, n_crit)
+    assert st["cells"] == len(t.cells)
+    assert st["groups"] == len(rst)
+    assert st["accepted"] == sum(c for c, _, _ in rst)
+    assert st["opened_leaves"] == sum(l for _, l, _ in rst)
+    assert st["depth"] == max(c.level for c in t.cells)
+    _close((acc, pot), (ra, rp), 1e-12)
+
+
+def test_theta_zero_is_the_direct_sum(ctx):
+    import torch
+    p = synth.plummer(2000, 7)
+    eps2 = 1e-3
+    acc, pot, st = _gpu(ctx, p.pos, p.mass, eps2, 0.0)
+    assert st["accepted"] == 0
+    a_ref, _, p_ref = ctx.forces(T(p.pos), T(p.vel), T(p.mass), T(np.arange(2000, dtype=np.int32)), eps2)
+    torch.cuda.synchronize()
+    _close((acc, pot), (a_ref.cpu().numpy(), p_ref.cpu().numpy()), 1e-13)
+
+
+def test_one_particle_and_a_small_set(ctx):
+    acc, pot, st = _gpu(ctx, np.array([[0.3, -0.2, 0.1]]), np.array([1.0]), 1e-3, 0.5)
+    assert np.all(acc == 0) and np.all(pot == 0)
+    assert st["cells"] == 1 and st["groups"] == 1
+    p = synth.plummer(40, 8)
+    acc, pot, st = _gpu(ctx, p.pos, p.mass, 1e-3, 0.5)
+    ra, rp, _, _ = _oracle(p.pos, p.mass, 1e-3, 0.5)
+    _close((acc, pot), (ra, rp), 1e-13)
+
+
+def test_coincident_particles_and_two_distant_clusters(ctx):
+    a = synth.plummer(1500, 9)
+    b = synth.plummer(1500, 10)
+    pos = np.concatenate([a.pos, b.pos * 0.5 + np.array([40.0, -25.0, 10.0])])
+    mass = np.concatenate([a.mass, b.mass * 3.0])
+    pos[17] = pos[1000]                      # two particles on one spot (softened)
+    pos[2500] = pos[2501]
+    acc, pot, st = _gpu(ctx, pos, mass, 1e-3, 0.6)
+    ra, rp, rst, t = _oracle(pos, mass, 1e-3, 0.6)
+    assert st["accepted"] == sum(c for c, _, _ in rst)
+    assert st["depth"] == max(c.level for c in t.cells)
+    _close((acc, pot), (ra, rp), 1e-12)
+
+
+def test_unsoftened_distinct_positions(ctx):
+    p = synth.plummer(3000, 11)
+    acc, pot, st = _gpu(ctx, p.pos, p.mass, 0.0, 0.5)
+    ra, rp, _, _ = _oracle(p.pos, p.mass, 0.0, 0.5)
+    _close((acc, pot), (ra, rp), 1e-12)
+
+
+def test_groups_split_by_size(ctx):
+    p = synth.plummer(3000, 12)
+    _, _, st1 = _gpu(ctx, p.pos, p.mass, 1e-3, 0.5, g_frac=0.0)
+    _, _, st2 = _gpu(ctx, p.pos, p.mass, 1e-3, 0.5, g_frac=1.0 / 64)
+    t = TR.build(p.pos, p.mass)
+    assert st1["groups"] == len(TR.groups(t, np.inf)) == (3000 + 63) // 64
+    assert st2["groups"] == len(TR.groups(t, t.side / 64)) > st1["groups"]
+
+
+def test_accuracy_against_direct_and_repeatability(ctx):
+    import torch
+    p = synth.plummer(65536, 13)
+    eps2 = 2.0 ** -16
+    acc1, pot1, st = _gpu(ctx, p.pos, p.mass, eps2, 0.5)
+    acc2, pot2, _ = _gpu(ctx, p.pos, p.mass, eps2, 0.5)
+    assert np.array_equal(acc1, acc2) and np.array_equal(pot1, pot2)
+    a_ref, _, _ = ctx.forces(T(p.pos), T(p.vel), T(p.mass), T(np.arange(65536, dtype=np.int32)), eps2)
+    torch.cuda.synchronize()
+    a_ref = a_ref.cpu().numpy()
+    rel = np.linalg.norm(acc1 - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+    assert np.sqrt(np.mean(rel ** 2)) < 1e-3
+    interactions = st["accepted"] * 64 + st["opened_leaves"] * 16
+    assert interactions < 0.1 * 65536 ** 2
+
+
+def test_argument_errors(ctx):
+    import paper_1409_5474_amd as nb
+    import torch
+    p = synth.plummer(100, 14)
+    with pytest.raises(nb.NbodyError):
+        ctx.tree_forces(T(p.pos), T(p.mass), -1.0, 0.5)
+    with pytest.raises(nb.NbodyError):
+        ctx.tree_forces(T(p.pos), T(p.mass), 1e-3, -0.1)
+    with pytest.raises(nb.NbodyError):
+        ctx.tree_forces(T(p.pos), T(p.mass), 1e-3, 0.5, n_crit=0)
+    torch.cuda.synchronize()

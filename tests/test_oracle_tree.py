@@ -148,7 +148,7 @@ def test_force_error_falls_with_theta():
         acc, pot, st = TR.forces(p.pos, p.mass, eps2, theta)
         rel = np.linalg.norm(acc - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
         errs.append(np.sqrt(np.mean(rel ** 2)))
-        work.append(sum(c + d for c, d in st))
+        work.append(sum(c + d for c, _, d in st))
     assert errs[0] > errs[1] > errs[2] and errs[0] > 5 * errs[2], errs
     assert errs[0] < 2e-3 and errs[2] < 1e-4, errs
     assert work[0] < work[1] < work[2] < 4000 * 4000
