@@ -43,7 +43,7 @@ def parse():
                     help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="", choices=["", "plummer1k", "hermite65k", "hermite262k", "batch128",
-                                                        "merger", "bridge", "hermite6"],
+                                                        "merger", "bridge", "hermite6", "tree"],
                     help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -87,10 +87,16 @@ def workloads(args):
                 to t=1/8 (eta=0.4, eta_s=0.02, graph-replayed) beside the
                 fourth-order run of the same model (eta=0.01): steps, time
                 and energy drift of each
+    tree        the Barnes-Hut tree code on Plummer spheres of 2^18 and 2^20
+                particles (eps=1/256, n_crit=16, groups of 64): wall time of
+                one force evaluation for theta = 0.75, 0.5, 0.4 (the call
+                includes the build), interaction pairs, and the acceleration
+                error against FP64 direct sums on 4096 sampled particles
     bridge      the same bodies under the kick-drift-kick split: c = the
                 point masses and the stars near them (FP64 Hermite block
-                steps, eta=0.01), g = every other star (mixed-precision
-                leapfrog with direct forces), cross field in mixed
+                steps, eta=0.01), g = every other star (leapfrog with the
+                FP64 tree code at theta=0.5 -- the paper's hybrid -- or with
+                mixed-precision direct forces), cross field in mixed
                 precision; bridge step 1/128; --steps bridge steps after one
                 warm-up step, each part timed
     """
@@ -224,6 +230,30 @@ def workloads(args):
             runs[f"order{order}"] = dict(steps=bi.steps, wall_s=round(wall, 3), drift=abs(E1 - E0) / abs(E0))
         out["plummer65k_to_t_1_8"] = runs
         ctx.close()
+    elif args.workload == "tree":
+        ctx = nb.Context(0, "fp64")
+        res = {}
+        for n in (262144, 1048576):
+            p = synth.plummer(n, 3)
+            P, V, M = t(p.pos), t(p.vel), t(p.mass)
+            sample = torch.from_numpy(np.linspace(0, n - 1, 4096).astype(np.int32)).to(dev)
+            a_ref, _, _ = ctx.forces(P, V, M, sample, 2.0 ** -16)
+            a_ref = a_ref.cpu().numpy()
+            for theta in (0.75, 0.5, 0.4):
+                acc, pot, st = ctx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)   # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    acc, pot, st = ctx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)
+                torch.cuda.synchronize()
+                wall = (time.perf_counter() - t0) / args.steps
+                a = acc[sample].cpu().numpy()
+                rel = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+                res[f"N{n}_theta{theta}"] = dict(ms=round(1e3 * wall, 2), particles_per_s=round(n / wall, 0),
+                                                 acc_rel_err_rms=float(np.sqrt(np.mean(rel ** 2))),
+                                                 acc_rel_err_max=float(rel.max()), **st)
+        out.update(res)
+        ctx.close()
     elif args.workload == "bridge":
         from paper_1409_5474_amd.bridge import Bridge
         m = synth.hernquist_merger()
@@ -231,42 +261,46 @@ def workloads(args):
         is_c[m.active] = True
         c, g = np.nonzero(is_c)[0], np.nonzero(~is_c)[0]
         dt = 1.0 / 128
-        c64, cmx = nb.Context(0, "fp64"), nb.Context(0, "mixed")
-        br = Bridge(c64, cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]), t(m.vel[c]), t(m.mass[c]),
-                    m.eps2, m.eps2, m.eps2, dt, n_sub=1, eta=0.01, max_level=30)
-        E0 = br.energy()
-        parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
-        block_steps = 0
-
-        def timed(key, fn):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            fn()
-            torch.cuda.synchronize()
-            parts[key] += time.perf_counter() - t0
-
-        for k in range(args.steps + 1):
-            if k == 1:                      # the first step is the warm-up
-                parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
-                block_steps = br.block_steps
-            timed("kick", lambda: br.kick(0.5 * dt))
-            timed("cluster", br.drift_cluster)
-            timed("galaxy", br.drift_galaxy)
-            timed("kick", lambda: br.kick(0.5 * dt))
-            br.steps += 1
-        E1 = br.energy()
-        nsteps = args.steps
         ng, nc = int(g.size), int(c.size)
-        wall = sum(parts.values())
-        cross = 4.0 * ng * nc                # two kicks, both directions
-        out.update(n_g=ng, n_c=nc, bridge_dt=dt, bridge_steps=nsteps,
-                   ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
-                   ms_per_part={k: round(1e3 * v / nsteps, 2) for k, v in parts.items()},
-                   cross_field_gint=round(cross * nsteps / parts["kick"] / 1e9, 1),
-                   galaxy_gint=round(float(ng) * ng * nsteps / parts["galaxy"] / 1e9, 1),
-                   cluster_block_steps_per_bridge_step=round((br.block_steps - block_steps) / nsteps, 1),
-                   energy_drift=abs(E1["E"] - E0["E"]) / abs(E0["E"]), time=br.time)
-        c64.close(); cmx.close()
+        out.update(n_g=ng, n_c=nc, bridge_dt=dt, bridge_steps=args.steps)
+        for field in ("tree", "direct"):
+            c64, cmx = nb.Context(0, "fp64"), nb.Context(0, "mixed")
+            # the tree code runs in FP64 on its context; the direct field and the cross field in mixed precision
+            br = Bridge(c64, c64 if field == "tree" else cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]),
+                        t(m.vel[c]), t(m.mass[c]), m.eps2, m.eps2, m.eps2, dt, n_sub=1, eta=0.01, max_level=30,
+                        ctx_x=cmx, field=field, theta=0.5)
+            E0 = br.energy()
+            parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
+            block_steps = 0
+
+            def timed(key, fn):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                parts[key] += time.perf_counter() - t0
+
+            for k in range(args.steps + 1):
+                if k == 1:                      # the first step is the warm-up
+                    parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
+                    block_steps = br.block_steps
+                timed("kick", lambda: br.kick(0.5 * dt))
+                timed("cluster", br.drift_cluster)
+                timed("galaxy", br.drift_galaxy)
+                timed("kick", lambda: br.kick(0.5 * dt))
+                br.steps += 1
+            E1 = br.energy()
+            nsteps = args.steps
+            wall = sum(parts.values())
+            cross = 4.0 * ng * nc                # two kicks, both directions
+            out[field] = dict(ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
+                              ms_per_part={k: round(1e3 * v / nsteps, 2) for k, v in parts.items()},
+                              cross_field_gint=round(cross * nsteps / parts["kick"] / 1e9, 1),
+                              cluster_block_steps_per_bridge_step=round((br.block_steps - block_steps) / nsteps, 1),
+                              energy_drift=abs(E1["E"] - E0["E"]) / abs(E0["E"]), time=br.time)
+            if field == "direct":
+                out[field]["galaxy_gint"] = round(float(ng) * ng * nsteps / parts["galaxy"] / 1e9, 1)
+            c64.close(); cmx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -18,9 +18,13 @@ evolutions of g and c because H_B has no cross term.  Written out
              drift restarts it: new a and jdot, start-up levels.  Its dt_max
              is the bridge step, so each drift ends on a synchronisation time.
              g advances under H_g alone with n_sub shared-step leapfrog
-             substeps (kick-drift-kick) of h = dt/n_sub with its own forces.
-             The paper advances g with a tree code; a direct sum stands in for
-             it here (the field solver is not part of the split).
+             substeps (kick-drift-kick) of h = dt/n_sub with its own forces
+             (the paper's tree code, or a direct sum; the field solver is not
+             part of the split).
+
+The field subsystem's own forces come from a routine passed in (``field``:
+positions and masses -> accelerations); by default the direct sum, or the
+oracle's tree code through ``tree_field``.
 
 Softening: eps2_g inside g, eps2_c inside c, eps2_gc across.  Arithmetic of
 the elementwise updates, in this order and without fused multiply-adds:
@@ -63,6 +67,23 @@ def self_forces(eps2):
     return f
 
 
+def direct_field(eps2):
+    """g's own accelerations by the direct sum."""
+    def f(x, m):
+        return self_forces(eps2)(x, np.zeros_like(x), m, np.arange(m.shape[0], dtype=np.int32))[0]
+    return f
+
+
+def tree_field(eps2, theta, n_crit=16, g_frac=1.0 / 16):
+    """g's own accelerations by the oracle's tree code."""
+    from . import tree as TR
+
+    def f(x, m):
+        t = TR.build(x, m, n_crit)
+        return TR.forces(x, m, eps2, theta, n_crit, g_max=g_frac * t.side, tree=t)[0]
+    return f
+
+
 @dataclass
 class BridgeState:
     xg: np.ndarray
@@ -75,6 +96,7 @@ class BridgeState:
     eps2_gc: float
     dt: float
     n_sub: int
+    field: object = None
     steps: int = 0
 
     @property
@@ -82,17 +104,16 @@ class BridgeState:
         return self.steps * self.dt
 
 
-def initialise(xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt, n_sub=1, eta=0.01, max_level=30):
+def initialise(xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt, n_sub=1, eta=0.01, max_level=30, field=None):
     xg = np.array(xg, dtype=np.float64)
     vg = np.array(vg, dtype=np.float64)
     mg = np.array(mg, dtype=np.float64)
-    if mg.shape[0]:
-        ag = self_forces(eps2_g)(xg, vg, mg, np.arange(mg.shape[0], dtype=np.int32))[0]
-    else:
-        ag = np.zeros((0, 3))
+    field = field if field is not None else direct_field(eps2_g)
+    ag = field(xg, mg) if mg.shape[0] else np.zeros((0, 3))
     cl = hermite.initialise(np.asarray(xc, dtype=np.float64), np.asarray(vc, dtype=np.float64),
                             np.asarray(mc, dtype=np.float64), eps2_c, eta, dt, max_level, self_forces(eps2_c))
-    return BridgeState(xg, vg, mg, ag, cl, float(eps2_g), float(eps2_c), float(eps2_gc), float(dt), int(n_sub))
+    return BridgeState(xg, vg, mg, ag, cl, float(eps2_g), float(eps2_c), float(eps2_gc), float(dt), int(n_sub),
+                       field)
 
 
 def kick(st: BridgeState, h):
@@ -119,12 +140,10 @@ def drift_cluster(st: BridgeState):
 def drift_galaxy(st: BridgeState):
     """g under H_g for one bridge step: n_sub leapfrog substeps (kick-drift-kick)."""
     h = st.dt / st.n_sub
-    f = self_forces(st.eps2_g)
-    act = np.arange(st.mg.shape[0], dtype=np.int32)
     for _ in range(st.n_sub):
         st.vg = st.vg + (0.5 * h) * st.ag
         st.xg = st.xg + h * st.vg
-        st.ag = f(st.xg, st.vg, st.mg, act)[0]
+        st.ag = st.field(st.xg, st.mg)
         st.vg = st.vg + (0.5 * h) * st.ag
 
 

@@ -13,8 +13,9 @@ length dt is e^{dt/2 A} e^{dt B} e^{dt/2 A}:
               changed its velocities, with dt_max = dt, so each drift ends on
               a synchronisation time;
               g: n_sub shared-step leapfrog substeps of dt/n_sub with its own
-              direct forces (``nb_kick_drift``, ``nbody_forces``, ``nb_kick``)
-              -- a direct sum standing in for the paper's tree code;
+              forces (``nb_kick_drift``, the field solver, ``nb_kick``): the
+              paper's tree code (``field="tree"``, ``nb_tree_forces``) or the
+              direct sum (``field="direct"``, ``nbody_forces``);
   kick(dt/2).
 
 Every arithmetic step runs in the library's kernels; this module only
@@ -32,7 +33,11 @@ from .integrator import BlockIntegrator
 
 class Bridge:
     def __init__(self, ctx_c: Context, ctx_g: Context, xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt,
-                 n_sub=1, eta=0.01, max_level=30, ctx_x: Context = None):
+                 n_sub=1, eta=0.01, max_level=30, ctx_x: Context = None, field="direct", theta=0.5, n_crit=16,
+                 g_frac=1.0 / 16):
+        if field not in ("direct", "tree"):
+            raise ValueError("field must be 'direct' or 'tree'")
+        self.field, self.theta, self.n_crit, self.g_frac = field, float(theta), int(n_crit), float(g_frac)
         self.ctx_c, self.ctx_g = ctx_c, ctx_g
         self.ctx_x = ctx_x if ctx_x is not None else ctx_g
         dev = ctx_c.device
@@ -62,7 +67,11 @@ class Bridge:
 
     # ---- pieces of the split ----------------------------------------------
     def _galaxy_forces(self):
-        self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, self.ag, self._jg, self._pg)
+        if self.field == "tree":
+            self.ctx_g.tree_forces(self.xg, self.mg, self.eps2_g, self.theta, self.n_crit, self.g_frac, self.ag,
+                                   self._pg)
+        else:
+            self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, self.ag, self._jg, self._pg)
 
     def cross_field(self):
         """Field of g on every particle of c and of c on every particle of g."""
@@ -124,7 +133,7 @@ class Bridge:
         parts = {}
         if self.ng:
             pot = torch.empty(self.ng, dtype=torch.float64, device=dev)
-            self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, None, None, pot)
+            self.ctx_g.forces(self.xg, self.vg, self.mg, self.idx_g, self.eps2_g, None, None, pot)   # W_g exactly
             o = self.ctx_g.energy(self.xg, self.vg, self.mg, pot, out).cpu().tolist()
             parts["Kg"], parts["Wg"] = o[0], o[1]
         else:

@@ -84,27 +84,42 @@ __global__ __launch_bounds__(kTB) void k_bbox_partial(const double* __restrict__
   if (threadIdx.x < 6) part[6 * blockIdx.x + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double* __restrict__ part, int nblk, Box* __restrict__ box) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kTB) void k_bbox_final(const double* __restrict__ part, int nblk,
+                                                    Box* __restrict__ box) {
+  __shared__ double red[6][kTB];
   double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nblk; ++b)
+  for (int b = threadIdx.x; b < nblk; b += kTB)
     for (int c = 0; c < 3; ++c) {
       mn[c] = fmin(mn[c], part[6 * b + c]);
       mx[c] = fmax(mx[c], part[6 * b + 3 + c]);
     }
+  for (int c = 0; c < 3; ++c) {
+    red[c][threadIdx.x] = mn[c];
+    red[3 + c][threadIdx.x] = mx[c];
+  }
+  __syncthreads();
+  for (int o = kTB / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int c = 0; c < 3; ++c) {
+        red[c][threadIdx.x] = fmin(red[c][threadIdx.x], red[c][threadIdx.x + o]);
+        red[3 + c][threadIdx.x] = fmax(red[3 + c][threadIdx.x], red[3 + c][threadIdx.x + o]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   double ext = 0.0;
-  for (int c = 0; c < 3; ++c) ext = fmax(ext, mx[c] - mn[c]);
+  for (int c = 0; c < 3; ++c) ext = fmax(ext, red[3 + c][0] - red[c][0]);
   double side = 1.0;
   if (ext > 0.0) {
     int e = 0;
     (void)frexp(ext * (1.0 + 0x1p-10), &e);
     side = ldexp(1.0, e);
   }
-  Box b;
-  for (int c = 0; c < 3; ++c) b.lo[c] = mn[c];
-  b.side = side;
-  b.h = ldexp(side, -kBits);
-  *box = b;
+  Box bx;
+  for (int c = 0; c < 3; ++c) bx.lo[c] = red[c][0];
+  bx.side = side;
+  bx.h = ldexp(side, -kBits);
+  *box = bx;
 }
 
 // --------------------------------------------------------------- keys -----
@@ -444,6 +459,14 @@ __global__ __launch_bounds__(kTB) void k_walk_write(const int32_t* __restrict__ 
   }
 }
 
+// s^{-1/2}: v_rsq_f64 (about 2^-24 accurate) refined by one third-order
+// Newton step y (1 + e/2 + 3e^2/8), e = 1 - s y^2, to double rounding.
+__device__ __forceinline__ double rsqrt_tree(double s) {
+  const double y = __builtin_amdgcn_rsq(s);
+  const double e = fma(-(s * y), y, 1.0);
+  return fma(y, e * fma(e, 0.375, 0.5), y);
+}
+
 // first index in [0, n) whose group is >= g (lists are sorted by group)
 __device__ __forceinline__ int64_t lower_bound_group(const int32_t* a, int64_t n, int32_t g) {
   int64_t lo = 0, hi = n;
@@ -498,7 +521,7 @@ __global__ __launch_bounds__(kGS) void k_tree_forces(const int32_t* __restrict__
       const CellLite& c = tile[t];
       const double y0 = x0 - c.X[0], y1 = x1 - c.X[1], y2 = x2 - c.X[2];
       const double s = y0 * y0 + y1 * y1 + y2 * y2 + eps2;
-      const double q = 1.0 / sqrt(s);
+      const double q = rsqrt_tree(s);
       const double q2 = q * q;
       const double q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
       const double Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
@@ -522,7 +545,7 @@ __global__ __launch_bounds__(kGS) void k_tree_forces(const int32_t* __restrict__
       const double r0 = pos_s[3 * j] - x0, r1 = pos_s[3 * j + 1] - x1, r2 = pos_s[3 * j + 2] - x2;
       const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
       const bool keep = j != i && s > 0.0;
-      const double q = keep ? 1.0 / sqrt(s) : 0.0;
+      const double q = keep ? rsqrt_tree(s) : 0.0;
       const double mq = mass_s[j] * q;
       const double mq3 = mq * q * q;
       a0 += mq3 * r0;
@@ -657,7 +680,7 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   int32_t* ijk_s = al.get<int32_t>(S_IJK, 3 * (int64_t)n);
   NB_TRY(need(ijk_s));
   hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kTB), 0, st, pos, (int64_t)n, part);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, part, nbb, box);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kTB), 0, st, part, nbb, box);
   hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kTB), 0, st, pos, (int64_t)n, box, keys, idx);
   NB_TRY(hipGetLastError());
   NB_TRY(sort_pairs(al, keys, keys_s, idx, idx_s, n, 3 * kBits));

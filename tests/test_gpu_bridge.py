@@ -213,3 +213,26 @@ def test_bridge_mixed_field_stays_close_to_fp64():
     assert dx < 1e-6, dx
     assert abs(mix.energy()["E"] - ref.energy()["E"]) < 1e-6 * abs(ref.energy()["E"])
     c64.close(); cmx.close()
+
+
+def test_bridge_with_the_tree_as_field_solver_follows_the_oracle():
+    # The paper's hybrid: the field subsystem advanced with the tree code.
+    import torch
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.bridge import Bridge
+    p, mass, g, c = _cluster_in_galaxy(n=1500, n_c=40, seed=31)
+    eps2_g, eps2_c, eps2_gc, dt, eta, ML, theta = 1e-3, 1e-4, 5e-4, 1.0 / 64, 0.01, 20, 0.5
+    ctx = nb.Context(0, "fp64")
+    br = Bridge(ctx, ctx, T(p.pos[g]), T(p.vel[g]), T(mass[g]), T(p.pos[c]), T(p.vel[c]), T(mass[c]),
+                eps2_g, eps2_c, eps2_gc, dt, eta=eta, max_level=ML, field="tree", theta=theta)
+    st = OB.initialise(p.pos[g], p.vel[g], mass[g], p.pos[c], p.vel[c], mass[c], eps2_g, eps2_c, eps2_gc, dt,
+                       eta=eta, max_level=ML, field=OB.tree_field(eps2_g, theta))
+    for _ in range(3):
+        br.step()
+        OB.step(st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(br.cluster.level.cpu().numpy(), st.cluster.level)
+    for got, ref in ((br.xg, st.xg), (br.vg, st.vg), (br.cluster.pos, st.cluster.x)):
+        d = np.abs(got.cpu().numpy() - ref).max()
+        assert d <= 1e-11 * np.abs(ref).max(), d
+    ctx.close()

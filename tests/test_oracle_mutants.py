@@ -160,12 +160,10 @@ def _mut_kick_c_only(st, h):
 def _mut_galaxy_drift_first(st):
     from oracle import bridge as B
     h = st.dt / st.n_sub
-    f = B.self_forces(st.eps2_g)
-    act = np.arange(st.mg.shape[0], dtype=np.int32)
     for _ in range(st.n_sub):
         st.xg = st.xg + h * st.vg          # drift before the half kick
         st.vg = st.vg + (0.5 * h) * st.ag
-        st.ag = f(st.xg, st.vg, st.mg, act)[0]
+        st.ag = st.field(st.xg, st.mg)
         st.vg = st.vg + (0.5 * h) * st.ag
 
 
