@@ -88,15 +88,16 @@ def workloads(args):
                 fourth-order run of the same model (eta=0.01): steps, time
                 and energy drift of each
     tree        the Barnes-Hut tree code on Plummer spheres of 2^18 and 2^20
-                particles (eps=1/256, n_crit=16, groups of 64): wall time of
-                one force evaluation for theta = 0.75, 0.5, 0.4 (the call
-                includes the build), interaction pairs, and the acceleration
-                error against FP64 direct sums on 4096 sampled particles
+                particles (eps=1/256, n_crit=16, groups of 64), FP64 and
+                mixed force terms: wall time of one force evaluation for
+                theta = 0.75, 0.5, 0.4 (the call includes the build),
+                interaction pairs, and the acceleration error against FP64
+                direct sums on 4096 sampled particles
     bridge      the same bodies under the kick-drift-kick split: c = the
                 point masses and the stars near them (FP64 Hermite block
                 steps, eta=0.01), g = every other star (leapfrog with the
-                FP64 tree code at theta=0.5 -- the paper's hybrid -- or with
-                mixed-precision direct forces), cross field in mixed
+                mixed-precision tree code at theta=0.5 -- the paper's hybrid
+                -- or with mixed-precision direct forces), cross field in mixed
                 precision; bridge step 1/128; --steps bridge steps after one
                 warm-up step, each part timed
     """
@@ -231,29 +232,33 @@ def workloads(args):
         out["plummer65k_to_t_1_8"] = runs
         ctx.close()
     elif args.workload == "tree":
-        ctx = nb.Context(0, "fp64")
         res = {}
+        ctx = nb.Context(0, "fp64")
+        cmx = nb.Context(0, "mixed")
         for n in (262144, 1048576):
             p = synth.plummer(n, 3)
             P, V, M = t(p.pos), t(p.vel), t(p.mass)
             sample = torch.from_numpy(np.linspace(0, n - 1, 4096).astype(np.int32)).to(dev)
             a_ref, _, _ = ctx.forces(P, V, M, sample, 2.0 ** -16)
             a_ref = a_ref.cpu().numpy()
-            for theta in (0.75, 0.5, 0.4):
-                acc, pot, st = ctx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)   # warm-up
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                for _ in range(args.steps):
-                    acc, pot, st = ctx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)
-                torch.cuda.synchronize()
-                wall = (time.perf_counter() - t0) / args.steps
-                a = acc[sample].cpu().numpy()
-                rel = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
-                res[f"N{n}_theta{theta}"] = dict(ms=round(1e3 * wall, 2), particles_per_s=round(n / wall, 0),
-                                                 acc_rel_err_rms=float(np.sqrt(np.mean(rel ** 2))),
-                                                 acc_rel_err_max=float(rel.max()), **st)
+            for prec, cx in (("fp64", ctx), ("mixed", cmx)):
+                for theta in (0.75, 0.5, 0.4):
+                    acc, pot, st = cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)   # warm-up
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(args.steps):
+                        acc, pot, st = cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)
+                    torch.cuda.synchronize()
+                    wall = (time.perf_counter() - t0) / args.steps
+                    a = acc[sample].cpu().numpy()
+                    rel = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+                    res[f"N{n}_theta{theta}_{prec}"] = dict(ms=round(1e3 * wall, 2),
+                                                            particles_per_s=round(n / wall, 0),
+                                                            acc_rel_err_rms=float(np.sqrt(np.mean(rel ** 2))),
+                                                            acc_rel_err_max=float(rel.max()), **st)
         out.update(res)
         ctx.close()
+        cmx.close()
     elif args.workload == "bridge":
         from paper_1409_5474_amd.bridge import Bridge
         m = synth.hernquist_merger()
@@ -265,8 +270,8 @@ def workloads(args):
         out.update(n_g=ng, n_c=nc, bridge_dt=dt, bridge_steps=args.steps)
         for field in ("tree", "direct"):
             c64, cmx = nb.Context(0, "fp64"), nb.Context(0, "mixed")
-            # the tree code runs in FP64 on its context; the direct field and the cross field in mixed precision
-            br = Bridge(c64, c64 if field == "tree" else cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]),
+            # the field (tree or direct sum) and the cross field in mixed precision, the cluster in FP64
+            br = Bridge(c64, cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]),
                         t(m.vel[c]), t(m.mass[c]), m.eps2, m.eps2, m.eps2, dt, n_sub=1, eta=0.01, max_level=30,
                         ctx_x=cmx, field=field, theta=0.5)
             E0 = br.energy()

@@ -41,7 +41,9 @@
  *    and a few bytes of device scratch.  If the environment variable
  *    NB_MAX_WORKSPACE_BYTES holds a decimal byte count, a call whose j-split
  *    (or scalar-path mirror) workspace would exceed it fails with NB_ENOMEM
- *    before anything is launched, leaving every output untouched.
+ *    before anything is launched, leaving every output untouched.  The tree
+ *    code keeps its own buffers (about 200 bytes per particle plus its
+ *    interaction lists), which the cap does not cover.
  */
 #ifndef NBODY_H
 #define NBODY_H
@@ -267,6 +269,9 @@ int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_ma
  *    (5/2)(y.Qy) y s^-7/2 and phi = -M s^-1/2 - (1/2)(y.Qy) s^-5/2 with
  *    y = x - X, s = |y|^2 + eps2; an opened leaf's particles j != i the
  *    softened pair terms (a pair at zero distance with eps2 = 0 is dropped).
+ * Keys, tree, moments, groups and walk are double precision; the force terms
+ * are double for an NB_PREC_FP64 context and otherwise float terms from
+ * double separations, summed in double per chunk of 64 cells and per leaf.
  * theta = 0 opens every leaf: the direct sum.  pos [N][3], mass [N] in,
  * acc [N][3], pot [N] out, all in the caller's order (device pointers).
  * stats (host array of 5, may be NULL): cells, groups, accepted (group, cell)

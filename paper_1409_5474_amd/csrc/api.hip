@@ -598,8 +598,8 @@ int nb_tree_forces(nb_ctx* c, const double* pos, const double* mass, int64_t N, 
   if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "the tree code reads counts on the host: no stream capture%s");
   const char* msg = "";
   nb::TreeStats st{};
-  hipError_t e = nb::tree_forces_run(c->tree, c->stream, pos, mass, (int32_t)N, eps2, theta, n_crit, g_frac, acc,
-                                     pot, &st, &msg);
+  hipError_t e = nb::tree_forces_run(c->tree, c->stream, pos, mass, (int32_t)N, eps2, theta, n_crit, g_frac,
+                                     c->prec != NB_PREC_FP64, acc, pot, &st, &msg);
   if (e == hipErrorInvalidValue) return fail(c, NB_ENOMEM, "%s", msg);
   if (e != hipSuccess) return hip_fail(c, e, msg);
   if (stats) {

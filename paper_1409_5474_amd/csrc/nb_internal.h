@@ -165,8 +165,8 @@ struct TreeScratch {
   void* host = nullptr;    // pinned, for the per-level counts
 };
 hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
-                           double eps2, double theta, int n_crit, double g_frac, double* acc, double* pot,
-                           TreeStats* stats, const char** msg);
+                           double eps2, double theta, int n_crit, double g_frac, bool mixed, double* acc,
+                           double* pot, TreeStats* stats, const char** msg);
 void tree_scratch_free(TreeScratch& s);
 
 // Sixth-order force kernel (forces6.hip).

@@ -29,7 +29,9 @@
 // count per level to size the next launch.  The force kernel runs one
 // wavefront per group: its 64 lanes are the group's particles, accepted
 // cells are staged 64 at a time in LDS and opened leaves are read with
-// wave-uniform loads.  Everything is double precision.  The opening test and
+// wave-uniform loads.  The build and the walk are double precision; the force
+// kernel is double or mixed (float terms from double separations, summed in
+// double per chunk) with the context's precision.  The opening test and
 // the cube geometry are computed without fused multiply-adds, in the order
 // stated above, so they match any implementation that rounds each operation.
 #include <hipcub/hipcub.hpp>
@@ -563,6 +565,103 @@ __global__ __launch_bounds__(kGS) void k_tree_forces(const int32_t* __restrict__
   }
 }
 
+// Mixed precision: the separation from a cell's centre of mass or from a
+// particle is formed in double and rounded to float, the rest of the term
+// is float; the float sums of one LDS chunk of cells, or of one leaf, are
+// added into double accumulators.  The walk, and so the interaction set, is
+// the double one.
+struct CellLiteF {
+  double X[3];
+  float M, Q[6], pad;
+};
+
+__global__ __launch_bounds__(kGS) void k_tree_forces_mixed(const int32_t* __restrict__ gb,
+                                                           const int32_t* __restrict__ ge, int32_t ngroups,
+                                                           const TreeCell* __restrict__ cells,
+                                                           const int32_t* __restrict__ ag,
+                                                           const int32_t* __restrict__ ac, int64_t na,
+                                                           const int32_t* __restrict__ lg,
+                                                           const int32_t* __restrict__ lc, int64_t nl,
+                                                           const double* __restrict__ pos_s,
+                                                           const double* __restrict__ mass_s, double eps2,
+                                                           const int32_t* __restrict__ idx_s,
+                                                           double* __restrict__ acc, double* __restrict__ pot) {
+  __shared__ CellLiteF tile[kGS];
+  const int32_t g = blockIdx.x;
+  if (g >= ngroups) return;
+  const int lane = threadIdx.x;
+  const int32_t b = gb[g], e = ge[g];
+  const int32_t i = b + lane;
+  const bool valid = i < e;
+  const int32_t ir = valid ? i : b;
+  const double x0 = pos_s[3 * ir], x1 = pos_s[3 * ir + 1], x2 = pos_s[3 * ir + 2];
+  const float e2 = (float)eps2;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, ph = 0.0;
+
+  const int64_t ab = lower_bound_group(ag, na, g), ae = lower_bound_group(ag, na, g + 1);
+  for (int64_t base = ab; base < ae; base += kGS) {
+    const int64_t k = base + lane;
+    if (k < ae) {
+      const TreeCell& c = cells[ac[k]];
+      CellLiteF cl;
+      cl.M = (float)c.M;
+      for (int q = 0; q < 3; ++q) cl.X[q] = c.X[q];
+      for (int q = 0; q < 6; ++q) cl.Q[q] = (float)c.Q[q];
+      cl.pad = 0.0f;
+      tile[lane] = cl;
+    }
+    __syncthreads();
+    const int cnt = (int)(ae - base < kGS ? ae - base : kGS);
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
+    for (int t = 0; t < cnt; ++t) {
+      const CellLiteF& c = tile[t];
+      const float y0 = (float)(x0 - c.X[0]), y1 = (float)(x1 - c.X[1]), y2 = (float)(x2 - c.X[2]);
+      const float s = y0 * y0 + y1 * y1 + y2 * y2 + e2;
+      const float q = __builtin_amdgcn_rsqf(s);
+      const float q2 = q * q;
+      const float q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+      const float Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
+      const float Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
+      const float Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
+      const float yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
+      const float f = -c.M * q3 - 2.5f * yQy * q7;
+      f0 += f * y0 + Qy0 * q5;
+      f1 += f * y1 + Qy1 * q5;
+      f2 += f * y2 + Qy2 * q5;
+      fp += -c.M * q - 0.5f * yQy * q5;
+    }
+    a0 += (double)f0; a1 += (double)f1; a2 += (double)f2; ph += (double)fp;
+    __syncthreads();
+  }
+
+  const int64_t lb = lower_bound_group(lg, nl, g), le = lower_bound_group(lg, nl, g + 1);
+  for (int64_t k = lb; k < le; ++k) {
+    const TreeCell& c = cells[lc[k]];
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
+    for (int32_t j = c.begin; j < c.end; ++j) {
+      const float r0 = (float)(pos_s[3 * j] - x0), r1 = (float)(pos_s[3 * j + 1] - x1),
+                  r2 = (float)(pos_s[3 * j + 2] - x2);
+      const float s = r0 * r0 + r1 * r1 + r2 * r2 + e2;
+      const bool keep = j != i && s > 0.0f;
+      const float q = keep ? __builtin_amdgcn_rsqf(s) : 0.0f;
+      const float mq = (float)mass_s[j] * q;
+      const float mq3 = mq * q * q;
+      f0 += mq3 * r0;
+      f1 += mq3 * r1;
+      f2 += mq3 * r2;
+      fp -= mq;
+    }
+    a0 += (double)f0; a1 += (double)f1; a2 += (double)f2; ph += (double)fp;
+  }
+  if (valid) {
+    const int32_t o = idx_s[i];
+    acc[3 * o] = a0;
+    acc[3 * o + 1] = a1;
+    acc[3 * o + 2] = a2;
+    pot[o] = ph;
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -660,8 +759,8 @@ hipError_t read_total(TreeScratch& s, hipStream_t st, const T* off, const T* cnt
   } while (0)
 
 hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
-                           double eps2, double theta, int n_crit, double g_frac, double* acc, double* pot,
-                           TreeStats* stats, const char** msg) {
+                           double eps2, double theta, int n_crit, double g_frac, bool mixed, double* acc,
+                           double* pot, TreeStats* stats, const char** msg) {
   *msg = "";
   if (!s.host) NB_TRY(hipHostMalloc(&s.host, 64 * sizeof(int64_t), hipHostMallocDefault));
   Alloc al{s, st};
@@ -869,8 +968,12 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   if (na > 0) NB_TRY(sort_pairs(al, ag, ag2, acl, ac2, na, end_bit));
   if (nl > 0) NB_TRY(sort_pairs(al, lg, lg2, lcl, lc2, nl, end_bit));
 
-  hipLaunchKernelGGL(k_tree_forces, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na, lg2, lc2,
-                     nl, pos_s, mass_s, eps2, idx_s, acc, pot);
+  if (mixed)
+    hipLaunchKernelGGL(k_tree_forces_mixed, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na,
+                       lg2, lc2, nl, pos_s, mass_s, eps2, idx_s, acc, pot);
+  else
+    hipLaunchKernelGGL(k_tree_forces, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na, lg2,
+                       lc2, nl, pos_s, mass_s, eps2, idx_s, acc, pot);
   NB_TRY(hipGetLastError());
   if (stats) {
     stats->cells = ncells;

@@ -2,7 +2,8 @@
 identical interaction sets (accepted cells and opened leaves per group) and
 forces within rounding of the oracle's, theta = 0 reproducing the direct
 sum, edge cases (one particle, coincident particles, two distant clusters,
-unsoftened), repeatability and argument errors."""
+unsoftened), repeatability, argument errors, and the mixed-precision force
+terms within float rounding of the oracle."""
 import numpy as np
 import pytest
 
@@ -141,3 +142,23 @@ def test_argument_errors(ctx):
     with pytest.raises(nb.NbodyError):
         ctx.tree_forces(T(p.pos), T(p.mass), 1e-3, 0.5, n_crit=0)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("theta", [0.3, 0.6])
+def test_mixed_precision_tree_forces(theta):
+    # Same walk (the double one), float terms: the interaction set is the
+    # oracle's and the forces are within float rounding of its.
+    import paper_1409_5474_amd as nb
+    from errors import vec_err
+    p = synth.plummer(4000, 15)
+    eps2 = 1e-4
+    cm = nb.Context(0, "mixed")
+    acc, pot, st = _gpu(cm, p.pos, p.mass, eps2, theta)
+    cm.close()
+    ra, rp, rst, t = _oracle(p.pos, p.mass, eps2, theta)
+    assert st["accepted"] == sum(c for c, _, _ in rst)
+    assert st["opened_leaves"] == sum(l for _, l, _ in rst)
+    ea = vec_err(acc, ra, np.linalg.norm(ra, axis=1))
+    ep = vec_err(pot, rp, np.abs(rp))
+    assert ea["rms"] < 1e-6 and ea["normwise"] < 1e-6, ea
+    assert ep["rms"] < 1e-6, ep
