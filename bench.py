@@ -314,7 +314,7 @@ def main():
     if args.workload:
         return workloads(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the library runs on one GPU; multi-GPU runs are not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import numpy as np

@@ -61,7 +61,7 @@ enum nb_status {
     NB_EINVAL = -1,    /* bad argument (size, null pointer, range, NaN eps2 ...) */
     NB_ENOMEM = -2,    /* device allocation failed or over NB_MAX_WORKSPACE_BYTES */
     NB_EDEVICE = -3,   /* HIP runtime error (launch, stream, device) */
-    NB_ENOTSUP = -6    /* combination not supported by this build */
+    NB_ENOTSUP = -6    /* combination the library does not provide */
 };
 
 enum nb_precision {

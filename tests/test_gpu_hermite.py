@@ -141,7 +141,7 @@ def test_energy(ctx):
     np.testing.assert_allclose(o[5:8], e["L"], atol=1e-14)
 
 
-class GpuRun:
+class DeviceRun:
     """Block-step integration on the GPU through nb_block_step."""
 
     def __init__(self, ctx, p, eps2, eta, dt_max, max_level):
@@ -180,7 +180,7 @@ def test_block_steps_match_cpu_hermite(ctx):
     n, eps2, eta, dt_max, ML = 1024, 1e-4, 0.02, 1.0 / 16, 30
     p = synth.plummer(n, 1)
     st = H.initialise(p.pos, p.vel, p.mass, eps2, eta, dt_max, ML, _cpu_forces(eps2))
-    g = GpuRun(ctx, p, eps2, eta, dt_max, ML)
+    g = DeviceRun(ctx, p, eps2, eta, dt_max, ML)
     assert np.array_equal(N(g.lev), st.level)
     end = int(round(0.125 / st.tick))
     hist_gpu = []
@@ -207,8 +207,8 @@ def test_block_step_graph_replay_matches_eager(ctx):
     import torch
     n, eps2, eta, dt_max, ML = 2000, 1e-4, 0.02, 1.0 / 16, 30
     p = synth.plummer(n, 8)
-    eager = GpuRun(ctx, p, eps2, eta, dt_max, ML)
-    graph_run = GpuRun(ctx, p, eps2, eta, dt_max, ML)
+    eager = DeviceRun(ctx, p, eps2, eta, dt_max, ML)
+    graph_run = DeviceRun(ctx, p, eps2, eta, dt_max, ML)
     s = torch.cuda.Stream()
     ctx.set_stream(s)
     with torch.cuda.stream(s):
