@@ -307,6 +307,16 @@ int nb_kick_drift(nb_ctx *ctx, double *pos, double *vel, const double *acc, int6
  * has time t_tick[i] and level dt_level[i] (its step is dt_max 2^-level,
  * i.e. 2^(max_level - level) ticks).  max_level must be in [0, 62]. */
 
+/* Stop tick in device memory: while t_stop_dev is set (non-NULL), every
+ * block-step call on this context (nb_block_step, nb_block_step_batch,
+ * nb_block_step6) reads its stop tick from *t_stop_dev when its scheduler
+ * runs, instead of its t_stop_tick argument, so one captured graph of block
+ * steps replays for any stop time the caller writes there.  NULL restores
+ * the argument.  The pointer is recorded by each launch (a graph keeps the
+ * pointer it was captured with); nb_schedule has no stop tick and ignores
+ * it. */
+int nb_set_stop_source(nb_ctx *ctx, const int64_t *t_stop_dev);
+
 /* Predict every particle to t_next: d = (t_next_tick - t_tick[i]) dt_min,
  * pos_p = pos + vel d + acc d^2/2 + jerk d^3/6, vel_p = vel + acc d + jerk d^2/2.
  * Inputs [N][3] and t_tick [N]; outputs [N][3] (may not alias the inputs). */

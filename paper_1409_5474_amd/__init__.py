@@ -60,6 +60,7 @@ _sig("nb_set_launch", _vp, _int, _int, _int)
 _sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int)
 _sig("nb_tune_clear", _vp)
+_sig("nb_set_stop_source", _vp, _vp)
 _sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
      ctypes.POINTER(_dbl))
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
@@ -183,6 +184,13 @@ class Context:
 
     def tune_clear(self):
         self._chk(_lib.nb_tune_clear(self._h))
+
+    def set_stop_source(self, stop=None):
+        """Block steps read their stop tick from ``stop`` (a one-element int64
+        device tensor) while it is set; None restores the argument."""
+        if stop is not None:
+            _check_1d(stop, 1, "stop", torch.int64, self.device)
+        self._chk(_lib.nb_set_stop_source(self._h, _p(stop)))
 
     # ---- forces -------------------------------------------------------------
     def forces(self, pos, vel, mass, active, eps2, acc=None, jerk=None, pot=None):

@@ -91,7 +91,7 @@ class Bridge:
         self.ctx_x.kick(self.cluster.vel, self.a_cg, h)
         self.ctx_x.kick(self.vg, self.a_gc, h)
 
-    def drift_cluster(self, use_graph=False):
+    def drift_cluster(self, use_graph=True):
         c = self.cluster
         before = c.steps
         c.restart()
@@ -105,7 +105,7 @@ class Bridge:
             self._galaxy_forces()
             self.ctx_g.kick(self.vg, self.ag, 0.5 * h)
 
-    def step(self, use_graph=False):
+    def step(self, use_graph=True):
         """One bridge step: half kick, both drifts, half kick."""
         self.kick(0.5 * self.dt)
         self.drift_cluster(use_graph)
@@ -115,7 +115,7 @@ class Bridge:
         self.steps += 1
         return self
 
-    def run(self, n_steps, use_graph=False):
+    def run(self, n_steps, use_graph=True):
         for _ in range(n_steps):
             self.step(use_graph)
         return self

@@ -342,6 +342,12 @@ int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_
   return NB_OK;
 }
 
+int nb_set_stop_source(nb_ctx* c, const int64_t* t_stop_dev) {
+  if (!c) return NB_EINVAL;
+  c->stop_dev = t_stop_dev;
+  return NB_OK;
+}
+
 int nb_tune_clear(nb_ctx* c) {
   if (!c) return NB_EINVAL;
   c->table.clear();
@@ -573,7 +579,7 @@ int nb_block_step6(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max,
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, t_stop_tick, c->stream);
+                                     c->nact32, t_stop_tick, c->stop_dev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_predict6(pos, vel, acc, jerk, snap, crackle, t_tick, 0, sched, dt_min, N, pos_p, vel_p, acc_p,
                           c->stream);
@@ -675,7 +681,7 @@ int nb_schedule(nb_ctx* c, const int64_t* t_tick, const int32_t* dt_level, int64
   int rc = ensure_sched(c, N);
   if (rc) return rc;
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, INT64_MAX, c->stream);
+                                     c->nact32, INT64_MAX, nullptr, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "schedule launch");
 }
 
@@ -695,7 +701,7 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, t_stop_tick, c->stream);
+                                     c->nact32, t_stop_tick, c->stop_dev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "predict launch");
@@ -914,7 +920,7 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   int* d_nit = reinterpret_cast<int*>(b + o_nit);
   const double dt_min = std::ldexp(dt_max, -max_level);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, t_stop_tick, c->stream);
+                                     c->nact32, t_stop_tick, c->stop_dev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "predict launch");

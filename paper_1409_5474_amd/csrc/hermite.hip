@@ -198,7 +198,8 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
                                                     const int32_t* __restrict__ block_cnt, int nblk,
                                                     const int64_t* sched_in,
                                                     int32_t* __restrict__ active, int64_t* sched,
-                                                    int32_t* __restrict__ n_active32, int64_t t_stop) {
+                                                    int32_t* __restrict__ n_active32, int64_t t_stop_host,
+                                                    const int64_t* __restrict__ t_stop_dev) {
   __shared__ int sc[kB];
   __shared__ int64_t off_s;
   const int64_t t_next = sched_in[0];
@@ -233,6 +234,7 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
   }
   if (blockIdx.x == (unsigned)(nblk - 1) && threadIdx.x == 0) {
     // past the stop time the step is empty: every later kernel does nothing
+    const int64_t t_stop = t_stop_dev ? *t_stop_dev : t_stop_host;
     const int64_t cnt = t_next <= t_stop ? off : 0;
     sched[1] = cnt;
     if (n_active32) *n_active32 = (int32_t)cnt;
@@ -337,13 +339,13 @@ int schedule_blocks(int64_t n) { return (int)((n + kSchedBlock - 1) / kSchedBloc
 
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level, int32_t* active,
                            int64_t* sched, int64_t* block_min, int32_t* block_cnt, int32_t* n_active32,
-                           int64_t t_stop, hipStream_t st) {
+                           int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st) {
   const int nblk = schedule_blocks(n);
   hipLaunchKernelGGL(k_sched_min, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min);
   hipLaunchKernelGGL(k_sched_count, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min, nblk,
                      block_cnt, sched);
   hipLaunchKernelGGL(k_sched_write, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_cnt, nblk,
-                     sched, active, sched, n_active32, t_stop);
+                     sched, active, sched, n_active32, t_stop, t_stop_dev);
   return hipGetLastError();
 }
 

@@ -138,7 +138,7 @@ hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, doub
                           int max_level, int32_t* level, hipStream_t st);
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level,
                            int32_t* active, int64_t* sched, int64_t* block_min, int32_t* block_cnt,
-                           int32_t* n_active32, int64_t t_stop, hipStream_t st);
+                           int32_t* n_active32, int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st);
 int schedule_blocks(int64_t n);
 hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
                          int64_t n, double* part, double* out, hipStream_t st);
@@ -225,6 +225,7 @@ struct nb_ctx {
   std::vector<int64_t> bp_off;    // host copy of the uploaded offsets
   std::vector<double> bp_eps2;    // host copy of the uploaded softenings
   nb::TreeScratch tree;           // buffers of the tree code
+  const int64_t* stop_dev = nullptr;  // block steps read their stop tick here when set
   void* bp_buf = nullptr;         // offsets, eps2, sys, nchunk, items, n_items
   size_t bp_cap = 0;
   int bp_max_items = 0;

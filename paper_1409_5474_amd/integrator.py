@@ -5,7 +5,8 @@ ABI's ``nb_block_step`` (schedule -> predict -> forces -> correct, no host
 synchronisation).  ``run_until`` captures ``graph_steps`` consecutive block
 steps into one HIP graph and replays it; a step beyond the stop time is
 empty, so the host reads the schedule once per replay to decide whether to
-go on.
+go on.  The stop time lives in device memory (``nb_set_stop_source``), so one
+captured graph serves every later stop time.
 
 Time is kept in integer ticks of dt_max 2^-max_level (see nbody.h).
 """
@@ -54,6 +55,7 @@ class BlockIntegrator:
     def _alloc_scratch(self):
         n, dev = self.n, self.dev
         f64 = dict(dtype=torch.float64, device=dev)
+        self.stop = torch.full((1,), INT64_MAX, dtype=torch.int64, device=dev)
         self.pos_p = torch.empty((n, 3), **f64)
         self.vel_p = torch.empty((n, 3), **f64)
         self.acc1 = torch.empty((n, 3), **f64)
@@ -71,8 +73,16 @@ class BlockIntegrator:
             self.ctx.forces(pos, vel, self.mass, self.all_idx, self.eps2, acc, jerk, pot)
 
     # ---- stepping ---------------------------------------------------------
-    def step(self, t_stop_tick=INT64_MAX):
-        """One block step, launched eagerly on the context stream."""
+    def step(self, t_stop_tick=None):
+        """One block step on the context stream.  Without ``t_stop_tick`` the
+        step stops at the tick held in ``self.stop`` (device memory)."""
+        self.ctx.set_stop_source(self.stop if t_stop_tick is None else None)
+        try:
+            self._step(INT64_MAX if t_stop_tick is None else t_stop_tick)
+        finally:
+            self.ctx.set_stop_source(None)
+
+    def _step(self, t_stop_tick):
         if self.batch:
             self.ctx.block_step_batch(self.offsets, self.eps2_sys, self.eta, self.dt_max, self.max_level, self.mass,
                                       self.pos, self.vel, self.acc, self.jerk, self.t_tick, self.level, self.pos_p,
@@ -83,9 +93,8 @@ class BlockIntegrator:
                                 self.vel, self.acc, self.jerk, self.t_tick, self.level, self.pos_p, self.vel_p,
                                 self.active, self.acc1, self.jerk1, self.pot1, self.sched, t_stop_tick)
 
-    def _graph(self, steps, t_stop_tick):
-        key = (steps, t_stop_tick)
-        g = self._graphs.get(key)
+    def _graph(self, steps):
+        g = self._graphs.get(steps)
         if g is None:
             stream = torch.cuda.Stream(self.dev)
             self.ctx.set_stream(stream)
@@ -93,10 +102,10 @@ class BlockIntegrator:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=stream):
                     for _ in range(steps):
-                        self.step(t_stop_tick)
+                        self.step()
             finally:
                 self.ctx.set_stream(None)
-            self._graphs[key] = g
+            self._graphs[steps] = g
         return g
 
     def run_until(self, t_end, graph_steps=32, use_graph=True):
@@ -118,17 +127,18 @@ class BlockIntegrator:
         end = int(end)
         if end % (1 << self.max_level):
             raise ValueError("t_end must be a multiple of dt_max (a synchronisation time)")
+        self.stop.fill_(end)
         # one eager step sizes every workspace before a graph is captured
-        self.step(end)
+        self.step()
         while int(self.t_tick.min().item()) < end:
             if use_graph:
-                g = self._graph(graph_steps, end)
+                g = self._graph(graph_steps)
                 torch.cuda.synchronize(self.dev)
                 g.replay()
                 torch.cuda.synchronize(self.dev)
             else:
                 for _ in range(graph_steps):
-                    self.step(end)
+                    self.step()
         return self
 
     # ---- checkpoint / resume ----------------------------------------------
@@ -241,7 +251,7 @@ class BlockIntegrator6(BlockIntegrator):
         self.crackle.zero_()
         self.ctx.startup6(self.acc, self.jerk, self.snap, self.eta_s, self.dt_max, self.max_level, self.level)
 
-    def step(self, t_stop_tick=INT64_MAX):
+    def _step(self, t_stop_tick):
         self.ctx.block_step6(self.n, self.eps2, self.eta, self.dt_max, self.max_level, self.mass, self.pos, self.vel,
                              self.acc, self.jerk, self.snap, self.crackle, self.t_tick, self.level, self.pos_p,
                              self.vel_p, self.acc_p, self.active, self.acc1, self.jerk1, self.snap1, self.pot1,

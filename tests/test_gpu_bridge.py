@@ -236,3 +236,19 @@ def test_bridge_with_the_tree_as_field_solver_follows_the_oracle():
         d = np.abs(got.cpu().numpy() - ref).max()
         assert d <= 1e-11 * np.abs(ref).max(), d
     ctx.close()
+
+
+def test_bridge_graph_replay_equals_eager():
+    import torch
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.bridge import Bridge
+    p, mass, g, c = _cluster_in_galaxy(n=800, n_c=40, seed=41)
+    ctx = nb.Context(0, "fp64")
+    args = (T(p.pos[g]), T(p.vel[g]), T(mass[g]), T(p.pos[c]), T(p.vel[c]), T(mass[c]), 1e-3, 1e-4, 5e-4, 1.0 / 64)
+    a = Bridge(ctx, ctx, *args).run(4, use_graph=True)
+    b = Bridge(ctx, ctx, *args).run(4, use_graph=False)
+    torch.cuda.synchronize()
+    assert len(a.cluster._graphs) == 1
+    for x, y in ((a.xg, b.xg), (a.vg, b.vg), (a.cluster.pos, b.cluster.pos), (a.cluster.vel, b.cluster.vel)):
+        assert torch.equal(x, y)
+    ctx.close()

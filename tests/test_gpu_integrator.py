@@ -96,3 +96,22 @@ def test_checkpoint_resume_is_bitwise(ctx, tmp_path, batch):
     for k in ("pos", "vel", "acc", "jerk", "t_tick", "level"):
         assert torch.equal(getattr(straight, k), getattr(resumed, k)), k
     assert straight.steps == resumed.steps
+
+
+def test_one_graph_serves_every_stop_time(ctx):
+    # The stop tick lives in device memory: the graph captured for the first
+    # stop time replays unchanged for the next ones, and matches eager steps.
+    import torch
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    p = synth.plummer(1200, 21)
+    args = (T(p.pos), T(p.vel), T(p.mass), 1e-4, 0.02, 1.0 / 16, 30)
+    g = BlockIntegrator(ctx, *args)
+    e = BlockIntegrator(ctx, *args)
+    for t_end in (0.0625, 0.125, 0.1875):
+        g.run_until(t_end, graph_steps=8, use_graph=True)
+        e.run_until(t_end, graph_steps=8, use_graph=False)
+        assert int(g.t_tick.min().item()) * g.tick == t_end
+    assert len(g._graphs) == 1
+    for k in ("pos", "vel", "acc", "jerk", "t_tick", "level"):
+        assert torch.equal(getattr(g, k), getattr(e, k)), k
+    assert g.steps == e.steps
