@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--prec", default="mixed", choices=["mixed", "mixed_ds", "fp64"])
     ap.add_argument("--force-only", action="store_true",
                     help="profiling target: only the all-active force launch, --steps times")
+    ap.add_argument("--kernel", default="direct", choices=["direct", "snap", "tree"],
+                    help="with --force-only: the direct force kernel, the sixth-order snap kernel (FP64) or the tree "
+                         "code (theta=0.5; FP64 or mixed force terms with --prec)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
                          "(calibrates the HBM byte counters)")
@@ -340,10 +343,21 @@ def main():
         act = torch.arange(args.n, dtype=torch.int32, device=dev)
         acc = torch.empty((args.n, 3), dtype=torch.float64, device=dev)
         jerk, pot = torch.empty_like(acc), torch.empty(args.n, dtype=torch.float64, device=dev)
-        for _ in range(args.warmup + args.steps):
+        if args.kernel == "snap":
+            snap = torch.empty_like(acc)
             ctx.forces(P, V, M, act, 2.0 ** -16, acc, jerk, pot)
+            A = acc.clone()
+            for _ in range(args.warmup + args.steps):
+                ctx.forces6(P, V, A, M, act, 2.0 ** -16, acc, jerk, snap, pot)
+        elif args.kernel == "tree":
+            for _ in range(args.warmup + args.steps):
+                ctx.tree_forces(P, M, 2.0 ** -16, 0.5, 16, 1.0 / 16, acc, pot)
+        else:
+            for _ in range(args.warmup + args.steps):
+                ctx.forces(P, V, M, act, 2.0 ** -16, acc, jerk, pot)
         torch.cuda.synchronize()
-        print(json.dumps({"force_only": args.prec, "n": args.n, "launches": args.warmup + args.steps,
+        print(json.dumps({"force_only": args.prec, "kernel": args.kernel, "n": args.n,
+                          "launches": args.warmup + args.steps,
                           "launch_KLS": ctx.get_launch(args.n, args.n)}), flush=True)
         return
     n = args.n

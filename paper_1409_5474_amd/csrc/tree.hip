@@ -469,6 +469,17 @@ __device__ __forceinline__ double rsqrt_tree(double s) {
   return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
+// the three list lengths of a walk level (last exclusive sum + last count)
+__global__ void k_walk_totals(const int64_t* __restrict__ oa, const int64_t* __restrict__ ca,
+                              const int64_t* __restrict__ ol, const int64_t* __restrict__ cl,
+                              const int64_t* __restrict__ of, const int64_t* __restrict__ cf, int64_t n,
+                              int64_t* __restrict__ out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  out[0] = oa[n - 1] + ca[n - 1];
+  out[1] = ol[n - 1] + cl[n - 1];
+  out[2] = of[n - 1] + cf[n - 1];
+}
+
 // first index in [0, n) whose group is >= g (lists are sorted by group)
 __device__ __forceinline__ int64_t lower_bound_group(const int32_t* a, int64_t n, int32_t g) {
   int64_t lo = 0, hi = n;
@@ -709,7 +720,7 @@ struct Alloc {
 enum Slot {
   S_BOXPART, S_BOX, S_KEYS, S_KEYS2, S_IDX, S_IDX2, S_POS, S_MASS, S_IJK, S_CELLS, S_CNT, S_OFF, S_TMP,
   S_GB, S_GE, S_GB2, S_GE2, S_GN, S_GBOX, S_FG, S_FC, S_FG2, S_FC2, S_CA, S_CL, S_CF, S_OA, S_OL, S_OF,
-  S_AG, S_AC, S_LG, S_LC, S_AG2, S_AC2, S_LG2, S_LC2
+  S_AG, S_AC, S_LG, S_LC, S_AG2, S_AC2, S_LG2, S_LC2, S_TOT
 };
 
 template <class T>
@@ -856,25 +867,20 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
     std::swap(ge, ge2);
     NB_TRY(hipMemcpyAsync(gn, gn + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
   }
-  int32_t ngroups = 0;
+  int32_t ngroups = 0, root_nchild = 0;
   {
     int32_t* h = static_cast<int32_t*>(s.host);
     NB_TRY(hipMemcpyAsync(h, gn, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    NB_TRY(hipMemcpyAsync(h + 1, &cells[0].nchild, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     NB_TRY(hipStreamSynchronize(st));
     ngroups = h[0];
+    root_nchild = h[1];
   }
   double* gbox = al.get<double>(S_GBOX, 6 * (int64_t)ngroups);
   NB_TRY(need(gbox));
   hipLaunchKernelGGL(k_group_box, dim3(blocks_for(ngroups)), dim3(kTB), 0, st, gb, ge, ngroups, pos_s, gbox);
 
   // walk, level-synchronous over (group, cell) pairs
-  int32_t root_nchild = 0;
-  {
-    int32_t* h = static_cast<int32_t*>(s.host);
-    NB_TRY(hipMemcpyAsync(h, &cells[0].nchild, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    NB_TRY(hipStreamSynchronize(st));
-    root_nchild = h[0];
-  }
   int64_t nf = (int64_t)ngroups * (root_nchild > 0 ? root_nchild : 1);
   int32_t* fg = al.get<int32_t>(S_FG, nf);
   int32_t* fc = al.get<int32_t>(S_FC, nf);
@@ -899,9 +905,17 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
     NB_TRY(exclusive_sum(al, cl, ol, nf));
     NB_TRY(exclusive_sum(al, cf, of, nf));
     int64_t ta = 0, tl = 0, tf = 0;
-    NB_TRY(read_total(s, st, oa, ca, nf, &ta));
-    NB_TRY(read_total(s, st, ol, cl, nf, &tl));
-    NB_TRY(read_total(s, st, of, cf, nf, &tf));
+    {
+      int64_t* tot = al.get<int64_t>(S_TOT, 3);
+      NB_TRY(need(tot));
+      hipLaunchKernelGGL(k_walk_totals, dim3(1), dim3(64), 0, st, oa, ca, ol, cl, of, cf, nf, tot);
+      int64_t* h = static_cast<int64_t*>(s.host);
+      NB_TRY(hipMemcpyAsync(h, tot, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+      NB_TRY(hipStreamSynchronize(st));
+      ta = h[0];
+      tl = h[1];
+      tf = h[2];
+    }
     if (na + ta > ((int64_t)1 << 31) - 1 || nl + tl > ((int64_t)1 << 31) - 1 || tf > ((int64_t)1 << 31) - 1) {
       *msg = "interaction lists exceed 2^31 entries (raise theta or n_crit)";
       return hipErrorInvalidValue;
