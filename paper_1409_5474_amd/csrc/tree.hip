@@ -22,21 +22,23 @@
 //    phi = -M s^-1/2 - (y.Qy)/2 s^-5/2 with y = x - X, s = |y|^2 + eps2,
 //    Q = sum m (3 d d^T - |d|^2 I) about the centre of mass X
 //
-// Structure on the chip: the build and the walk are level-synchronous and
-// data-parallel -- one thread per cell or per (group, cell) pair, with
-// stable scans (hipCUB) placing the outputs, so every list keeps curve
-// order and the results are reproducible run to run; the host reads one
-// count per level to size the next launch.  The force kernel runs one
-// wavefront per group: its 64 lanes are the group's particles, accepted
-// cells are staged 64 at a time in LDS and opened leaves are read with
-// wave-uniform loads.  The build and the walk are double precision; the force
-// kernel is double or mixed (float terms from double separations, summed in
-// double per chunk) with the context's precision.  The opening test and
-// the cube geometry are computed without fused multiply-adds, in the order
-// stated above, so they match any implementation that rounds each operation.
+// Structure on the chip: the build is level-synchronous and data-parallel
+// -- one thread per particle or per cell, with stable scans (hipCUB) placing
+// the outputs, so every array keeps curve order and the results are
+// reproducible run to run; the host reads one count per level to size the
+// next launch.  The walk and the force evaluation are one kernel, as in the
+// paper's GPU tree code: one wavefront per group walks the tree for its 64
+// particles and evaluates accepted cells and opened leaves 64 at a time from
+// LDS as it finds them, so no interaction list is written to memory.  The
+// build and the walk are double precision; the force terms are double or
+// mixed (float terms from double separations, summed in double per chunk)
+// with the context's precision.  The opening test and the cube geometry are
+// computed without fused multiply-adds, in the order stated above, so they
+// match any implementation that rounds each operation.
 #include <hipcub/hipcub.hpp>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "nb_internal.h"
@@ -405,7 +407,31 @@ __global__ __launch_bounds__(kTB) void k_group_box(const int32_t* __restrict__ g
   }
 }
 
-// --------------------------------------------------------------- walk -----
+// ------------------------------------------------- walk and forces -----
+// One kernel does the walk and the force evaluation, as the paper's GPU
+// tree code does: a wavefront takes a group (its lanes are the group's
+// particles), walks the tree for the whole group, and evaluates the accepted
+// cells and the particles of opened leaves as soon as 64 of them are
+// pending.  No interaction list goes to memory; the only memory beyond the
+// tree is a per-wavefront stack of cells still to be tested.
+//
+// Walk step: pop up to 64 cells from the top of the stack, one per lane;
+// each lane tests its cell and the wavefront appends accepted cells and
+// opened leaves to two LDS lists (ballot + rank) and pushes the children of
+// opened internal cells, in lane order, onto the stack (wave prefix sum).
+// Bound on the stack: the pushes keep it ordered by level from bottom to
+// top (lane order is stack order, children sit one level below their
+// parents, and what is left after a pop is no deeper than what was popped).
+// Level-l entries are pushed only by a pop that took level-(l-1) entries,
+// and such a pop took every entry of level >= l, which lie above them; so
+// the level-l entries on the stack always come from one push of at most
+// 8 x 64 entries, and the stack holds at most 8 x 64 x 21 entries (levels
+// 1 to 21).  It also never holds more entries than there are cells, since
+// a cell is pushed at most once per group.  The kernel still checks every
+// push against the capacity and reports an overflow instead of writing
+// past it.
+constexpr int kStackCap = 8 * kGS * kBits;
+
 __device__ __forceinline__ bool accepted(const TreeCell& c, const double* gbox, double theta) {
 #pragma clang fp contract(off)
   double d2 = 0.0;
@@ -419,48 +445,6 @@ __device__ __forceinline__ bool accepted(const TreeCell& c, const double* gbox, 
   return theta * theta * d2 > c.side * c.side;
 }
 
-// kind per pair: 0 accepted, 1 opened leaf, 2 opened internal cell
-__global__ __launch_bounds__(kTB) void k_walk_count(const int32_t* __restrict__ fg, const int32_t* __restrict__ fc,
-                                                    int64_t nf, const TreeCell* __restrict__ cells,
-                                                    const double* __restrict__ gbox, double theta,
-                                                    int64_t* __restrict__ ca, int64_t* __restrict__ cl,
-                                                    int64_t* __restrict__ cf) {
-  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < nf; i += (int64_t)gridDim.x * kTB) {
-    const TreeCell& c = cells[fc[i]];
-    const bool acc = fc[i] != 0 && accepted(c, gbox + 6 * fg[i], theta);
-    ca[i] = acc ? 1 : 0;
-    cl[i] = (!acc && c.nchild == 0) ? 1 : 0;
-    cf[i] = (!acc && c.nchild > 0) ? c.nchild : 0;
-  }
-}
-
-__global__ __launch_bounds__(kTB) void k_walk_write(const int32_t* __restrict__ fg, const int32_t* __restrict__ fc,
-                                                    int64_t nf, const TreeCell* __restrict__ cells,
-                                                    const int64_t* __restrict__ ca, const int64_t* __restrict__ cl,
-                                                    const int64_t* __restrict__ cf, const int64_t* __restrict__ oa,
-                                                    const int64_t* __restrict__ ol, const int64_t* __restrict__ of,
-                                                    int64_t base_a, int64_t base_l, int32_t* __restrict__ ag,
-                                                    int32_t* __restrict__ ac, int32_t* __restrict__ lg,
-                                                    int32_t* __restrict__ lc, int32_t* __restrict__ ng_,
-                                                    int32_t* __restrict__ nc_) {
-  for (int64_t i = (int64_t)blockIdx.x * kTB + threadIdx.x; i < nf; i += (int64_t)gridDim.x * kTB) {
-    const int32_t g = fg[i], ci = fc[i];
-    if (ca[i]) {
-      ag[base_a + oa[i]] = g;
-      ac[base_a + oa[i]] = ci;
-    } else if (cl[i]) {
-      lg[base_l + ol[i]] = g;
-      lc[base_l + ol[i]] = ci;
-    } else if (cf[i]) {
-      const TreeCell& c = cells[ci];
-      for (int32_t k = 0; k < c.nchild; ++k) {
-        ng_[of[i] + k] = g;
-        nc_[of[i] + k] = c.child0 + k;
-      }
-    }
-  }
-}
-
 // s^{-1/2}: v_rsq_f64 (about 2^-24 accurate) refined by one third-order
 // Newton step y (1 + e/2 + 3e^2/8), e = 1 - s y^2, to double rounding.
 __device__ __forceinline__ double rsqrt_tree(double s) {
@@ -469,163 +453,76 @@ __device__ __forceinline__ double rsqrt_tree(double s) {
   return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
-// the three list lengths of a walk level (last exclusive sum + last count)
-__global__ void k_walk_totals(const int64_t* __restrict__ oa, const int64_t* __restrict__ ca,
-                              const int64_t* __restrict__ ol, const int64_t* __restrict__ cl,
-                              const int64_t* __restrict__ of, const int64_t* __restrict__ cf, int64_t n,
-                              int64_t* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  out[0] = oa[n - 1] + ca[n - 1];
-  out[1] = ol[n - 1] + cl[n - 1];
-  out[2] = of[n - 1] + cf[n - 1];
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// first index in [0, n) whose group is >= g (lists are sorted by group)
-__device__ __forceinline__ int64_t lower_bound_group(const int32_t* a, int64_t n, int32_t g) {
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = lo + (hi - lo) / 2;
-    if (a[mid] < g) lo = mid + 1;
-    else hi = mid;
+__device__ __forceinline__ int wave_inclusive_sum(int v, int lane) {
+  for (int d = 1; d < kGS; d <<= 1) {
+    const int t = __shfl_up(v, d, kGS);
+    if (lane >= d) v += t;
   }
-  return lo;
+  return v;
 }
 
-// -------------------------------------------------------------- forces ----
 struct CellLite {
   double M, X[3], Q[6];
 };
-
-__global__ __launch_bounds__(kGS) void k_tree_forces(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
-                                                     int32_t ngroups, const TreeCell* __restrict__ cells,
-                                                     const int32_t* __restrict__ ag, const int32_t* __restrict__ ac,
-                                                     int64_t na, const int32_t* __restrict__ lg,
-                                                     const int32_t* __restrict__ lc, int64_t nl,
-                                                     const double* __restrict__ pos_s,
-                                                     const double* __restrict__ mass_s, double eps2,
-                                                     const int32_t* __restrict__ idx_s, double* __restrict__ acc,
-                                                     double* __restrict__ pot) {
-  __shared__ CellLite tile[kGS];
-  const int32_t g = blockIdx.x;
-  if (g >= ngroups) return;
-  const int lane = threadIdx.x;
-  const int32_t b = gb[g], e = ge[g];
-  const int32_t i = b + lane;
-  const bool valid = i < e;
-  const int32_t ir = valid ? i : b;
-  const double x0 = pos_s[3 * ir], x1 = pos_s[3 * ir + 1], x2 = pos_s[3 * ir + 2];
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, ph = 0.0;
-
-  // accepted cells, 64 at a time through LDS
-  const int64_t ab = lower_bound_group(ag, na, g), ae = lower_bound_group(ag, na, g + 1);
-  for (int64_t base = ab; base < ae; base += kGS) {
-    const int64_t k = base + lane;
-    if (k < ae) {
-      const TreeCell& c = cells[ac[k]];
-      CellLite cl;
-      cl.M = c.M;
-      for (int q = 0; q < 3; ++q) cl.X[q] = c.X[q];
-      for (int q = 0; q < 6; ++q) cl.Q[q] = c.Q[q];
-      tile[lane] = cl;
-    }
-    __syncthreads();
-    const int cnt = (int)(ae - base < kGS ? ae - base : kGS);
-    for (int t = 0; t < cnt; ++t) {
-      const CellLite& c = tile[t];
-      const double y0 = x0 - c.X[0], y1 = x1 - c.X[1], y2 = x2 - c.X[2];
-      const double s = y0 * y0 + y1 * y1 + y2 * y2 + eps2;
-      const double q = rsqrt_tree(s);
-      const double q2 = q * q;
-      const double q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
-      const double Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
-      const double Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
-      const double Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
-      const double yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
-      const double f = -c.M * q3 - 2.5 * yQy * q7;
-      a0 += f * y0 + Qy0 * q5;
-      a1 += f * y1 + Qy1 * q5;
-      a2 += f * y2 + Qy2 * q5;
-      ph += -c.M * q - 0.5 * yQy * q5;
-    }
-    __syncthreads();
-  }
-
-  // opened leaves: their particles, wave-uniform loads
-  const int64_t lb = lower_bound_group(lg, nl, g), le = lower_bound_group(lg, nl, g + 1);
-  for (int64_t k = lb; k < le; ++k) {
-    const TreeCell& c = cells[lc[k]];
-    for (int32_t j = c.begin; j < c.end; ++j) {
-      const double r0 = pos_s[3 * j] - x0, r1 = pos_s[3 * j + 1] - x1, r2 = pos_s[3 * j + 2] - x2;
-      const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
-      const bool keep = j != i && s > 0.0;
-      const double q = keep ? rsqrt_tree(s) : 0.0;
-      const double mq = mass_s[j] * q;
-      const double mq3 = mq * q * q;
-      a0 += mq3 * r0;
-      a1 += mq3 * r1;
-      a2 += mq3 * r2;
-      ph -= mq;
-    }
-  }
-  if (valid) {
-    const int32_t o = idx_s[i];
-    acc[3 * o] = a0;
-    acc[3 * o + 1] = a1;
-    acc[3 * o + 2] = a2;
-    pot[o] = ph;
-  }
-}
-
 // Mixed precision: the separation from a cell's centre of mass or from a
 // particle is formed in double and rounded to float, the rest of the term
-// is float; the float sums of one LDS chunk of cells, or of one leaf, are
-// added into double accumulators.  The walk, and so the interaction set, is
-// the double one.
+// is float; the float sums of one staged chunk (at most 64 cells or 64
+// particles) are added into double accumulators.  The walk, and so the
+// interaction set, is the double one.
 struct CellLiteF {
   double X[3];
   float M, Q[6], pad;
 };
 
-__global__ __launch_bounds__(kGS) void k_tree_forces_mixed(const int32_t* __restrict__ gb,
-                                                           const int32_t* __restrict__ ge, int32_t ngroups,
-                                                           const TreeCell* __restrict__ cells,
-                                                           const int32_t* __restrict__ ag,
-                                                           const int32_t* __restrict__ ac, int64_t na,
-                                                           const int32_t* __restrict__ lg,
-                                                           const int32_t* __restrict__ lc, int64_t nl,
-                                                           const double* __restrict__ pos_s,
-                                                           const double* __restrict__ mass_s, double eps2,
-                                                           const int32_t* __restrict__ idx_s,
-                                                           double* __restrict__ acc, double* __restrict__ pot) {
-  __shared__ CellLiteF tile[kGS];
-  const int32_t g = blockIdx.x;
-  if (g >= ngroups) return;
-  const int lane = threadIdx.x;
-  const int32_t b = gb[g], e = ge[g];
-  const int32_t i = b + lane;
-  const bool valid = i < e;
-  const int32_t ir = valid ? i : b;
-  const double x0 = pos_s[3 * ir], x1 = pos_s[3 * ir + 1], x2 = pos_s[3 * ir + 2];
-  const float e2 = (float)eps2;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, ph = 0.0;
+template <bool MIXED>
+struct WalkLds {
+  using Cell = typename std::conditional<MIXED, CellLiteF, CellLite>::type;
+  Cell tile[kGS];
+  double px[kGS], py[kGS], pz[kGS], pm[kGS];
+  int32_t pj[kGS];
+  int32_t acc_list[2 * kGS];
+  int32_t leaf_list[2 * kGS];
+  int32_t leaf_begin[kGS];
+  int32_t leaf_pre[kGS + 1];
+};
 
-  const int64_t ab = lower_bound_group(ag, na, g), ae = lower_bound_group(ag, na, g + 1);
-  for (int64_t base = ab; base < ae; base += kGS) {
-    const int64_t k = base + lane;
-    if (k < ae) {
-      const TreeCell& c = cells[ac[k]];
+struct Accum {
+  double a0, a1, a2, ph;
+};
+
+// The first `cnt` (<= 64) accepted cells of the list: each lane stages one
+// cell, then every lane adds all of them to its particle.
+template <bool MIXED>
+__device__ __forceinline__ void eval_cells(WalkLds<MIXED>& L, int cnt, const TreeCell* __restrict__ cells,
+                                           double x0, double x1, double x2, double eps2, Accum& A, int lane) {
+  if (lane < cnt) {
+    const TreeCell& c = cells[L.acc_list[lane]];
+    if constexpr (MIXED) {
       CellLiteF cl;
       cl.M = (float)c.M;
       for (int q = 0; q < 3; ++q) cl.X[q] = c.X[q];
       for (int q = 0; q < 6; ++q) cl.Q[q] = (float)c.Q[q];
       cl.pad = 0.0f;
-      tile[lane] = cl;
+      L.tile[lane] = cl;
+    } else {
+      CellLite cl;
+      cl.M = c.M;
+      for (int q = 0; q < 3; ++q) cl.X[q] = c.X[q];
+      for (int q = 0; q < 6; ++q) cl.Q[q] = c.Q[q];
+      L.tile[lane] = cl;
     }
-    __syncthreads();
-    const int cnt = (int)(ae - base < kGS ? ae - base : kGS);
+  }
+  __syncthreads();
+  if constexpr (MIXED) {
+    const float e2 = (float)eps2;
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
     for (int t = 0; t < cnt; ++t) {
-      const CellLiteF& c = tile[t];
+      const CellLiteF& c = L.tile[t];
       const float y0 = (float)(x0 - c.X[0]), y1 = (float)(x1 - c.X[1]), y2 = (float)(x2 - c.X[2]);
       const float s = y0 * y0 + y1 * y1 + y2 * y2 + e2;
       const float q = __builtin_amdgcn_rsqf(s);
@@ -641,53 +538,224 @@ __global__ __launch_bounds__(kGS) void k_tree_forces_mixed(const int32_t* __rest
       f2 += f * y2 + Qy2 * q5;
       fp += -c.M * q - 0.5f * yQy * q5;
     }
-    a0 += (double)f0; a1 += (double)f1; a2 += (double)f2; ph += (double)fp;
+    A.a0 += (double)f0; A.a1 += (double)f1; A.a2 += (double)f2; A.ph += (double)fp;
+  } else {
+    for (int t = 0; t < cnt; ++t) {
+      const CellLite& c = L.tile[t];
+      const double y0 = x0 - c.X[0], y1 = x1 - c.X[1], y2 = x2 - c.X[2];
+      const double s = y0 * y0 + y1 * y1 + y2 * y2 + eps2;
+      const double q = rsqrt_tree(s);
+      const double q2 = q * q;
+      const double q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+      const double Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
+      const double Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
+      const double Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
+      const double yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
+      const double f = -c.M * q3 - 2.5 * yQy * q7;
+      A.a0 += f * y0 + Qy0 * q5;
+      A.a1 += f * y1 + Qy1 * q5;
+      A.a2 += f * y2 + Qy2 * q5;
+      A.ph += -c.M * q - 0.5 * yQy * q5;
+    }
+  }
+  __syncthreads();
+}
+
+// The particles of the first `cnt` (<= 64) opened leaves of the list, 64 at
+// a time: lane p stages particle p of the chunk (found by a binary search
+// over the leaves' prefix sums), then every lane adds the chunk's pair terms
+// to its particle, skipping itself and coincident particles.
+template <bool MIXED>
+__device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const TreeCell* __restrict__ cells,
+                                            const double* __restrict__ pos_s, const double* __restrict__ mass_s,
+                                            int32_t i, double x0, double x1, double x2, double eps2, Accum& A,
+                                            int lane) {
+  int size = 0, begin = 0;
+  if (lane < cnt) {
+    const TreeCell& c = cells[L.leaf_list[lane]];
+    begin = c.begin;
+    size = c.end - c.begin;
+  }
+  const int incl = wave_inclusive_sum(size, lane);
+  const int total = __shfl(incl, kGS - 1, kGS);
+  L.leaf_begin[lane] = begin;
+  L.leaf_pre[lane + 1] = incl;
+  if (lane == 0) L.leaf_pre[0] = 0;
+  __syncthreads();
+  for (int base = 0; base < total; base += kGS) {
+    const int f = base + lane;
+    if (f < total) {
+      // the leaf k < cnt with leaf_pre[k] <= f < leaf_pre[k + 1]
+      int lo = 0, hi = cnt - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.leaf_pre[mid] <= f) lo = mid;
+        else hi = mid - 1;
+      }
+      const int32_t j = L.leaf_begin[lo] + (f - L.leaf_pre[lo]);
+      L.px[lane] = pos_s[3 * j];
+      L.py[lane] = pos_s[3 * j + 1];
+      L.pz[lane] = pos_s[3 * j + 2];
+      L.pm[lane] = mass_s[j];
+      L.pj[lane] = j;
+    }
+    __syncthreads();
+    const int m = total - base < kGS ? total - base : kGS;
+    if constexpr (MIXED) {
+      const float e2 = (float)eps2;
+      float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
+      for (int t = 0; t < m; ++t) {
+        const float r0 = (float)(L.px[t] - x0), r1 = (float)(L.py[t] - x1), r2 = (float)(L.pz[t] - x2);
+        const float s = r0 * r0 + r1 * r1 + r2 * r2 + e2;
+        const bool keep = L.pj[t] != i && s > 0.0f;
+        const float q = keep ? __builtin_amdgcn_rsqf(s) : 0.0f;
+        const float mq = (float)L.pm[t] * q;
+        const float mq3 = mq * q * q;
+        f0 += mq3 * r0;
+        f1 += mq3 * r1;
+        f2 += mq3 * r2;
+        fp -= mq;
+      }
+      A.a0 += (double)f0; A.a1 += (double)f1; A.a2 += (double)f2; A.ph += (double)fp;
+    } else {
+      for (int t = 0; t < m; ++t) {
+        const double r0 = L.px[t] - x0, r1 = L.py[t] - x1, r2 = L.pz[t] - x2;
+        const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
+        const bool keep = L.pj[t] != i && s > 0.0;
+        const double q = keep ? rsqrt_tree(s) : 0.0;
+        const double mq = L.pm[t] * q;
+        const double mq3 = mq * q * q;
+        A.a0 += mq3 * r0;
+        A.a1 += mq3 * r1;
+        A.a2 += mq3 * r2;
+        A.ph -= mq;
+      }
+    }
     __syncthreads();
   }
+}
 
-  const int64_t lb = lower_bound_group(lg, nl, g), le = lower_bound_group(lg, nl, g + 1);
-  for (int64_t k = lb; k < le; ++k) {
-    const TreeCell& c = cells[lc[k]];
-    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
-    for (int32_t j = c.begin; j < c.end; ++j) {
-      const float r0 = (float)(pos_s[3 * j] - x0), r1 = (float)(pos_s[3 * j + 1] - x1),
-                  r2 = (float)(pos_s[3 * j + 2] - x2);
-      const float s = r0 * r0 + r1 * r1 + r2 * r2 + e2;
-      const bool keep = j != i && s > 0.0f;
-      const float q = keep ? __builtin_amdgcn_rsqf(s) : 0.0f;
-      const float mq = (float)mass_s[j] * q;
-      const float mq3 = mq * q * q;
-      f0 += mq3 * r0;
-      f1 += mq3 * r1;
-      f2 += mq3 * r2;
-      fp -= mq;
+// drop the first 64 entries of a list of n (64 <= n < 128)
+__device__ __forceinline__ void shift_list(int32_t* list, int n, int lane) {
+  const int32_t v = lane + kGS < n ? list[lane + kGS] : 0;
+  __syncthreads();
+  if (lane + kGS < n) list[lane] = v;
+  __syncthreads();
+}
+
+// counters[0]: next group, [1]: accepted (group, cell) pairs, [2]: opened
+// (group, leaf) pairs, [3]: stack overflow flag
+template <bool MIXED>
+__global__ __launch_bounds__(kGS) void k_tree_walk_forces(const int32_t* __restrict__ gb,
+                                                          const int32_t* __restrict__ ge, int32_t ngroups,
+                                                          const double* __restrict__ gbox,
+                                                          const TreeCell* __restrict__ cells, double theta,
+                                                          const double* __restrict__ pos_s,
+                                                          const double* __restrict__ mass_s, double eps2,
+                                                          const int32_t* __restrict__ idx_s,
+                                                          int32_t* __restrict__ stack_all, int32_t stack_cap,
+                                                          unsigned long long* __restrict__ counters,
+                                                          double* __restrict__ acc, double* __restrict__ pot) {
+  __shared__ WalkLds<MIXED> L;
+  const int lane = threadIdx.x;
+  int32_t* stack = stack_all + (int64_t)blockIdx.x * stack_cap;
+  const int32_t root_child0 = cells[0].child0, root_nchild = cells[0].nchild;
+  for (;;) {
+    int32_t g = 0;
+    if (lane == 0) g = (int32_t)atomicAdd(&counters[0], 1ull);
+    g = __shfl(g, 0, kGS);
+    if (g >= ngroups) break;
+    const int32_t b = gb[g], e = ge[g];
+    const int32_t i = b + lane;
+    const bool valid = i < e;
+    const int32_t ir = valid ? i : b;
+    const double x0 = pos_s[3 * ir], x1 = pos_s[3 * ir + 1], x2 = pos_s[3 * ir + 2];
+    double box[6];
+    for (int k = 0; k < 6; ++k) box[k] = gbox[6 * g + k];
+    Accum A{0.0, 0.0, 0.0, 0.0};
+    // the root is never accepted: the walk starts from its children, or
+    // opens it when it is a leaf
+    int sp = 0, n_acc = 0, n_leaf = 0;
+    unsigned long long tot_acc = 0, tot_leaf = 0;
+    bool overflow = false;
+    if (root_nchild > 0) {
+      if (lane < root_nchild) stack[lane] = root_child0 + lane;
+      sp = root_nchild;
+    } else {
+      if (lane == 0) L.leaf_list[0] = 0;
+      n_leaf = 1;
+      tot_leaf = 1;
     }
-    a0 += (double)f0; a1 += (double)f1; a2 += (double)f2; ph += (double)fp;
-  }
-  if (valid) {
-    const int32_t o = idx_s[i];
-    acc[3 * o] = a0;
-    acc[3 * o + 1] = a1;
-    acc[3 * o + 2] = a2;
-    pot[o] = ph;
+    __syncthreads();
+    while (sp > 0) {
+      const int k = sp < kGS ? sp : kGS;
+      const int base = sp - k;
+      int kind = 3, nch = 0, ch0 = 0;
+      int32_t cid = 0;
+      if (lane < k) {
+        cid = stack[base + lane];
+        const TreeCell& c = cells[cid];
+        if (accepted(c, box, theta)) {
+          kind = 0;
+        } else if (c.nchild == 0) {
+          kind = 1;
+        } else {
+          kind = 2;
+          nch = c.nchild;
+          ch0 = c.child0;
+        }
+      }
+      sp = base;
+      const uint64_t ma = __ballot(kind == 0), ml = __ballot(kind == 1);
+      if (kind == 0) L.acc_list[n_acc + lane_rank(ma)] = cid;
+      if (kind == 1) L.leaf_list[n_leaf + lane_rank(ml)] = cid;
+      n_acc += __popcll(ma);
+      n_leaf += __popcll(ml);
+      tot_acc += __popcll(ma);
+      tot_leaf += __popcll(ml);
+      const int incl = wave_inclusive_sum(nch, lane);
+      const int pushed = __shfl(incl, kGS - 1, kGS);
+      if (sp + pushed > stack_cap) {
+        overflow = true;
+        break;
+      }
+      for (int t = 0; t < nch; ++t) stack[sp + incl - nch + t] = ch0 + t;
+      sp += pushed;
+      __syncthreads();
+      if (n_acc >= kGS) {
+        eval_cells<MIXED>(L, kGS, cells, x0, x1, x2, eps2, A, lane);
+        shift_list(L.acc_list, n_acc, lane);
+        n_acc -= kGS;
+      }
+      if (n_leaf >= kGS) {
+        eval_leaves<MIXED>(L, kGS, cells, pos_s, mass_s, i, x0, x1, x2, eps2, A, lane);
+        shift_list(L.leaf_list, n_leaf, lane);
+        n_leaf -= kGS;
+      }
+    }
+    __syncthreads();
+    if (!overflow) {
+      if (n_acc > 0) eval_cells<MIXED>(L, n_acc, cells, x0, x1, x2, eps2, A, lane);
+      if (n_leaf > 0) eval_leaves<MIXED>(L, n_leaf, cells, pos_s, mass_s, i, x0, x1, x2, eps2, A, lane);
+      if (valid) {
+        const int32_t o = idx_s[i];
+        acc[3 * o] = A.a0;
+        acc[3 * o + 1] = A.a1;
+        acc[3 * o + 2] = A.a2;
+        pot[o] = A.ph;
+      }
+    }
+    if (lane == 0) {
+      atomicAdd(&counters[1], tot_acc);
+      atomicAdd(&counters[2], tot_leaf);
+      if (overflow) atomicOr(&counters[3], 1ull);
+    }
+    __syncthreads();
   }
 }
 
-__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
-__global__ void k_root_pairs(int32_t ng, const TreeCell* __restrict__ cells, int32_t* __restrict__ fg,
-                             int32_t* __restrict__ fc) {
-  // the root is never accepted: each group starts from the root's children
-  // (or from the root itself when it is a leaf)
-  const TreeCell root = cells[0];
-  const int32_t per = root.nchild > 0 ? root.nchild : 1;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)ng * per;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    fg[t] = (int32_t)(t / per);
-    fc[t] = root.nchild > 0 ? root.child0 + (int32_t)(t % per) : 0;
-  }
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 // ------------------------------------------------------- host helpers -----
@@ -719,8 +787,7 @@ struct Alloc {
 
 enum Slot {
   S_BOXPART, S_BOX, S_KEYS, S_KEYS2, S_IDX, S_IDX2, S_POS, S_MASS, S_IJK, S_CELLS, S_CNT, S_OFF, S_TMP,
-  S_GB, S_GE, S_GB2, S_GE2, S_GN, S_GBOX, S_FG, S_FC, S_FG2, S_FC2, S_CA, S_CL, S_CF, S_OA, S_OL, S_OF,
-  S_AG, S_AC, S_LG, S_LC, S_AG2, S_AC2, S_LG2, S_LC2, S_TOT
+  S_GB, S_GE, S_GB2, S_GE2, S_GN, S_GBOX, S_STACK, S_CTR
 };
 
 template <class T>
@@ -867,128 +934,52 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
     std::swap(ge, ge2);
     NB_TRY(hipMemcpyAsync(gn, gn + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
   }
-  int32_t ngroups = 0, root_nchild = 0;
+  int32_t ngroups = 0;
   {
     int32_t* h = static_cast<int32_t*>(s.host);
     NB_TRY(hipMemcpyAsync(h, gn, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    NB_TRY(hipMemcpyAsync(h + 1, &cells[0].nchild, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     NB_TRY(hipStreamSynchronize(st));
     ngroups = h[0];
-    root_nchild = h[1];
   }
   double* gbox = al.get<double>(S_GBOX, 6 * (int64_t)ngroups);
   NB_TRY(need(gbox));
   hipLaunchKernelGGL(k_group_box, dim3(blocks_for(ngroups)), dim3(kTB), 0, st, gb, ge, ngroups, pos_s, gbox);
 
-  // walk, level-synchronous over (group, cell) pairs
-  int64_t nf = (int64_t)ngroups * (root_nchild > 0 ? root_nchild : 1);
-  int32_t* fg = al.get<int32_t>(S_FG, nf);
-  int32_t* fc = al.get<int32_t>(S_FC, nf);
-  NB_TRY(need(fc));
-  hipLaunchKernelGGL(k_root_pairs, dim3(blocks_for(nf)), dim3(kTB), 0, st, ngroups, cells, fg, fc);
+  // walk and forces: one wavefront per group, groups handed out by a counter
+  int dev = 0, num_cus = 0, per_cu = 0;
+  NB_TRY(hipGetDevice(&dev));
+  NB_TRY(hipDeviceGetAttribute(&num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  if (mixed)
+    NB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tree_walk_forces<true>, kGS, 0));
+  else
+    NB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tree_walk_forces<false>, kGS, 0));
+  int64_t grid = (int64_t)(num_cus > 0 ? num_cus : 1) * (per_cu > 0 ? per_cu : 1);
+  if (grid > ngroups) grid = ngroups;
+  const int32_t cap = (int32_t)(ncells < kStackCap ? ncells : kStackCap);
+  int32_t* stack = al.get<int32_t>(S_STACK, grid * cap);
+  unsigned long long* ctr = al.get<unsigned long long>(S_CTR, 4);
+  NB_TRY(need(ctr));
+  NB_TRY(need(stack));
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ctr, 4);
+  if (mixed)
+    hipLaunchKernelGGL(k_tree_walk_forces<true>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, ngroups, gbox,
+                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, acc, pot);
+  else
+    hipLaunchKernelGGL(k_tree_walk_forces<false>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, ngroups, gbox,
+                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, acc, pot);
   NB_TRY(hipGetLastError());
-  int64_t na = 0, nl = 0, cap_a = 0, cap_l = 0;
-  int32_t *ag = nullptr, *acl = nullptr, *lg = nullptr, *lcl = nullptr;
-  int fslot = 0;
-  while (nf > 0) {
-    int64_t* ca = al.get<int64_t>(S_CA, nf);
-    int64_t* cl = al.get<int64_t>(S_CL, nf);
-    int64_t* cf = al.get<int64_t>(S_CF, nf);
-    int64_t* oa = al.get<int64_t>(S_OA, nf);
-    int64_t* ol = al.get<int64_t>(S_OL, nf);
-    int64_t* of = al.get<int64_t>(S_OF, nf);
-    NB_TRY(need(of));
-    hipLaunchKernelGGL(k_walk_count, dim3(blocks_for(nf)), dim3(kTB), 0, st, fg, fc, nf, cells, gbox, theta, ca, cl,
-                       cf);
-    NB_TRY(hipGetLastError());
-    NB_TRY(exclusive_sum(al, ca, oa, nf));
-    NB_TRY(exclusive_sum(al, cl, ol, nf));
-    NB_TRY(exclusive_sum(al, cf, of, nf));
-    int64_t ta = 0, tl = 0, tf = 0;
-    {
-      int64_t* tot = al.get<int64_t>(S_TOT, 3);
-      NB_TRY(need(tot));
-      hipLaunchKernelGGL(k_walk_totals, dim3(1), dim3(64), 0, st, oa, ca, ol, cl, of, cf, nf, tot);
-      int64_t* h = static_cast<int64_t*>(s.host);
-      NB_TRY(hipMemcpyAsync(h, tot, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, st));
-      NB_TRY(hipStreamSynchronize(st));
-      ta = h[0];
-      tl = h[1];
-      tf = h[2];
-    }
-    if (na + ta > ((int64_t)1 << 31) - 1 || nl + tl > ((int64_t)1 << 31) - 1 || tf > ((int64_t)1 << 31) - 1) {
-      *msg = "interaction lists exceed 2^31 entries (raise theta or n_crit)";
+  int64_t na = 0, nl = 0;
+  {
+    unsigned long long* h = static_cast<unsigned long long*>(s.host);
+    NB_TRY(hipMemcpyAsync(h, ctr + 1, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    NB_TRY(hipStreamSynchronize(st));
+    if (h[2]) {
+      *msg = "tree walk stack exceeded its bound";
       return hipErrorInvalidValue;
     }
-    // grow the accumulated lists, keeping their contents
-    auto grow = [&](int slot_g, int slot_c, int32_t*& pg, int32_t*& pc, int64_t& cap, int64_t used,
-                    int64_t want) -> hipError_t {
-      if (used + want <= cap) return hipSuccess;
-      const int64_t nc = 2 * (used + want) + 1024;
-      int32_t *ng_ = nullptr, *nc_ = nullptr;
-      hipError_t e = hipMalloc(&ng_, (size_t)nc * sizeof(int32_t));
-      if (e == hipSuccess) e = hipMalloc(&nc_, (size_t)nc * sizeof(int32_t));
-      if (e != hipSuccess) return e;
-      if (used > 0) {
-        e = hipMemcpyAsync(ng_, pg, (size_t)used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(nc_, pc, (size_t)used * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
-      }
-      if ((int)s.slots.size() <= slot_c) s.slots.resize(slot_c + 1, {nullptr, 0});
-      if (s.slots[slot_g].first) (void)hipFree(s.slots[slot_g].first);
-      if (s.slots[slot_c].first) (void)hipFree(s.slots[slot_c].first);
-      s.slots[slot_g] = {ng_, (size_t)nc * sizeof(int32_t)};
-      s.slots[slot_c] = {nc_, (size_t)nc * sizeof(int32_t)};
-      pg = ng_;
-      pc = nc_;
-      cap = nc;
-      return hipSuccess;
-    };
-    if (!ag) {
-      ag = al.get<int32_t>(S_AG, 1024); acl = al.get<int32_t>(S_AC, 1024);
-      lg = al.get<int32_t>(S_LG, 1024); lcl = al.get<int32_t>(S_LC, 1024);
-      NB_TRY(need(lcl));
-      cap_a = (int64_t)(s.slots[S_AG].second < s.slots[S_AC].second ? s.slots[S_AG].second : s.slots[S_AC].second) /
-              (int64_t)sizeof(int32_t);
-      cap_l = (int64_t)(s.slots[S_LG].second < s.slots[S_LC].second ? s.slots[S_LG].second : s.slots[S_LC].second) /
-              (int64_t)sizeof(int32_t);
-    }
-    NB_TRY(grow(S_AG, S_AC, ag, acl, cap_a, na, ta));
-    NB_TRY(grow(S_LG, S_LC, lg, lcl, cap_l, nl, tl));
-    const int nslot_g = fslot ? S_FG : S_FG2, nslot_c = fslot ? S_FC : S_FC2;
-    int32_t* ng_ = al.get<int32_t>(nslot_g, tf);
-    int32_t* nc_ = al.get<int32_t>(nslot_c, tf);
-    NB_TRY(need(nc_));
-    hipLaunchKernelGGL(k_walk_write, dim3(blocks_for(nf)), dim3(kTB), 0, st, fg, fc, nf, cells, ca, cl, cf, oa, ol,
-                       of, na, nl, ag, acl, lg, lcl, ng_, nc_);
-    NB_TRY(hipGetLastError());
-    na += ta;
-    nl += tl;
-    fg = ng_;
-    fc = nc_;
-    nf = tf;
-    fslot ^= 1;
+    na = (int64_t)h[0];
+    nl = (int64_t)h[1];
   }
-
-  // lists grouped by group (stable: curve and level order kept inside a group)
-  int32_t* ag2 = al.get<int32_t>(S_AG2, na);
-  int32_t* ac2 = al.get<int32_t>(S_AC2, na);
-  int32_t* lg2 = al.get<int32_t>(S_LG2, nl);
-  int32_t* lc2 = al.get<int32_t>(S_LC2, nl);
-  NB_TRY(need(lc2));
-  int end_bit = 1;
-  while (end_bit < 31 && ((int64_t)1 << end_bit) <= ngroups) ++end_bit;
-  if (na > 0) NB_TRY(sort_pairs(al, ag, ag2, acl, ac2, na, end_bit));
-  if (nl > 0) NB_TRY(sort_pairs(al, lg, lg2, lcl, lc2, nl, end_bit));
-
-  if (mixed)
-    hipLaunchKernelGGL(k_tree_forces_mixed, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na,
-                       lg2, lc2, nl, pos_s, mass_s, eps2, idx_s, acc, pot);
-  else
-    hipLaunchKernelGGL(k_tree_forces, dim3(ngroups), dim3(kGS), 0, st, gb, ge, ngroups, cells, ag2, ac2, na, lg2,
-                       lc2, nl, pos_s, mass_s, eps2, idx_s, acc, pot);
-  NB_TRY(hipGetLastError());
   if (stats) {
     stats->cells = ncells;
     stats->groups = ngroups;
