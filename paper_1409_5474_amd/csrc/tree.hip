@@ -479,12 +479,19 @@ struct CellLiteF {
   float M, Q[6], pad;
 };
 
+// LDS of one wavefront: the staged cells and the staged leaf particles are
+// never live at the same time and share their storage.
 template <bool MIXED>
 struct WalkLds {
   using Cell = typename std::conditional<MIXED, CellLiteF, CellLite>::type;
-  Cell tile[kGS];
-  double px[kGS], py[kGS], pz[kGS], pm[kGS];
-  int32_t pj[kGS];
+  struct Parts {
+    double px[kGS], py[kGS], pz[kGS], pm[kGS];
+    int32_t pj[kGS];
+  };
+  union {
+    Cell tile[kGS];
+    Parts p;
+  };
   int32_t acc_list[2 * kGS];
   int32_t leaf_list[2 * kGS];
   int32_t leaf_begin[kGS];
@@ -593,11 +600,11 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
         else hi = mid - 1;
       }
       const int32_t j = L.leaf_begin[lo] + (f - L.leaf_pre[lo]);
-      L.px[lane] = pos_s[3 * j];
-      L.py[lane] = pos_s[3 * j + 1];
-      L.pz[lane] = pos_s[3 * j + 2];
-      L.pm[lane] = mass_s[j];
-      L.pj[lane] = j;
+      L.p.px[lane] = pos_s[3 * j];
+      L.p.py[lane] = pos_s[3 * j + 1];
+      L.p.pz[lane] = pos_s[3 * j + 2];
+      L.p.pm[lane] = mass_s[j];
+      L.p.pj[lane] = j;
     }
     __syncthreads();
     const int m = total - base < kGS ? total - base : kGS;
@@ -605,11 +612,11 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
       const float e2 = (float)eps2;
       float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
       for (int t = 0; t < m; ++t) {
-        const float r0 = (float)(L.px[t] - x0), r1 = (float)(L.py[t] - x1), r2 = (float)(L.pz[t] - x2);
+        const float r0 = (float)(L.p.px[t] - x0), r1 = (float)(L.p.py[t] - x1), r2 = (float)(L.p.pz[t] - x2);
         const float s = r0 * r0 + r1 * r1 + r2 * r2 + e2;
-        const bool keep = L.pj[t] != i && s > 0.0f;
+        const bool keep = L.p.pj[t] != i && s > 0.0f;
         const float q = keep ? __builtin_amdgcn_rsqf(s) : 0.0f;
-        const float mq = (float)L.pm[t] * q;
+        const float mq = (float)L.p.pm[t] * q;
         const float mq3 = mq * q * q;
         f0 += mq3 * r0;
         f1 += mq3 * r1;
@@ -619,11 +626,11 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
       A.a0 += (double)f0; A.a1 += (double)f1; A.a2 += (double)f2; A.ph += (double)fp;
     } else {
       for (int t = 0; t < m; ++t) {
-        const double r0 = L.px[t] - x0, r1 = L.py[t] - x1, r2 = L.pz[t] - x2;
+        const double r0 = L.p.px[t] - x0, r1 = L.p.py[t] - x1, r2 = L.p.pz[t] - x2;
         const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
-        const bool keep = L.pj[t] != i && s > 0.0;
+        const bool keep = L.p.pj[t] != i && s > 0.0;
         const double q = keep ? rsqrt_tree(s) : 0.0;
-        const double mq = L.pm[t] * q;
+        const double mq = L.p.pm[t] * q;
         const double mq3 = mq * q * q;
         A.a0 += mq3 * r0;
         A.a1 += mq3 * r1;
@@ -643,10 +650,15 @@ __device__ __forceinline__ void shift_list(int32_t* list, int n, int lane) {
   __syncthreads();
 }
 
+// Waves per SIMD asked of the register allocator.
+#ifndef NB_TREE_WAVES
+#define NB_TREE_WAVES 1
+#endif
+
 // counters[0]: next group, [1]: accepted (group, cell) pairs, [2]: opened
 // (group, leaf) pairs, [3]: stack overflow flag
 template <bool MIXED>
-__global__ __launch_bounds__(kGS) void k_tree_walk_forces(const int32_t* __restrict__ gb,
+__global__ __launch_bounds__(kGS, NB_TREE_WAVES) void k_tree_walk_forces(const int32_t* __restrict__ gb,
                                                           const int32_t* __restrict__ ge, int32_t ngroups,
                                                           const double* __restrict__ gbox,
                                                           const TreeCell* __restrict__ cells, double theta,
