@@ -235,19 +235,22 @@ __device__ __forceinline__ void child_ranges(const TreeCell& c, const uint64_t* 
   ends[7] = c.end;
 }
 
+// The child boundaries of every cell that splits, found once (eight binary
+// searches) and kept in `ends` [ncell][8] for the write pass.
 __global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restrict__ cells, int32_t ncell,
                                                         const uint64_t* __restrict__ keys, int n_crit,
-                                                        int32_t* __restrict__ cnt) {
+                                                        int32_t* __restrict__ cnt, int32_t* __restrict__ ends) {
   for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
     const TreeCell c = cells[i];
     int32_t m = 0;
     if (c.end - c.begin > n_crit && c.level < kBits) {
-      int32_t ends[8];
-      child_ranges(c, keys, ends);
+      int32_t e[8];
+      child_ranges(c, keys, e);
       int32_t b = c.begin;
       for (int k = 0; k < 8; ++k) {
-        m += ends[k] > b;
-        b = ends[k];
+        m += e[k] > b;
+        b = e[k];
+        ends[8 * (int64_t)i + k] = e[k];
       }
     }
     cnt[i] = m;
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restri
 }
 
 __global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
-                                                        const uint64_t* __restrict__ keys,
+                                                        const int32_t* __restrict__ ends,
                                                         const int32_t* __restrict__ ijk_s,
                                                         const Box* __restrict__ box, int n_crit,
                                                         const int32_t* __restrict__ off, int32_t next) {
@@ -267,19 +270,18 @@ __global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ c
       c.nchild = 0;
       continue;
     }
-    int32_t ends[8];
-    child_ranges(c, keys, ends);
     const int32_t base = next + off[i];
     int32_t b = c.begin, m = 0;
     for (int k = 0; k < 8; ++k) {
-      if (ends[k] > b) {
+      const int32_t e = ends[8 * (int64_t)i + k];
+      if (e > b) {
         TreeCell ch{};
-        ch.begin = b; ch.end = ends[k]; ch.child0 = -1; ch.nchild = 0; ch.level = c.level + 1;
+        ch.begin = b; ch.end = e; ch.child0 = -1; ch.nchild = 0; ch.level = c.level + 1;
         set_geometry(ch, ijk_s, bx);
         cells[base + m] = ch;
         ++m;
       }
-      b = ends[k];
+      b = e;
     }
     c.child0 = base;
     c.nchild = m;
@@ -347,47 +349,57 @@ __device__ __forceinline__ double extent(const double* pos_s, int32_t b, int32_t
   return fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
 }
 
-__global__ __launch_bounds__(kTB) void k_groups_init(int32_t n, int32_t* __restrict__ gb, int32_t* __restrict__ ge,
-                                                     int32_t cap, int32_t* __restrict__ ng) {
-  const int32_t g0 = (n + kGS - 1) / kGS;
-  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < cap; i += gridDim.x * kTB) {
-    gb[i] = i < g0 ? i * kGS : 0;
-    ge[i] = i < g0 ? (i * kGS + kGS < n ? i * kGS + kGS : n) : 0;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ng = g0;
-}
-
-__global__ __launch_bounds__(kTB) void k_groups_count(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
-                                                      const int32_t* __restrict__ ng, int32_t cap,
-                                                      const double* __restrict__ pos_s, const Box* __restrict__ box,
-                                                      double g_frac, int32_t* __restrict__ cnt) {
-  const int32_t m = *ng;
-  const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
-  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < cap; i += gridDim.x * kTB) {
-    int32_t c = 0;
-    if (i < m) c = (ge[i] - gb[i] > 1 && extent(pos_s, gb[i], ge[i]) > g_max) ? 2 : 1;
-    cnt[i] = c;
-  }
-}
-
-__global__ __launch_bounds__(kTB) void k_groups_write(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
-                                                      const int32_t* __restrict__ ng, int32_t cap,
-                                                      const int32_t* __restrict__ cnt,
-                                                      const int32_t* __restrict__ off, int32_t* __restrict__ gb2,
-                                                      int32_t* __restrict__ ge2, int32_t* __restrict__ ng2) {
-  const int32_t m = *ng;
-  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < m; i += gridDim.x * kTB) {
-    const int32_t o = off[i];
-    if (cnt[i] == 2) {
-      const int32_t mid = gb[i] + (ge[i] - gb[i] + 1) / 2;
-      gb2[o] = gb[i]; ge2[o] = mid;
-      gb2[o + 1] = mid; ge2[o + 1] = ge[i];
+// Groups of one curve chunk of up to 64 particles: the chunk is halved
+// (first half ceil(n/2)) while a piece holding more than one particle is
+// wider than g_max, first half first.  An explicit stack replaces the
+// recursion; a chunk of 64 is halved at most six times, so seven entries
+// suffice.  Returns the number of groups; writes them when `gb` is set.
+__device__ __forceinline__ int32_t split_chunk(const double* __restrict__ pos_s, int32_t b0, int32_t e0,
+                                               double g_max, int32_t* __restrict__ gb, int32_t* __restrict__ ge) {
+  int32_t sb[8], se[8];
+  int sp = 1;
+  sb[0] = b0;
+  se[0] = e0;
+  int32_t cnt = 0;
+  while (sp > 0) {
+    --sp;
+    const int32_t b = sb[sp], e = se[sp];
+    if (e - b > 1 && sp + 2 <= 8 && extent(pos_s, b, e) > g_max) {
+      const int32_t m = b + (e - b + 1) / 2;
+      sb[sp] = m; se[sp] = e; ++sp;
+      sb[sp] = b; se[sp] = m; ++sp;
     } else {
-      gb2[o] = gb[i]; ge2[o] = ge[i];
+      if (gb) {
+        gb[cnt] = b;
+        ge[cnt] = e;
+      }
+      ++cnt;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ng2 = m > 0 ? off[m - 1] + cnt[m - 1] : 0;
-  (void)cap;
+  return cnt;
+}
+
+__global__ __launch_bounds__(kTB) void k_groups_count(int32_t n, int32_t nchunk, const double* __restrict__ pos_s,
+                                                      const Box* __restrict__ box, double g_frac,
+                                                      int32_t* __restrict__ cnt) {
+  const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
+  for (int32_t c = blockIdx.x * kTB + threadIdx.x; c < nchunk; c += gridDim.x * kTB) {
+    const int32_t b = c * kGS, e = b + kGS < n ? b + kGS : n;
+    cnt[c] = split_chunk(pos_s, b, e, g_max, nullptr, nullptr);
+  }
+}
+
+__global__ __launch_bounds__(kTB) void k_groups_write(int32_t n, int32_t nchunk, const double* __restrict__ pos_s,
+                                                      const Box* __restrict__ box, double g_frac,
+                                                      const int32_t* __restrict__ cnt,
+                                                      const int32_t* __restrict__ off, int32_t* __restrict__ gb,
+                                                      int32_t* __restrict__ ge, int32_t* __restrict__ ng) {
+  const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
+  for (int32_t c = blockIdx.x * kTB + threadIdx.x; c < nchunk; c += gridDim.x * kTB) {
+    const int32_t b = c * kGS, e = b + kGS < n ? b + kGS : n;
+    split_chunk(pos_s, b, e, g_max, gb + off[c], ge + off[c]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *ng = off[nchunk - 1] + cnt[nchunk - 1];
 }
 
 __global__ __launch_bounds__(kTB) void k_group_box(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
@@ -531,38 +543,38 @@ __device__ __forceinline__ void eval_cells(WalkLds<MIXED>& L, int cnt, const Tre
     for (int t = 0; t < cnt; ++t) {
       const CellLiteF& c = L.tile[t];
       const float y0 = (float)(x0 - c.X[0]), y1 = (float)(x1 - c.X[1]), y2 = (float)(x2 - c.X[2]);
-      const float s = y0 * y0 + y1 * y1 + y2 * y2 + e2;
+      const float s = fmaf(y2, y2, fmaf(y1, y1, fmaf(y0, y0, e2)));
       const float q = __builtin_amdgcn_rsqf(s);
       const float q2 = q * q;
-      const float q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+      const float q3 = q2 * q, q5 = q3 * q2;
       const float Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
       const float Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
       const float Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
-      const float yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
-      const float f = -c.M * q3 - 2.5f * yQy * q7;
-      f0 += f * y0 + Qy0 * q5;
-      f1 += f * y1 + Qy1 * q5;
-      f2 += f * y2 + Qy2 * q5;
-      fp += -c.M * q - 0.5f * yQy * q5;
+      const float w = (y0 * Qy0 + y1 * Qy1 + y2 * Qy2) * q5;  // (y.Qy) s^-5/2
+      const float f = fmaf(-2.5f * w, q2, -c.M * q3);         // -M s^-3/2 - (5/2)(y.Qy) s^-7/2
+      f0 = fmaf(Qy0, q5, fmaf(f, y0, f0));
+      f1 = fmaf(Qy1, q5, fmaf(f, y1, f1));
+      f2 = fmaf(Qy2, q5, fmaf(f, y2, f2));
+      fp = fmaf(-0.5f, w, fmaf(-c.M, q, fp));
     }
     A.a0 += (double)f0; A.a1 += (double)f1; A.a2 += (double)f2; A.ph += (double)fp;
   } else {
     for (int t = 0; t < cnt; ++t) {
       const CellLite& c = L.tile[t];
       const double y0 = x0 - c.X[0], y1 = x1 - c.X[1], y2 = x2 - c.X[2];
-      const double s = y0 * y0 + y1 * y1 + y2 * y2 + eps2;
+      const double s = fma(y2, y2, fma(y1, y1, fma(y0, y0, eps2)));
       const double q = rsqrt_tree(s);
       const double q2 = q * q;
-      const double q3 = q2 * q, q5 = q3 * q2, q7 = q5 * q2;
+      const double q3 = q2 * q, q5 = q3 * q2;
       const double Qy0 = c.Q[0] * y0 + c.Q[3] * y1 + c.Q[4] * y2;
       const double Qy1 = c.Q[3] * y0 + c.Q[1] * y1 + c.Q[5] * y2;
       const double Qy2 = c.Q[4] * y0 + c.Q[5] * y1 + c.Q[2] * y2;
-      const double yQy = y0 * Qy0 + y1 * Qy1 + y2 * Qy2;
-      const double f = -c.M * q3 - 2.5 * yQy * q7;
-      A.a0 += f * y0 + Qy0 * q5;
-      A.a1 += f * y1 + Qy1 * q5;
-      A.a2 += f * y2 + Qy2 * q5;
-      A.ph += -c.M * q - 0.5 * yQy * q5;
+      const double w = (y0 * Qy0 + y1 * Qy1 + y2 * Qy2) * q5;  // (y.Qy) s^-5/2
+      const double f = fma(-2.5 * w, q2, -c.M * q3);          // -M s^-3/2 - (5/2)(y.Qy) s^-7/2
+      A.a0 = fma(Qy0, q5, fma(f, y0, A.a0));
+      A.a1 = fma(Qy1, q5, fma(f, y1, A.a1));
+      A.a2 = fma(Qy2, q5, fma(f, y2, A.a2));
+      A.ph = fma(-0.5, w, fma(-c.M, q, A.ph));
     }
   }
   __syncthreads();
@@ -613,7 +625,7 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
       float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
       for (int t = 0; t < m; ++t) {
         const float r0 = (float)(L.p.px[t] - x0), r1 = (float)(L.p.py[t] - x1), r2 = (float)(L.p.pz[t] - x2);
-        const float s = r0 * r0 + r1 * r1 + r2 * r2 + e2;
+        const float s = fmaf(r2, r2, fmaf(r1, r1, fmaf(r0, r0, e2)));
         const bool keep = L.p.pj[t] != i && s > 0.0f;
         const float q = keep ? __builtin_amdgcn_rsqf(s) : 0.0f;
         const float mq = (float)L.p.pm[t] * q;
@@ -627,7 +639,7 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
     } else {
       for (int t = 0; t < m; ++t) {
         const double r0 = L.p.px[t] - x0, r1 = L.p.py[t] - x1, r2 = L.p.pz[t] - x2;
-        const double s = r0 * r0 + r1 * r1 + r2 * r2 + eps2;
+        const double s = fma(r2, r2, fma(r1, r1, fma(r0, r0, eps2)));
         const bool keep = L.p.pj[t] != i && s > 0.0;
         const double q = keep ? rsqrt_tree(s) : 0.0;
         const double mq = L.p.pm[t] * q;
@@ -799,7 +811,7 @@ struct Alloc {
 
 enum Slot {
   S_BOXPART, S_BOX, S_KEYS, S_KEYS2, S_IDX, S_IDX2, S_POS, S_MASS, S_IJK, S_CELLS, S_CNT, S_OFF, S_TMP,
-  S_GB, S_GE, S_GB2, S_GE2, S_GN, S_GBOX, S_STACK, S_CTR
+  S_GB, S_GE, S_GN, S_GBOX, S_STACK, S_CTR, S_ENDS
 };
 
 template <class T>
@@ -887,9 +899,10 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
     const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
     int32_t* cntc = al.get<int32_t>(S_CNT, cnt);
     int32_t* offc = al.get<int32_t>(S_OFF, cnt);
-    NB_TRY(need(offc));
+    int32_t* ends = al.get<int32_t>(S_ENDS, 8 * cnt);
+    NB_TRY(need(ends));
     hipLaunchKernelGGL(k_count_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells + first, (int32_t)cnt,
-                       keys_s, n_crit, cntc);
+                       keys_s, n_crit, cntc, ends);
     NB_TRY(hipGetLastError());
     NB_TRY(exclusive_sum(al, cntc, offc, cnt));
     int64_t total = 0;
@@ -910,7 +923,7 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
       cap_cells = newcap;
     }
     hipLaunchKernelGGL(k_write_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells, (int32_t)first,
-                       (int32_t)cnt, keys_s, ijk_s, box, n_crit, offc, (int32_t)next);
+                       (int32_t)cnt, ends, ijk_s, box, n_crit, offc, (int32_t)next);
     NB_TRY(hipGetLastError());
     lvl.push_back(next + total);
   }
@@ -924,28 +937,21 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   NB_TRY(hipGetLastError());
   const int64_t ncells = lvl[depth + 1];
 
-  // groups: chunks of 64, halved while wider than g_max
-  const int32_t gcap = n;
-  int32_t* gb = al.get<int32_t>(S_GB, gcap);
-  int32_t* ge = al.get<int32_t>(S_GE, gcap);
-  int32_t* gb2 = al.get<int32_t>(S_GB2, gcap);
-  int32_t* ge2 = al.get<int32_t>(S_GE2, gcap);
-  int32_t* gn = al.get<int32_t>(S_GN, 2);
-  int32_t* gcnt = al.get<int32_t>(S_CNT, gcap);
-  int32_t* goff = al.get<int32_t>(S_OFF, gcap);
+  // groups: chunks of 64, halved while wider than g_max (one pass to count,
+  // one to write)
+  const int32_t nchunk = (n + kGS - 1) / kGS;
+  int32_t* gb = al.get<int32_t>(S_GB, n);
+  int32_t* ge = al.get<int32_t>(S_GE, n);
+  int32_t* gn = al.get<int32_t>(S_GN, 1);
+  int32_t* gcnt = al.get<int32_t>(S_CNT, nchunk);
+  int32_t* goff = al.get<int32_t>(S_OFF, nchunk);
   NB_TRY(need(goff));
-  hipLaunchKernelGGL(k_groups_init, dim3(blocks_for(gcap)), dim3(kTB), 0, st, n, gb, ge, gcap, gn);
-  for (int round = 0; round < 7; ++round) {
-    hipLaunchKernelGGL(k_groups_count, dim3(blocks_for(gcap)), dim3(kTB), 0, st, gb, ge, gn, gcap, pos_s, box,
-                       g_frac, gcnt);
-    NB_TRY(exclusive_sum(al, gcnt, goff, gcap));
-    hipLaunchKernelGGL(k_groups_write, dim3(blocks_for(gcap)), dim3(kTB), 0, st, gb, ge, gn, gcap, gcnt, goff,
-                       gb2, ge2, gn + 1);
-    NB_TRY(hipGetLastError());
-    std::swap(gb, gb2);
-    std::swap(ge, ge2);
-    NB_TRY(hipMemcpyAsync(gn, gn + 1, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
-  }
+  hipLaunchKernelGGL(k_groups_count, dim3(blocks_for(nchunk)), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac,
+                     gcnt);
+  NB_TRY(exclusive_sum(al, gcnt, goff, nchunk));
+  hipLaunchKernelGGL(k_groups_write, dim3(blocks_for(nchunk)), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac,
+                     gcnt, goff, gb, ge, gn);
+  NB_TRY(hipGetLastError());
   int32_t ngroups = 0;
   {
     int32_t* h = static_cast<int32_t*>(s.host);
