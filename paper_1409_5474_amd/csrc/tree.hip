@@ -221,39 +221,35 @@ __device__ __forceinline__ int32_t lower_bound_key(const uint64_t* keys, int32_t
   return lo;
 }
 
-// Child k of a cell at level l covers keys [(p<<3|k) << s, (p<<3|k)+1 << s)
-// with s = 3(20 - l); the last child ends with its parent.
-__device__ __forceinline__ void child_ranges(const TreeCell& c, const uint64_t* keys, int32_t* ends) {
-  const int s = 3 * (kBits - c.level - 1);
-  const uint64_t prefix = keys[c.begin] >> (s + 3);
-  int32_t b = c.begin;
-  for (int k = 0; k < 7; ++k) {
-    const uint64_t bound = ((prefix << 3) | (uint64_t)(k + 1)) << s;
-    b = lower_bound_key(keys, b, c.end, bound);
-    ends[k] = b;
-  }
-  ends[7] = c.end;
-}
-
-// The child boundaries of every cell that splits, found once (eight binary
-// searches) and kept in `ends` [ncell][8] for the write pass.
+// The child boundaries of every cell that splits, kept in `ends` [ncell][8]
+// for the write pass: eight consecutive lanes per cell, lane k finds where
+// child k ends (a binary search over the cell's keys; child k of a cell at
+// level l covers the keys [(p<<3|k) << s, (p<<3|k)+1 << s), s = 3(20 - l),
+// and the last child ends with the cell), and the cell's count of non-empty
+// children is summed over the eight lanes.
 __global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restrict__ cells, int32_t ncell,
                                                         const uint64_t* __restrict__ keys, int n_crit,
                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ ends) {
-  for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
-    const TreeCell c = cells[i];
-    int32_t m = 0;
-    if (c.end - c.begin > n_crit && c.level < kBits) {
-      int32_t e[8];
-      child_ranges(c, keys, e);
-      int32_t b = c.begin;
-      for (int k = 0; k < 8; ++k) {
-        m += e[k] > b;
-        b = e[k];
-        ends[8 * (int64_t)i + k] = e[k];
-      }
+  const int64_t total = 8 * (int64_t)ncell;  // whole groups of eight lanes
+  for (int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kTB) {
+    const int32_t i = (int32_t)(t >> 3);
+    const int k = (int)(t & 7);
+    const TreeCell& c = cells[i];
+    const bool split = c.end - c.begin > n_crit && c.level < kBits;
+    int32_t e = c.end;
+    if (split && k < 7) {
+      const int sh = 3 * (kBits - c.level - 1);
+      const uint64_t prefix = keys[c.begin] >> (sh + 3);
+      e = lower_bound_key(keys, c.begin, c.end, ((prefix << 3) | (uint64_t)(k + 1)) << sh);
     }
-    cnt[i] = m;
+    const int32_t prev = __shfl_up(e, 1, 8);
+    const int32_t b = k == 0 ? c.begin : prev;
+    int m = (split && e > b) ? 1 : 0;
+    m += __shfl_xor(m, 1, 8);
+    m += __shfl_xor(m, 2, 8);
+    m += __shfl_xor(m, 4, 8);
+    if (split) ends[t] = e;
+    if (k == 0) cnt[i] = m;
   }
 }
 
@@ -901,8 +897,8 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
     int32_t* offc = al.get<int32_t>(S_OFF, cnt);
     int32_t* ends = al.get<int32_t>(S_ENDS, 8 * cnt);
     NB_TRY(need(ends));
-    hipLaunchKernelGGL(k_count_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells + first, (int32_t)cnt,
-                       keys_s, n_crit, cntc, ends);
+    hipLaunchKernelGGL(k_count_children, dim3(blocks_for(8 * cnt)), dim3(kTB), 0, st, cells + first,
+                       (int32_t)cnt, keys_s, n_crit, cntc, ends);
     NB_TRY(hipGetLastError());
     NB_TRY(exclusive_sum(al, cntc, offc, cnt));
     int64_t total = 0;
