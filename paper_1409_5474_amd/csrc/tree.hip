@@ -251,6 +251,7 @@ __global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restri
     if (split) ends[t] = e;
     if (k == 0) cnt[i] = m;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) cnt[ncell] = 0;
 }
 
 __global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
@@ -830,18 +831,13 @@ hipError_t sort_pairs(Alloc& al, const K* kin, K* kout, const V* vin, V* vout, i
   return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, n, 0, end_bit, al.st);
 }
 
-// last exclusive-sum entry + last count, read to the host (synchronises)
+// the entry at `pos` of a device array, read to the host (synchronises)
 template <class T>
-hipError_t read_total(TreeScratch& s, hipStream_t st, const T* off, const T* cnt, int64_t n, int64_t* total) {
-  if (n <= 0) {
-    *total = 0;
-    return hipSuccess;
-  }
+hipError_t read_entry(TreeScratch& s, hipStream_t st, const T* a, int64_t pos, int64_t* out) {
   T* h = static_cast<T*>(s.host);
-  hipError_t e = hipMemcpyAsync(h, off + n - 1, sizeof(T), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(h + 1, cnt + n - 1, sizeof(T), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(h, a + pos, sizeof(T), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess) *total = (int64_t)h[0] + (int64_t)h[1];
+  if (e == hipSuccess) *out = (int64_t)h[0];
   return e;
 }
 
@@ -893,16 +889,17 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   std::vector<int64_t> lvl = {0, 1};
   for (int l = 0; l < kBits; ++l) {
     const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
-    int32_t* cntc = al.get<int32_t>(S_CNT, cnt);
-    int32_t* offc = al.get<int32_t>(S_OFF, cnt);
+    // one extra zero count makes the last exclusive sum the level's total
+    int32_t* cntc = al.get<int32_t>(S_CNT, cnt + 1);
+    int32_t* offc = al.get<int32_t>(S_OFF, cnt + 1);
     int32_t* ends = al.get<int32_t>(S_ENDS, 8 * cnt);
     NB_TRY(need(ends));
     hipLaunchKernelGGL(k_count_children, dim3(blocks_for(8 * cnt)), dim3(kTB), 0, st, cells + first,
                        (int32_t)cnt, keys_s, n_crit, cntc, ends);
     NB_TRY(hipGetLastError());
-    NB_TRY(exclusive_sum(al, cntc, offc, cnt));
+    NB_TRY(exclusive_sum(al, cntc, offc, cnt + 1));
     int64_t total = 0;
-    NB_TRY(read_total(s, st, offc, cntc, cnt, &total));
+    NB_TRY(read_entry(s, st, offc, cnt, &total));
     if (total == 0) break;
     const int64_t next = lvl[l + 1];
     if (next + total > cap_cells) {
