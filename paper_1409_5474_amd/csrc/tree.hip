@@ -620,6 +620,7 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
     if constexpr (MIXED) {
       const float e2 = (float)eps2;
       float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f, fp = 0.0f;
+#pragma unroll 4
       for (int t = 0; t < m; ++t) {
         const float r0 = (float)(L.p.px[t] - x0), r1 = (float)(L.p.py[t] - x1), r2 = (float)(L.p.pz[t] - x2);
         const float s = fmaf(r2, r2, fmaf(r1, r1, fmaf(r0, r0, e2)));
@@ -634,6 +635,7 @@ __device__ __forceinline__ void eval_leaves(WalkLds<MIXED>& L, int cnt, const Tr
       }
       A.a0 += (double)f0; A.a1 += (double)f1; A.a2 += (double)f2; A.ph += (double)fp;
     } else {
+#pragma unroll 4
       for (int t = 0; t < m; ++t) {
         const double r0 = L.p.px[t] - x0, r1 = L.p.py[t] - x1, r2 = L.p.pz[t] - x2;
         const double s = fma(r2, r2, fma(r1, r1, fma(r0, r0, eps2)));
