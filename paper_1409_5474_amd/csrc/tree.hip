@@ -346,6 +346,11 @@ __device__ __forceinline__ double extent(const double* pos_s, int32_t b, int32_t
   return fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
 }
 
+// number of set bits of `mask` below this lane
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 // Groups of one curve chunk of up to 64 particles: the chunk is halved
 // (first half ceil(n/2)) while a piece holding more than one particle is
 // wider than g_max, first half first.  An explicit stack replaces the
@@ -376,27 +381,58 @@ __device__ __forceinline__ int32_t split_chunk(const double* __restrict__ pos_s,
   return cnt;
 }
 
-__global__ __launch_bounds__(kTB) void k_groups_count(int32_t n, int32_t nchunk, const double* __restrict__ pos_s,
-                                                      const Box* __restrict__ box, double g_frac,
-                                                      int32_t* __restrict__ cnt) {
+// One wavefront per chunk.  A full chunk of 64 is only ever cut at aligned
+// halves, and a piece that fits (extent <= g_max) has pieces that fit, so
+// the group holding particle j is the largest aligned piece around j that
+// fits (a single particle always does): lane j reduces the minimum and
+// maximum position over the aligned pieces of 2, 4, ..., 64 around it by
+// butterfly shuffles and keeps the largest size that fits.  The last,
+// shorter chunk takes the recursion above on lane 0.  WRITE = false counts
+// the groups per chunk, WRITE = true writes them at their offsets.
+template <bool WRITE>
+__global__ __launch_bounds__(kTB) void k_groups(int32_t n, int32_t nchunk, const double* __restrict__ pos_s,
+                                                const Box* __restrict__ box, double g_frac,
+                                                int32_t* __restrict__ cnt, const int32_t* __restrict__ off,
+                                                int32_t* __restrict__ gb, int32_t* __restrict__ ge,
+                                                int32_t* __restrict__ ng) {
   const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
-  for (int32_t c = blockIdx.x * kTB + threadIdx.x; c < nchunk; c += gridDim.x * kTB) {
-    const int32_t b = c * kGS, e = b + kGS < n ? b + kGS : n;
-    cnt[c] = split_chunk(pos_s, b, e, g_max, nullptr, nullptr);
+  const int lane = threadIdx.x & (kGS - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * kTB + threadIdx.x) / kGS;
+  const int64_t nwaves = (int64_t)gridDim.x * kTB / kGS;
+  for (int64_t c = wave; c < nchunk; c += nwaves) {
+    const int32_t b = (int32_t)c * kGS, e = b + kGS < n ? b + kGS : n;
+    if (e - b < kGS) {
+      if (lane == 0) {
+        if (WRITE) split_chunk(pos_s, b, e, g_max, gb + off[c], ge + off[c]);
+        else cnt[c] = split_chunk(pos_s, b, e, g_max, nullptr, nullptr);
+      }
+      continue;
+    }
+    const int32_t j = b + lane;
+    double mn[3], mx[3];
+    for (int k = 0; k < 3; ++k) mn[k] = mx[k] = pos_s[3 * j + k];
+    int size = 1;
+    for (int h = 1; h < kGS; h <<= 1) {
+      for (int k = 0; k < 3; ++k) {
+        mn[k] = fmin(mn[k], __shfl_xor(mn[k], h, kGS));
+        mx[k] = fmax(mx[k], __shfl_xor(mx[k], h, kGS));
+      }
+      const double ext = fmax(mx[0] - mn[0], fmax(mx[1] - mn[1], mx[2] - mn[2]));
+      if (size == h && !(ext > g_max)) size = 2 * h;
+    }
+    const bool start = (lane & (size - 1)) == 0;
+    const uint64_t starts = __ballot(start);
+    if (WRITE) {
+      if (start) {
+        const int32_t o = off[c] + lane_rank(starts);
+        gb[o] = j;
+        ge[o] = j + size;
+      }
+    } else if (lane == 0) {
+      cnt[c] = __popcll(starts);
+    }
   }
-}
-
-__global__ __launch_bounds__(kTB) void k_groups_write(int32_t n, int32_t nchunk, const double* __restrict__ pos_s,
-                                                      const Box* __restrict__ box, double g_frac,
-                                                      const int32_t* __restrict__ cnt,
-                                                      const int32_t* __restrict__ off, int32_t* __restrict__ gb,
-                                                      int32_t* __restrict__ ge, int32_t* __restrict__ ng) {
-  const double g_max = g_frac > 0.0 ? g_frac * box->side : INFINITY;
-  for (int32_t c = blockIdx.x * kTB + threadIdx.x; c < nchunk; c += gridDim.x * kTB) {
-    const int32_t b = c * kGS, e = b + kGS < n ? b + kGS : n;
-    split_chunk(pos_s, b, e, g_max, gb + off[c], ge + off[c]);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *ng = off[nchunk - 1] + cnt[nchunk - 1];
+  if (WRITE && blockIdx.x == 0 && threadIdx.x == 0) *ng = off[nchunk - 1] + cnt[nchunk - 1];
 }
 
 __global__ __launch_bounds__(kTB) void k_group_box(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
@@ -462,10 +498,6 @@ __device__ __forceinline__ double rsqrt_tree(double s) {
   return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
-// number of set bits of `mask` below this lane
-__device__ __forceinline__ int lane_rank(uint64_t mask) {
-  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-}
 
 __device__ __forceinline__ int wave_inclusive_sum(int v, int lane) {
   for (int d = 1; d < kGS; d <<= 1) {
@@ -941,11 +973,12 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   int32_t* gcnt = al.get<int32_t>(S_CNT, nchunk);
   int32_t* goff = al.get<int32_t>(S_OFF, nchunk);
   NB_TRY(need(goff));
-  hipLaunchKernelGGL(k_groups_count, dim3(blocks_for(nchunk)), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac,
-                     gcnt);
+  const int gblocks = blocks_for((int64_t)nchunk * kGS);
+  hipLaunchKernelGGL(k_groups<false>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, gcnt,
+                     nullptr, nullptr, nullptr, nullptr);
   NB_TRY(exclusive_sum(al, gcnt, goff, nchunk));
-  hipLaunchKernelGGL(k_groups_write, dim3(blocks_for(nchunk)), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac,
-                     gcnt, goff, gb, ge, gn);
+  hipLaunchKernelGGL(k_groups<true>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, gcnt, goff,
+                     gb, ge, gn);
   NB_TRY(hipGetLastError());
   int32_t ngroups = 0;
   {
