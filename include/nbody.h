@@ -271,7 +271,9 @@ int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_ma
  *    softened pair terms (a pair at zero distance with eps2 = 0 is dropped).
  * Keys, tree, moments, groups and walk are double precision; the force terms
  * are double for an NB_PREC_FP64 context and otherwise float terms from
- * double separations, summed in double per chunk of 64 cells and per leaf.
+ * double separations, summed in double per staged chunk of up to 64 cells or
+ * 64 leaf particles.  The walk and the force evaluation are one kernel (one
+ * wavefront per group); no interaction list is stored.
  * theta = 0 opens every leaf: the direct sum.  pos [N][3], mass [N] in,
  * acc [N][3], pot [N] out, all in the caller's order (device pointers).
  * stats (host array of 5, may be NULL): cells, groups, accepted (group, cell)
@@ -279,7 +281,9 @@ int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_ma
  * (the host reads one count per tree level) and cannot be captured in a
  * graph (NB_ENOTSUP).  Errors: NB_EINVAL for N outside [1, 2^31), negative
  * or non-finite eps2 or theta, n_crit < 1, non-finite g_frac, null
- * pointers; NB_ENOMEM when the interaction lists would exceed 2^31 entries. */
+ * pointers; NB_ENOMEM when device memory runs out or a walk's stack would
+ * exceed its bound (8 x 64 x 21 entries, which an octree of 21 levels cannot
+ * reach); the outputs are then undefined. */
 int nb_tree_forces(nb_ctx *ctx, const double *pos, const double *mass, int64_t N, double eps2, double theta,
                    int32_t n_crit, double g_frac, double *acc, double *pot, int64_t *stats);
 
