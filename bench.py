@@ -78,7 +78,10 @@ def workloads(args):
     hermite65k  Plummer N=65536, eps=1/256, FP64 Hermite block steps (eta=0.01,
                 dt_max=1/16) to t=1/8, graph-replayed; energy drift, steps
     hermite262k Plummer N=262144, eps=1/256, block steps to t=1/8 in FP64 and
-                in mixed precision: drift of each and the time of each
+                in mixed precision: drift of each and the time of each.  Both
+                Hermite workloads also report the active-set sizes and the
+                interactions (sum of n_active x N, from an untimed eager replay
+                of the FP64 run) and the effective rate over the timed run
     batch128    128 Plummer clusters, N log-uniform in [128, 16384],
                 eps_c = 0.05 N_c^-1/3, mixed, block steps to t=1/16, one
                 graph replay per 8 steps vs eager launches
@@ -147,6 +150,21 @@ def workloads(args):
             out[prec] = dict(n=n, steps=bi.steps, clamps=bi.clamps, wall_s=round(wall, 3),
                              E0=E0, E1=E1["E"], drift=abs(E1["E"] - E0) / abs(E0),
                              level_histogram=np.bincount(bi.level.cpu().numpy(), minlength=31).tolist())
+            if prec == precs[0]:
+                # untimed eager replay of the same run: the active-set sizes of every step
+                bc = BlockIntegrator(ctx, t(p.pos), t(p.vel), t(p.mass), 2.0 ** -16, 0.01, 1.0 / 16, 30)
+                end = int(round(0.125 / bc.tick))
+                bc.stop.fill_(end)
+                sizes = []
+                while int(bc.t_tick.min().item()) < end:
+                    bc.step()
+                    sizes.append(int(bc.sched[1].item()))
+                sizes = np.array(sizes, dtype=np.int64)
+                active_stats = dict(steps=len(sizes), mean_active=round(float(sizes.mean()), 1),
+                                    median_active=int(np.median(sizes)), max_active=int(sizes.max()),
+                                    interactions=int(sizes.sum()) * n)
+            out[prec].update(active_stats)
+            out[prec]["gint_effective"] = round(active_stats["interactions"] / wall / 1e9, 1)
             if n == 65536:
                 out[prec]["pos_sample"] = bi.pos.cpu().numpy()[::4096].tolist()
             ctx.close()

@@ -285,6 +285,7 @@ int nb_destroy(nb_ctx* c) {
   if (c->sched_tmp) (void)hipFree(c->sched_tmp);
   if (c->sched_cnt) (void)hipFree(c->sched_cnt);
   if (c->nact32) (void)hipFree(c->nact32);
+  if (c->s_dev) (void)hipFree(c->s_dev);
   if (c->energy_part) (void)hipFree(c->energy_part);
   if (c->batch_buf) (void)hipFree(c->batch_buf);
   if (c->batch_host) (void)hipHostFree(c->batch_host);
@@ -445,6 +446,14 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
     rc = ensure_mirror(c, N);
     if (rc) return rc;
   }
+  if (!c->s_dev) {
+    if (capturing(c->stream)) return fail(c, NB_ENOMEM, "the split slot must be allocated before capture%s");
+    if (hipMalloc(&c->s_dev, sizeof(int)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(c, NB_ENOMEM, "hipMalloc of the split slot failed%s");
+    }
+  }
+  nb::ForceArgs red{};
   for (const Regime& r : regs) {
     if (r.lo > max_active) break;
     const int64_t top = r.hi < max_active ? r.hi : max_active;
@@ -457,8 +466,9 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
     a.act_lo = r.lo;
     a.last = (top == max_active) ? 1 : 0;
     a.eps2 = eps2; a.S = 1; a.target_items = items;
-    a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = nullptr;
+    a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = c->s_dev;
     a.rec = c->mirror;
+    red = a;
     const int IB = nb::ib_of(cfg);
     const int64_t n_iblk_max = (top + IB - 1) / IB;
     // persistent: at most one round of resident workgroups walks the items
@@ -467,9 +477,13 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
     if (grid > rg) grid = rg;
     hipError_t e = nb::launch_forces(c->prec, cfg, mask, a, c->stream, (int)grid, 0);
     if (e != hipSuccess) return hip_fail(c, e, "force kernel launch (device count)");
-    e = nb::launch_reduce_ib(c->prec, a, 1, IB, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch (device count)");
   }
+  // one reduce for all regimes: the regime that worked left its S in s_dev
+  red.n_active = max_active;
+  red.act_lo = 0;
+  red.last = 1;
+  hipError_t e = nb::launch_reduce_ib(c->prec, red, 1, 1, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch (device count)");
   return NB_OK;
 }
 

@@ -582,6 +582,7 @@ __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;  // another regime's launch
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
     S = choose_S(n_act, IB, a.target_items, a.n);
+    if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
@@ -598,15 +599,22 @@ __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
 }
 
 // Fixed-order sum of the S partial blocks, self-term removal, output.
+// With a device count and s_dev set, one reduce serves every regime of the
+// call: the regime that worked left its S in *s_dev.
 template <class P>
 __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB) {
   int64_t n_act = a.n_active;
   int S = S_host;
   if (a.n_active_dev) {
     const int64_t d = *a.n_active_dev;
-    if (d < a.act_lo || (d > a.n_active && !a.last)) return;
-    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-    S = choose_S(n_act, IB, a.target_items, a.n);
+    if (a.s_dev) {
+      n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+      S = *a.s_dev;
+    } else {
+      if (d < a.act_lo || (d > a.n_active && !a.last)) return;
+      n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+      S = choose_S(n_act, IB, a.target_items, a.n);
+    }
   }
   if (S <= 1) return;
   const int64_t total = 7 * n_act;
@@ -755,6 +763,7 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
     S = choose_S(n_act, IB, a.target_items, a.n);
+    if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
@@ -888,6 +897,7 @@ __global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
     S = choose_S(n_act, IB, a.target_items, a.n);
+    if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;

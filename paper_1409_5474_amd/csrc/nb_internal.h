@@ -49,7 +49,7 @@ struct ForceArgs {
   double* jerk;
   double* pot;
   double* part;                 // [S][7][n_active] partial sums when S > 1
-  int* s_dev;                   // unused
+  int* s_dev;                   // device count: the working regime's S, for the shared reduce
   int64_t act_lo;               // device-count mode: work only when count >= act_lo and
   int last;                     // count <= n_active (or any larger count when `last`)
   void* rec;                    // scalar j-path: mirror of n j-records (context-owned)
@@ -209,7 +209,7 @@ struct nb_ctx {
   size_t ws_bytes = 0;
   void* mirror = nullptr;       // j-records of the scalar j-path
   size_t mirror_bytes = 0;
-  int* s_dev = nullptr;         // device-chosen S of the last devcount launch
+  int* s_dev = nullptr;         // S chosen on the device by the last device-count launch
   int64_t* sched_tmp = nullptr; // block minima for the scheduler
   int32_t* sched_cnt = nullptr;
   int32_t* nact32 = nullptr;    // int32 copy of the scheduled active count
