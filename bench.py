@@ -46,7 +46,7 @@ def parse():
                     help="profiling target: a plain device-to-device copy of this many bytes, --steps times "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="", choices=["", "plummer1k", "hermite65k", "hermite262k", "batch128",
-                                                        "merger", "bridge", "hermite6", "tree"],
+                                                        "merger", "bridge", "hermite6", "tree", "passes"],
                     help="instead of the headline line, measure one of the other workloads (see workloads())")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -106,6 +106,12 @@ def workloads(args):
                 -- or with mixed-precision direct forces), cross field in mixed
                 precision; bridge step 1/128; --steps bridge steps after one
                 warm-up step, each part timed
+    passes      the HBM-bound passes of a block step on 2^22 particles (all
+                active): predictor, corrector, scheduler, energy sums, kick
+                and kick-drift; HIP events over --steps launches of each; the
+                algorithmic bytes per particle (every array the pass must read
+                or write, once) over the mean launch time, against the 8 TB/s
+                HBM peak
     """
     import numpy as np
     import torch
@@ -251,6 +257,54 @@ def workloads(args):
             E1 = bi.energy()["E"]
             runs[f"order{order}"] = dict(steps=bi.steps, wall_s=round(wall, 3), drift=abs(E1 - E0) / abs(E0))
         out["plummer65k_to_t_1_8"] = runs
+        ctx.close()
+    elif args.workload == "passes":
+        n = 1 << 22
+        g = torch.Generator(device=dev).manual_seed(7)
+        rnd = lambda *shape: torch.rand(*shape, generator=g, dtype=torch.float64, device=dev)
+        ctx = nb.Context(0, "fp64")
+        pos, vel, acc, jerk = rnd(n, 3), rnd(n, 3), rnd(n, 3), rnd(n, 3)
+        pos_p, vel_p, acc1, jerk1 = rnd(n, 3), rnd(n, 3), rnd(n, 3), rnd(n, 3)
+        mass, pot = rnd(n) + 1.0, -rnd(n)
+        max_level, dt_max = 30, 1.0 / 16
+        level = torch.full((n,), 10, dtype=torch.int32, device=dev)
+        t_tick = torch.zeros(n, dtype=torch.int64, device=dev)
+        active = torch.arange(n, dtype=torch.int32, device=dev)
+        sched = torch.zeros(4, dtype=torch.int64, device=dev)
+        eout = torch.zeros(8, dtype=torch.float64, device=dev)
+        tick = dt_max * 2.0 ** -max_level
+        # bytes per particle: predictor x, v, a, j, t read, x_p, v_p written; corrector (every
+        # particle in the active list; the values only move levels and ticks) index, level, t,
+        # a, j, x_p, v_p, a1, j1 read, x, v, a, j, t, level written; scheduler three passes
+        # over t and level, index written per active particle; energy x, v, m, phi; kick v read
+        # and written, a read; kick-drift x and v read and written, a read
+        passes = {
+            "predict": (152, lambda: ctx.predict(pos, vel, acc, jerk, t_tick, 1 << 20, tick, pos_p, vel_p)),
+            "correct": (268, lambda: ctx.correct(active, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick,
+                                                 level, 0.01, dt_max, max_level)),
+            "schedule": (40, lambda: ctx.schedule(t_tick, level, max_level, active, sched)),
+            "energy": (64, lambda: ctx.energy(pos, vel, mass, pot, eout)),
+            "kick": (72, lambda: ctx.kick(vel_p, acc1, 1e-9)),
+            "kick_drift": (120, lambda: ctx.kick_drift(pos_p, vel_p, acc1, 1e-9, 1e-9)),
+        }
+        res = {}
+        for name, (bpp, fn) in passes.items():
+            fn()
+            torch.cuda.synchronize()
+            reps = max(1, args.steps)
+            e0, e1 = ev(), ev()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            if name == "schedule":
+                # three reads of t and level, and the index of each active particle
+                bpp = 36 + 4 * int(sched[1].item()) / n
+            res[name] = dict(bytes_per_particle=round(bpp, 2), ms=round(ms, 4), gb_s=round(bpp * n / ms / 1e6, 1),
+                             frac_of_8tbs=round(bpp * n / ms / 1e6 / 8000.0, 3))
+        out.update(n=n, passes=res)
         ctx.close()
     elif args.workload == "tree":
         res = {}

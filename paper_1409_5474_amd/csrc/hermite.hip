@@ -277,13 +277,22 @@ __global__ __launch_bounds__(kB) void k_energy_part(const double* __restrict__ p
   if (threadIdx.x < 8) part[(int64_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
 }
 
-__global__ __launch_bounds__(64) void k_energy_final(const double* __restrict__ part, int nblk,
+// Fixed-order sum of the block partials: thread (c, l) of 8 x 32 adds the
+// partials l, l + 32, ... of component c (consecutive threads read
+// consecutive words), then each component's 32 sums are added pairwise.
+__global__ __launch_bounds__(kB) void k_energy_final(const double* __restrict__ part, int nblk,
                                                      double* __restrict__ out) {
-  if (threadIdx.x < 8) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * 8 + threadIdx.x];
-    out[threadIdx.x] = s;
+  __shared__ double red[8][33];
+  const int c = threadIdx.x & 7, l = threadIdx.x >> 3;
+  double s = 0.0;
+  for (int b = l; b < nblk; b += 32) s += part[(int64_t)b * 8 + c];
+  red[c][l] = s;
+  __syncthreads();
+  for (int o = 16; o > 0; o >>= 1) {
+    if (l < o) red[c][l] += red[c][l + o];
+    __syncthreads();
   }
+  if (threadIdx.x < 8) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
 inline int grid_for(int64_t work, int cap) {
@@ -355,7 +364,7 @@ hipError_t launch_energy(const double* pos, const double* vel, const double* mas
                          double* part, double* out, hipStream_t st) {
   const int nblk = energy_blocks(n);
   hipLaunchKernelGGL(k_energy_part, dim3(nblk), dim3(kB), 0, st, pos, vel, mass, pot, n, part);
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, st, part, nblk, out);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kB), 0, st, part, nblk, out);
   return hipGetLastError();
 }
 
