@@ -308,7 +308,7 @@ hipError_t launch_predict(const double* pos, const double* vel, const double* ac
                           const int64_t* t_tick, int64_t t_next, const int64_t* t_next_dev, double dt_min, int64_t n,
                           double* pos_p, double* vel_p, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_predict, dim3(grid_for(3 * n, 8192)), dim3(kB), 0, st, pos, vel, acc, jerk, t_tick, t_next,
+  hipLaunchKernelGGL(k_predict, dim3(grid_for(3 * n, 32768)), dim3(kB), 0, st, pos, vel, acc, jerk, t_tick, t_next,
                      t_next_dev, dt_min, 3 * n, pos_p, vel_p);
   return hipGetLastError();
 }
@@ -318,7 +318,7 @@ hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t
                           double* acc, double* jerk, int64_t* t_tick, int32_t* level, double eta, double dt_max,
                           int max_level, int64_t* clamp_dev, hipStream_t st) {
   if (n_active <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_correct, dim3(grid_for(n_active, 1024)), dim3(kB), 0, st, active, n_active, n_active_dev,
+  hipLaunchKernelGGL(k_correct, dim3(grid_for(n_active, 16384)), dim3(kB), 0, st, active, n_active, n_active_dev,
                      pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, level, eta, dt_max, max_level,
                      reinterpret_cast<unsigned long long*>(clamp_dev), nullptr);
   return hipGetLastError();
