@@ -216,21 +216,24 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
   __syncthreads();
   int64_t off = off_s;
   const int64_t base = (int64_t)blockIdx.x * kSchedBlock;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = 0; r < kSchedPerThread; ++r) {
     const int64_t i = base + r * kB + threadIdx.x;
-    const int flag = (i < n && t_end_of(t_tick, level, i, max_level) == t_next) ? 1 : 0;
-    // inclusive scan of the flags over the block (Hillis-Steele in LDS)
+    const bool flag = i < n && t_end_of(t_tick, level, i, max_level) == t_next;
+    // rank among the flagged lanes of the wavefront, then the wavefronts in order
+    const uint64_t mask = __ballot(flag);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     __syncthreads();
-    sc[threadIdx.x] = flag;
+    if (lane == 0) sc[wave] = __popcll(mask);
     __syncthreads();
-    for (int o = 1; o < kB; o <<= 1) {
-      const int v = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
-      __syncthreads();
-      sc[threadIdx.x] += v;
-      __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < kB / 64; ++w) {
+      before += w < wave ? sc[w] : 0;
+      total += sc[w];
     }
-    if (flag) active[off + sc[threadIdx.x] - 1] = (int32_t)i;
-    off += sc[kB - 1];
+    if (flag) active[off + before + rank] = (int32_t)i;
+    off += total;
   }
   if (blockIdx.x == (unsigned)(nblk - 1) && threadIdx.x == 0) {
     // past the stop time the step is empty: every later kernel does nothing
