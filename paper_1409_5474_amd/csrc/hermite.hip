@@ -282,14 +282,22 @@ __global__ __launch_bounds__(kB) void k_energy_part(const double* __restrict__ p
 
 // Fixed-order sum of the block partials: thread (c, l) of 8 x 32 adds the
 // partials l, l + 32, ... of component c (consecutive threads read
-// consecutive words), then each component's 32 sums are added pairwise.
+// consecutive words) into four running sums taken in turn, so four loads are
+// in flight; then each component's 32 sums are added pairwise.
 __global__ __launch_bounds__(kB) void k_energy_final(const double* __restrict__ part, int nblk,
                                                      double* __restrict__ out) {
   __shared__ double red[8][33];
   const int c = threadIdx.x & 7, l = threadIdx.x >> 3;
-  double s = 0.0;
-  for (int b = l; b < nblk; b += 32) s += part[(int64_t)b * 8 + c];
-  red[c][l] = s;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int b = l;
+  for (; b + 96 < nblk; b += 128) {
+    s0 += part[(int64_t)b * 8 + c];
+    s1 += part[(int64_t)(b + 32) * 8 + c];
+    s2 += part[(int64_t)(b + 64) * 8 + c];
+    s3 += part[(int64_t)(b + 96) * 8 + c];
+  }
+  for (; b < nblk; b += 32) s0 += part[(int64_t)b * 8 + c];
+  red[c][l] = (s0 + s1) + (s2 + s3);
   __syncthreads();
   for (int o = 16; o > 0; o >>= 1) {
     if (l < o) red[c][l] += red[c][l + o];
