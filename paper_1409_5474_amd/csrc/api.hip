@@ -423,7 +423,18 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   if (max_active == 0) return NB_OK;
   const bool mask = kernel_mask(c->prec, eps2);
   // One fixed launch per regime; the count decides on the device which one works.
-  const std::vector<Regime> regs = regimes(c, N);
+  // Adjacent regimes with the same K and L share one launch (every launch,
+  // empty or not, costs a few microseconds in each block step); the merged
+  // regime keeps the work-item target of its upper part, where the work is.
+  std::vector<Regime> regs;
+  for (const Regime& r : regimes(c, N)) {
+    if (!regs.empty() && regs.back().cfg.K == r.cfg.K && regs.back().cfg.L == r.cfg.L) {
+      regs.back().hi = r.hi;
+      regs.back().cfg.items = r.cfg.items;
+    } else {
+      regs.push_back(r);
+    }
+  }
   size_t ws_need = 0;
   for (const Regime& r : regs) {
     if (r.lo > max_active) break;
