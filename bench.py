@@ -372,7 +372,7 @@ def workloads(args):
             E1 = br.energy()
             nsteps = args.steps
             wall = sum(parts.values())
-            cross = 4.0 * ng * nc                # two kicks, both directions
+            cross = 2.0 * ng * nc                # both directions once: the closing kick's field serves the next opening kick
             out[field] = dict(ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
                               ms_per_part={k: round(1e3 * v / nsteps, 2) for k, v in parts.items()},
                               cross_field_gint=round(cross * nsteps / parts["kick"] / 1e9, 1),

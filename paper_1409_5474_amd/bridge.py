@@ -18,6 +18,10 @@ length dt is e^{dt/2 A} e^{dt B} e^{dt/2 A}:
               direct sum (``field="direct"``, ``nbody_forces``);
   kick(dt/2).
 
+The closing kick of one step and the opening kick of the next see the same
+positions, so the cross field computed for the first serves the second
+(kicks change velocities only); any drift invalidates it.
+
 Every arithmetic step runs in the library's kernels; this module only
 sequences the calls on the contexts' streams.  The subsystems may use
 different contexts (and so precisions): ``ctx_c`` for c, ``ctx_g`` for g's
@@ -64,6 +68,7 @@ class Bridge:
         if self.ng:
             self._galaxy_forces()
         self.block_steps = 0
+        self._cross_valid = False   # a_cg, a_gc belong to the current positions
 
     # ---- pieces of the split ----------------------------------------------
     def _galaxy_forces(self):
@@ -86,12 +91,20 @@ class Bridge:
             self.a_gc.zero_()
 
     def kick(self, h):
-        """e^{h A}: velocities of both subsystems move in the other's field."""
-        self.cross_field()
+        """e^{h A}: velocities of both subsystems move in the other's field
+        (computed at the current positions unless a kick already did)."""
+        if not self._cross_valid:
+            self.cross_field()
+            self._cross_valid = True
         self.ctx_x.kick(self.cluster.vel, self.a_cg, h)
         self.ctx_x.kick(self.vg, self.a_gc, h)
 
+    def invalidate(self):
+        """Forget the stored cross field (call after moving positions by hand)."""
+        self._cross_valid = False
+
     def drift_cluster(self, use_graph=True):
+        self._cross_valid = False
         c = self.cluster
         before = c.steps
         c.restart()
@@ -99,6 +112,7 @@ class Bridge:
         self.block_steps += c.steps - before
 
     def drift_galaxy(self):
+        self._cross_valid = False
         h = self.dt / self.n_sub
         for _ in range(self.n_sub):
             self.ctx_g.kick_drift(self.xg, self.vg, self.ag, 0.5 * h, h)
