@@ -2,8 +2,9 @@
 identical interaction sets (accepted cells and opened leaves per group) and
 forces within rounding of the oracle's, theta = 0 reproducing the direct
 sum, edge cases (one particle, coincident particles, two distant clusters,
-unsoftened), repeatability, argument errors, and the mixed-precision force
-terms within float rounding of the oracle."""
+unsoftened, leaves of one particle and of several hundred, a deep clustered
+tree), repeatability, argument errors, and the mixed-precision force terms
+within float rounding of the oracle."""
 import numpy as np
 import pytest
 
@@ -162,3 +163,38 @@ def test_mixed_precision_tree_forces(theta):
     ep = vec_err(pot, rp, np.abs(rp))
     assert ea["rms"] < 1e-6 and ea["normwise"] < 1e-6, ea
     assert ep["rms"] < 1e-6, ep
+
+
+def _clustered(n, seed):
+    """Nested clumps packed ever tighter: a deep octree."""
+    rng = np.random.default_rng(seed)
+    pos = rng.standard_normal((n, 3))
+    m = n // 3
+    for _ in range(7):
+        pos[:m] = pos[:m] * 0.1 + 0.3
+        m //= 2
+    return pos, np.full(n, 1.0 / n)
+
+
+@pytest.mark.parametrize("n_crit,theta", [(1, 0.5), (100, 0.5), (200, 0.0), (300, 0.7)])
+def test_leaf_sizes_from_one_to_beyond_a_wavefront(ctx, n_crit, theta):
+    # leaves of one particle (the deepest tree) and leaves far larger than the
+    # 64 particles the kernel stages at a time
+    p = synth.plummer(2500, 16)
+    acc, pot, st = _gpu(ctx, p.pos, p.mass, 1e-4, theta, n_crit)
+    ra, rp, rst, t = _oracle(p.pos, p.mass, 1e-4, theta, n_crit)
+    assert st["accepted"] == sum(c for c, _, _ in rst)
+    assert st["opened_leaves"] == sum(l for _, l, _ in rst)
+    assert st["cells"] == len(t.cells)
+    _close((acc, pot), (ra, rp), 1e-12)
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.6])
+def test_deep_clustered_tree(ctx, theta):
+    pos, mass = _clustered(3000, 17)
+    acc, pot, st = _gpu(ctx, pos, mass, 1e-8, theta, 8)
+    ra, rp, rst, t = _oracle(pos, mass, 1e-8, theta, 8)
+    assert st["depth"] == max(c.level for c in t.cells) >= 10
+    assert st["accepted"] == sum(c for c, _, _ in rst)
+    assert st["opened_leaves"] == sum(l for _, l, _ in rst)
+    _close((acc, pot), (ra, rp), 1e-12)
