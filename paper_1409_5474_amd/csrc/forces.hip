@@ -942,19 +942,21 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
   }
 }
 
-// One workgroup per system with more than one chunk; fixed-order sums.
+// Systems with more than one chunk (grid y) over a few workgroups each (grid
+// x); each output is the fixed-order sum of its chunks.
 template <class P>
 __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict__ sys,
                                                       const int32_t* __restrict__ nchunk, const double* mass,
                                                       const int32_t* active, double* acc, double* jerk,
                                                       double* pot, const double* part) {
-  const BatchSys sy = sys[blockIdx.x];
-  const int S = nchunk[blockIdx.x];
+  const BatchSys sy = sys[blockIdx.y];
+  const int S = nchunk[blockIdx.y];
   if (S <= 1) return;
   const int64_t n_act = sy.a1 - sy.a0;
   const double* pb = part + sy.part_off * 7;
   const bool self_on = P::eps(sy.eps2) > 0;
-  for (int64_t idx = threadIdx.x; idx < 7 * n_act; idx += blockDim.x) {
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 7 * n_act;
+       idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = idx / n_act;
     const int64_t k = idx - c * n_act;
     double s = 0.0;
@@ -1320,17 +1322,22 @@ hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int
 hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const int32_t* chunks_per_sys,
                                const double* mass, const int32_t* active, int64_t n_act_total, double* acc,
                                double* jerk, double* pot, const double* part, hipStream_t st) {
-  (void)n_act_total;
   if (n_sys <= 0) return hipSuccess;
+  // blocks per system (grid x): enough for a system with the mean share of
+  // the rows to give each thread a few sums; a system's blocks past its rows
+  // return at once
+  int64_t nx = (7 * (n_act_total > 0 ? n_act_total : 1) + (int64_t)n_sys * 1024 - 1) / ((int64_t)n_sys * 1024);
+  nx = nx < 1 ? 1 : (nx > 32 ? 32 : nx);
+  const dim3 grid((unsigned)nx, (unsigned)n_sys);
   if (prec == NB_PREC_FP64)
-    hipLaunchKernelGGL(k_batch_reduce<F64>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
-                       jerk, pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<F64>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc, jerk,
+                       pot, part);
   else if (prec == NB_PREC_MIXED_DS)
-    hipLaunchKernelGGL(k_batch_reduce<MixedDS>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active,
-                       acc, jerk, pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<MixedDS>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
+                       jerk, pot, part);
   else
-    hipLaunchKernelGGL(k_batch_reduce<Mixed>, dim3(n_sys), dim3(256), 0, st, sys, chunks_per_sys, mass, active,
-                       acc, jerk, pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<Mixed>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
+                       jerk, pot, part);
   return hipGetLastError();
 }
 
