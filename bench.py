@@ -104,8 +104,9 @@ def workloads(args):
                 steps, eta=0.01), g = every other star (leapfrog with the
                 mixed-precision tree code at theta=0.5 -- the paper's hybrid
                 -- or with mixed-precision direct forces), cross field in mixed
-                precision; bridge step 1/128; --steps bridge steps after one
-                warm-up step, each part timed
+                precision, direct both ways or (tree_cross) the field of g on c
+                from the tree evaluation; bridge step 1/128; --steps bridge
+                steps after one warm-up step, each part timed
     passes      the HBM-bound passes of a block step on 2^22 particles (all
                 active): predictor, corrector, scheduler, energy sums, kick
                 and kick-drift; HIP events over --steps launches of each; the
@@ -343,12 +344,13 @@ def workloads(args):
         dt = 1.0 / 128
         ng, nc = int(g.size), int(c.size)
         out.update(n_g=ng, n_c=nc, bridge_dt=dt, bridge_steps=args.steps)
-        for field in ("tree", "direct"):
+        for name, field, xfield in (("tree", "tree", "direct"), ("tree_cross", "tree", "tree"),
+                                    ("direct", "direct", "direct")):
             c64, cmx = nb.Context(0, "fp64"), nb.Context(0, "mixed")
             # the field (tree or direct sum) and the cross field in mixed precision, the cluster in FP64
             br = Bridge(c64, cmx, t(m.pos[g]), t(m.vel[g]), t(m.mass[g]), t(m.pos[c]),
                         t(m.vel[c]), t(m.mass[c]), m.eps2, m.eps2, m.eps2, dt, n_sub=1, eta=0.01, max_level=30,
-                        ctx_x=cmx, field=field, theta=0.5)
+                        ctx_x=cmx, field=field, theta=0.5, cross=xfield)
             E0 = br.energy()
             parts = dict(kick=0.0, cluster=0.0, galaxy=0.0)
             block_steps = 0
@@ -372,14 +374,16 @@ def workloads(args):
             E1 = br.energy()
             nsteps = args.steps
             wall = sum(parts.values())
-            cross = 2.0 * ng * nc                # both directions once: the closing kick's field serves the next opening kick
-            out[field] = dict(ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
+            # both directions once (the closing kick's field serves the next opening kick);
+            # with the tree giving the field of g on c, only the field of c on g is a direct sum
+            cross = (1.0 if xfield == "tree" else 2.0) * ng * nc
+            out[name] = dict(ms_per_bridge_step=round(1e3 * wall / nsteps, 2),
                               ms_per_part={k: round(1e3 * v / nsteps, 2) for k, v in parts.items()},
                               cross_field_gint=round(cross * nsteps / parts["kick"] / 1e9, 1),
                               cluster_block_steps_per_bridge_step=round((br.block_steps - block_steps) / nsteps, 1),
                               energy_drift=abs(E1["E"] - E0["E"]) / abs(E0["E"]), time=br.time)
             if field == "direct":
-                out[field]["galaxy_gint"] = round(float(ng) * ng * nsteps / parts["galaxy"] / 1e9, 1)
+                out[name]["galaxy_gint"] = round(float(ng) * ng * nsteps / parts["galaxy"] / 1e9, 1)
             c64.close(); cmx.close()
     print(json.dumps(out), flush=True)
 

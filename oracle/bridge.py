@@ -26,6 +26,15 @@ The field subsystem's own forces come from a routine passed in (``field``:
 positions and masses -> accelerations); by default the direct sum, or the
 oracle's tree code through ``tree_field``.
 
+Cross field (``cross``).  "direct": both directions are direct sums.  "tree":
+each subsystem's own solver gives the field it exerts, as when the two codes
+of the paper's hybrid are coupled -- the field of g on c comes from g's tree
+code, evaluated together with g's own forces on the combined set [g | c] with
+the masses of c set to zero (so c feels g and exerts nothing), and the field
+of c on g is the direct sum over c.  It needs eps2_gc = eps2_g (one tree
+evaluation serves both) and is taken at every evaluation of g's forces, which
+the bridge step makes at the positions its closing kick uses.
+
 Softening: eps2_g inside g, eps2_c inside c, eps2_gc across.  Arithmetic of
 the elementwise updates, in this order and without fused multiply-adds:
 v + (h/2) a, then x + h v.
@@ -84,6 +93,18 @@ def tree_field(eps2, theta, n_crit=16, g_frac=1.0 / 16):
     return f
 
 
+def galaxy_and_cross_tree(xg, mg, xc, eps2, theta, n_crit=16, g_frac=1.0 / 16):
+    """One tree evaluation on [g | c] with c massless: (g's own acceleration,
+    the acceleration of c in the field of g)."""
+    from . import tree as TR
+    ng = np.asarray(mg).shape[0]
+    x = np.concatenate([np.asarray(xg, dtype=np.float64), np.asarray(xc, dtype=np.float64)])
+    m = np.concatenate([np.asarray(mg, dtype=np.float64), np.zeros(np.asarray(xc).shape[0])])
+    t = TR.build(x, m, n_crit)
+    a = TR.forces(x, m, eps2, theta, n_crit, g_max=g_frac * t.side, tree=t)[0]
+    return a[:ng], a[ng:]
+
+
 @dataclass
 class BridgeState:
     xg: np.ndarray
@@ -98,28 +119,51 @@ class BridgeState:
     n_sub: int
     field: object = None
     steps: int = 0
+    cross: str = "direct"
+    tree_args: tuple = ()          # (theta, n_crit, g_frac) for cross = "tree"
+    a_cg: np.ndarray = None        # field of g on c from g's tree (cross = "tree")
 
     @property
     def time(self):
         return self.steps * self.dt
 
 
-def initialise(xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt, n_sub=1, eta=0.01, max_level=30, field=None):
+def initialise(xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt, n_sub=1, eta=0.01, max_level=30, field=None,
+               cross="direct", theta=0.5, n_crit=16, g_frac=1.0 / 16):
     xg = np.array(xg, dtype=np.float64)
     vg = np.array(vg, dtype=np.float64)
     mg = np.array(mg, dtype=np.float64)
+    if cross not in ("direct", "tree"):
+        raise ValueError("cross must be 'direct' or 'tree'")
+    if cross == "tree" and eps2_gc != eps2_g:
+        raise ValueError("cross = 'tree' needs eps2_gc == eps2_g")
     field = field if field is not None else direct_field(eps2_g)
-    ag = field(xg, mg) if mg.shape[0] else np.zeros((0, 3))
     cl = hermite.initialise(np.asarray(xc, dtype=np.float64), np.asarray(vc, dtype=np.float64),
                             np.asarray(mc, dtype=np.float64), eps2_c, eta, dt, max_level, self_forces(eps2_c))
-    return BridgeState(xg, vg, mg, ag, cl, float(eps2_g), float(eps2_c), float(eps2_gc), float(dt), int(n_sub),
-                       field)
+    st = BridgeState(xg, vg, mg, np.zeros((0, 3)), cl, float(eps2_g), float(eps2_c), float(eps2_gc), float(dt),
+                     int(n_sub), field, cross=cross, tree_args=(float(theta), int(n_crit), float(g_frac)))
+    st.a_cg = np.zeros_like(cl.x)
+    if mg.shape[0]:
+        galaxy_forces(st)
+    return st
+
+
+def galaxy_forces(st: BridgeState):
+    """g's own accelerations at the current positions (and, with cross = "tree",
+    the field of g on c from the same tree evaluation)."""
+    if st.cross == "tree":
+        st.ag, st.a_cg = galaxy_and_cross_tree(st.xg, st.mg, st.cluster.x, st.eps2_g, *st.tree_args)
+    else:
+        st.ag = st.field(st.xg, st.mg)
 
 
 def kick(st: BridgeState, h):
     """e^{h A}: both subsystems take the other's field at the current positions."""
     c = st.cluster
-    a_cg = cross_forces(c.x, c.v, st.xg, st.vg, st.mg, st.eps2_gc)[0]
+    if st.cross == "tree":
+        a_cg = st.a_cg
+    else:
+        a_cg = cross_forces(c.x, c.v, st.xg, st.vg, st.mg, st.eps2_gc)[0]
     a_gc = cross_forces(st.xg, st.vg, c.x, c.v, c.m, st.eps2_gc)[0]
     c.v = c.v + h * a_cg
     st.vg = st.vg + h * a_gc
@@ -143,7 +187,7 @@ def drift_galaxy(st: BridgeState):
     for _ in range(st.n_sub):
         st.vg = st.vg + (0.5 * h) * st.ag
         st.xg = st.xg + h * st.vg
-        st.ag = st.field(st.xg, st.mg)
+        galaxy_forces(st)
         st.vg = st.vg + (0.5 * h) * st.ag
 
 

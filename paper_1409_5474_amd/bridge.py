@@ -22,6 +22,14 @@ The closing kick of one step and the opening kick of the next see the same
 positions, so the cross field computed for the first serves the second
 (kicks change velocities only); any drift invalidates it.
 
+Cross field: ``cross="direct"`` sums both directions directly
+(``nbody_forces_ij``).  ``cross="tree"`` (with ``field="tree"``) lets each
+subsystem's solver give the field it exerts, as when the two codes of the
+paper's hybrid are coupled: the field of g on c comes from the tree code,
+evaluated together with g's own forces on the combined set [g | c] with the
+masses of c set to zero, and the field of c on g is the direct sum over c.
+It needs eps2_gc == eps2_g (one tree evaluation serves both).
+
 Every arithmetic step runs in the library's kernels; this module only
 sequences the calls on the contexts' streams.  The subsystems may use
 different contexts (and so precisions): ``ctx_c`` for c, ``ctx_g`` for g's
@@ -38,17 +46,21 @@ from .integrator import BlockIntegrator
 class Bridge:
     def __init__(self, ctx_c: Context, ctx_g: Context, xg, vg, mg, xc, vc, mc, eps2_g, eps2_c, eps2_gc, dt,
                  n_sub=1, eta=0.01, max_level=30, ctx_x: Context = None, field="direct", theta=0.5, n_crit=16,
-                 g_frac=1.0 / 16):
+                 g_frac=1.0 / 16, cross="direct"):
         if field not in ("direct", "tree"):
             raise ValueError("field must be 'direct' or 'tree'")
+        if cross not in ("direct", "tree"):
+            raise ValueError("cross must be 'direct' or 'tree'")
+        if cross == "tree" and (field != "tree" or float(eps2_gc) != float(eps2_g)):
+            raise ValueError("cross='tree' needs field='tree' and eps2_gc == eps2_g")
         self.field, self.theta, self.n_crit, self.g_frac = field, float(theta), int(n_crit), float(g_frac)
+        self.cross = cross
         self.ctx_c, self.ctx_g = ctx_c, ctx_g
         self.ctx_x = ctx_x if ctx_x is not None else ctx_g
         dev = ctx_c.device
         f64 = dict(dtype=torch.float64, device=dev)
         self.eps2_g, self.eps2_c, self.eps2_gc = float(eps2_g), float(eps2_c), float(eps2_gc)
         self.dt, self.n_sub, self.steps = float(dt), int(n_sub), 0
-        self.xg = xg.to(**f64).contiguous().clone()
         self.vg = vg.to(**f64).contiguous().clone()
         self.mg = mg.to(**f64).contiguous()
         self.ng = self.mg.shape[0]
@@ -56,10 +68,24 @@ class Bridge:
         self.nc = self.cluster.n
         self.idx_g = torch.arange(self.ng, dtype=torch.int32, device=dev)
         self.idx_c = torch.arange(self.nc, dtype=torch.int32, device=dev)
-        self.ag = torch.zeros((self.ng, 3), **f64)
+        if cross == "tree":
+            # g's positions and accelerations, and the field of g at c, are
+            # views of the combined [g | c] arrays of the tree evaluation
+            self._xgc = torch.empty((self.ng + self.nc, 3), **f64)
+            self._xgc[:self.ng] = xg.to(**f64)
+            self._mgc = torch.cat([self.mg, torch.zeros(self.nc, **f64)])
+            self._agc = torch.zeros((self.ng + self.nc, 3), **f64)
+            self._pgc = torch.empty(self.ng + self.nc, **f64)
+            self.xg = self._xgc[:self.ng]
+            self.ag = self._agc[:self.ng]
+            self.a_cg = self._agc[self.ng:]
+        else:
+            self.xg = xg.to(**f64).contiguous().clone()
+            self.ag = torch.zeros((self.ng, 3), **f64)
+            self.a_cg = torch.empty((self.nc, 3), **f64)
+        self._tree_cg_valid = False  # the tree's field of g on c belongs to the current positions
         self._jg = torch.empty((self.ng, 3), **f64)
         self._pg = torch.empty(self.ng, **f64)
-        self.a_cg = torch.empty((self.nc, 3), **f64)
         self._j_cg = torch.empty((self.nc, 3), **f64)
         self._p_cg = torch.empty(self.nc, **f64)
         self.a_gc = torch.empty((self.ng, 3), **f64)
@@ -72,7 +98,12 @@ class Bridge:
 
     # ---- pieces of the split ----------------------------------------------
     def _galaxy_forces(self):
-        if self.field == "tree":
+        if self.cross == "tree":
+            self._xgc[self.ng:] = self.cluster.pos
+            self.ctx_g.tree_forces(self._xgc, self._mgc, self.eps2_g, self.theta, self.n_crit, self.g_frac,
+                                   self._agc, self._pgc)
+            self._tree_cg_valid = True
+        elif self.field == "tree":
             self.ctx_g.tree_forces(self.xg, self.mg, self.eps2_g, self.theta, self.n_crit, self.g_frac, self.ag,
                                    self._pg)
         else:
@@ -82,8 +113,12 @@ class Bridge:
         """Field of g on every particle of c and of c on every particle of g."""
         c = self.cluster
         if self.ng and self.nc:
-            self.ctx_x.forces_ij(self.xg, self.vg, self.mg, c.pos, c.vel, self.idx_c, self.eps2_gc,
-                                 self.a_cg, self._j_cg, self._p_cg)
+            if self.cross == "tree":
+                if not self._tree_cg_valid:
+                    self._galaxy_forces()
+            else:
+                self.ctx_x.forces_ij(self.xg, self.vg, self.mg, c.pos, c.vel, self.idx_c, self.eps2_gc,
+                                     self.a_cg, self._j_cg, self._p_cg)
             self.ctx_x.forces_ij(c.pos, c.vel, c.mass, self.xg, self.vg, self.idx_g, self.eps2_gc,
                                  self.a_gc, self._j_gc, self._p_gc)
         else:
@@ -102,9 +137,11 @@ class Bridge:
     def invalidate(self):
         """Forget the stored cross field (call after moving positions by hand)."""
         self._cross_valid = False
+        self._tree_cg_valid = False
 
     def drift_cluster(self, use_graph=True):
         self._cross_valid = False
+        self._tree_cg_valid = False
         c = self.cluster
         before = c.steps
         c.restart()

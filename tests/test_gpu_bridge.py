@@ -238,6 +238,34 @@ def test_bridge_with_the_tree_as_field_solver_follows_the_oracle():
     ctx.close()
 
 
+def test_bridge_with_the_tree_giving_the_cross_field_follows_the_oracle():
+    # Each subsystem's solver gives the field it exerts: g's tree code (over
+    # [g | c] with c massless) gives the field of g on c, the direct sum over
+    # c the field of c on g.
+    import torch
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.bridge import Bridge
+    p, mass, g, c = _cluster_in_galaxy(n=1500, n_c=40, seed=32)
+    eps2_g, eps2_c, dt, eta, ML, theta = 1e-3, 1e-4, 1.0 / 64, 0.01, 20, 0.5
+    ctx = nb.Context(0, "fp64")
+    with pytest.raises(ValueError):
+        Bridge(ctx, ctx, T(p.pos[g]), T(p.vel[g]), T(mass[g]), T(p.pos[c]), T(p.vel[c]), T(mass[c]),
+               eps2_g, eps2_c, 2 * eps2_g, dt, field="tree", cross="tree")
+    br = Bridge(ctx, ctx, T(p.pos[g]), T(p.vel[g]), T(mass[g]), T(p.pos[c]), T(p.vel[c]), T(mass[c]),
+                eps2_g, eps2_c, eps2_g, dt, eta=eta, max_level=ML, field="tree", theta=theta, cross="tree")
+    st = OB.initialise(p.pos[g], p.vel[g], mass[g], p.pos[c], p.vel[c], mass[c], eps2_g, eps2_c, eps2_g, dt,
+                       eta=eta, max_level=ML, field=OB.tree_field(eps2_g, theta), cross="tree", theta=theta)
+    for _ in range(3):
+        br.step()
+        OB.step(st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(br.cluster.level.cpu().numpy(), st.cluster.level)
+    for got, ref in ((br.xg, st.xg), (br.vg, st.vg), (br.cluster.pos, st.cluster.x), (br.cluster.vel, st.cluster.v)):
+        d = np.abs(got.cpu().numpy() - ref).max()
+        assert d <= 1e-11 * np.abs(ref).max(), d
+    ctx.close()
+
+
 def test_bridge_graph_replay_equals_eager():
     import torch
     import paper_1409_5474_amd as nb

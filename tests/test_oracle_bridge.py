@@ -142,3 +142,38 @@ def test_cluster_in_galaxy_converges_at_second_order_in_the_bridge_step():
     d1, d2 = np.abs(xs[0] - xs[1]).max(), np.abs(xs[1] - xs[2]).max()
     assert 3.6 < d1 / d2 < 4.4, (d1, d2)
     assert max(drift) < 1e-4, drift
+
+
+def test_tree_cross_field_at_theta_zero_is_the_direct_bridge():
+    # cross = "tree": the field of g on c comes from g's tree code on [g | c]
+    # with c massless.  At theta = 0 the tree opens every leaf, so the bridge
+    # equals the direct-sum bridge to rounding, and c exerts nothing on g in
+    # that evaluation (g's own forces are those of the tree over g alone).
+    p, g, c = _split(n=260, n_c=20, seed=23)
+    eps2, dt = 1e-3, 1.0 / 64
+    args = (p.pos[g], p.vel[g], p.mass[g], p.pos[c], p.vel[c], p.mass[c], eps2, 1e-4, eps2, dt)
+    a = B.initialise(*args, eta=0.01, max_level=20)
+    b = B.initialise(*args, eta=0.01, max_level=20, field=B.tree_field(eps2, 0.0), cross="tree", theta=0.0)
+    ag_tree = B.tree_field(eps2, 0.0)(p.pos[g], p.mass[g])
+    assert np.abs(b.ag - ag_tree).max() <= 1e-13 * np.abs(ag_tree).max()
+    for _ in range(3):
+        B.step(a)
+        B.step(b)
+    np.testing.assert_array_equal(a.cluster.level, b.cluster.level)
+    for x, y in ((a.xg, b.xg), (a.vg, b.vg), (a.cluster.x, b.cluster.x), (a.cluster.v, b.cluster.v)):
+        assert np.abs(x - y).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_tree_cross_field_conserves_energy_and_needs_one_softening():
+    import pytest
+    p, g, c = _split(n=260, n_c=20, seed=24)
+    eps2, dt = 1e-3, 1.0 / 64
+    args = (p.pos[g], p.vel[g], p.mass[g], p.pos[c], p.vel[c], p.mass[c], eps2, 1e-4)
+    with pytest.raises(ValueError):
+        B.initialise(*args, 2 * eps2, dt, cross="tree")
+    st = B.initialise(*args, eps2, dt, eta=0.01, max_level=20, field=B.tree_field(eps2, 0.5), cross="tree",
+                      theta=0.5)
+    E0 = B.energy(st)["E"]
+    for _ in range(8):
+        B.step(st)
+    assert abs(B.energy(st)["E"] - E0) < 1e-4 * abs(E0)
