@@ -130,7 +130,9 @@ def _bridge_pins():
     return [T.test_cross_field_adds_up_to_the_whole, T.test_kicks_conserve_total_momentum_and_keep_positions,
             T.test_two_body_split_is_the_textbook_leapfrog, T.test_two_body_split_converges_at_second_order,
             T.test_massless_cluster_leaves_the_galaxy_a_plain_leapfrog,
-            T.test_cluster_in_galaxy_converges_at_second_order_in_the_bridge_step]
+            T.test_cluster_in_galaxy_converges_at_second_order_in_the_bridge_step,
+            T.test_tree_cross_field_at_theta_zero_is_the_direct_bridge,
+            T.test_tree_cross_field_conserves_energy_and_needs_one_softening]
 
 
 def _mut_step_first_order(st):
@@ -177,11 +179,23 @@ def _mut_cross_includes_receivers(x_i, v_i, x_j, v_j, m_j, eps2):
     return a, j, p
 
 
+def _mut_tree_cross_c_massive(xg, mg, xc, eps2, theta, n_crit=16, g_frac=1.0 / 16):
+    from oracle import tree as TR
+    ng = np.asarray(mg).shape[0]
+    x = np.concatenate([xg, xc])
+    # c keeps a mass in the tree: it pulls on g and on itself
+    m = np.concatenate([mg, np.full(np.asarray(xc).shape[0], float(np.mean(mg)))])
+    t = TR.build(x, m, n_crit)
+    a = TR.forces(x, m, eps2, theta, n_crit, g_max=g_frac * t.side, tree=t)[0]
+    return a[:ng], a[ng:]
+
+
 BRIDGE_MUTANTS = [("whole kick first (first-order split)", "step", _mut_step_first_order),
                   ("cross field sign", "cross_forces", _mut_cross_sign),
                   ("g never kicked", "kick", _mut_kick_c_only),
                   ("galaxy drifts before its half kick", "drift_galaxy", _mut_galaxy_drift_first),
-                  ("receivers exert forces", "cross_forces", _mut_cross_includes_receivers)]
+                  ("receivers exert forces", "cross_forces", _mut_cross_includes_receivers),
+                  ("c exerts in the tree cross field", "galaxy_and_cross_tree", _mut_tree_cross_c_massive)]
 
 
 @pytest.mark.slow
