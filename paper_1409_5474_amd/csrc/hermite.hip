@@ -244,6 +244,62 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
   }
 }
 
+// Small systems: one workgroup does all three passes (a launch costs more
+// than the passes themselves below a few thousand particles).  Same t_next,
+// same ascending active list as the three-kernel form.
+constexpr int kSchedSingleThreads = 1024;
+constexpr int64_t kSchedSingleMax = 16384;
+
+__global__ __launch_bounds__(kSchedSingleThreads) void k_sched_single(const int64_t* __restrict__ t_tick,
+                                                                      const int32_t* __restrict__ level, int64_t n,
+                                                                      int max_level, int32_t* __restrict__ active,
+                                                                      int64_t* __restrict__ sched,
+                                                                      int32_t* __restrict__ n_active32,
+                                                                      int64_t t_stop_host,
+                                                                      const int64_t* __restrict__ t_stop_dev) {
+  constexpr int W = kSchedSingleThreads / 64;
+  __shared__ int64_t red[kSchedSingleThreads];
+  __shared__ int wc[W];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int64_t m = INT64_MAX;
+  for (int64_t i = t; i < n; i += kSchedSingleThreads) {
+    const int64_t te = t_end_of(t_tick, level, i, max_level);
+    m = te < m ? te : m;
+  }
+  red[t] = m;
+  __syncthreads();
+  for (int o = kSchedSingleThreads / 2; o > 0; o >>= 1) {
+    if (t < o && red[t + o] < red[t]) red[t] = red[t + o];
+    __syncthreads();
+  }
+  const int64_t t_next = red[0];
+  int64_t off = 0;
+  for (int64_t base = 0; base < n; base += kSchedSingleThreads) {
+    const int64_t i = base + t;
+    const bool flag = i < n && t_end_of(t_tick, level, i, max_level) == t_next;
+    const uint64_t mask = __ballot(flag);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+    __syncthreads();
+    if (lane == 0) wc[wave] = __popcll(mask);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < W; ++w) {
+      before += w < wave ? wc[w] : 0;
+      total += wc[w];
+    }
+    if (flag) active[off + before + rank] = (int32_t)i;
+    off += total;
+  }
+  if (t == 0) {
+    const int64_t t_stop = t_stop_dev ? *t_stop_dev : t_stop_host;
+    const int64_t cnt = t_next <= t_stop ? off : 0;
+    sched[0] = t_next;
+    sched[1] = cnt;
+    if (n_active32) *n_active32 = (int32_t)cnt;
+  }
+}
+
 // ----------------------------------------------------------------- energy --
 // Per-block sums of K, m phi, m v, m x cross v (tree order), then one block
 // adds the block sums in index order.
@@ -360,6 +416,11 @@ int schedule_blocks(int64_t n) { return (int)((n + kSchedBlock - 1) / kSchedBloc
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level, int32_t* active,
                            int64_t* sched, int64_t* block_min, int32_t* block_cnt, int32_t* n_active32,
                            int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st) {
+  if (n <= kSchedSingleMax) {
+    hipLaunchKernelGGL(k_sched_single, dim3(1), dim3(kSchedSingleThreads), 0, st, t_tick, level, n, max_level,
+                       active, sched, n_active32, t_stop, t_stop_dev);
+    return hipGetLastError();
+  }
   const int nblk = schedule_blocks(n);
   hipLaunchKernelGGL(k_sched_min, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min);
   hipLaunchKernelGGL(k_sched_count, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min, nblk,
