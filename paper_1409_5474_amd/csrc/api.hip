@@ -150,7 +150,7 @@ struct Regime {
   int64_t lo, hi;
   Launch cfg;
 };
-constexpr int64_t kSmallSystem = 16384;  // device-count launches: one regime up to this N
+constexpr int64_t kSmallSystem = 16384;  // untuned systems up to this N: one launch shape
 const Regime kDefaultRegimes[5] = {{0, 127, Launch{1, 64, 0, 0}},
                                    {128, 1023, Launch{1, 16, 0, 0}},
                                    {1024, 8191, Launch{1, 4, 0, 0}},
@@ -159,8 +159,18 @@ const Regime kDefaultRegimes[5] = {{0, 127, Launch{1, 64, 0, 0}},
 
 // The active-count regimes of this context and precision: the tuned table
 // entries that apply to N (later entries override earlier ones on their
-// range), else the built-in breakpoints.  Regimes tile [0, inf).
+// range), else the built-in breakpoints.  Regimes tile [0, inf).  A system
+// of at most kSmallSystem particles without tuned entries takes one shape
+// for every count: its force work is a few microseconds, so in a block step
+// the empty launches of other regimes would cost more than the shape loses
+// (K = 1, L = 16 stays within 1.3x of the best shape from 1 to N active at
+// N = 3899 and 16384); host-count launches use the same rule, so both paths
+// split the work identically.
 std::vector<Regime> regimes(const nb_ctx* c, int64_t n) {
+  bool tuned = false;
+  for (const nb::TuneEntry& e : c->table)
+    if (e.prec == c->prec && n >= e.n_min) tuned = true;
+  if (!tuned && n <= kSmallSystem) return {Regime{0, INT64_MAX, Launch{1, 16, 0, 0}}};
   std::vector<Regime> r(std::begin(kDefaultRegimes), std::end(kDefaultRegimes));
   for (const nb::TuneEntry& e : c->table) {
     if (e.prec != c->prec || n < e.n_min) continue;
@@ -428,23 +438,12 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   // empty or not, costs a few microseconds in each block step); the merged
   // regime keeps the work-item target of its upper part, where the work is.
   std::vector<Regime> regs;
-  // A small system without tuned entries takes one shape for every count:
-  // its force work is a few microseconds, so the empty launches of the
-  // other regimes would cost more than the shape loses (K = 1, L = 16 stays
-  // within 1.3x of the best shape from 1 to N active at N = 3899 and 16384).
-  bool tuned = false;
-  for (const nb::TuneEntry& e : c->table)
-    if (e.prec == c->prec && N >= e.n_min) tuned = true;
-  if (N <= kSmallSystem && !tuned) {
-    regs.push_back(Regime{0, INT64_MAX, Launch{1, 16, 0, 0}});
-  } else {
-    for (const Regime& r : regimes(c, N)) {
-      if (!regs.empty() && regs.back().cfg.K == r.cfg.K && regs.back().cfg.L == r.cfg.L) {
-        regs.back().hi = r.hi;
-        regs.back().cfg.items = r.cfg.items;
-      } else {
-        regs.push_back(r);
-      }
+  for (const Regime& r : regimes(c, N)) {
+    if (!regs.empty() && regs.back().cfg.K == r.cfg.K && regs.back().cfg.L == r.cfg.L) {
+      regs.back().hi = r.hi;
+      regs.back().cfg.items = r.cfg.items;
+    } else {
+      regs.push_back(r);
     }
   }
   size_t ws_need = 0;
