@@ -108,12 +108,22 @@ class BlockIntegrator:
             self._graphs[steps] = g
         return g
 
-    def run_until(self, t_end, graph_steps=32, use_graph=True):
-        """Integrate until every particle reaches t_end (a multiple of dt_max)."""
+    def run_until(self, t_end, graph_steps=32, use_graph=True, log=None):
+        """Integrate until every particle reaches t_end (a multiple of dt_max).
+        With ``log`` (a callable), stop at every synchronisation time (each
+        multiple of dt_max) on the way and pass it ``diagnostics()``."""
         end = int(round(t_end / self.tick))
         if end * self.tick != t_end:
             raise ValueError("t_end must be a whole number of ticks")
-        return self.run_to_tick(end, graph_steps, use_graph)
+        if log is None:
+            return self.run_to_tick(end, graph_steps, use_graph)
+        sync = 1 << self.max_level
+        tick = (int(self.t_tick.min().item()) // sync + 1) * sync
+        while tick <= end:
+            self.run_to_tick(tick, graph_steps, use_graph)
+            log(self.diagnostics())
+            tick += sync
+        return self
 
     def restart(self):
         """Start afresh from the current (synchronised) state: forces on every
@@ -213,6 +223,17 @@ class BlockIntegrator:
         self.ctx.energy(self.pos, self.vel, self.mass, pot, out)
         o = out.cpu().tolist()
         return dict(K=o[0], W=o[1], E=o[0] + o[1], P=o[2:5], L=o[5:8])
+
+    def diagnostics(self):
+        """The state at a synchronisation time: time, steps so far, clamped
+        level changes, energy and its change since the first call, momentum,
+        angular momentum and the virial ratio 2K/|W|."""
+        e = self.energy()
+        if not hasattr(self, "_E0"):
+            self._E0 = e["E"]
+        return dict(t=self.time, steps=self.steps, clamps=self.clamps, E=e["E"], K=e["K"], W=e["W"],
+                    dE_rel=abs(e["E"] - self._E0) / abs(self._E0) if self._E0 else 0.0, P=e["P"], L=e["L"],
+                    virial=2.0 * e["K"] / abs(e["W"]) if e["W"] else float("inf"))
 
 
 class BlockIntegrator6(BlockIntegrator):

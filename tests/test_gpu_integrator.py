@@ -115,3 +115,23 @@ def test_one_graph_serves_every_stop_time(ctx):
     for k in ("pos", "vel", "acc", "jerk", "t_tick", "level"):
         assert torch.equal(getattr(g, k), getattr(e, k)), k
     assert g.steps == e.steps
+
+
+def test_run_until_logs_every_synchronisation_time(ctx):
+    # log(diagnostics()) at t = dt_max, 2 dt_max, ... and the same end state
+    # as a run without stops (the stop tick only ends graphs, steps are equal)
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    p = synth.plummer(2048, 51)
+    a = BlockIntegrator(ctx, T(p.pos), T(p.vel), T(p.mass), 1e-3, 0.02, 1.0 / 32, 20)
+    b = BlockIntegrator(ctx, T(p.pos), T(p.vel), T(p.mass), 1e-3, 0.02, 1.0 / 32, 20)
+    rec = []
+    a.run_until(1.0 / 8, log=rec.append)
+    b.run_until(1.0 / 8)
+    assert [r["t"] for r in rec] == [k / 32 for k in range(1, 5)]
+    assert rec[-1]["steps"] == b.steps
+    import torch
+    assert torch.equal(a.pos, b.pos) and torch.equal(a.vel, b.vel)
+    for r in rec:
+        assert r["dE_rel"] < 1e-4 and 0.5 < r["virial"] < 1.5
+        assert set(r) >= {"t", "steps", "clamps", "E", "K", "W", "dE_rel", "P", "L", "virial"}
