@@ -49,7 +49,7 @@ def test_all_active_cost_grows_as_n_squared():
     import torch
     import paper_1409_5474_amd as nb
     ctx = nb.Context(0, "fp64")
-    ns, ts = [65536, 131072, 262144], []
+    ns, ts = [131072, 262144, 524288], []   # sizes that fill the chip
     for n in ns:
         p = synth.plummer(n, 32)
         act = torch.arange(n, dtype=torch.int32, device="cuda")
