@@ -619,12 +619,17 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
   if (S <= 1) return;
   const int64_t total = 7 * n_act;
   const bool self_on = P::eps(a.eps2) > 0;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  // g lanes per output (a power of two dividing the 256-thread block, so the
+  // index below is the same across each output's lanes)
+  const int g = chunk_lanes(S);
+  const int lg = __builtin_ctz(g);
+  const int lane = threadIdx.x & (g - 1);
+  for (int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg; idx < total;
+       idx += ((int64_t)gridDim.x * blockDim.x) >> lg) {
     const int64_t c = idx / n_act;
     const int64_t k = idx - c * n_act;
-    double s = 0.0;
-    for (int ch = 0; ch < S; ++ch) s += a.part[((int64_t)ch * 7 + c) * n_act + k];
+    const double s = sum_blocks(a.part + c * n_act + k, 7 * n_act, S, lane, g);
+    if (lane != 0) continue;
     if (c < 3) {
       a.acc[3 * k + c] = s;
     } else if (c < 6) {
@@ -955,12 +960,15 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict
   const int64_t n_act = sy.a1 - sy.a0;
   const double* pb = part + sy.part_off * 7;
   const bool self_on = P::eps(sy.eps2) > 0;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < 7 * n_act;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  const int g = chunk_lanes(S);
+  const int lg = __builtin_ctz(g);
+  const int lane = threadIdx.x & (g - 1);
+  for (int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg; idx < 7 * n_act;
+       idx += ((int64_t)gridDim.x * blockDim.x) >> lg) {
     const int64_t c = idx / n_act;
     const int64_t k = idx - c * n_act;
-    double s = 0.0;
-    for (int ch = 0; ch < S; ++ch) s += pb[((int64_t)ch * 7 + c) * n_act + k];
+    const double s = sum_blocks(pb + c * n_act + k, 7 * n_act, S, lane, g);
+    if (lane != 0) continue;
     const int64_t row = sy.a0 + k;
     if (c < 3) {
       acc[3 * row + c] = s;
@@ -1284,16 +1292,25 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
 
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st) {
   if (!a.n_active_dev && S <= 1) return hipSuccess;
-  const int64_t total = 7 * a.n_active;
-  int grid = (int)((total + 255) / 256);
+  // threads: 7 outputs per row times the lanes per output; with the count
+  // and S on the device, at least the rows' threads, and up to 1024 blocks
+  // for a small count with many blocks to add (a grid-stride loop covers the
+  // rest)
+  const int64_t rows = 7 * a.n_active;
+  int64_t threads = rows * chunk_lanes(S);
+  if (a.n_active_dev) {
+    threads = rows * 64 < (int64_t)1024 * 256 ? rows * 64 : (int64_t)1024 * 256;
+    if (threads < rows) threads = rows;
+  }
+  int64_t grid = (threads + 255) / 256;
   if (grid > 4096) grid = 4096;
   if (grid < 1) grid = 1;
   if (prec == NB_PREC_FP64)
-    hipLaunchKernelGGL(k_reduce<F64>, dim3(grid), dim3(256), 0, st, a, S, IB);
+    hipLaunchKernelGGL(k_reduce<F64>, dim3((unsigned)grid), dim3(256), 0, st, a, S, IB);
   else if (prec == NB_PREC_MIXED_DS)
-    hipLaunchKernelGGL(k_reduce<MixedDS>, dim3(grid), dim3(256), 0, st, a, S, IB);
+    hipLaunchKernelGGL(k_reduce<MixedDS>, dim3((unsigned)grid), dim3(256), 0, st, a, S, IB);
   else
-    hipLaunchKernelGGL(k_reduce<Mixed>, dim3(grid), dim3(256), 0, st, a, S, IB);
+    hipLaunchKernelGGL(k_reduce<Mixed>, dim3((unsigned)grid), dim3(256), 0, st, a, S, IB);
   return hipGetLastError();
 }
 
@@ -1324,9 +1341,9 @@ hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const i
                                double* jerk, double* pot, const double* part, hipStream_t st) {
   if (n_sys <= 0) return hipSuccess;
   // blocks per system (grid x): enough for a system with the mean share of
-  // the rows to give each thread a few sums; a system's blocks past its rows
-  // return at once
-  int64_t nx = (7 * (n_act_total > 0 ? n_act_total : 1) + (int64_t)n_sys * 1024 - 1) / ((int64_t)n_sys * 1024);
+  // the rows, at up to 16 lanes per output, to give each thread a few sums; a
+  // system's blocks past its rows return at once
+  int64_t nx = (7 * 16 * (n_act_total > 0 ? n_act_total : 1) + (int64_t)n_sys * 1024 - 1) / ((int64_t)n_sys * 1024);
   nx = nx < 1 ? 1 : (nx > 32 ? 32 : nx);
   const dim3 grid((unsigned)nx, (unsigned)n_sys);
   if (prec == NB_PREC_FP64)

@@ -195,12 +195,15 @@ __global__ __launch_bounds__(256) void k_reduce6(Force6Args a) {
   const int S = a.n_active_dev ? split6(n_act, a.target_items, a.n) : a.S;
   if (S <= 1) return;
   const int64_t total = kC6 * n_act;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
+  const int g = chunk_lanes(S);
+  const int lg = __builtin_ctz(g);
+  const int lane = threadIdx.x & (g - 1);
+  for (int64_t idx = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> lg; idx < total;
+       idx += ((int64_t)gridDim.x * blockDim.x) >> lg) {
     const int64_t c = idx / n_act;
     const int64_t k = idx - c * n_act;
-    double s = 0.0;
-    for (int ch = 0; ch < S; ++ch) s += a.part[((int64_t)ch * kC6 + c) * n_act + k];
+    const double s = sum_blocks(a.part + c * n_act + k, kC6 * n_act, S, lane, g);
+    if (lane != 0) continue;
     if (c < 3) {
       a.acc[3 * k + c] = s;
     } else if (c < 6) {
@@ -251,7 +254,16 @@ hipError_t launch_forces6(const Force6Args& a, bool mask, int grid, hipStream_t 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!a.n_active_dev && a.S <= 1) return hipSuccess;
-  int64_t rg = (kC6 * a.n_active + 255) / 256;
+  // threads: the outputs times the lanes per output (with the count on the
+  // device, as for the fourth-order reduce: up to 1024 blocks, at least the
+  // outputs' threads)
+  const int64_t outs = kC6 * a.n_active;
+  int64_t threads = outs * chunk_lanes(a.S);
+  if (a.n_active_dev) {
+    threads = outs * 64 < (int64_t)1024 * 256 ? outs * 64 : (int64_t)1024 * 256;
+    if (threads < outs) threads = outs;
+  }
+  int64_t rg = (threads + 255) / 256;
   if (rg > 4096) rg = 4096;
   if (rg < 1) rg = 1;
   hipLaunchKernelGGL(k_reduce6, dim3((int)rg), dim3(256), 0, st, a);

@@ -25,6 +25,28 @@ struct Launch {
 // one i-slot per lane like L = 1).
 inline int ib_of(const Launch& c) { return (kWG / (c.L > 0 ? c.L : 1)) * c.K; }
 
+// Lanes that share one output of a j-split sum over S partial blocks: the
+// fewest (a power of two, at most a wavefront) with no lane adding more than
+// four blocks.  A small active set gets many blocks, and one lane reading
+// them all in turn is bound by their load latency.
+__host__ __device__ constexpr int chunk_lanes(int S) {
+  int g = 1;
+  while (g < 64 && 4 * g < S) g <<= 1;
+  return g;
+}
+
+// The sum of one output over its S blocks p[0], p[stride], ...: `lane` of g
+// (g = chunk_lanes(S), the g lanes consecutive and g-aligned in the
+// wavefront, all of them calling) adds blocks lane, lane + g, ... in
+// ascending order, then a fixed butterfly folds the g sums.  The value lane 0
+// returns depends on S alone, not on the launch.
+__device__ __forceinline__ double sum_blocks(const double* __restrict__ p, int64_t stride, int S, int lane, int g) {
+  double s = 0.0;
+  for (int ch = lane; ch < S; ch += g) s += p[(int64_t)ch * stride];
+  for (int m = g >> 1; m > 0; m >>= 1) s += __shfl_xor(s, m);
+  return s;
+}
+
 struct TuneEntry {
   int prec;
   int64_t n_min, act_min, act_max;

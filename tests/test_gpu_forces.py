@@ -159,6 +159,20 @@ def test_zero_softening_masks_coincident_pairs(ctx, prec, L):
         check_mixed(res, ref, acc_rms=1e-5, jerk_rms=1e-4, pot_rms=1e-5)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("S", [3, 7, 13, 61, 256])
+def test_split_sum_over_many_blocks(ctx, prec, S):
+    # A few rows against up to 256 j-blocks: the partial sums of one output
+    # are added by 1 to 64 lanes (at most four blocks each) and folded.
+    p = _case(66000, 31)
+    act = np.array([0, 17, 17, 40000, 65999], dtype=np.int32)
+    ref = oracle.forces_ld(p.pos, p.vel, p.mass, 2.0 ** -16, act)
+    res = run_gpu(ctx, prec, p, 2.0 ** -16, act, (1, 64, S))
+    (check_fp64 if prec == "fp64" else check_mixed)(res, ref)
+    for arr in res:
+        assert np.array_equal(arr[1], arr[2])
+
+
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("launch", [(1, 4, 3), (2, 0, 2)])
 def test_bitwise_deterministic(ctx, prec, launch):
