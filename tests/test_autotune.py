@@ -32,6 +32,27 @@ def test_save_and_load_order(tmp_path):
     assert json.load(open(p))["meta"]["device"] == "test"
 
 
+def test_shape_runs_merge_only_within_the_launch_cost():
+    # A run of buckets takes a neighbouring run's shape only when that costs
+    # each of its buckets at most one launch; merges repeat until none fits,
+    # and a bucket's loss never exceeds the launches saved.
+    from paper_1409_5474_amd.autotune import _merge_shapes
+    A, B, C, D = (1, 256), (1, 64), (1, 16), (2, 1)
+    times = [{A: 15, B: 17, C: 20, D: 90}, {A: 18, B: 19, C: 30, D: 80},
+             {A: 30, B: 24, C: 25, D: 60}, {A: 60, B: 50, C: 44, D: 50}, {A: 900, B: 400, C: 300, D: 100}]
+    fastest = [min(t, key=t.get) for t in times]
+    assert fastest == [A, A, B, C, D]
+    assert _merge_shapes(fastest, times, 0) == fastest
+    got = _merge_shapes(fastest, times, 3)
+    assert got == [A, A, C, C, D]          # B -> C costs 1 at bucket 2; nothing else within 3
+    saved = len({*fastest}) - len({*got})
+    assert all(times[b][got[b]] - times[b][fastest[b]] <= 3 * saved for b in range(5))
+    assert _merge_shapes(fastest, times, 10**6) in ([A] * 5, [B] * 5, [C] * 5, [D] * 5)
+    # a shape not timed at some bucket of the run (K > 1 below 64 K rows) is never taken there
+    t2 = [{A: 10}, {A: 12, D: 12}]
+    assert _merge_shapes([A, D], t2, 5) == [A, A]
+
+
 @pytest.mark.gpu
 def test_small_tuning_run_keeps_parity(tmp_path):
     import torch
