@@ -160,12 +160,13 @@ def test_zero_softening_masks_coincident_pairs(ctx, prec, L):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("S", [3, 7, 13, 61, 256])
-def test_split_sum_over_many_blocks(ctx, prec, S):
-    # A few rows against up to 256 j-blocks: the partial sums of one output
-    # are added by 1 to 64 lanes (at most four blocks each) and folded.
-    p = _case(66000, 31)
-    act = np.array([0, 17, 17, 40000, 65999], dtype=np.int32)
+@pytest.mark.parametrize("n,S", [(66000, 3), (66000, 7), (66000, 13), (66000, 61), (66000, 256), (160000, 600)])
+def test_split_sum_over_many_blocks(ctx, prec, n, S):
+    # A few rows against up to 600 j-blocks: the partial sums of one output
+    # are added by 1 to 64 lanes (at most four blocks each up to S = 256,
+    # more beyond) and folded.
+    p = _case(n, 31)
+    act = np.array([0, 17, 17, 40000, n - 1], dtype=np.int32)
     ref = oracle.forces_ld(p.pos, p.vel, p.mass, 2.0 ** -16, act)
     res = run_gpu(ctx, prec, p, 2.0 ** -16, act, (1, 64, S))
     (check_fp64 if prec == "fp64" else check_mixed)(res, ref)
