@@ -189,3 +189,76 @@ def test_f64_agrees_with_extended_within_rounding():
     ep = np.abs(ph - r["pot"]) / r["abs_pot"]
     # N=1024 terms, a few roundings each: well under 1024 * 2^-53.
     assert ea.max() < 1e-13 and ej.max() < 1e-13 and ep.max() < 1e-13
+
+
+def _mp_forces(pos, vel, m, eps2, dps=50):
+    """The force sum of the method's definition (i/j sum of section
+    'Optimizations for the GPU'; Plummer softening, G = 1), evaluated with
+    50-digit mpmath numbers from the double inputs: an evaluation that
+    shares nothing with the oracle's C code or its rounding."""
+    import mpmath
+    with mpmath.workdps(dps):
+        mp = mpmath.mpf
+        n = len(m)
+        P = [[mp(float(c)) for c in row] for row in pos]
+        V = [[mp(float(c)) for c in row] for row in vel]
+        M = [mp(float(c)) for c in m]
+        e2 = mp(float(eps2))
+        out = []
+        for i in range(n):
+            a = [mp(0)] * 3
+            jk = [mp(0)] * 3
+            ph = mp(0)
+            for j in range(n):
+                if j == i:
+                    continue
+                r = [P[j][c] - P[i][c] for c in range(3)]
+                u = [V[j][c] - V[i][c] for c in range(3)]
+                s = r[0] ** 2 + r[1] ** 2 + r[2] ** 2 + e2
+                rs = mpmath.sqrt(s)
+                ru = r[0] * u[0] + r[1] * u[1] + r[2] * u[2]
+                for c in range(3):
+                    a[c] += M[j] * r[c] / (s * rs)
+                    jk[c] += M[j] * u[c] / (s * rs) - 3 * M[j] * ru * r[c] / (s * s * rs)
+                ph -= M[j] / rs
+            out.append(([float(x) for x in a], [float(x) for x in jk], float(ph)))
+    acc = np.array([o[0] for o in out])
+    jerk = np.array([o[1] for o in out])
+    pot = np.array([o[2] for o in out])
+    return acc, jerk, pot
+
+
+@pytest.mark.parametrize("eps2", [0.0, 1e-2])
+def test_mpmath_brute_force_small_sets(eps2):
+    # Random sets of 2..8 particles with unequal masses: both oracle
+    # evaluations agree with the 50-digit sum of the definition.  Per
+    # particle, e = |got - exact| / |exact| and kappa = sum_j |term_j| / |exact|
+    # (the condition of the sum).  Extended precision: e <= 1e-15 (kappa/8 times
+    # that where the sum cancels).  Plain double: each term takes about ten
+    # roundings and the sum n - 1 more, so e <= (n + 12) u max(1, kappa),
+    # u = 2^-53 -- a dropped term, a wrong sign or index is off by O(1).
+    rng = np.random.default_rng(2024)
+    worst = 0.0
+    for trial in range(24):
+        n = 2 + trial % 7
+        pos = rng.uniform(-1.0, 1.0, (n, 3))
+        vel = rng.uniform(-0.5, 0.5, (n, 3))
+        m = rng.uniform(0.1, 1.0, n)
+        ea, ej, ep = _mp_forces(pos, vel, m, eps2)
+        a, j, p, sk = oracle.forces_f64(pos, vel, m, eps2)
+        r = oracle.forces_ld(pos, vel, m, eps2)
+        assert sk == 0 and r["skipped"] == 0
+        for k in range(n):
+            for got_a, got_j, got_p, name in ((a, j, p, "f64"), (r["acc"], r["jerk"], r["pot"], "ld")):
+                for got, ref, absum in ((got_a[k], ea[k], r["abs_acc"][k]), (got_j[k], ej[k], r["abs_jerk"][k]),
+                                        (np.array([got_p[k]]), np.array([ep[k]]), r["abs_pot"][k])):
+                    nrm = np.linalg.norm(ref)
+                    err = np.linalg.norm(got - ref) / nrm
+                    kappa = absum / nrm
+                    if name == "ld":
+                        bound = 1e-15 * max(1.0, kappa / 8.0)
+                    else:
+                        bound = (n + 12) * 2.0 ** -53 * max(1.0, kappa)
+                    assert err <= bound, (trial, n, k, name, err, kappa)
+                    worst = max(worst, err / bound)
+    assert worst > 0.0   # the comparison really ran on rounded values

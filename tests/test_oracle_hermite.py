@@ -183,3 +183,53 @@ def test_energy_drift_falls_with_eta():
     # should give ~16x; demand at least 4x.
     assert drifts[1] * 4 < drifts[0], drifts
     assert drifts[1] < 1e-5, drifts
+
+
+def _circular_pair(m1=0.3, m2=0.9, d=1.5):
+    """Two bodies on a circular orbit in the xy plane, centre of mass at rest
+    at the origin (Kepler: relative speed sqrt(M/d)).  Returns x, v, m and the
+    potentials phi_1 = -m2/d, phi_2 = -m1/d written out by hand."""
+    M = m1 + m2
+    v = np.sqrt(M / d)
+    x = np.array([[-m2 / M * d, 0, 0], [m1 / M * d, 0, 0]])
+    vv = np.array([[0, -m2 / M * v, 0], [0, m1 / M * v, 0]])
+    m = np.array([m1, m2])
+    pot = np.array([-m2 / d, -m1 / d])
+    return x, vv, m, pot
+
+
+def test_energy_circular_two_body_closed_form():
+    # K = m1 m2 / (2d), W = -m1 m2 / d, P = 0 and L = m1 m2 sqrt(d/M) along +z
+    # (the orbit turns counter-clockwise seen from +z).
+    m1, m2, d = 0.3, 0.9, 1.5
+    x, v, m, pot = _circular_pair(m1, m2, d)
+    e = H.energy(x, v, m, pot)
+    assert e["K"] == pytest.approx(m1 * m2 / (2 * d), rel=1e-15)
+    assert e["W"] == pytest.approx(-m1 * m2 / d, rel=1e-15)
+    assert e["E"] == pytest.approx(-m1 * m2 / (2 * d), rel=1e-15)
+    assert np.abs(e["P"]).max() < 1e-16
+    assert e["L"] == pytest.approx([0, 0, m1 * m2 * np.sqrt(d / (m1 + m2))], rel=1e-15, abs=1e-16)
+    # W from the oracle's own potentials equals the hand value too
+    r = oracle.forces_ld(x, v, m, 0.0)
+    assert H.energy(x, v, m, r["pot"])["W"] == pytest.approx(-m1 * m2 / d, rel=1e-15)
+
+
+def test_energy_rotated_and_boosted_pair():
+    # Rotate by R, shift by X0 and boost by V: P = M V, L = R L0 + M X0 x V,
+    # K = K0 + M |V|^2 / 2, W unchanged (fixes the order of the cross
+    # product, the mass weighting of P and the halves in K and W).
+    m1, m2, d = 0.3, 0.9, 1.5
+    M = m1 + m2
+    x, v, m, pot = _circular_pair(m1, m2, d)
+    e0 = H.energy(x, v, m, pot)
+    rng = np.random.default_rng(11)
+    R, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    if np.linalg.det(R) < 0:
+        R[:, 0] = -R[:, 0]
+    X0 = np.array([0.4, -1.1, 2.0])
+    V = np.array([-0.3, 0.25, 0.7])
+    e = H.energy(x @ R.T + X0, v @ R.T + V, m, pot)
+    assert e["P"] == pytest.approx(M * V, rel=1e-14, abs=1e-15)
+    assert e["L"] == pytest.approx(R @ e0["L"] + M * np.cross(X0, V), rel=1e-13, abs=1e-14)
+    assert e["K"] == pytest.approx(e0["K"] + 0.5 * M * V @ V, rel=1e-14)
+    assert e["W"] == pytest.approx(e0["W"], rel=1e-15)

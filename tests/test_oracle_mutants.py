@@ -51,6 +51,27 @@ def test_force_pins_catch_mutant(tmp_path, name, pat, rep):
     assert r.returncode == 1, f"mutant {name!r} survived:\n{r.stdout[-2000:]}"
 
 
+# Mutants that the 50-digit brute-force pin alone must catch (it runs by itself
+# against each of them).
+BRUTE_FORCE_MUTANTS = [
+    ("i's mass weights the acceleration", r"mass\[j\] \* inv_sqrt_s \* inv_s;", "mass[i] * inv_sqrt_s * inv_s;"),
+    ("r.u takes u_y for u_z", r"rz \* uz;", "rz * uy;"),
+    ("last j dropped", r"int64_t j = 0; j < n;", "int64_t j = 0; j < n - 1;"),
+    ("softening counted twice", r" \+ \(long double\)eps2;| \+ eps2;", " + 2 * eps2;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,pat,rep", BRUTE_FORCE_MUTANTS, ids=[m[0] for m in BRUTE_FORCE_MUTANTS])
+def test_brute_force_pin_catches_mutant(tmp_path, name, pat, rep):
+    so = _build_mutant(tmp_path, name, pat, rep)
+    env = dict(os.environ, NB_ORACLE_LIB=str(so), PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_forces.py") + "::test_mpmath_brute_force_small_sets"],
+                       env=env, capture_output=True, text=True, cwd=ROOT)
+    assert r.returncode == 1, f"mutant {name!r} survived the brute-force pin:\n{r.stdout[-2000:]}"
+
+
 # Hermite mutants: patch one function of oracle.hermite and run a pin.
 def _hermite_pins():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
@@ -121,6 +142,55 @@ def test_hermite_pins_catch_mutant(monkeypatch, name, attr, fn):
             caught = True
             break
     assert caught, f"mutant {name!r} survived every Hermite pin"
+
+
+def _mut_energy_L_reversed(pos, vel, mass, pot):
+    e = _ENERGY(pos, vel, mass, pot)
+    e["L"] = (mass[:, None] * np.cross(vel, pos)).sum(0)     # v x x instead of x x v
+    return e
+
+
+def _mut_energy_no_half_W(pos, vel, mass, pot):
+    e = _ENERGY(pos, vel, mass, pot)
+    e["W"] = 2.0 * e["W"]                                    # every pair counted twice
+    e["E"] = e["K"] + e["W"]
+    return e
+
+
+def _mut_energy_P_unweighted(pos, vel, mass, pot):
+    e = _ENERGY(pos, vel, mass, pot)
+    e["P"] = vel.sum(0)
+    return e
+
+
+def _mut_energy_L_unweighted(pos, vel, mass, pot):
+    e = _ENERGY(pos, vel, mass, pot)
+    e["L"] = np.cross(pos, vel).sum(0)
+    return e
+
+
+from oracle.hermite import energy as _ENERGY  # noqa: E402
+
+ENERGY_MUTANTS = [("angular momentum v x x", _mut_energy_L_reversed),
+                  ("potential energy without the half", _mut_energy_no_half_W),
+                  ("momentum without masses", _mut_energy_P_unweighted),
+                  ("angular momentum without masses", _mut_energy_L_unweighted)]
+
+
+@pytest.mark.parametrize("name,fn", ENERGY_MUTANTS, ids=[m[0] for m in ENERGY_MUTANTS])
+def test_energy_pins_catch_mutant(monkeypatch, name, fn):
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_oracle_hermite as T
+    from oracle import hermite as H
+    monkeypatch.setattr(H, "energy", fn)
+    caught = False
+    for pin in (T.test_energy_circular_two_body_closed_form, T.test_energy_rotated_and_boosted_pair):
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived the energy pins"
 
 
 # Bridge mutants: patch one function of oracle.bridge and run its pins.
@@ -378,3 +448,51 @@ def test_tree_pins_catch_mutant(monkeypatch, name, attr, fn):
             caught = True
             break
     assert caught, f"mutant {name!r} survived every tree pin"
+
+
+# Generator mutants: one mistake planted in a copy of the synth source, loaded
+# as its own module whose functions replace synth's for the pins.
+SYNTH_SRC = os.path.join(ROOT, "synth", "__init__.py")
+SYNTH_MUTANTS = [
+    ("Plummer radius exponent -1/2", r"np\.power\(x, -2\.0 / 3\.0\)", "np.power(x, -0.5)"),
+    ("Plummer speed density exponent 5/2", r"np\.power\(1\.0 - qq \* qq, 3\.5\)", "np.power(1.0 - qq * qq, 2.5)"),
+    ("Plummer escape factor sqrt(2) dropped", r"speed = q \* np\.sqrt\(2\.0\) \*", "speed = q *"),
+    ("Plummer length unit not scaled", r"pos \*= 3\.0 \* np\.pi / 16\.0", "pos *= 1.0"),
+    ("Hernquist radius X/(1-X)", r"r = sx / \(1\.0 - sx\)", "r = x / (1.0 - x)"),
+    ("Hernquist dispersion without 1/sqrt(3)", r"sig = np\.sqrt\(r\) / \(1\.0 \+ r\) / np\.sqrt\(3\.0\)",
+     "sig = np.sqrt(r) / (1.0 + r)"),
+    ("i-set selection on squared distance", r"sel \|= np\.sqrt\(\(d \* d\)\.sum\(1\)\) < r_sel", "sel |= (d * d).sum(1) < r_sel"),
+    ("cluster sizes uniform instead of log-uniform",
+     r"np\.floor\(n_min \* np\.power\(n_max / n_min, u\)\)", "np.floor(n_min + (n_max - n_min) * u)"),
+]
+
+
+def _synth_pins():
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import test_synth as T
+    return [lambda: T.test_plummer_radii_follow_the_truncated_cumulative_mass(3),
+            lambda: T.test_plummer_energies_and_virial_ratio(3),
+            T.test_hernquist_galaxies_cumulative_mass_and_dispersion,
+            T.test_merger_i_set_size_and_membership,
+            T.test_cluster_batch_sizes_softening_and_clusters]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,pat,rep", SYNTH_MUTANTS, ids=[m[0] for m in SYNTH_MUTANTS])
+def test_synth_pins_catch_mutant(monkeypatch, name, pat, rep):
+    import types
+    import synth
+    src, n = re.subn(pat, rep, open(SYNTH_SRC).read())
+    assert n > 0, f"mutation {name!r} did not apply"
+    mod = types.ModuleType("synth_mutant")
+    exec(compile(src, "synth_mutant", "exec"), mod.__dict__)
+    for attr in ("plummer", "cluster_batch", "hernquist_merger"):
+        monkeypatch.setattr(synth, attr, getattr(mod, attr))
+    caught = False
+    for pin in _synth_pins():
+        try:
+            pin()
+        except AssertionError:
+            caught = True
+            break
+    assert caught, f"mutant {name!r} survived every generator pin"
