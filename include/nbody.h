@@ -146,6 +146,28 @@ int nbody_forces(nb_ctx *ctx, const double *pos, const double *vel, const double
                  const int32_t *active_idx, int64_t n_active, double eps2,
                  double *acc, double *jerk, double *pot);
 
+/* nbody_forces for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, launch choice, kernels and results (bit for bit), but
+ * the j-split partials and the j-record mirror live in a fixed scratch array
+ * of NB_NOALLOC_SCRATCH_BYTES (128 MiB) compiled into the library, one per
+ * device, held until the process ends.  The call allocates nothing.
+ * Scratch needed: S*7*n_active*8 bytes of partials when the chosen j-split
+ * S > 1 (rounded up to 256), plus (N+1) j-records (40 B mixed, 56 B FP64)
+ * when the scalar j-path is chosen; the launch is the one nb_get_launch
+ * reports.  Errors: as nbody_forces, plus NB_ENOMEM (nothing launched,
+ * message with the bytes needed) when that exceeds the fixed size -- force a
+ * smaller S with nb_set_launch, or use nbody_forces -- and NB_EDEVICE when
+ * the scratch's device address could not be resolved.  Every call on one
+ * device shares that device's scratch, which keeps the last call's contents
+ * (the kernels write every element they read, nothing needs clearing): calls
+ * that overlap on one device -- other streams, other contexts, other host
+ * threads -- race and must be ordered by the caller. */
+#define NB_NOALLOC_SCRATCH_BYTES (128u << 20)
+int nbody_forces_noalloc(nb_ctx *ctx, const double *pos, const double *vel, const double *mass, int64_t N,
+                         const int32_t *active_idx, int64_t n_active, double eps2,
+                         double *acc, double *jerk, double *pot);
+
 /* Forces on particles that are not part of the j-set (the paper's section
  * on GPU optimisations lets the i-set be a different set of particles from
  * the j-set; the coupling kicks of a Hamiltonian split need exactly this):

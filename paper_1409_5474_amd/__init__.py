@@ -15,7 +15,7 @@ import os
 import torch
 
 __all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", "lib_path", "library",
-           "nbody_forces", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
+           "nbody_forces", "nbody_forces_noalloc", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
            "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy",
            "nbody_forces_ij", "nb_kick", "nb_kick_drift", "nbody_forces6", "hermite6_predict",
            "hermite6_correct", "hermite6_startup", "nb_block_step6", "nb_tree_forces"]
@@ -64,6 +64,7 @@ _sig("nb_set_stop_source", _vp, _vp)
 _sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
      ctypes.POINTER(_dbl))
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
+_sig("nbody_forces_noalloc", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_devcount", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_ij", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces6", _vp, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _vp)
@@ -211,6 +212,22 @@ class Context:
         _check_1d(pot, na, "pot", torch.float64, self.device)
         self._chk(_lib.nbody_forces(self._h, _p(pos), _p(vel), _p(mass), n, _p(active), na, float(eps2),
                                     _p(acc), _p(jerk), _p(pot)))
+        return acc, jerk, pot
+
+    def forces_noalloc(self, pos, vel, mass, active, eps2, acc, jerk, pot):
+        """``nbody_forces`` with the library's fixed scratch (``nbody_forces_noalloc``):
+        the outputs must be given, nothing is allocated."""
+        n = mass.shape[0]
+        na = active.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        _check_vec(vel, n, "vel", self.device)
+        _check_1d(mass, n, "mass", torch.float64, self.device)
+        _check_1d(active, na, "active_idx", torch.int32, self.device)
+        _check_vec(acc, na, "acc", self.device)
+        _check_vec(jerk, na, "jerk", self.device)
+        _check_1d(pot, na, "pot", torch.float64, self.device)
+        self._chk(_lib.nbody_forces_noalloc(self._h, _p(pos), _p(vel), _p(mass), n, _p(active), na, float(eps2),
+                                            _p(acc), _p(jerk), _p(pot)))
         return acc, jerk, pot
 
     def forces_ij(self, pos_j, vel_j, mass_j, pos_i, vel_i, active, eps2, acc=None, jerk=None, pot=None):
@@ -385,6 +402,10 @@ class Context:
 # Function-style aliases with the C names (the context is the first argument).
 def nbody_forces(ctx, pos, vel, mass, active_idx, eps2, acc=None, jerk=None, pot=None):
     return ctx.forces(pos, vel, mass, active_idx, eps2, acc, jerk, pot)
+
+
+def nbody_forces_noalloc(ctx, pos, vel, mass, active_idx, eps2, acc, jerk, pot):
+    return ctx.forces_noalloc(pos, vel, mass, active_idx, eps2, acc, jerk, pot)
 
 
 def nbody_forces_devcount(ctx, *a, **k):

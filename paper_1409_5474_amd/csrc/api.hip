@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "nb_internal.h"
@@ -214,9 +215,56 @@ bool kernel_mask(int prec, double eps2) {
   return prec == NB_PREC_FP64 ? eps2 == 0.0 : (float)eps2 == 0.0f;
 }
 
+// Fixed scratch of the no-allocation entry point: the j-split partials and
+// the j-record mirror of one call live here instead of in context memory.
+// Each device the library runs on holds its own copy for the life of the
+// process.  Host code never uses the array's name as an address: the device
+// address is resolved once per device (scratch_address) and passed on.
+constexpr size_t kScratchBytes = NB_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_done[kMaxDevices] = {};
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Resolve the device address of `scratch` on `device`, which must be the
+// current device; the first call per device does the lookup.
+void* scratch_address(int device, hipError_t* err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_done[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+    }
+    g_scratch_ptr[device] = p;
+    g_scratch_err[device] = e;
+    g_scratch_done[device] = true;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
+
+// Caller-provided buffers for run_forces: partials and mirror are taken from
+// here instead of being grown in the context.
+struct FixedScratch {
+  double* part;
+  void* rec;
+};
+
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
 int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* vel, const double* mass, int64_t N,
                const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot,
-               const double* ipos = nullptr, const double* ivel = nullptr, bool no_self = false) {
+               const double* ipos = nullptr, const double* ivel = nullptr, bool no_self = false,
+               const FixedScratch* fixed = nullptr) {
   nb::ForceArgs a{};
   a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
   a.ipos = ipos; a.ivel = ivel; a.no_self = no_self ? 1 : 0;
@@ -228,15 +276,23 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
   if (mask) eff.K = 1;
   const int max_grid = resident_grid(c, eff, mask);
   if (eff.L <= 0) {
-    int rc = ensure_mirror(c, N);
-    if (rc) return rc;
-    a.rec = c->mirror;
+    if (fixed) {
+      a.rec = fixed->rec;
+    } else {
+      int rc = ensure_mirror(c, N);
+      if (rc) return rc;
+      a.rec = c->mirror;
+    }
   }
   if (cfg.S > 1) {
-    const size_t bytes = (size_t)cfg.S * 7 * (size_t)n_active * sizeof(double);
-    int rc = ensure_ws(c, bytes);
-    if (rc) return rc;
-    a.part = static_cast<double*>(c->ws);
+    if (fixed) {
+      a.part = fixed->part;
+    } else {
+      const size_t bytes = (size_t)cfg.S * 7 * (size_t)n_active * sizeof(double);
+      int rc = ensure_ws(c, bytes);
+      if (rc) return rc;
+      a.part = static_cast<double*>(c->ws);
+    }
   }
   hipError_t e = nb::launch_forces(c->prec, eff, mask, a, c->stream, 0, max_grid);
   if (e != hipSuccess) return hip_fail(c, e, "force kernel launch");
@@ -282,6 +338,10 @@ int nb_create(nb_ctx** out, int device, int precision) {
   c->prec = precision;
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, device) == hipSuccess && p.multiProcessorCount > 0) c->num_cus = p.multiProcessorCount;
+  // the fixed scratch's address on this device, looked up once per device
+  // (a failure is reported by the entry point that needs it)
+  hipError_t se = hipSuccess;
+  (void)scratch_address(device, &se);
   *out = c;
   return NB_OK;
 }
@@ -373,6 +433,33 @@ int nbody_forces(nb_ctx* c, const double* pos, const double* vel, const double* 
   if (n_active == 0) return NB_OK;
   const Launch cfg = choose(c, N, n_active);
   return run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+}
+
+int nbody_forces_noalloc(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                         const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk,
+                         double* pot) {
+  int rc = check_forces_args(c, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
+  if (rc) return rc;
+  if (n_active == 0) return NB_OK;
+  hipError_t se = hipSuccess;
+  unsigned char* base = static_cast<unsigned char*>(scratch_address(c->device, &se));
+  if (!base) return hip_fail(c, se, "address of the fixed scratch");
+  // the launch nbody_forces would take, so the two give identical results
+  const Launch cfg = choose(c, N, n_active);
+  const size_t part = cfg.S > 1 ? align256((size_t)cfg.S * 7 * (size_t)n_active * sizeof(double)) : 0;
+  const size_t rec = cfg.L <= 0 ? nb::mirror_bytes(c->prec, N) : 0;
+  if (part + rec > kScratchBytes) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "launch (K=%d, L=%d, S=%d) needs %zu bytes of scratch, more than the fixed %zu; "
+                  "use nbody_forces, or a smaller S through nb_set_launch",
+                  cfg.K, cfg.L, cfg.S, part + rec, kScratchBytes);
+    c->err = buf;
+    return NB_ENOMEM;
+  }
+  const FixedScratch fx{reinterpret_cast<double*>(base), rec ? base + part : nullptr};
+  return run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot, nullptr, nullptr, false,
+                    &fx);
 }
 
 int nbody_forces_ij(nb_ctx* c, const double* pos_j, const double* vel_j, const double* mass_j, int64_t N_j,
