@@ -71,6 +71,70 @@ def measured_traffic(prec):
     return None
 
 
+def spread(xs):
+    """Median, minimum and maximum of a list of times (ms)."""
+    ys = sorted(xs)
+    m = len(ys) // 2
+    med = ys[m] if len(ys) % 2 else 0.5 * (ys[m - 1] + ys[m])
+    return {"median": round(med, 4), "min": round(ys[0], 4), "max": round(ys[-1], 4)}
+
+
+def cpu_model():
+    """The host CPU's model name and logical CPU count, from lscpu."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+    except (OSError, subprocess.SubprocessError):
+        return None
+    info = {}
+    for ln in out.splitlines():
+        k, _, v = ln.partition(":")
+        info[k.strip()] = v.strip()
+    return {"model": info.get("Model name"), "logical_cpus": info.get("CPU(s)"),
+            "threads_per_core": info.get("Thread(s) per core")}
+
+
+class ClockSampler:
+    """Samples the GPU's graphics clocks with amd-smi in a background thread
+    while the timed runs go on (one sample = the mean over the GPU's dies);
+    summary() gives the median and range of the samples taken while kernels
+    ran (None when amd-smi is not available)."""
+
+    def __init__(self, period=0.5):
+        import threading
+        self.period, self.samples, self._stop = period, [], threading.Event()
+        self._t = threading.Thread(target=self._loop, daemon=True)
+
+    def _loop(self):
+        import re
+        import subprocess
+        while not self._stop.is_set():
+            try:
+                out = subprocess.run(["amd-smi", "metric", "-g", "0", "-c"], capture_output=True, text=True,
+                                     timeout=10).stdout
+            except (OSError, subprocess.SubprocessError):
+                return
+            mhz = [int(x) for x in re.findall(r"GFX_\d+:\s*\n\s*CLK: (\d+) MHz", out)]
+            if mhz:
+                self.samples.append(sum(mhz) / len(mhz))
+            self._stop.wait(self.period)
+
+    def start(self):
+        self._t.start()
+
+    def stop(self):
+        self._stop.set()
+        self._t.join(timeout=15)
+
+    def summary(self):
+        busy = [x for x in self.samples if x > 1000]   # samples taken while kernels ran
+        if not busy:
+            return None
+        d = spread(busy)
+        d["samples"] = len(busy)
+        return d
+
+
 def workloads(args):
     """Measurements of the other workloads (one JSON line each).
 
@@ -475,15 +539,19 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        # one event before every step and one after the last: the mean over the
+        # whole timed region, plus the spread of single steps
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
+        ev[0].record(stream)
+        for k in range(args.steps):
             step()
-        e1.record(stream)
+            ev[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms_step = e0.elapsed_time(e1) / args.steps
+        per_step = [ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)]
+        ms_step = ev[0].elapsed_time(ev[-1]) / args.steps
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         sched = st["sched"].cpu().tolist()
         assert sched[1] == n, f"block step was not all-active: {sched}"
         # the force kernel alone, same inputs and launch, HIP events on its stream
@@ -501,11 +569,15 @@ def main():
         launch = ctx.get_launch(n, n)
         finite = bool(torch.isfinite(st["pos"]).all().item())
         ctx.close()
-        return dict(ms_step=ms_step, wall_s=wall, ms_force=ms_force, launch=launch, sched=sched, finite=finite)
+        return dict(ms_step=ms_step, wall_s=wall, ms_force=ms_force, launch=launch, sched=sched, finite=finite,
+                    step_ms=spread(per_step))
 
+    clocks = ClockSampler()
+    clocks.start()
     res = {args.prec: run(args.prec)}
     other = "fp64" if args.prec == "mixed" else "mixed"
     res[other] = run(other)
+    clocks.stop()
     main_r = res[args.prec]
     inter = float(n) * float(n)
     value = inter / (main_r["ms_step"] * 1e-3) / 1e9
@@ -527,9 +599,11 @@ def main():
         t0 = time.perf_counter()
         oracle.forces_f64(p.pos, p.vel, p.mass, eps2, sample, nthreads=threads)
         dt = time.perf_counter() - t0
+        from oracle import build as oracle_build
         cpu = {"value": rows * n / dt / 1e9, "unit": "G-interactions/s", "cores": threads, "kind": "oracle",
                "sample": f"{rows} evenly spaced i-rows of the N={n} Plummer workload against all {n} j "
-                         f"(FP64 oracle, {dt:.1f} s)"}
+                         f"(FP64 oracle, {dt:.1f} s)",
+               "cpu_model": cpu_model(), "compiler_flags": "gcc " + " ".join(oracle_build.CFLAGS)}
 
     line = {
         "metric": "G-interactions/s (acc+jerk) and % vector peak at N=262144; mixed vs FP64",
@@ -555,6 +629,8 @@ def main():
                   "pct_fp32_vector_peak": round(100 * FLOPS_PER_INTERACTION * inter /
                                                 (res["mixed"]["ms_force"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 2)},
         "mixed_vs_fp64_speedup": round(res["fp64"]["ms_step"] / res["mixed"]["ms_step"], 3),
+        "step_ms": main_r["step_ms"],
+        "gpu_clock_mhz": clocks.summary(),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.prec),
                      "kernel": f"force kernel ({args.prec}), {FLOPS_PER_INTERACTION} flops x N^2 per launch",

@@ -84,6 +84,28 @@ int nb_create(nb_ctx **out, int device, int precision);
 int nb_destroy(nb_ctx *ctx);
 /* Stream for all later launches (a hipStream_t; NULL = the null stream). */
 int nb_set_stream(nb_ctx *ctx, void *hip_stream);
+
+/* Wait for the context's stream and report errors the kernels found on the
+ * device since the last nb_sync: an active_idx entry outside its valid range
+ * ([0, N) for nbody_forces, nbody_forces_devcount, nbody_forces6,
+ * hermite_correct, hermite6_correct and the block steps; [0, N_i) for
+ * nbody_forces_ij; the system's own rows for nbody_forces_batch) is skipped
+ * by every kernel that reads it -- no output row, no particle update is
+ * written for it and nothing is read through it -- and sets a bit in device
+ * memory, so no call has to copy active_idx to the host.  Returns
+ * NB_EINVAL (message in nb_last_error) once for any such entries and clears
+ * the bit; NB_OK otherwise; NB_EDEVICE on a failed synchronisation. */
+int nb_sync(nb_ctx *ctx);
+
+/* The same range test on a host array: NB_OK when every active[k], k <
+ * n_active, lies in [lo, hi), else NB_EINVAL with the first offending k in
+ * *first_bad (-1 when all pass; first_bad may be NULL).  Needs no device. */
+int nb_check_active_host(const int32_t *active, int64_t n_active, int64_t lo, int64_t hi, int64_t *first_bad);
+
+/* Device memory held by the context's growable buffers -- the j-split
+ * workspace and the scalar j-path's record mirror, the two that
+ * NB_MAX_WORKSPACE_BYTES bounds -- in *bytes.  NB_EINVAL for null arguments. */
+int nb_workspace_bytes(const nb_ctx *ctx, int64_t *bytes);
 int nb_set_precision(nb_ctx *ctx, int precision);
 int nb_get_precision(const nb_ctx *ctx);
 const char *nb_last_error(const nb_ctx *ctx);
@@ -140,30 +162,34 @@ int nb_time_forces(nb_ctx *ctx, int K, int L, int S,
  *             particle active_idx[k]
  * Errors: NB_EINVAL for N < 1 or N >= 2^31, n_active < 0, negative or
  * non-finite eps2, a null pointer when n_active > 0.  n_active == 0 does
- * nothing.  active_idx is device memory and is not range-checked: every
- * entry must lie in [0, N). */
+ * nothing.  active_idx is device memory and is checked on the device: an
+ * entry outside [0, N) gets no output row (its rows of acc/jerk/pot are left
+ * as they were) and is reported by the next nb_sync as NB_EINVAL. */
 int nbody_forces(nb_ctx *ctx, const double *pos, const double *vel, const double *mass, int64_t N,
                  const int32_t *active_idx, int64_t n_active, double eps2,
                  double *acc, double *jerk, double *pot);
 
 /* nbody_forces for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
- * the same arguments, launch choice, kernels and results (bit for bit), but
- * the j-split partials and the j-record mirror live in a fixed scratch array
- * of NB_NOALLOC_SCRATCH_BYTES (128 MiB) compiled into the library, one per
+ * the same arguments, launch choice and kernels, but the j-split partials
+ * and the j-record mirror live in a fixed scratch array of
+ * NB_NOALLOC_SCRATCH_BYTES (256 MiB) compiled into the library, one per
  * device, held until the process ends.  The call allocates nothing.
- * Scratch needed: S*7*n_active*8 bytes of partials when the chosen j-split
- * S > 1 (rounded up to 256), plus (N+1) j-records (40 B mixed, 56 B FP64)
- * when the scalar j-path is chosen; the launch is the one nb_get_launch
- * reports.  Errors: as nbody_forces, plus NB_ENOMEM (nothing launched,
- * message with the bytes needed) when that exceeds the fixed size -- force a
- * smaller S with nb_set_launch, or use nbody_forces -- and NB_EDEVICE when
+ * Scratch needed: S*7*n_active*8 bytes of partials when the j-split S > 1
+ * (rounded up to 256), plus (N+1) j-records (40 B mixed, 56 B FP64) when the
+ * scalar j-path is chosen.  The launch is the one nb_get_launch reports, and
+ * the results equal nbody_forces' bit for bit, unless its partials do not
+ * fit: then the automatic choice takes the largest S that fits (the sums
+ * differ only in their order).  Errors: as nbody_forces, plus NB_ENOMEM
+ * (nothing launched, message with the bytes needed) when a launch forced by
+ * nb_set_launch does not fit, or when the mirror alone does not (N above
+ * about 4.7 million in FP64) -- use nbody_forces then -- and NB_EDEVICE when
  * the scratch's device address could not be resolved.  Every call on one
  * device shares that device's scratch, which keeps the last call's contents
  * (the kernels write every element they read, nothing needs clearing): calls
  * that overlap on one device -- other streams, other contexts, other host
  * threads -- race and must be ordered by the caller. */
-#define NB_NOALLOC_SCRATCH_BYTES (128u << 20)
+#define NB_NOALLOC_SCRATCH_BYTES (256u << 20)
 int nbody_forces_noalloc(nb_ctx *ctx, const double *pos, const double *vel, const double *mass, int64_t N,
                          const int32_t *active_idx, int64_t n_active, double eps2,
                          double *acc, double *jerk, double *pot);
@@ -177,7 +203,7 @@ int nbody_forces_noalloc(nb_ctx *ctx, const double *pos, const double *vel, cons
  * with eps2 == 0 a pair at zero distance contributes nothing.  Outputs as
  * nbody_forces.  Errors as nbody_forces (with N_j for N), plus NB_EINVAL for
  * N_i outside [0, 2^31) or empty or null i arrays when n_active > 0.
- * active_idx entries must lie in [0, N_i) (not range-checked). */
+ * active_idx entries outside [0, N_i) are skipped and reported by nb_sync. */
 int nbody_forces_ij(nb_ctx *ctx, const double *pos_j, const double *vel_j, const double *mass_j, int64_t N_j,
                     const double *pos_i, const double *vel_i, int64_t N_i,
                     const int32_t *active_idx, int64_t n_active, double eps2,
@@ -200,7 +226,8 @@ int nbody_forces_devcount(nb_ctx *ctx, const double *pos, const double *vel, con
  * Pairs across systems never interact.  One launch covers every system:
  * the work list (system, i-block, j-chunk) is built on the host and the
  * persistent kernel walks it.  Errors as nbody_forces, plus NB_EINVAL for
- * decreasing offsets or act_offsets or C < 1. */
+ * decreasing offsets or act_offsets or C < 1; an entry outside its system's
+ * rows is skipped and reported by nb_sync. */
 int nbody_forces_batch(nb_ctx *ctx, const int64_t *offsets, int64_t C, const double *eps2,
                        const double *pos, const double *vel, const double *mass,
                        const int32_t *active_idx, const int64_t *act_offsets,
@@ -243,8 +270,9 @@ int hermite6_predict(nb_ctx *ctx, const double *pos, const double *vel, const do
  * comes from dt* = eta ((sqrt(|a1||s1|) + |j1|)/(sqrt(|c1||q0|) + |p1|))^(1/3),
  * p1 = p0 + q0 h (dt_max when the denominator is 0), with the level rules of
  * hermite_correct (clamps counted in *clamp_count_dev, may be NULL).
- * active_idx must not repeat an index. */
-int hermite6_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active, const double *acc1,
+ * active_idx must not repeat an index; N is the number of particles, and
+ * entries outside [0, N) are skipped and reported by nb_sync. */
+int hermite6_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active, int64_t N, const double *acc1,
                      const double *jerk1, const double *snap1, double *pos, double *vel, double *acc, double *jerk,
                      double *snap, double *crackle, int64_t *t_tick, int32_t *dt_level, double eta, double dt_max,
                      int32_t max_level, int64_t *clamp_count_dev);
@@ -363,8 +391,12 @@ int hermite_predict(nb_ctx *ctx, const double *pos, const double *vel, const dou
  * 2 dt.  Levels beyond max_level are clamped to it and counted in
  * *clamp_count_dev (device int64, may be NULL; not reset by the call).
  * pos, vel, acc, jerk [N][3], t_tick, dt_level [N] are updated in place for
- * the active rows only.  active_idx must not repeat an index. */
-int hermite_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active,
+ * the active rows only.  active_idx must not repeat an index; N is the
+ * number of particles, and entries outside [0, N) are skipped (nothing of
+ * theirs is read or written) and reported by nb_sync.  Errors: NB_EINVAL for
+ * n_active outside [0, 2^31), N outside [1, 2^31), bad level parameters or a
+ * null pointer when n_active > 0. */
+int hermite_correct(nb_ctx *ctx, const int32_t *active_idx, int64_t n_active, int64_t N,
                     const double *pos_p, const double *vel_p, const double *acc1, const double *jerk1,
                     double *pos, double *vel, double *acc, double *jerk,
                     int64_t *t_tick, int32_t *dt_level, double eta, double dt_max, int32_t max_level,

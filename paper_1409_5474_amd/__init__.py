@@ -18,7 +18,8 @@ __all__ = ["NbodyError", "Context", "PREC_FP64", "PREC_MIXED", "PREC_MIXED_DS", 
            "nbody_forces", "nbody_forces_noalloc", "nbody_forces_devcount", "nbody_forces_batch", "hermite_predict",
            "hermite_correct", "hermite_startup", "nb_schedule", "nb_block_step", "nb_energy",
            "nbody_forces_ij", "nb_kick", "nb_kick_drift", "nbody_forces6", "hermite6_predict",
-           "hermite6_correct", "hermite6_startup", "nb_block_step6", "nb_tree_forces"]
+           "hermite6_correct", "hermite6_startup", "nb_block_step6", "nb_tree_forces", "nb_sync",
+           "check_active_host"]
 
 PREC_FP64 = 0
 PREC_MIXED = 1
@@ -54,6 +55,7 @@ _sig("nb_create", ctypes.POINTER(_vp), _int, _int)
 _sig("nb_destroy", _vp)
 _sig("nb_set_stream", _vp, _vp)
 _sig("nb_set_precision", _vp, _int)
+_sig("nb_workspace_bytes", _vp, ctypes.POINTER(_i64))
 _lib.nb_get_precision.restype = _int
 _lib.nb_get_precision.argtypes = [_vp]
 _sig("nb_set_launch", _vp, _int, _int, _int)
@@ -69,8 +71,8 @@ _sig("nbody_forces_devcount", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _dbl, _v
 _sig("nbody_forces_ij", _vp, _vp, _vp, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces6", _vp, _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _vp)
 _sig("hermite6_predict", _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp, _vp)
-_sig("hermite6_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32,
-     _vp)
+_sig("hermite6_correct", _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl,
+     _i32, _vp)
 _sig("hermite6_startup", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
 _sig("nb_block_step6", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64)
@@ -78,7 +80,10 @@ _sig("nb_tree_forces", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _dbl, _vp, _vp, _v
 _sig("nb_kick", _vp, _vp, _vp, _i64, _dbl)
 _sig("nb_kick_drift", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl)
 _sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
-_sig("hermite_correct", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32, _vp)
+_sig("hermite_correct", _vp, _vp, _i64, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dbl, _dbl, _i32,
+     _vp)
+_sig("nb_sync", _vp)
+_sig("nb_check_active_host", _vp, _i64, _i64, _i64, ctypes.POINTER(_i64))
 _sig("hermite_startup", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
 _sig("nb_schedule", _vp, _vp, _vp, _i64, _i32, _vp, _vp)
 _sig("nb_block_step", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -87,6 +92,18 @@ _sig("nb_energy", _vp, _vp, _vp, _vp, _vp, _i64, _vp)
 _sig("nbody_forces_batch", _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp)
 _sig("nb_block_step_batch", _vp, _vp, _i64, _vp, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
      _vp, _vp, _vp, _vp, _vp, _i64)
+
+
+def check_active_host(active, lo, hi):
+    """Index of the first entry of the host int32 array ``active`` outside
+    [lo, hi), or -1 (``nb_check_active_host``; no device needed)."""
+    import numpy as np
+    a = np.ascontiguousarray(active, dtype=np.int32)
+    bad = _i64()
+    rc = _lib.nb_check_active_host(a.ctypes.data_as(_vp), a.shape[0], int(lo), int(hi), ctypes.byref(bad))
+    if rc not in (0, -1):
+        raise NbodyError(rc, "nb_check_active_host")
+    return bad.value
 
 
 def library():
@@ -155,6 +172,23 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def sync(self):
+        """Wait for the context's stream; raise NbodyError (NB_EINVAL) if a
+        kernel met an active_idx entry outside its valid range since the last
+        sync (``nb_sync``)."""
+        self._chk(_lib.nb_sync(self._h))
+
+    def workspace_bytes(self):
+        """Device bytes held by the growable workspace and mirror (``nb_workspace_bytes``)."""
+        b = _i64()
+        self._chk(_lib.nb_workspace_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    @property
+    def stream(self):
+        """The torch.cuda.Stream the context launches on."""
+        return self._stream
 
     def set_stream(self, stream=None):
         """Launch on ``stream`` (a torch.cuda.Stream), default torch's current stream."""
@@ -280,7 +314,8 @@ class Context:
 
     def correct6(self, active, acc1, jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick, dt_level, eta, dt_max,
                  max_level, clamp_count=None):
-        self._chk(_lib.hermite6_correct(self._h, _p(active), active.shape[0], _p(acc1), _p(jerk1), _p(snap1),
+        self._chk(_lib.hermite6_correct(self._h, _p(active), active.shape[0], pos.shape[0], _p(acc1), _p(jerk1),
+                                        _p(snap1),
                                         _p(pos), _p(vel), _p(acc), _p(jerk), _p(snap), _p(crackle), _p(t_tick),
                                         _p(dt_level), float(eta), float(dt_max), int(max_level), _p(clamp_count)))
 
@@ -363,7 +398,8 @@ class Context:
 
     def correct(self, active, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max,
                 max_level, clamp_dev=None):
-        self._chk(_lib.hermite_correct(self._h, _p(active), active.shape[0], _p(pos_p), _p(vel_p), _p(acc1),
+        self._chk(_lib.hermite_correct(self._h, _p(active), active.shape[0], pos.shape[0], _p(pos_p), _p(vel_p),
+                                       _p(acc1),
                                        _p(jerk1), _p(pos), _p(vel), _p(acc), _p(jerk), _p(t_tick), _p(dt_level),
                                        float(eta), float(dt_max), int(max_level), _p(clamp_dev)))
 
@@ -478,3 +514,7 @@ def nb_block_step6(ctx, *a, **k):
 
 def nb_tree_forces(ctx, *a, **k):
     return ctx.tree_forces(*a, **k)
+
+
+def nb_sync(ctx):
+    return ctx.sync()

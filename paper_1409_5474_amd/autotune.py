@@ -36,15 +36,22 @@ DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning
 TILE, WG = 256, 256
 
 
+# j-split counts tried: every S up to 8, then steps of about a quarter.  The
+# time is not monotone in S (items are handed out from a queue, and how the
+# last items fall across the compute units matters), so powers of two alone
+# miss good values.
+_S_STEPS = [1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 128, 160, 192, 256]
+
+
 def _s_candidates(n, n_act, K, L, num_cus):
     ib = (WG // max(L, 1)) * K
     n_iblk = -(-n_act // ib)
     max_s = -(-n // TILE)
     out = {0}
-    s = 1
-    while s <= max_s and n_iblk * s <= 32 * num_cus:
+    for s in _S_STEPS:
+        if s > max_s or n_iblk * s > 32 * num_cus:
+            break
         out.add(s)
-        s *= 2
     return sorted(out), n_iblk
 
 
@@ -121,6 +128,8 @@ def tune(ctx, n, precisions=("fp64", "mixed", "mixed_ds"), buckets=BUCKETS, seed
                         per_shape[(K, L)] = (ms, S, n_iblk)
             times.append({sh: v[0] for sh, v in per_shape.items()})
             best_of.append(per_shape)
+            sh, v = min(per_shape.items(), key=lambda kv: kv[1][0])
+            log(f"# {prec} N={n} n_active={b}: fastest K={sh[0]} L={sh[1]} S={v[1]} {v[0]:.5f} ms")
         fastest = [min(t, key=t.get) for t in times]
         choice = _merge_shapes(fastest, times, launch_ms)
         for i, (b, (lo, hi)) in enumerate(zip(bks, ranges)):
@@ -134,6 +143,14 @@ def tune(ctx, n, precisions=("fp64", "mixed", "mixed_ds"), buckets=BUCKETS, seed
             entries.append(e)
             log(json.dumps(e))
     return entries
+
+
+def forces_source_hash():
+    """sha256 of the force kernels' source the table was measured on."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "forces.hip")
+    with open(src, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def save(entries, path, meta=None):
@@ -157,18 +174,26 @@ def main():
     ap.add_argument("--prec", nargs="+", default=["fp64", "mixed", "mixed_ds"])
     ap.add_argument("--out", default="tuning.json")
     ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--max-active", type=int, default=0,
+                    help="largest active-set bucket to time (0: up to N); the top bucket's range then covers every larger count")
+    ap.add_argument("--append", default="", help="start from the entries of this table")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_1409_5474_amd as nb
     ctx = nb.Context(0, "fp64", load_tuning=False)
     t0 = time.time()
     entries = []
+    if args.append:
+        with open(args.append) as f:
+            entries = json.load(f)["entries"]
+    buckets = [b for b in BUCKETS if not args.max_active or b <= args.max_active]
     for n in sorted(args.n):
-        entries += tune(ctx, n, args.prec, reps=args.reps)
+        entries += tune(ctx, n, args.prec, buckets=buckets, reps=args.reps, log=lambda m: print(m, flush=True))
         print(f"# N={n} done after {time.time() - t0:.0f} s", flush=True)
     props = torch.cuda.get_device_properties(0)
     save(entries, args.out, meta={"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
-                                  "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1)})
+                                  "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1),
+                                  "forces_hip_sha256": forces_source_hash()})
     print(f"wrote {args.out} ({len(entries)} entries)", flush=True)
 
 

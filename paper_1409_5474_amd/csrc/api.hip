@@ -63,7 +63,9 @@ int ensure_ws(nb_ctx* c, size_t bytes) {
     c->ws = nullptr;
     c->ws_bytes = 0;
   }
+  // grow with some headroom, but never past the cap
   size_t b = bytes + bytes / 4;
+  if (b > workspace_cap()) b = workspace_cap();
   if (hipMalloc(&c->ws, b) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, NB_ENOMEM, "hipMalloc of the j-split workspace failed%s");
@@ -264,13 +266,14 @@ constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* vel, const double* mass, int64_t N,
                const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot,
                const double* ipos = nullptr, const double* ivel = nullptr, bool no_self = false,
-               const FixedScratch* fixed = nullptr) {
+               const FixedScratch* fixed = nullptr, int64_t n_rows = -1) {
   nb::ForceArgs a{};
   a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
   a.ipos = ipos; a.ivel = ivel; a.no_self = no_self ? 1 : 0;
   a.active = active; a.n_active = n_active; a.n_active_dev = nullptr;
   a.eps2 = eps2; a.S = cfg.S; a.target_items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
-  a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr;
+  a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr; a.wq = c->wq;
+  a.row_lo = 0; a.row_hi = n_rows >= 0 ? n_rows : N; a.err = c->wq + nb::kErrorWord;
   const bool mask = kernel_mask(c->prec, eps2);
   Launch eff = cfg;
   if (mask) eff.K = 1;
@@ -342,6 +345,15 @@ int nb_create(nb_ctx** out, int device, int precision) {
   // (a failure is reported by the entry point that needs it)
   hipError_t se = hipSuccess;
   (void)scratch_address(device, &se);
+  // the force grids' work queue starts at zero and every launch leaves it
+  // at zero
+  if (hipMalloc(&c->wq, nb::kWorkQueueWords * sizeof(unsigned int)) != hipSuccess ||
+      hipMemset(c->wq, 0, nb::kWorkQueueWords * sizeof(unsigned int)) != hipSuccess) {
+    (void)hipGetLastError();
+    if (c->wq) (void)hipFree(c->wq);
+    delete c;
+    return NB_ENOMEM;
+  }
   *out = c;
   return NB_OK;
 }
@@ -357,6 +369,7 @@ int nb_destroy(nb_ctx* c) {
   if (c->sched_cnt) (void)hipFree(c->sched_cnt);
   if (c->nact32) (void)hipFree(c->nact32);
   if (c->s_dev) (void)hipFree(c->s_dev);
+  if (c->wq) (void)hipFree(c->wq);
   if (c->energy_part) (void)hipFree(c->energy_part);
   if (c->batch_buf) (void)hipFree(c->batch_buf);
   if (c->batch_host) (void)hipHostFree(c->batch_host);
@@ -364,6 +377,40 @@ int nb_destroy(nb_ctx* c) {
   if (c->bp_buf) (void)hipFree(c->bp_buf);
   nb::tree_scratch_free(c->tree);
   delete c;
+  return NB_OK;
+}
+
+int nb_sync(nb_ctx* c) {
+  if (!c) return NB_EINVAL;
+  (void)hipSetDevice(c->device);
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
+  unsigned int bits = 0;
+  e = hipMemcpy(&bits, c->wq + nb::kErrorWord, sizeof bits, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the device error word");
+  if (!bits) return NB_OK;
+  const unsigned int zero = 0;
+  e = hipMemcpy(c->wq + nb::kErrorWord, &zero, sizeof zero, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(c, e, "clearing the device error word");
+  return fail(c, NB_EINVAL,
+              "an active_idx entry outside its valid range was passed since the last nb_sync; its rows were "
+              "skipped (outputs not written)%s");
+}
+
+int nb_check_active_host(const int32_t* active, int64_t n_active, int64_t lo, int64_t hi, int64_t* first_bad) {
+  if (n_active < 0 || (n_active > 0 && !active)) return NB_EINVAL;
+  for (int64_t k = 0; k < n_active; ++k)
+    if (!nb::row_in_range(active[k], lo, hi)) {
+      if (first_bad) *first_bad = k;
+      return NB_EINVAL;
+    }
+  if (first_bad) *first_bad = -1;
+  return NB_OK;
+}
+
+int nb_workspace_bytes(const nb_ctx* c, int64_t* bytes) {
+  if (!c || !bytes) return NB_EINVAL;
+  *bytes = (int64_t)(c->ws_bytes + c->mirror_bytes);
   return NB_OK;
 }
 
@@ -445,18 +492,28 @@ int nbody_forces_noalloc(nb_ctx* c, const double* pos, const double* vel, const 
   unsigned char* base = static_cast<unsigned char*>(scratch_address(c->device, &se));
   if (!base) return hip_fail(c, se, "address of the fixed scratch");
   // the launch nbody_forces would take, so the two give identical results
-  const Launch cfg = choose(c, N, n_active);
-  const size_t part = cfg.S > 1 ? align256((size_t)cfg.S * 7 * (size_t)n_active * sizeof(double)) : 0;
+  Launch cfg = choose(c, N, n_active);
+  const size_t row_bytes = 7 * sizeof(double) * (size_t)n_active;  // one j-chunk's partial sums
+  auto part_bytes = [&](int S) { return S > 1 ? align256((size_t)S * row_bytes) : (size_t)0; };
   const size_t rec = cfg.L <= 0 ? nb::mirror_bytes(c->prec, N) : 0;
-  if (part + rec > kScratchBytes) {
-    char buf[256];
-    std::snprintf(buf, sizeof buf,
-                  "launch (K=%d, L=%d, S=%d) needs %zu bytes of scratch, more than the fixed %zu; "
-                  "use nbody_forces, or a smaller S through nb_set_launch",
-                  cfg.K, cfg.L, cfg.S, part + rec, kScratchBytes);
-    c->err = buf;
-    return NB_ENOMEM;
+  if (part_bytes(cfg.S) + rec > kScratchBytes) {
+    // an automatic launch takes the largest j-split whose partials fit (the
+    // sums then differ from nbody_forces only in their order); a forced
+    // launch, or a mirror that alone does not fit, is refused
+    const size_t avail = rec < kScratchBytes ? kScratchBytes - rec : 0;
+    const int64_t s_fit = avail > 255 ? (int64_t)((avail - 255) / row_bytes) : 0;
+    if (c->have_forced || rec > kScratchBytes) {
+      char buf[256];
+      std::snprintf(buf, sizeof buf,
+                    "launch (K=%d, L=%d, S=%d) needs %zu bytes of scratch, more than the fixed %zu; "
+                    "use nbody_forces, or a smaller S through nb_set_launch",
+                    cfg.K, cfg.L, cfg.S, part_bytes(cfg.S) + rec, kScratchBytes);
+      c->err = buf;
+      return NB_ENOMEM;
+    }
+    cfg.S = s_fit >= 2 ? (int)std::min<int64_t>(s_fit, cfg.S) : 1;
   }
+  const size_t part = part_bytes(cfg.S);
   const FixedScratch fx{reinterpret_cast<double*>(base), rec ? base + part : nullptr};
   return run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot, nullptr, nullptr, false,
                     &fx);
@@ -472,7 +529,8 @@ int nbody_forces_ij(nb_ctx* c, const double* pos_j, const double* vel_j, const d
     return fail(c, NB_EINVAL, "i-particle arrays are empty or null%s");
   if (n_active == 0) return NB_OK;
   const Launch cfg = choose(c, N_j, n_active);
-  return run_forces(c, cfg, pos_j, vel_j, mass_j, N_j, active, n_active, eps2, acc, jerk, pot, pos_i, vel_i, true);
+  return run_forces(c, cfg, pos_j, vel_j, mass_j, N_j, active, n_active, eps2, acc, jerk, pot, pos_i, vel_i, true,
+                    nullptr, N_i);
 }
 
 int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const double* vel, const double* mass,
@@ -522,35 +580,58 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   const bool mask = kernel_mask(c->prec, eps2);
   // One fixed launch per regime; the count decides on the device which one works.
   // Adjacent regimes with the same K and L share one launch (every launch,
-  // empty or not, costs a few microseconds in each block step); the merged
-  // regime keeps the work-item target of its upper part, where the work is.
-  std::vector<Regime> regs;
+  // empty or not, costs a few microseconds in each block step); the shared
+  // launch carries each regime's work-item target, so a count gets the same
+  // j-split as a host-count launch.
+  struct Group {
+    Regime r;                   // merged count range and the shape
+    int n_sub;
+    int64_t sub_lo[nb::kMaxSubRegimes];
+    int sub_items[nb::kMaxSubRegimes];
+  };
+  std::vector<Group> groups;
   for (const Regime& r : regimes(c, N)) {
-    if (!regs.empty() && regs.back().cfg.K == r.cfg.K && regs.back().cfg.L == r.cfg.L) {
-      regs.back().hi = r.hi;
-      regs.back().cfg.items = r.cfg.items;
-    } else {
-      regs.push_back(r);
-    }
-  }
-  size_t ws_need = 0;
-  for (const Regime& r : regs) {
-    if (r.lo > max_active) break;
-    const int64_t top = r.hi < max_active ? r.hi : max_active;
     Launch cfg = c->have_forced ? c->forced : r.cfg;
     if (mask) cfg.K = 1;
     const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
+    if (!groups.empty() && groups.back().r.cfg.K == r.cfg.K && groups.back().r.cfg.L == r.cfg.L &&
+        groups.back().n_sub < nb::kMaxSubRegimes) {
+      Group& g = groups.back();
+      g.r.hi = r.hi;
+      g.sub_lo[g.n_sub] = r.lo;
+      g.sub_items[g.n_sub] = items;
+      ++g.n_sub;
+    } else {
+      Group g{};
+      g.r = r;
+      g.n_sub = 1;
+      g.sub_lo[0] = r.lo;
+      g.sub_items[0] = items;
+      groups.push_back(g);
+    }
+  }
+  auto max_items = [](const Group& g) {
+    int m = 0;
+    for (int k = 0; k < g.n_sub; ++k) m = std::max(m, g.sub_items[k]);
+    return m;
+  };
+  size_t ws_need = 0;
+  for (const Group& g : groups) {
+    if (g.r.lo > max_active) break;
+    const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
+    Launch cfg = c->have_forced ? c->forced : g.r.cfg;
+    if (mask) cfg.K = 1;
     const int IB = nb::ib_of(cfg);
     const int64_t n_iblk_max = (top + IB - 1) / IB;
-    const size_t rows = (size_t)(items + n_iblk_max) * IB;
+    const size_t rows = (size_t)(max_items(g) + n_iblk_max) * IB;
     const size_t need = rows * 7 * sizeof(double);
     if (need > ws_need) ws_need = need;
   }
   rc = ensure_ws(c, ws_need);
   if (rc) return rc;
   bool need_mirror = false;
-  for (const Regime& r : regs)
-    if (r.lo <= max_active && (c->have_forced ? c->forced.L : r.cfg.L) <= 0) need_mirror = true;
+  for (const Group& g : groups)
+    if (g.r.lo <= max_active && (c->have_forced ? c->forced.L : g.r.cfg.L) <= 0) need_mirror = true;
   if (need_mirror) {
     rc = ensure_mirror(c, N);
     if (rc) return rc;
@@ -563,20 +644,27 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
     }
   }
   nb::ForceArgs red{};
-  for (const Regime& r : regs) {
-    if (r.lo > max_active) break;
-    const int64_t top = r.hi < max_active ? r.hi : max_active;
-    Launch cfg = c->have_forced ? c->forced : r.cfg;
+  for (const Group& g : groups) {
+    if (g.r.lo > max_active) break;
+    const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
+    Launch cfg = c->have_forced ? c->forced : g.r.cfg;
     if (mask) cfg.K = 1;
-    const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
+    const int items = max_items(g);
     nb::ForceArgs a{};
     a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
     a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
-    a.act_lo = r.lo;
+    a.act_lo = g.r.lo;
     a.last = (top == max_active) ? 1 : 0;
-    a.eps2 = eps2; a.S = 1; a.target_items = items;
+    a.eps2 = eps2; a.S = 1; a.target_items = g.sub_items[0];
+    a.n_sub = g.n_sub;
+    for (int k = 0; k < g.n_sub; ++k) {
+      a.sub_lo[k] = g.sub_lo[k];
+      a.sub_items[k] = g.sub_items[k];
+    }
     a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = c->s_dev;
     a.rec = c->mirror;
+    a.wq = c->wq;
+    a.row_lo = 0; a.row_hi = N; a.err = c->wq + nb::kErrorWord;
     red = a;
     const int IB = nb::ib_of(cfg);
     const int64_t n_iblk_max = (top + IB - 1) / IB;
@@ -621,6 +709,7 @@ static int run_forces6(nb_ctx* c, const double* pos, const double* vel, const do
   a.target_items = target;
   a.S = nb::forces6_split(n_max, target, N);
   a.acc = acc; a.jerk = jerk; a.snap = snap; a.pot = pot;
+  a.err = c->wq + nb::kErrorWord;
   const int64_t rows = n_active_dev ? nb::forces6_workspace_rows(n_max, target, N) : (int64_t)a.S * n_max;
   if (n_active_dev || a.S > 1) {
     int rc = ensure_ws(c, (size_t)rows * 10 * sizeof(double));
@@ -656,19 +745,22 @@ int hermite6_predict(nb_ctx* c, const double* pos, const double* vel, const doub
 
 static int check_levels(nb_ctx* c, double eta, double dt_max, int32_t max_level);
 
-int hermite6_correct(nb_ctx* c, const int32_t* active, int64_t n_active, const double* acc1, const double* jerk1,
+int hermite6_correct(nb_ctx* c, const int32_t* active, int64_t n_active, int64_t N, const double* acc1,
+                     const double* jerk1,
                      const double* snap1, double* pos, double* vel, double* acc, double* jerk, double* snap,
                      double* crackle, int64_t* t_tick, int32_t* dt_level, double eta, double dt_max,
                      int32_t max_level, int64_t* clamp_count_dev) {
   if (!c) return NB_EINVAL;
   if (n_active < 0 || n_active >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "n_active must be in [0, 2^31)%s");
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
   int rc = check_levels(c, eta, dt_max, max_level);
   if (rc) return rc;
   if (n_active == 0) return NB_OK;
   if (!active || !acc1 || !jerk1 || !snap1 || !pos || !vel || !acc || !jerk || !snap || !crackle || !t_tick ||
       !dt_level)
     return fail(c, NB_EINVAL, "null pointer%s");
-  hipError_t e = nb::launch_correct6(active, n_active, nullptr, acc1, jerk1, snap1, pos, vel, acc, jerk, snap,
+  hipError_t e = nb::launch_correct6(active, n_active, nullptr, N, c->wq + nb::kErrorWord, acc1, jerk1, snap1, pos, vel, acc,
+                                     jerk, snap,
                                      crackle, t_tick, dt_level, eta, dt_max, max_level, clamp_count_dev, nullptr,
                                      c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
@@ -709,7 +801,8 @@ int nb_block_step6(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max,
   if (e != hipSuccess) return hip_fail(c, e, "sixth-order predict launch");
   rc = run_forces6(c, pos_p, vel_p, acc_p, mass, N, active, N, c->nact32, eps2, acc1, jerk1, snap1, pot1);
   if (rc) return rc;
-  e = nb::launch_correct6(active, N, sched + 1, acc1, jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick,
+  e = nb::launch_correct6(active, N, sched + 1, N, c->wq + nb::kErrorWord, acc1, jerk1, snap1, pos, vel, acc, jerk, snap,
+                          crackle, t_tick,
                           dt_level, eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
 }
@@ -768,18 +861,21 @@ static int check_levels(nb_ctx* c, double eta, double dt_max, int32_t max_level)
   return NB_OK;
 }
 
-int hermite_correct(nb_ctx* c, const int32_t* active, int64_t n_active, const double* pos_p, const double* vel_p,
+int hermite_correct(nb_ctx* c, const int32_t* active, int64_t n_active, int64_t N, const double* pos_p,
+                    const double* vel_p,
                     const double* acc1, const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
                     int64_t* t_tick, int32_t* dt_level, double eta, double dt_max, int32_t max_level,
                     int64_t* clamp_count_dev) {
   if (!c) return NB_EINVAL;
   if (n_active < 0 || n_active >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "bad n_active%s");
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
   int rc = check_levels(c, eta, dt_max, max_level);
   if (rc) return rc;
   if (n_active == 0) return NB_OK;
   if (!active || !pos_p || !vel_p || !acc1 || !jerk1 || !pos || !vel || !acc || !jerk || !t_tick || !dt_level)
     return fail(c, NB_EINVAL, "null pointer%s");
-  hipError_t e = nb::launch_correct(active, n_active, nullptr, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
+  hipError_t e = nb::launch_correct(active, n_active, nullptr, N, c->wq + nb::kErrorWord, pos_p, vel_p, acc1, jerk1, pos, vel,
+                                    acc, jerk,
                                     t_tick, dt_level, eta, dt_max, max_level, clamp_count_dev, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
 }
@@ -830,7 +926,8 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
   if (e != hipSuccess) return hip_fail(c, e, "predict launch");
   rc = nbody_forces_devcount(c, pos_p, vel_p, mass, N, active, c->nact32, N, eps2, acc1, jerk1, pot1);
   if (rc) return rc;
-  e = nb::launch_correct_step(active, N, sched + 1, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level,
+  e = nb::launch_correct_step(active, N, sched + 1, N, c->wq + nb::kErrorWord, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
+                              t_tick, dt_level,
                               eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
 }
@@ -953,7 +1050,7 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   const nb::BatchSys* d_sys = reinterpret_cast<const nb::BatchSys*>(db + off_sys);
   const int32_t* d_nch = reinterpret_cast<const int32_t*>(db + off_nch);
   e = nb::launch_batch(c->prec, cfg, d_items, (int)items.size(), nullptr, d_sys, pos, vel, mass, active, acc, jerk,
-                       pot, static_cast<double*>(c->ws), part_rows, any_mask, 0, c->stream);
+                       pot, static_cast<double*>(c->ws), part_rows, any_mask, 0, c->wq + nb::kErrorWord, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
   if (part_rows > 0) {
     e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, a_total, acc, jerk, pot,
@@ -1051,12 +1148,13 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
                             d_nit, part_cap, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch plan launch");
   e = nb::launch_batch(c->prec, cfg, d_items, max_items, d_nit, d_sys, pos_p, vel_p, mass, active, acc1, jerk1, pot1,
-                       static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->stream);
+                       static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->wq + nb::kErrorWord, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
   e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, N, acc1, jerk1, pot1,
                               static_cast<double*>(c->ws), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch reduce launch");
-  e = nb::launch_correct_step(active, N, sched + 1, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, dt_level,
+  e = nb::launch_correct_step(active, N, sched + 1, N, c->wq + nb::kErrorWord, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
+                              t_tick, dt_level,
                               eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
   return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
 }

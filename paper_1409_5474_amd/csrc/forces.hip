@@ -452,9 +452,79 @@ __host__ __device__ inline int choose_S(int64_t n_act, int IB, int target_items,
   return (int)s;
 }
 
+// The work-item target of a device-count launch for count d (see n_sub).
+// The loop is unrolled so that every table entry is read at a fixed offset
+// of the kernel arguments: an index known only at run time would make the
+// compiler copy the arguments to scratch memory, which upsets the register
+// allocation of the whole kernel.
+__device__ __forceinline__ int target_for(const ForceArgs& a, int64_t d) {
+  int t = a.target_items;
+#pragma unroll
+  for (int r = 0; r < kMaxSubRegimes; ++r)
+    if (r < a.n_sub && d >= a.sub_lo[r]) t = a.sub_items[r];
+  return t;
+}
+
+// An i-set entry: its row, or -1 when it lies outside [lo, hi) -- the row is
+// then skipped and the context's error word flags it for nb_sync.
+__device__ __forceinline__ int64_t checked_row(const int32_t* active, int64_t k, int64_t lo, int64_t hi,
+                                               unsigned int* err) {
+  const int64_t r = active[k];
+  if (row_in_range(r, lo, hi)) return r;
+  if (err) atomicOr(err, kErrActiveRange);
+  return -1;
+}
+
 __host__ __device__ inline int64_t chunk_len(int64_t n, int S) {
   const int64_t per = (n + S - 1) / S;
   return ((per + kTile - 1) / kTile) * kTile;
+}
+
+// Work queues of the persistent force grids.  The items -- (i-block,
+// j-chunk) pairs in chunk-major order -- are cut into kXcd equal ranges, one
+// per XCD: the hardware hands workgroups to the chip's 8 XCDs round-robin by
+// blockIdx, so range x is worked by the workgroups on XCD x, and that XCD's
+// L2 holds only the j-chunks of its own range.  Within a range, workgroups
+// take items from a counter in device memory (wq[x]), so a faster compute
+// unit takes more; once its own range is exhausted, a workgroup takes from
+// the other ranges in turn, so the XCDs (whose clocks differ by a few
+// percent) also finish together.  Each item is computed the same way
+// whichever workgroup takes it: results do not depend on the assignment.
+// wq[0..kXcd-1] are the range counters and wq[kXcd] counts finished
+// workgroups; all are zero before a launch and the last workgroup to finish
+// sets them back to zero.  Without a queue (wq null) the grid strides over
+// the items in the same order.
+constexpr int kXcd = 8;
+constexpr int kQueueWords = kXcd + 1;
+static_assert(kQueueWords <= kWorkQueueWords, "work queue larger than its buffer");
+
+__device__ __forceinline__ int64_t queue_take(unsigned int* wq, unsigned int& slot, int64_t items,
+                                              int64_t w_stride) {
+  if (!wq) return w_stride;
+  __syncthreads();  // every thread has read `slot` before it is replaced
+  if (threadIdx.x == 0) {
+    const int x0 = blockIdx.x % kXcd;
+    int64_t got = items;
+    for (int d = 0; d < kXcd && got == items; ++d) {
+      const int x = (x0 + d) % kXcd;
+      const int64_t lo = items * x / kXcd, len = items * (x + 1) / kXcd - lo;
+      if ((int64_t)atomicAdd(&wq[x], 0u) >= len) continue;  // exhausted: look further
+      const int64_t k = atomicAdd(&wq[x], 1u);
+      if (k < len) got = lo + k;
+    }
+    slot = (unsigned int)got;
+  }
+  __syncthreads();
+  // one value for the whole wave: read into a scalar register, so everything
+  // derived from the item (chunk bounds, record addresses) stays uniform
+  return (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)slot);
+}
+
+// Every workgroup calls this once, after its last queue_take.
+__device__ __forceinline__ void queue_done(unsigned int* wq) {
+  if (wq && threadIdx.x == 0 && atomicAdd(&wq[kXcd], 1u) == gridDim.x - 1) {
+    for (int x = 0; x < kQueueWords; ++x) atomicExch(&wq[x], 0u);
+  }
 }
 
 // Shared body: one workgroup processes one (i-block, j-chunk) item.
@@ -468,7 +538,8 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
                                              int64_t jbeg, int64_t jend, const int32_t* __restrict__ active,
                                              int64_t n_act, int64_t k0, double eps2, bool final_out,
                                              double* __restrict__ acc, double* __restrict__ jerk,
-                                             double* __restrict__ pot, double* __restrict__ part) {
+                                             double* __restrict__ pot, double* __restrict__ part, int64_t row_lo,
+                                             int64_t row_hi, unsigned int* err) {
   constexpr int SLOTS = kWG / L;
   constexpr int PER = kTile / L;                          // pairs per lane and tile
   constexpr int RUN = P::kRun < PER ? P::kRun : PER;      // pairs per float run
@@ -481,7 +552,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * SLOTS + slot;
-    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    irow[kk] = (k < n_act) ? checked_row(active, k, row_lo, row_hi, err) : -1;
     I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const typename P::T e2 = in_vgpr(P::eps(eps2));
@@ -551,7 +622,7 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
       }
     }
     const int64_t k = k0 + kk * SLOTS + slot;
-    if (sub == 0 && k < n_act) {
+    if (sub == 0 && irow[kk] >= 0) {
       if (final_out) {
         const double self = (e2 > 0 && smass) ? P::self_term(smass[irow[kk]], eps2) : 0.0;
         acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
@@ -581,21 +652,26 @@ __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
     const int64_t d = *a.n_active_dev;
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;  // another regime's launch
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-    S = choose_S(n_act, IB, a.target_items, a.n);
+    S = choose_S(n_act, IB, target_for(a, d), a.n);
     if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
   const int64_t clen = chunk_len(a.n, S);
-  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+  __shared__ unsigned int slot;
+  int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
+  while (w < items) {
     const int64_t chunk = w / n_iblk;
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
     process_item<P, K, L, MASK>(sm.tile, sm.red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
                                 a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
-                                a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+                                a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi,
+                                a.err);
+    w = queue_take(a.wq, slot, items, w + gridDim.x);
   }
+  queue_done(a.wq);
 }
 
 // Fixed-order sum of the S partial blocks, self-term removal, output.
@@ -613,7 +689,7 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
     } else {
       if (d < a.act_lo || (d > a.n_active && !a.last)) return;
       n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-      S = choose_S(n_act, IB, a.target_items, a.n);
+      S = choose_S(n_act, IB, target_for(a, d), a.n);
     }
   }
   if (S <= 1) return;
@@ -630,6 +706,7 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
     const int64_t k = idx - c * n_act;
     const double s = sum_blocks(a.part + c * n_act + k, 7 * n_act, S, lane, g);
     if (lane != 0) continue;
+    if (!row_in_range(a.active[k], a.row_lo, a.row_hi)) continue;  // skipped row (flagged by the force pass)
     if (c < 3) {
       a.acc[3 * k + c] = s;
     } else if (c < 6) {
@@ -666,7 +743,8 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
                                                 const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
                                                 double eps2, bool final_out, double* __restrict__ acc,
                                                 double* __restrict__ jerk, double* __restrict__ pot,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int64_t row_lo,
+                                                int64_t row_hi, unsigned int* err) {
   constexpr int RUN = P::kRun;  // pairs per float run
   const int t = threadIdx.x;
   typename P::IPart I[K];
@@ -674,7 +752,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
-    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    irow[kk] = (k < n_act) ? checked_row(active, k, row_lo, row_hi, err) : -1;
     I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const typename P::T e2 = in_vgpr(P::eps(eps2));
@@ -731,7 +809,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
-    if (k < n_act) {
+    if (irow[kk] >= 0) {
       double v[7];
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
@@ -767,21 +845,25 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
     const int64_t d = *a.n_active_dev;
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-    S = choose_S(n_act, IB, a.target_items, a.n);
+    S = choose_S(n_act, IB, target_for(a, d), a.n);
     if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
   const int64_t clen = chunk_len(a.n, S);
-  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+  __shared__ unsigned int slot;
+  int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
+  while (w < items) {
     const int64_t chunk = w / n_iblk;
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
     process_item_sj<P, K, MASK>(rec, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass,
                                 jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
-                                a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+                                a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi, a.err);
+    w = queue_take(a.wq, slot, items, w + gridDim.x);
   }
+  queue_done(a.wq);
 }
 
 
@@ -797,7 +879,8 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
                                                 const int32_t* __restrict__ active, int64_t n_act, int64_t k0,
                                                 double eps2, bool final_out, double* __restrict__ acc,
                                                 double* __restrict__ jerk, double* __restrict__ pot,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int64_t row_lo,
+                                                int64_t row_hi, unsigned int* err) {
   using P = Mixed;
   constexpr int RUN = P::kRun;  // pairs per float run
   const int t = threadIdx.x;
@@ -806,7 +889,7 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
-    irow[kk] = (k < n_act) ? (int64_t)active[k] : -1;
+    irow[kk] = (k < n_act) ? checked_row(active, k, row_lo, row_hi, err) : -1;
     I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
   const float e2 = in_vgpr(P::eps(eps2));
@@ -874,7 +957,7 @@ __device__ __forceinline__ void process_item_hy(const Mixed::JReg* __restrict__ 
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
     const int64_t k = k0 + kk * kWG + t;
-    if (k < n_act) {
+    if (irow[kk] >= 0) {
       double v[7];
 #pragma unroll
       for (int c = 0; c < 7; ++c) v[c] = P::value(Tt[kk], c);
@@ -901,21 +984,25 @@ __global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a
     const int64_t d = *a.n_active_dev;
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-    S = choose_S(n_act, IB, a.target_items, a.n);
+    S = choose_S(n_act, IB, target_for(a, d), a.n);
     if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
   const int64_t clen = chunk_len(a.n, S);
-  for (int64_t w = blockIdx.x; w < items; w += gridDim.x) {
+  __shared__ unsigned int slot;
+  int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
+  while (w < items) {
     const int64_t chunk = w / n_iblk;
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
     process_item_hy<K>(rec, vm_tile, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel,
                        a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
-                       a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act);
+                       a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi, a.err);
+    w = queue_take(a.wq, slot, items, w + gridDim.x);
   }
+  queue_done(a.wq);
 }
 
 // ---------------------------------------------------------------- batch ----
@@ -925,7 +1012,7 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
                                                       const BatchSys* __restrict__ sys, const double* pos,
                                                       const double* vel, const double* mass,
                                                       const int32_t* active, double* acc, double* jerk,
-                                                      double* pot, double* part) {
+                                                      double* pot, double* part, unsigned int* err) {
   __shared__ Smem<P, L> sm;
   constexpr int IB = (kWG / L) * K;
   if (n_items_dev) {
@@ -943,7 +1030,7 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
     process_item<P, K, L, MASK>(sm.tile, sm.red, pos, vel, mass, pos, vel, mass, jb, je, active + sy.a0, n_act,
                                 (int64_t)it.iblk * IB, sy.eps2, it.nchunk == 1, acc + 3 * sy.a0,
                                 jerk + 3 * sy.a0, pot + sy.a0,
-                                part + (sy.part_off + (int64_t)it.chunk * n_act) * 7);
+                                part + (sy.part_off + (int64_t)it.chunk * n_act) * 7, sy.j0, sy.j1, err);
   }
 }
 
@@ -970,6 +1057,7 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict
     const double s = sum_blocks(pb + c * n_act + k, 7 * n_act, S, lane, g);
     if (lane != 0) continue;
     const int64_t row = sy.a0 + k;
+    if (!row_in_range(active[row], sy.j0, sy.j1)) continue;  // skipped row (flagged by the force pass)
     if (c < 3) {
       acc[3 * row + c] = s;
     } else if (c < 6) {
@@ -1121,7 +1209,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
 // ------------------------------------------------------------- dispatch ----
 using ForceFn = void (*)(ForceArgs);
 using BatchFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const double*, const double*,
-                         const double*, const int32_t*, double*, double*, double*, double*);
+                         const double*, const int32_t*, double*, double*, double*, double*, unsigned int*);
 
 template <class P, bool MASK>
 ForceFn pick_force(int K, int L) {
@@ -1317,7 +1405,7 @@ hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStre
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
                         const BatchSys* sys, const double* pos, const double* vel, const double* mass,
                         const int32_t* active, double* acc, double* jerk, double* pot, double* part,
-                        int64_t part_rows, bool any_mask, int max_grid, hipStream_t st) {
+                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, hipStream_t st) {
   (void)part_rows;
   const int K = any_mask ? 1 : cfg.K;
   BatchFn fn = nullptr;
@@ -1332,7 +1420,7 @@ hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int
   int grid = n_items;
   if (max_grid > 0 && grid > max_grid) grid = max_grid;
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, items, n_items, n_items_dev, sys, pos, vel, mass, active, acc,
-                     jerk, pot, part);
+                     jerk, pot, part, err);
   return hipGetLastError();
 }
 

@@ -108,7 +108,11 @@ __device__ __forceinline__ void item6(Tile6& tile, const Force6Args& a, int64_t 
                                       int64_t k0, bool final_out, double* part) {
   const int t = threadIdx.x;
   const int64_t k = k0 + t;
-  const int64_t irow = k < n_act ? (int64_t)a.active[k] : -1;
+  int64_t irow = k < n_act ? (int64_t)a.active[k] : -1;
+  if (k < n_act && !row_in_range(irow, 0, a.n)) {  // not a particle: skipped, and reported by nb_sync
+    if (a.err) atomicOr(a.err, kErrActiveRange);
+    irow = -1;
+  }
   const int64_t ir = irow >= 0 ? irow : 0;
   double I[9];
 #pragma unroll
@@ -144,7 +148,7 @@ __device__ __forceinline__ void item6(Tile6& tile, const Force6Args& a, int64_t 
       T[c] = 0.0;
     }
   }
-  if (k >= n_act) return;
+  if (irow < 0) return;
   double v[kC6];
 #pragma unroll
   for (int c = 0; c < kC6; ++c) v[c] = hi[c] + lo[c];
@@ -204,6 +208,7 @@ __global__ __launch_bounds__(256) void k_reduce6(Force6Args a) {
     const int64_t k = idx - c * n_act;
     const double s = sum_blocks(a.part + c * n_act + k, kC6 * n_act, S, lane, g);
     if (lane != 0) continue;
+    if (!row_in_range(a.active[k], 0, a.n)) continue;  // skipped row (flagged by the force pass)
     if (c < 3) {
       a.acc[3 * k + c] = s;
     } else if (c < 6) {

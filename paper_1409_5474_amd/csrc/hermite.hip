@@ -42,7 +42,8 @@ __device__ __forceinline__ double norm3(double x, double y, double z) { return s
 
 // ---------------------------------------------------------------- correct --
 __global__ __launch_bounds__(kB) void k_correct(const int32_t* __restrict__ active, int64_t n_active_host,
-                                                const int64_t* __restrict__ n_active_dev,
+                                                const int64_t* __restrict__ n_active_dev, int64_t n_rows,
+                                                unsigned int* __restrict__ err,
                                                 const double* __restrict__ pos_p, const double* __restrict__ vel_p,
                                                 const double* __restrict__ acc1, const double* __restrict__ jerk1,
                                                 double* __restrict__ pos, double* __restrict__ vel,
@@ -59,6 +60,10 @@ __global__ __launch_bounds__(kB) void k_correct(const int32_t* __restrict__ acti
   if (step_dev && n_act > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(step_dev, 1ull);
   for (int64_t k = (int64_t)blockIdx.x * kB + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * kB) {
     const int64_t i = active[k];
+    if (!row_in_range(i, 0, n_rows)) {  // not a particle: skipped, and reported by nb_sync
+      if (err) atomicOr(err, kErrActiveRange);
+      continue;
+    }
     const int L = level[i];
     const double dt = ldexp(dt_max, -L);
     const double dt2 = dt * dt, dt3 = dt2 * dt;
@@ -380,23 +385,25 @@ hipError_t launch_predict(const double* pos, const double* vel, const double* ac
   return hipGetLastError();
 }
 
-hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t* n_active_dev, const double* pos_p,
-                          const double* vel_p, const double* acc1, const double* jerk1, double* pos, double* vel,
-                          double* acc, double* jerk, int64_t* t_tick, int32_t* level, double eta, double dt_max,
-                          int max_level, int64_t* clamp_dev, hipStream_t st) {
+hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t* n_active_dev, int64_t n_rows,
+                          unsigned int* err, const double* pos_p, const double* vel_p, const double* acc1,
+                          const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
+                          int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                          int64_t* clamp_dev, hipStream_t st) {
   if (n_active <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_correct, dim3(grid_for(n_active, 16384)), dim3(kB), 0, st, active, n_active, n_active_dev,
-                     pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, level, eta, dt_max, max_level,
+                     n_rows, err, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, level, eta, dt_max, max_level,
                      reinterpret_cast<unsigned long long*>(clamp_dev), nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64_t* n_active_dev,
-                               const double* pos_p, const double* vel_p, const double* acc1, const double* jerk1,
-                               double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick, int32_t* level,
-                               double eta, double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_correct, dim3(grid_for(n_max, 1024)), dim3(kB), 0, st, active, n_max, n_active_dev, pos_p,
+hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, int64_t n_rows,
+                               unsigned int* err, const double* pos_p, const double* vel_p, const double* acc1,
+                               const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
+                               int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                               int64_t* clamp_dev, int64_t* step_dev, hipStream_t st) {
+  hipLaunchKernelGGL(k_correct, dim3(grid_for(n_max, 1024)), dim3(kB), 0, st, active, n_max, n_active_dev, n_rows,
+                     err, pos_p,
                      vel_p, acc1, jerk1, pos, vel, acc, jerk, t_tick, level, eta, dt_max, max_level,
                      reinterpret_cast<unsigned long long*>(clamp_dev),
                      reinterpret_cast<unsigned long long*>(step_dev));

@@ -70,7 +70,8 @@ __device__ __forceinline__ int new_level6(int L, double ds, int64_t t_new, doubl
 }
 
 __global__ __launch_bounds__(kB6) void k_correct6(const int32_t* __restrict__ active, int64_t n_active_host,
-                                                  const int64_t* __restrict__ n_active_dev,
+                                                  const int64_t* __restrict__ n_active_dev, int64_t n_rows,
+                                                  unsigned int* __restrict__ err,
                                                   const double* __restrict__ acc1, const double* __restrict__ jerk1,
                                                   const double* __restrict__ snap1, double* __restrict__ pos,
                                                   double* __restrict__ vel, double* __restrict__ acc,
@@ -87,6 +88,10 @@ __global__ __launch_bounds__(kB6) void k_correct6(const int32_t* __restrict__ ac
   if (step_dev && n_act > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(step_dev, 1ull);
   for (int64_t k = (int64_t)blockIdx.x * kB6 + threadIdx.x; k < n_act; k += (int64_t)gridDim.x * kB6) {
     const int64_t i = active[k];
+    if (!row_in_range(i, 0, n_rows)) {  // not a particle: skipped, and reported by nb_sync
+      if (err) atomicOr(err, kErrActiveRange);
+      continue;
+    }
     const int L = level[i];
     const double h = ldexp(dt_max, -L);
     const double h2 = h * h, h3 = h2 * h;
@@ -161,12 +166,14 @@ hipError_t launch_predict6(const double* pos, const double* vel, const double* a
   return hipGetLastError();
 }
 
-hipError_t launch_correct6(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, const double* acc1,
-                           const double* jerk1, const double* snap1, double* pos, double* vel, double* acc,
-                           double* jerk, double* snap, double* crackle, int64_t* t_tick, int32_t* level, double eta,
-                           double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev, hipStream_t st) {
+hipError_t launch_correct6(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, int64_t n_rows,
+                           unsigned int* err, const double* acc1, const double* jerk1, const double* snap1,
+                           double* pos, double* vel, double* acc, double* jerk, double* snap, double* crackle,
+                           int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                           int64_t* clamp_dev, int64_t* step_dev, hipStream_t st) {
   if (n_max <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_correct6, dim3(grid6(n_max, 1024)), dim3(kB6), 0, st, active, n_max, n_active_dev, acc1,
+  hipLaunchKernelGGL(k_correct6, dim3(grid6(n_max, 1024)), dim3(kB6), 0, st, active, n_max, n_active_dev, n_rows,
+                     err, acc1,
                      jerk1, snap1, pos, vel, acc, jerk, snap, crackle, t_tick, level, eta, dt_max, max_level,
                      reinterpret_cast<unsigned long long*>(clamp_dev),
                      reinterpret_cast<unsigned long long*>(step_dev));

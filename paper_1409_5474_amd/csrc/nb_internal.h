@@ -12,6 +12,14 @@ namespace nb {
 
 constexpr int kWG = 256;    // threads per workgroup of every force kernel
 constexpr int kTile = 256;  // j-particles staged in LDS per tile
+constexpr int kWorkQueueWords = 16;  // words of a context's work queue (9 used)
+constexpr int kMaxSubRegimes = 16;   // active-count regimes one device-count launch can serve
+constexpr int kErrorWord = kWorkQueueWords - 1;  // word of that buffer holding the device error bits
+constexpr unsigned int kErrActiveRange = 1u;     // an active_idx entry outside its valid range was skipped
+
+// The range test of every kernel that reads an i-set entry: r must lie in
+// [lo, hi).  Host and device share it, so a host test exercises this code.
+__host__ __device__ inline bool row_in_range(int64_t r, int64_t lo, int64_t hi) { return r >= lo && r < hi; }
 
 // One launch configuration of the force kernel family.
 struct Launch {
@@ -74,13 +82,28 @@ struct ForceArgs {
   int* s_dev;                   // device count: the working regime's S, for the shared reduce
   int64_t act_lo;               // device-count mode: work only when count >= act_lo and
   int last;                     // count <= n_active (or any larger count when `last`)
+  // Device-count mode, one launch serving several adjacent regimes of one
+  // shape: regime r starts at count sub_lo[r] and aims at sub_items[r] work
+  // items, so the count picks the same S as a host-count launch would
+  // (n_sub == 0: target_items for every count).
+  int n_sub;
+  int64_t sub_lo[kMaxSubRegimes];
+  int sub_items[kMaxSubRegimes];
   void* rec;                    // scalar j-path: mirror of n j-records (context-owned)
+  // Work queue of the persistent grid (per-XCD item counters, then the count
+  // of finished workgroups): zero before a launch, and the launch's last
+  // workgroup sets it back to zero (context-owned, kWorkQueueWords words).
+  unsigned int* wq;
   // Receiving particles given apart from the j-set: `active` then indexes
   // ipos/ivel (null: the j arrays) and, with no_self set, no self pair is
   // removed from the potential (the i-set is not part of the j-set).
   const double* ipos;
   const double* ivel;
   int no_self;
+  // Valid i-set entries lie in [row_lo, row_hi): others are skipped (no
+  // output row is written for them) and set kErrActiveRange in *err.
+  int64_t row_lo, row_hi;
+  unsigned int* err;
 };
 
 // Arguments of the sixth-order force kernel (forces6.hip): acceleration,
@@ -103,6 +126,7 @@ struct Force6Args {
   double* snap;
   double* pot;
   double* part;                 // [S][10][n_active] partial sums when S > 1
+  unsigned int* err;            // i-set entries outside [0, n) are skipped and flagged here
 };
 
 // Batched work list item: one (system, i-block, j-chunk) triple.
@@ -132,7 +156,7 @@ int items_for(const Launch& cfg, int64_t n_active, int S);
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
                         const BatchSys* sys, const double* pos, const double* vel, const double* mass,
                         const int32_t* active, double* acc, double* jerk, double* pot, double* part,
-                        int64_t part_rows, bool any_mask, int max_grid, hipStream_t st);
+                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, hipStream_t st);
 hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, const int32_t* active,
                              const int64_t* n_act_dev, int IB, int target, BatchSys* sys, int32_t* nchunk,
                              BatchItem* items, int max_items, int* n_items_dev, int64_t part_cap_rows,
@@ -146,16 +170,16 @@ hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const i
 hipError_t launch_predict(const double* pos, const double* vel, const double* acc, const double* jerk,
                           const int64_t* t_tick, int64_t t_next, const int64_t* t_next_dev, double dt_min,
                           int64_t n, double* pos_p, double* vel_p, hipStream_t st);
-hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t* n_active_dev,
-                          const double* pos_p, const double* vel_p, const double* acc1, const double* jerk1,
-                          double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick,
-                          int32_t* level, double eta, double dt_max, int max_level, int64_t* clamp_dev,
-                          hipStream_t st);
-hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64_t* n_active_dev,
-                               const double* pos_p, const double* vel_p, const double* acc1, const double* jerk1,
-                               double* pos, double* vel, double* acc, double* jerk, int64_t* t_tick, int32_t* level,
-                               double eta, double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev,
-                               hipStream_t st);
+hipError_t launch_correct(const int32_t* active, int64_t n_active, const int64_t* n_active_dev, int64_t n_rows,
+                          unsigned int* err, const double* pos_p, const double* vel_p, const double* acc1,
+                          const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
+                          int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                          int64_t* clamp_dev, hipStream_t st);
+hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, int64_t n_rows,
+                               unsigned int* err, const double* pos_p, const double* vel_p, const double* acc1,
+                               const double* jerk1, double* pos, double* vel, double* acc, double* jerk,
+                               int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                               int64_t* clamp_dev, int64_t* step_dev, hipStream_t st);
 hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, double eta, double dt_max,
                           int max_level, int32_t* level, hipStream_t st);
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level,
@@ -202,10 +226,11 @@ hipError_t launch_predict6(const double* pos, const double* vel, const double* a
                            const double* snap, const double* crackle, const int64_t* t_tick, int64_t t_next,
                            const int64_t* t_next_dev, double dt_min, int64_t n, double* pos_p, double* vel_p,
                            double* acc_p, hipStream_t st);
-hipError_t launch_correct6(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, const double* acc1,
-                           const double* jerk1, const double* snap1, double* pos, double* vel, double* acc,
-                           double* jerk, double* snap, double* crackle, int64_t* t_tick, int32_t* level, double eta,
-                           double dt_max, int max_level, int64_t* clamp_dev, int64_t* step_dev, hipStream_t st);
+hipError_t launch_correct6(const int32_t* active, int64_t n_max, const int64_t* n_active_dev, int64_t n_rows,
+                           unsigned int* err, const double* acc1, const double* jerk1, const double* snap1,
+                           double* pos, double* vel, double* acc, double* jerk, double* snap, double* crackle,
+                           int64_t* t_tick, int32_t* level, double eta, double dt_max, int max_level,
+                           int64_t* clamp_dev, int64_t* step_dev, hipStream_t st);
 hipError_t launch_startup6(const double* acc, const double* jerk, const double* snap, int64_t n, double eta_s,
                            double dt_max, int max_level, int32_t* level, hipStream_t st);
 
@@ -232,6 +257,7 @@ struct nb_ctx {
   void* mirror = nullptr;       // j-records of the scalar j-path
   size_t mirror_bytes = 0;
   int* s_dev = nullptr;         // S chosen on the device by the last device-count launch
+  unsigned int* wq = nullptr;   // work queue of the force grids (zero between launches)
   int64_t* sched_tmp = nullptr; // block minima for the scheduler
   int32_t* sched_cnt = nullptr;
   int32_t* nact32 = nullptr;    // int32 copy of the scheduled active count

@@ -96,6 +96,7 @@ class BlockIntegrator:
     def _graph(self, steps):
         g = self._graphs.get(steps)
         if g is None:
+            prev = self.ctx.stream
             stream = torch.cuda.Stream(self.dev)
             self.ctx.set_stream(stream)
             try:
@@ -104,7 +105,7 @@ class BlockIntegrator:
                     for _ in range(steps):
                         self.step()
             finally:
-                self.ctx.set_stream(None)
+                self.ctx.set_stream(prev)
             self._graphs[steps] = g
         return g
 
@@ -115,9 +116,11 @@ class BlockIntegrator:
         end = int(round(t_end / self.tick))
         if end * self.tick != t_end:
             raise ValueError("t_end must be a whole number of ticks")
+        sync = 1 << self.max_level
+        if end % sync:
+            raise ValueError("t_end must be a multiple of dt_max (a synchronisation time)")
         if log is None:
             return self.run_to_tick(end, graph_steps, use_graph)
-        sync = 1 << self.max_level
         tick = (int(self.t_tick.min().item()) // sync + 1) * sync
         while tick <= end:
             self.run_to_tick(tick, graph_steps, use_graph)
@@ -131,6 +134,7 @@ class BlockIntegrator:
         the velocities, e.g. a kick, the stored jerks are stale)."""
         self._all_forces(self.pos, self.vel, self.acc, self.jerk, self.pot1)
         self.ctx.startup(self.acc, self.jerk, self.eta, self.dt_max, self.max_level, self.level)
+        self._E0 = self._energy_from(self.pot1)["E"]
 
     def run_to_tick(self, end, graph_steps=32, use_graph=True):
         """Integrate until every particle reaches tick ``end`` (a multiple of 2^max_level)."""
@@ -161,7 +165,7 @@ class BlockIntegrator:
         torch.cuda.synchronize(self.dev)
         arrays = {k: getattr(self, k).cpu().numpy() for k in self._STATE}
         arrays["mass"] = self.mass.cpu().numpy()
-        meta = np.array([self.eta, self.dt_max, float(self.max_level), float(self.batch)], dtype=np.float64)
+        meta = np.array([self.eta, self.dt_max, float(self.max_level), float(self.batch), self._E0], dtype=np.float64)
         arrays["meta"] = meta
         if self.batch:
             arrays["offsets"] = self.offsets
@@ -175,7 +179,7 @@ class BlockIntegrator:
         """Rebuild an integrator from ``checkpoint`` output."""
         import numpy as np
         d = np.load(path, allow_pickle=False)
-        eta, dt_max, max_level, batch = d["meta"].tolist()
+        eta, dt_max, max_level, batch, E0 = d["meta"].tolist()
         dev = ctx.device
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
         self = cls.__new__(cls)
@@ -189,6 +193,7 @@ class BlockIntegrator:
             self.eps2 = float(d["eps2"][0])
         self.eta, self.dt_max, self.max_level = float(eta), float(dt_max), int(max_level)
         self.tick = self.dt_max * 2.0 ** -self.max_level
+        self._E0 = float(E0)
         self.mass = t(d["mass"])
         for k in self._STATE:
             setattr(self, k, t(d[k]))
@@ -219,18 +224,24 @@ class BlockIntegrator:
         jerk = torch.empty_like(self.jerk)
         pot = torch.empty_like(self.pot1)
         self._all_forces(self.pos, self.vel, acc, jerk, pot)
+        return self._energy_from(pot)
+
+    def _energy_from(self, pot):
         out = torch.zeros(8, dtype=torch.float64, device=self.dev)
         self.ctx.energy(self.pos, self.vel, self.mass, pot, out)
         o = out.cpu().tolist()
         return dict(K=o[0], W=o[1], E=o[0] + o[1], P=o[2:5], L=o[5:8])
 
+    @property
+    def E0(self):
+        """Total energy at the last start (construction or ``restart``)."""
+        return self._E0
+
     def diagnostics(self):
         """The state at a synchronisation time: time, steps so far, clamped
-        level changes, energy and its change since the first call, momentum,
-        angular momentum and the virial ratio 2K/|W|."""
+        level changes, energy and its change since the start (``E0``),
+        momentum, angular momentum and the virial ratio 2K/|W|."""
         e = self.energy()
-        if not hasattr(self, "_E0"):
-            self._E0 = e["E"]
         return dict(t=self.time, steps=self.steps, clamps=self.clamps, E=e["E"], K=e["K"], W=e["W"],
                     dE_rel=abs(e["E"] - self._E0) / abs(self._E0) if self._E0 else 0.0, P=e["P"], L=e["L"],
                     virial=2.0 * e["K"] / abs(e["W"]) if e["W"] else float("inf"))
@@ -271,6 +282,7 @@ class BlockIntegrator6(BlockIntegrator):
         self.acc.copy_(self.acc1)
         self.crackle.zero_()
         self.ctx.startup6(self.acc, self.jerk, self.snap, self.eta_s, self.dt_max, self.max_level, self.level)
+        self._E0 = self._energy_from(self.pot1)["E"]
 
     def _step(self, t_stop_tick):
         self.ctx.block_step6(self.n, self.eps2, self.eta, self.dt_max, self.max_level, self.mass, self.pos, self.vel,

@@ -73,3 +73,21 @@ def test_import_fails_loudly_without_the_library(tmp_path, monkeypatch):
     mod = importlib.util.module_from_spec(spec)
     with pytest.raises(ImportError):
         spec.loader.exec_module(mod)
+
+
+def test_active_range_rule_on_the_host():
+    # The range test every kernel applies to an i-set entry (the library's
+    # row_in_range, run here through its host entry point): [lo, hi), the
+    # first bad entry reported, negative and past-the-end values caught.
+    import numpy as np
+    import paper_1409_5474_amd as nb
+    assert nb.check_active_host(np.arange(10, dtype=np.int32), 0, 10) == -1
+    assert nb.check_active_host(np.array([3, 9, 10, 2], np.int32), 0, 10) == 2
+    assert nb.check_active_host(np.array([0, -1], np.int32), 0, 10) == 1
+    assert nb.check_active_host(np.array([5, 4, 7], np.int32), 5, 8) == 1     # a batch system's rows [5, 8)
+    assert nb.check_active_host(np.array([2 ** 31 - 1], np.int32), 0, 2 ** 31 - 1) == 0
+    assert nb.check_active_host(np.zeros(0, np.int32), 0, 1) == -1
+    lib = nb.library()
+    assert lib.nb_check_active_host(None, 3, 0, 10, None) == -1               # null array with entries
+    assert lib.nb_check_active_host(None, 0, 0, 10, None) == 0
+    assert lib.nb_sync(None) == -1

@@ -235,3 +235,116 @@ except nb.NbodyError as e:
     env = dict(os.environ, NB_MAX_WORKSPACE_BYTES="1024")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
     assert "CODE -2 True" in r.stdout, (r.stdout, r.stderr[-2000:])
+
+
+def test_workspace_growth_stays_within_the_cap(ctx):
+    # A request just under the cap succeeds and the workspace it grows stays
+    # within the cap (growth headroom is clamped to it).
+    import os
+    import subprocess
+    import sys
+    code = r'''
+import sys, numpy as np, torch
+sys.path.insert(0, %r)
+import paper_1409_5474_amd as nb, synth
+p = synth.plummer(4096, 3)
+ctx = nb.Context(0, "fp64", load_tuning=False)
+ctx.set_launch(1, 64, 32)
+t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+acc, jerk, pot = ctx.forces(t(p.pos), t(p.vel), t(p.mass), torch.arange(16, dtype=torch.int32, device="cuda"), 1e-4)
+torch.cuda.synchronize()
+print("BYTES", ctx.workspace_bytes(), bool(torch.isfinite(acc).all()))
+''' % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    need = 16 * 7 * 16 * 8      # S x 7 x n_active doubles (S = 32 is capped at N / 256 = 16 chunks)
+    env = dict(os.environ, NB_MAX_WORKSPACE_BYTES=str(need + 100))
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
+    assert "BYTES" in r.stdout, (r.stdout, r.stderr[-2000:])
+    got = r.stdout.split("BYTES")[1].split()
+    assert need <= int(got[0]) <= need + 100 and got[1] == "True", r.stdout
+
+
+# ---- i-set entries outside their valid range -------------------------------
+# Every kernel that reads active_idx tests each entry first: a bad entry gets
+# no output row and nothing is read through it; the context's device error
+# word records it, and the next nb_sync reports NB_EINVAL once.
+
+def _with_bad(valid, n, at, bad):
+    a = list(valid)
+    for pos_, b in zip(at, bad):
+        a.insert(pos_, b)
+    return np.array(a, dtype=np.int32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(2, 0, 4), (1, 16, 4), (1, 1, 1)])
+def test_out_of_range_entries_are_skipped_and_reported(nb, prec, shape):
+    import torch
+    c = nb.Context(0, prec, load_tuning=False)
+    n = 5000
+    p = synth.plummer(n, 31)
+    P, V, M = _dev(p.pos), _dev(p.vel), _dev(p.mass)
+    valid = np.arange(0, n, 7, dtype=np.int32)
+    bad_at, bad = [0, 100, 300], [-1, n, 2 ** 31 - 1]
+    act = _with_bad(valid, n, bad_at, bad)
+    isbad = np.isin(np.arange(act.size), bad_at)
+    c.set_launch(*shape)
+    print(f"range check {prec} K,L,S={shape}: {act.size} entries, {len(bad)} bad", flush=True)
+    out = [torch.full(s, 7.0, dtype=torch.float64, device="cuda") for s in ((act.size, 3), (act.size, 3), (act.size,))]
+    c.forces(P, V, M, _dev(act), 1e-3, *out)
+    with pytest.raises(nb.NbodyError) as ei:
+        c.sync()
+    assert ei.value.code == -1 and "active_idx" in str(ei.value)
+    c.sync()                                   # reported once, then clear
+    ref = c.forces(P, V, M, _dev(valid), 1e-3)
+    torch.cuda.synchronize()
+    for o, r in zip(out, ref):
+        o = o.cpu().numpy(); r = r.cpu().numpy()
+        assert np.all(o[isbad] == 7.0)
+        assert o[~isbad].tobytes() == r.tobytes()
+    c.close()
+
+
+def test_out_of_range_entries_in_the_other_entry_points(nb):
+    import torch
+    c = nb.Context(0, "fp64")
+    n = 3000
+    p = synth.plummer(n, 32)
+    P, V, M = _dev(p.pos), _dev(p.vel), _dev(p.mass)
+    # separate i-set: N_i = 40 rows, one entry 40
+    pi = synth.plummer(40, 33)
+    act = np.array([0, 39, 40, 5], np.int32)
+    out = [torch.full(s, 7.0, dtype=torch.float64, device="cuda") for s in ((4, 3), (4, 3), (4,))]
+    c.forces_ij(P, V, M, _dev(pi.pos), _dev(pi.vel), _dev(act), 1e-3, *out)
+    with pytest.raises(nb.NbodyError):
+        c.sync()
+    assert bool((out[0][2] == 7.0).all()) and bool((out[0][3] != 7.0).all())
+    # batch: system 1 owns rows [1000, 3000); an entry of system 0 in its list
+    off = np.array([0, 1000, n], np.int64)
+    act_b = np.array([3, 999, 1000, 5, 2999], np.int32)       # 5 lies in system 0, listed under system 1
+    aoff = np.array([0, 2, 5], np.int64)
+    out = [torch.full(s, 7.0, dtype=torch.float64, device="cuda") for s in ((5, 3), (5, 3), (5,))]
+    c.forces_batch(off, [1e-3, 1e-3], P, V, M, _dev(act_b), aoff, *out)
+    with pytest.raises(nb.NbodyError):
+        c.sync()
+    assert bool((out[2][3] == 7.0).all()) and bool((out[2][[0, 1, 2, 4]] != 7.0).all())
+    # snap kernel
+    act6 = np.array([1, n, 2], np.int32)
+    a6 = [torch.full(s, 7.0, dtype=torch.float64, device="cuda") for s in ((3, 3), (3, 3), (3, 3), (3,))]
+    c.forces6(P, V, torch.zeros_like(P), M, _dev(act6), 1e-3, *a6)
+    with pytest.raises(nb.NbodyError):
+        c.sync()
+    assert bool((a6[0][1] == 7.0).all()) and bool((a6[0][0] != 7.0).all())
+    # corrector: an entry N touches nothing; the valid rows are corrected
+    pos, vel = _dev(p.pos), _dev(p.vel)
+    acc = torch.zeros_like(pos); jerk = torch.zeros_like(pos)
+    tt = torch.zeros(n, dtype=torch.int64, device="cuda"); lv = torch.zeros(n, dtype=torch.int32, device="cuda")
+    actc = np.array([7, n, 9], np.int32)
+    a1 = torch.ones((3, 3), dtype=torch.float64, device="cuda"); j1 = torch.zeros_like(a1)
+    before = pos.clone()
+    c.correct(_dev(actc), pos.clone(), vel.clone(), a1, j1, pos, vel, acc, jerk, tt, lv, 0.01, 1.0 / 16, 20)
+    with pytest.raises(nb.NbodyError):
+        c.sync()
+    changed = (pos != before).any(1).cpu().numpy()
+    assert changed[7] and changed[9] and changed.sum() == 2
+    c.sync()
+    c.close()

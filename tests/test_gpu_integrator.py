@@ -135,3 +135,43 @@ def test_run_until_logs_every_synchronisation_time(ctx):
     for r in rec:
         assert r["dE_rel"] < 1e-4 and 0.5 < r["virial"] < 1.5
         assert set(r) >= {"t", "steps", "clamps", "E", "K", "W", "dE_rel", "P", "L", "virial"}
+    # the drift is measured from the energy at t = 0, so the first stop
+    # already shows the drift of the first dt_max
+    assert rec[0]["dE_rel"] > 0.0
+    assert rec[0]["dE_rel"] == abs(rec[0]["E"] - a.E0) / abs(a.E0)
+
+
+def test_run_until_rejects_a_time_between_synchronisation_times(ctx, tmp_path):
+    # t = 0.1 is a whole number of ticks but not a multiple of dt_max = 1/16:
+    # with or without a log the call refuses instead of stopping early
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    p = synth.plummer(256, 52)
+    a = BlockIntegrator(ctx, T(p.pos), T(p.vel), T(p.mass), 1e-3, 0.02, 1.0 / 16, 20)
+    t0 = a.t_tick.clone()
+    for log in (None, lambda r: None):
+        with pytest.raises(ValueError):
+            a.run_until(0.0625 + 2.0 ** -10, log=log)
+    assert bool((a.t_tick == t0).all())
+    # E0 survives a checkpoint
+    a.run_until(0.0625)
+    path = tmp_path / "st.npz"
+    a.checkpoint(str(path))
+    b = BlockIntegrator.restore(ctx, str(path))
+    assert b.E0 == a.E0
+
+
+def test_graph_capture_keeps_the_context_stream(ctx):
+    # a context built on an explicit stream stays on it after run_until
+    # captured its graph on a side stream
+    import torch
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    s = torch.cuda.Stream()
+    c2 = nb.Context(0, "fp64", stream=s)
+    p = synth.plummer(512, 53)
+    with torch.cuda.stream(s):
+        a = BlockIntegrator(c2, T(p.pos), T(p.vel), T(p.mass), 1e-3, 0.02, 1.0 / 16, 20)
+        a.run_until(0.0625, graph_steps=4, use_graph=True)
+    assert c2.stream is s
+    torch.cuda.synchronize()
+    c2.close()

@@ -95,3 +95,56 @@ def test_merger_direct_part_sampled(prec):
     else:
         assert e["acc"]["rms"] < 1e-6 and e["pot"]["rms"] < 1e-6 and e["jerk"]["rms"] < 1e-5, e
     ctx.close()
+
+
+def test_cluster_batch_128_mixed_block_steps_follow_the_oracle():
+    # The 128-cluster batch in its own configuration: mixed precision, block
+    # steps of the whole batch replayed from HIP graphs, to t = 1/16.  Eight
+    # clusters spread over the size range (128 .. 16384) are integrated
+    # separately by the CPU oracle in FP64 from the same start.
+    # Gates, from the mixed force bar (RMS relative acceleration error
+    # <= 1e-6 per evaluation):
+    #  * energy: |E_gpu(t) - E_cpu(t)| <= 0.1 |E_cpu(t) - E0| + 1e-7 |E0| (the
+    #    drift agrees within 10%, above a floor of float rounding in the
+    #    forces over the run);
+    #  * particles whose final level agrees with the oracle's (no level
+    #    flip): positions within 1e-6 (lengths are O(1); a 1e-6 relative
+    #    force error over t = 1/16 moves a body by ~1e-9 |a|);
+    #  * at most 1% of a cluster's particles end on another level.
+    import torch
+    import paper_1409_5474_amd as nb
+    from oracle import hermite as H
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    b = synth.cluster_batch()
+    eta, dt_max, ML, t_end = 0.01, 1.0 / 16, 30, 0.0625
+    ctx = nb.Context(0, "mixed")
+    bi = BlockIntegrator(ctx, T(b.pos), T(b.vel), T(b.mass), b.eps2, eta, dt_max, ML, offsets=b.offsets)
+    bi.run_until(t_end, graph_steps=16)
+    torch.cuda.synchronize()
+    X, V, L = bi.pos.cpu().numpy(), bi.vel.cpu().numpy(), bi.level.cpu().numpy()
+    order = np.argsort(b.sizes, kind="stable")
+    picks = order[::16]
+    print("clusters", [(int(c), int(b.sizes[c])) for c in picks], flush=True)
+    for c in picks:
+        lo, hi = int(b.offsets[c]), int(b.offsets[c + 1])
+        e2 = float(b.eps2[c])
+
+        def f(x, v, m, act):
+            a, j, ph, _ = oracle.forces_f64(x, v, m, e2, act)
+            return a, j, ph
+        st = H.initialise(b.pos[lo:hi], b.vel[lo:hi], b.mass[lo:hi], e2, eta, dt_max, ML, f)
+        H.run_until(st, t_end, f)
+
+        def energy(x, v):
+            W = oracle.pair_potential_energy(x, b.mass[lo:hi], e2)
+            return 0.5 * float((b.mass[lo:hi] * (v * v).sum(1)).sum()) + W
+        E0 = energy(b.pos[lo:hi], b.vel[lo:hi])
+        Ec, Eg = energy(st.x, st.v), energy(X[lo:hi], V[lo:hi])
+        same = L[lo:hi] == st.level
+        dx = np.abs(X[lo:hi][same] - st.x[same]).max()
+        print(f"cluster {c} N={hi - lo}: drift cpu {abs(Ec - E0) / abs(E0):.3e} gpu {abs(Eg - E0) / abs(E0):.3e}, "
+              f"level flips {int((~same).sum())}, max |dx| (no flip) {dx:.2e}", flush=True)
+        assert abs(Eg - Ec) <= 0.1 * abs(Ec - E0) + 1e-7 * abs(E0), c
+        assert (~same).sum() <= 0.01 * (hi - lo), c
+        assert dx <= 1e-6, c
+    ctx.close()

@@ -2,7 +2,9 @@
 that cannot allocate) against nbody_forces through the C ABI: same launch,
 same kernels, so the outputs must be identical bit for bit -- on two calls in
 a row, the second smaller than the first, so stale scratch contents from the
-first cannot leak into the second."""
+first cannot leak into the second.  Where the automatic launch's partial sums
+do not fit the fixed scratch, the entry point lowers the j-split: it then
+equals nbody_forces forced to that j-split."""
 import numpy as np
 import pytest
 import torch
@@ -13,6 +15,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 NB_ENOMEM = -2
+SCRATCH_BYTES = 256 << 20
 
 
 def _dev(x):
@@ -79,9 +82,9 @@ def test_noalloc_forced_split_and_rejection(prec):
     act_s = act[:101]
     ref, got = _both(ctx, p, act_s, 1e-4)
     _same(ref, got)
-    # a launch whose partials exceed the fixed scratch is refused before any
-    # kernel runs: 64 chunks x 56 B x 65536 rows = 235 MB > 128 MiB
-    ctx.set_launch(1, 0, 64)
+    # a forced launch whose partials exceed the fixed scratch is refused before
+    # any kernel runs: 128 chunks x 56 B x 65536 rows = 470 MB > 256 MiB
+    ctx.set_launch(1, 0, 128)
     q = synth.plummer(65536, 2)
     n = 65536
     pos, vel, mass = _dev(q.pos), _dev(q.vel), _dev(q.mass)
@@ -92,4 +95,26 @@ def test_noalloc_forced_split_and_rejection(prec):
     assert ei.value.code == NB_ENOMEM and "scratch" in str(ei.value)
     torch.cuda.synchronize()
     assert all(bool((t == 7.0).all()) for t in out)
+    ctx.close()
+
+
+def test_noalloc_lowers_an_automatic_split_that_does_not_fit():
+    import paper_1409_5474_amd as nb
+    ctx = nb.Context(0, "mixed", load_tuning=False)
+    n = 65536
+    # a table entry asking for the most chunks the j-set allows (S = 256):
+    # 256 x 56 B x 65536 rows = 940 MB of partials, more than the scratch
+    ctx.tune_add("mixed", n, 0, 2 ** 31 - 1, 1, 1, 256 * 256)
+    assert ctx.get_launch(n, n) == (1, 1, 256)
+    s_fit = (SCRATCH_BYTES - 255) // (56 * n)
+    p = synth.plummer(n, 21)
+    pos, vel, mass = _dev(p.pos), _dev(p.vel), _dev(p.mass)
+    a = _dev(np.arange(n, dtype=np.int32))
+    out = [torch.full(sh, np.nan, dtype=torch.float64, device="cuda:0") for sh in ((n, 3), (n, 3), (n,))]
+    print(f"noalloc mixed: N=65536 all active, automatic S=256 lowered to {s_fit}", flush=True)
+    ctx.forces_noalloc(pos, vel, mass, a, 2.0 ** -16, *out)
+    ctx.set_launch(1, 1, s_fit)
+    ref = ctx.forces(pos, vel, mass, a, 2.0 ** -16)
+    torch.cuda.synchronize()
+    _same([t.cpu().numpy() for t in ref], [t.cpu().numpy() for t in out])
     ctx.close()
