@@ -33,7 +33,11 @@
  *    row-major [n][3] doubles (torch shape (n, 3), contiguous).
  *  - Calls are asynchronous on the context's stream (nb_set_stream); outputs
  *    are valid once that stream has been synchronised.  A context is used
- *    by one host thread at a time.
+ *    by one host thread at a time, and its calls must not overlap on the
+ *    device: they share the context's work-queue counters and workspace, so
+ *    every call -- and every replay of a graph that captured calls -- goes to
+ *    one stream, or to streams ordered with events.  Overlapping calls give
+ *    wrong results; nb_sync detects the counters they leave behind.
  *  - Index arrays are int32; an index outside [0, N) is an error only where
  *    stated (device-resident indices cannot be checked without a copy).
  *  - The context owns only its launch table, a workspace for j-split
@@ -94,7 +98,12 @@ int nb_set_stream(nb_ctx *ctx, void *hip_stream);
  * written for it and nothing is read through it -- and sets a bit in device
  * memory, so no call has to copy active_idx to the host.  Returns
  * NB_EINVAL (message in nb_last_error) once for any such entries and clears
- * the bit; NB_OK otherwise; NB_EDEVICE on a failed synchronisation. */
+ * the bit; NB_OK otherwise; NB_EDEVICE on a failed synchronisation.
+ * It also checks the context's work-queue counters, which every force
+ * launch leaves at zero: non-zero counters mean that calls overlapped on the
+ * device (see the conventions above).  They are then cleared, so later calls
+ * are correct again, and NB_EINVAL reports that results since the last
+ * nb_sync cannot be trusted. */
 int nb_sync(nb_ctx *ctx);
 
 /* The same range test on a host array: NB_OK when every active[k], k <

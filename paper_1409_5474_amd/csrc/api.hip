@@ -385,13 +385,22 @@ int nb_sync(nb_ctx* c) {
   (void)hipSetDevice(c->device);
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "stream synchronize");
-  unsigned int bits = 0;
-  e = hipMemcpy(&bits, c->wq + nb::kErrorWord, sizeof bits, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(c, e, "reading the device error word");
-  if (!bits) return NB_OK;
-  const unsigned int zero = 0;
-  e = hipMemcpy(c->wq + nb::kErrorWord, &zero, sizeof zero, hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(c, e, "clearing the device error word");
+  unsigned int words[nb::kWorkQueueWords];
+  e = hipMemcpy(words, c->wq, sizeof words, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "reading the device work queue");
+  bool queue_dirty = false;
+  for (int k = 0; k < nb::kWorkQueueWords; ++k) queue_dirty |= k != nb::kErrorWord && words[k] != 0;
+  const unsigned int bits = words[nb::kErrorWord];
+  if (!bits && !queue_dirty) return NB_OK;
+  // clear everything, so the calls after this one start from a clean queue
+  e = hipMemsetAsync(c->wq, 0, sizeof words, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "clearing the device work queue");
+  if (queue_dirty)
+    return fail(c, NB_EINVAL,
+                "the work-queue counters were not zero after synchronising: calls on this context overlapped on "
+                "the device (another stream, or a graph replayed on another stream); results since the last "
+                "nb_sync cannot be trusted%s");
   return fail(c, NB_EINVAL,
               "an active_idx entry outside its valid range was passed since the last nb_sync; its rows were "
               "skipped (outputs not written)%s");
@@ -570,9 +579,16 @@ int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const doub
 // launch configuration is fixed per regime of the count and each regime's
 // kernels return at once when the count is outside it.  Every regime's
 // workspace need is bounded on the host from max_active.
-int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
-                          const int32_t* active, const int32_t* n_active_dev, int64_t max_active, double eps2,
-                          double* acc, double* jerk, double* pot) {
+}  // extern "C"
+
+namespace {
+
+// The device-count force launches; with `reduce` also the shared reduce,
+// otherwise its arguments go to *red for a caller that fuses it with the
+// next pass (the block step).
+int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                    const int32_t* active, const int32_t* n_active_dev, int64_t max_active, double eps2,
+                    double* acc, double* jerk, double* pot, bool reduce, nb::ForceArgs* red_out) {
   int rc = check_forces_args(c, pos, vel, mass, N, active, max_active, eps2, acc, jerk, pot);
   if (rc) return rc;
   if (!n_active_dev) return fail(c, NB_EINVAL, "n_active_dev is null%s");
@@ -679,9 +695,22 @@ int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const
   red.n_active = max_active;
   red.act_lo = 0;
   red.last = 1;
+  if (red_out) *red_out = red;
+  if (!reduce) return NB_OK;
   hipError_t e = nb::launch_reduce_ib(c->prec, red, 1, 1, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reduce kernel launch (device count)");
   return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nbody_forces_devcount(nb_ctx* c, const double* pos, const double* vel, const double* mass, int64_t N,
+                          const int32_t* active, const int32_t* n_active_dev, int64_t max_active, double eps2,
+                          double* acc, double* jerk, double* pot) {
+  return devcount_forces(c, pos, vel, mass, N, active, n_active_dev, max_active, eps2, acc, jerk, pot, true,
+                         nullptr);
 }
 
 int hermite_predict(nb_ctx* c, const double* pos, const double* vel, const double* acc, const double* jerk,
@@ -919,17 +948,20 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
   rc = ensure_sched(c, N);
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
+  // schedule and predict (the predictor runs in the scheduler's last pass)
+  const nb::PredictArgs pred{pos, vel, acc, jerk, dt_min, pos_p, vel_p};
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, t_stop_tick, c->stop_dev, c->stream);
+                                     c->nact32, t_stop_tick, c->stop_dev, c->stream, &pred);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
-  e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "predict launch");
-  rc = nbody_forces_devcount(c, pos_p, vel_p, mass, N, active, c->nact32, N, eps2, acc1, jerk1, pot1);
+  nb::ForceArgs red{};
+  rc = devcount_forces(c, pos_p, vel_p, mass, N, active, c->nact32, N, eps2, acc1, jerk1, pot1, false, &red);
   if (rc) return rc;
-  e = nb::launch_correct_step(active, N, sched + 1, N, c->wq + nb::kErrorWord, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
-                              t_tick, dt_level,
-                              eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
-  return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
+  // the partial sums' reduce and the corrector in one pass
+  const nb::StepArgs st{pos_p, vel_p, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max, max_level,
+                        reinterpret_cast<unsigned long long*>(sched + 3),
+                        reinterpret_cast<unsigned long long*>(sched + 2)};
+  e = nb::launch_reduce_correct(c->prec, red, st, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "reduce and correct launch");
 }
 
 
@@ -962,12 +994,9 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
   // One kernel shape for the batch, from the typical active-set size.
   Launch cfg = choose(c, n_total, (a_total + C - 1) / C);
-  if (any_mask) cfg.K = 1;
-  if (!nb::launch_supported(cfg) || (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64) ||
-      (cfg.K == 4) || (cfg.K == 2 && cfg.L == 64)) {
-    cfg.K = 1;
+  cfg.K = 1;  // as in the batched block steps
+  if (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64)
     cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
-  }
   const int IB = nb::ib_of(cfg);
   // total work in (i-slot x j) units and the chunk length that splits it
   double work = 0.0;
@@ -1086,13 +1115,13 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
     return fail(c, NB_EINVAL, "null pointer%s");
   rc = ensure_sched(c, N);
   if (rc) return rc;
-  // one kernel shape for the batch, from the typical system size
+  // one kernel shape for the batch, from the typical system size; one
+  // i-particle per lane (K = 1): a block step's active rows are spread over
+  // many small systems, and a wider i-block would mostly carry empty lanes
   Launch cfg = choose(c, N, (N + C - 1) / C);
-  if (any_mask) cfg.K = 1;
-  if (cfg.K == 4 || (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64) || (cfg.K == 2 && cfg.L == 64)) {
-    cfg.K = 1;
+  cfg.K = 1;
+  if (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64)
     cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
-  }
   const int IB = nb::ib_of(cfg);
   const int rgrid = resident_grid(c, cfg, any_mask);
   const int target = 2 * rgrid;
@@ -1139,11 +1168,10 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   nb::BatchItem* d_items = reinterpret_cast<nb::BatchItem*>(b + o_items);
   int* d_nit = reinterpret_cast<int*>(b + o_nit);
   const double dt_min = std::ldexp(dt_max, -max_level);
+  const nb::PredictArgs pred{pos, vel, acc, jerk, dt_min, pos_p, vel_p};
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
-                                     c->nact32, t_stop_tick, c->stop_dev, c->stream);
+                                     c->nact32, t_stop_tick, c->stop_dev, c->stream, &pred);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
-  e = nb::launch_predict(pos, vel, acc, jerk, t_tick, 0, sched, dt_min, N, pos_p, vel_p, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "predict launch");
   e = nb::launch_batch_plan(d_off, d_eps, (int)C, active, sched + 1, IB, target, d_sys, d_nch, d_items, max_items,
                             d_nit, part_cap, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch plan launch");

@@ -60,6 +60,7 @@
 #endif
 
 #include "nb_internal.h"
+#include "hermite_step.h"
 
 namespace nb {
 namespace {
@@ -719,6 +720,79 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
 }
 
 
+// Block steps: the fixed-order sum of the S partial blocks of every active
+// row (the same sums, lane for lane, as k_reduce) followed by that row's
+// Hermite correction (the same arithmetic as the corrector kernel), so a
+// block step runs one kernel after its force pass instead of two.  Each of a
+// row's 7 outputs is summed by its own group of g = chunk_lanes(S) lanes, as
+// in k_reduce, so a block takes R = 256 / (7 g) rows at a time (at least
+// one): the sums of a pass run side by side, never one after another.  With
+// S = 1 the force kernel has written the final rows and only the
+// correction runs.
+template <class P>
+__global__ __launch_bounds__(256) void k_reduce_correct(ForceArgs a, StepArgs s) {
+  __shared__ double vals[256];
+  int64_t n_act = a.n_active;
+  int S = 1;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    S = a.s_dev ? *a.s_dev : 1;
+  }
+  if (s.step_dev && n_act > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(s.step_dev, 1ull);
+  const bool self_on = P::eps(a.eps2) > 0;
+  const int g = S > 1 ? chunk_lanes(S) : 1;
+  const int lane = threadIdx.x & (g - 1);
+  const int grp = threadIdx.x / g, ngrp = 256 / g;
+  const int R = ngrp >= 7 ? ngrp / 7 : 1;  // rows per pass; 7 R <= 256
+  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < n_act; row0 += (int64_t)gridDim.x * R) {
+    if (S > 1) {
+      // element e = (component c, row r), rows fastest so that neighbouring
+      // groups read neighbouring words; one g-lane group per element
+      for (int e = grp; e < 7 * R; e += ngrp) {
+        const int c = e / R, r = e - R * c;
+        const int64_t k = row0 + r;
+        if (k >= n_act) continue;  // the whole group alike
+        const double v = sum_blocks(a.part + c * n_act + k, 7 * n_act, S, lane, g);
+        if (lane == 0) vals[r * 7 + c] = v;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < R) {
+      const int64_t k = row0 + threadIdx.x;
+      if (k < n_act) {
+        const int64_t i = a.active[k];
+        if (row_in_range(i, a.row_lo, a.row_hi)) {
+          double a1[3], j1[3];
+          if (S > 1) {
+            const double* v = vals + threadIdx.x * 7;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              a1[c] = v[c];
+              j1[c] = v[3 + c];
+              a.acc[3 * k + c] = a1[c];
+              a.jerk[3 * k + c] = j1[c];
+            }
+            const double self = (self_on && !a.no_self) ? P::self_term(a.mass[i], a.eps2) : 0.0;
+            a.pot[k] = -(v[6] - self);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              a1[c] = a.acc[3 * k + c];
+              j1[c] = a.jerk[3 * k + c];
+            }
+          }
+          correct_particle(i, a1, j1, s.pos_p, s.vel_p, s.pos, s.vel, s.acc, s.jerk, s.t_tick, s.level, s.eta,
+                           s.dt_max, s.max_level, s.clamp_dev);
+        } else if (a.err) {
+          atomicOr(a.err, kErrActiveRange);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------- scalar j-path -----
 // Variant of the i-parallel layout (L = 1) without LDS: the j-records are
 // first converted once per call into the kernel's layout (a mirror array),
@@ -1376,6 +1450,21 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
   }
   cache[reinterpret_cast<const void*>(fn)] = nblk;
   return nblk;
+}
+
+hipError_t launch_reduce_correct(int prec, const ForceArgs& a, const StepArgs& s, hipStream_t st) {
+  // one block per row when the count is known only on the device and the
+  // split is wide (R = 1); a grid-stride loop covers the rest
+  int64_t grid = a.n_active;
+  if (grid > 1024) grid = 1024;
+  if (grid < 1) grid = 1;
+  if (prec == NB_PREC_FP64)
+    hipLaunchKernelGGL(k_reduce_correct<F64>, dim3((int)grid), dim3(256), 0, st, a, s);
+  else if (prec == NB_PREC_MIXED_DS)
+    hipLaunchKernelGGL(k_reduce_correct<MixedDS>, dim3((int)grid), dim3(256), 0, st, a, s);
+  else
+    hipLaunchKernelGGL(k_reduce_correct<Mixed>, dim3((int)grid), dim3(256), 0, st, a, s);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st) {

@@ -11,13 +11,24 @@
 // paper gives no formulas; the library follows the Makino-Aarseth form
 // described in nbody.h.
 #include "nb_internal.h"
+#include "hermite_step.h"
 
 namespace nb {
 namespace {
 
 constexpr int kB = 256;
 constexpr int kSchedPerThread = 4;
-constexpr int kSchedBlock = kB * kSchedPerThread;  // particles per scheduler block
+constexpr int kSchedBlock = kB * kSchedPerThread;  // particles per block of the energy sums
+// The scheduler's passes take ppt particles per thread: the smallest power of
+// two that keeps the block table within kSchedMaxBlocks entries (every block
+// of the second pass reads the whole table), so that small systems still
+// spread over many compute units.
+constexpr int kSchedMaxBlocks = 1024;
+inline int sched_ppt(int64_t n) {
+  int p = 1;
+  while ((n + (int64_t)kB * p - 1) / ((int64_t)kB * p) > kSchedMaxBlocks) p <<= 1;
+  return p;
+}
 
 // ---------------------------------------------------------------- predict --
 // One thread per (particle, component): every array is read with unit
@@ -64,46 +75,10 @@ __global__ __launch_bounds__(kB) void k_correct(const int32_t* __restrict__ acti
       if (err) atomicOr(err, kErrActiveRange);
       continue;
     }
-    const int L = level[i];
-    const double dt = ldexp(dt_max, -L);
-    const double dt2 = dt * dt, dt3 = dt2 * dt;
-    double a1[3], j1[3], a2[3], a3[3], a2e[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double a0 = acc[3 * i + c], j0 = jerk[3 * i + c];
-      a1[c] = acc1[3 * k + c];
-      j1[c] = jerk1[3 * k + c];
-      a2[c] = (-6.0 * (a0 - a1[c]) - dt * (4.0 * j0 + 2.0 * j1[c])) / dt2;
-      a3[c] = (12.0 * (a0 - a1[c]) + 6.0 * dt * (j0 + j1[c])) / dt3;
-      const double dt4 = dt2 * dt2;
-      pos[3 * i + c] = pos_p[3 * i + c] + a2[c] * (dt4 / 24.0) + a3[c] * (dt4 * dt / 120.0);
-      vel[3 * i + c] = vel_p[3 * i + c] + a2[c] * (dt3 / 6.0) + a3[c] * (dt4 / 24.0);
-      acc[3 * i + c] = a1[c];
-      jerk[3 * i + c] = j1[c];
-      a2e[c] = a2[c] + a3[c] * dt;
-    }
-    const double na1 = norm3(a1[0], a1[1], a1[2]);
-    const double nj1 = norm3(j1[0], j1[1], j1[2]);
-    const double na2 = norm3(a2e[0], a2e[1], a2e[2]);
-    const double na3 = norm3(a3[0], a3[1], a3[2]);
-    const double num = na1 * na2 + nj1 * nj1;
-    const double den = nj1 * na3 + na2 * na2;
-    const double ds = den > 0.0 ? sqrt(eta * num / den) : dt_max;
-    const int64_t t_new = t_tick[i] + ((int64_t)1 << (max_level - L));
-    int Ln = L;
-    double dtc = dt;
-    if (ds < dtc) {
-      while (dtc > ds && Ln < max_level) {
-        ++Ln;
-        dtc = ldexp(dt_max, -Ln);
-      }
-      if (dtc > ds && clamp_dev) atomicAdd(clamp_dev, 1ull);
-    } else if (ds >= 2.0 * dtc && Ln > 0) {
-      const int64_t two_dt = (int64_t)1 << (max_level - Ln + 1);
-      if (t_new % two_dt == 0) --Ln;
-    }
-    t_tick[i] = t_new;
-    level[i] = Ln;
+    const double a1[3] = {acc1[3 * k], acc1[3 * k + 1], acc1[3 * k + 2]};
+    const double j1[3] = {jerk1[3 * k], jerk1[3 * k + 1], jerk1[3 * k + 2]};
+    correct_particle(i, a1, j1, pos_p, vel_p, pos, vel, acc, jerk, t_tick, level, eta, dt_max, max_level,
+                     clamp_dev);
   }
 }
 
@@ -124,67 +99,60 @@ __global__ __launch_bounds__(kB) void k_startup(const double* __restrict__ acc, 
 }
 
 // --------------------------------------------------------------- schedule --
-// Three deterministic passes, no atomics: per-block minimum of t_i + dt_i;
-// per-block count of particles reaching the global minimum; ordered write
-// of their indices (block offset + in-block exclusive scan).
+// Two deterministic passes, no atomics.  Pass 1: per block, the minimum of
+// t_i + dt_i and how many of its particles reach that minimum.  Pass 2: every
+// block takes the global minimum t_next from the block table, its offset as
+// the counts of the earlier blocks whose minimum is t_next, writes the
+// indices of its particles due at t_next in ascending order, and (when
+// given the arrays) predicts all its particles to t_next -- the predictor
+// reads what the scheduler's pass already has at hand, so it costs no
+// launch of its own.
 __device__ __forceinline__ int64_t t_end_of(const int64_t* t_tick, const int32_t* level, int64_t i, int max_level) {
   return t_tick[i] + ((int64_t)1 << (max_level - level[i]));
 }
 
-__global__ __launch_bounds__(kB) void k_sched_min(const int64_t* __restrict__ t_tick,
-                                                  const int32_t* __restrict__ level, int64_t n, int max_level,
-                                                  int64_t* __restrict__ block_min) {
-  __shared__ int64_t red[kB];
-  int64_t m = INT64_MAX;
-  const int64_t base = (int64_t)blockIdx.x * kSchedBlock;
-  for (int r = 0; r < kSchedPerThread; ++r) {
-    const int64_t i = base + r * kB + threadIdx.x;
-    if (i < n) {
-      const int64_t te = t_end_of(t_tick, level, i, max_level);
-      m = te < m ? te : m;
-    }
+// x_p, v_p at t_next of the particles [base, base + count) (below n), one
+// thread per component so that every array is read with unit stride; the
+// formulas of k_predict.
+__device__ __forceinline__ void predict_range(const PredictArgs& p, const int64_t* t_tick, int64_t base,
+                                              int64_t count, int64_t n, int64_t t_next, int threads) {
+  const int64_t e_end = 3 * (base + count < n ? base + count : n);
+  for (int64_t e = 3 * base + threadIdx.x; e < e_end; e += threads) {
+    const int64_t i = e / 3;
+    const double d = (double)(t_next - t_tick[i]) * p.dt_min;
+    const double x = p.pos[e], v = p.vel[e], a = p.acc[e], j = p.jerk[e];
+    p.pos_p[e] = x + d * (v + d * (0.5 * a + d * (j * (1.0 / 6.0))));
+    p.vel_p[e] = v + d * (a + d * (0.5 * j));
   }
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const int64_t b = red[threadIdx.x + o];
-      if (b < red[threadIdx.x]) red[threadIdx.x] = b;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) block_min[blockIdx.x] = red[0];
 }
 
-__device__ int64_t global_min(const int64_t* block_min, int nblk, int64_t* red) {
-  int64_t m = INT64_MAX;
-  for (int b = threadIdx.x; b < nblk; b += kB) m = block_min[b] < m ? block_min[b] : m;
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const int64_t b = red[threadIdx.x + o];
-      if (b < red[threadIdx.x]) red[threadIdx.x] = b;
-    }
-    __syncthreads();
-  }
-  const int64_t r = red[0];
-  __syncthreads();
-  return r;
-}
-
-__global__ __launch_bounds__(kB) void k_sched_count(const int64_t* __restrict__ t_tick,
-                                                    const int32_t* __restrict__ level, int64_t n, int max_level,
-                                                    const int64_t* __restrict__ block_min, int nblk,
-                                                    int32_t* __restrict__ block_cnt, int64_t* __restrict__ sched) {
+__global__ __launch_bounds__(kB) void k_sched_minc(const int64_t* __restrict__ t_tick,
+                                                   const int32_t* __restrict__ level, int64_t n, int max_level,
+                                                   int ppt, int64_t* __restrict__ block_min,
+                                                   int32_t* __restrict__ block_cnt) {
   __shared__ int64_t red[kB];
   __shared__ int cnt[kB];
-  const int64_t t_next = global_min(block_min, nblk, red);
-  int c = 0;
-  const int64_t base = (int64_t)blockIdx.x * kSchedBlock;
-  for (int r = 0; r < kSchedPerThread; ++r) {
+  int64_t m = INT64_MAX;
+  const int64_t base = (int64_t)blockIdx.x * kB * ppt;
+  for (int r = 0; r < ppt; ++r) {
     const int64_t i = base + r * kB + threadIdx.x;
-    if (i < n && t_end_of(t_tick, level, i, max_level) == t_next) ++c;
+    const int64_t te = i < n ? t_end_of(t_tick, level, i, max_level) : INT64_MAX;
+    m = te < m ? te : m;
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const int64_t b = red[threadIdx.x + o];
+      if (b < red[threadIdx.x]) red[threadIdx.x] = b;
+    }
+    __syncthreads();
+  }
+  const int64_t bm = red[0];
+  int c = 0;
+  for (int r = 0; r < ppt; ++r) {
+    const int64_t i = base + r * kB + threadIdx.x;
+    c += (i < n && t_end_of(t_tick, level, i, max_level) == bm) ? 1 : 0;
   }
   cnt[threadIdx.x] = c;
   __syncthreads();
@@ -193,36 +161,47 @@ __global__ __launch_bounds__(kB) void k_sched_count(const int64_t* __restrict__ 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    block_min[blockIdx.x] = bm;
     block_cnt[blockIdx.x] = cnt[0];
-    if (blockIdx.x == 0) sched[0] = t_next;
   }
 }
 
 __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ t_tick,
                                                     const int32_t* __restrict__ level, int64_t n, int max_level,
+                                                    int ppt, const int64_t* __restrict__ block_min,
                                                     const int32_t* __restrict__ block_cnt, int nblk,
-                                                    const int64_t* sched_in,
-                                                    int32_t* __restrict__ active, int64_t* sched,
+                                                    int32_t* __restrict__ active, int64_t* __restrict__ sched,
                                                     int32_t* __restrict__ n_active32, int64_t t_stop_host,
-                                                    const int64_t* __restrict__ t_stop_dev) {
-  __shared__ int sc[kB];
-  __shared__ int64_t off_s;
-  const int64_t t_next = sched_in[0];
-  // offset of this block = sum of the counts of the blocks before it
+                                                    const int64_t* __restrict__ t_stop_dev, PredictArgs pred) {
+  __shared__ int64_t red[kB];
+  __shared__ int64_t sc[kB];
+  __shared__ int wc[kB / 64];
+  // the global minimum, then this block's offset (earlier blocks reaching
+  // it) and the total count, both in a fixed order
+  int64_t m = INT64_MAX;
+  for (int b = threadIdx.x; b < nblk; b += kB) m = block_min[b] < m ? block_min[b] : m;
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kB / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o && red[threadIdx.x + o] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const int64_t t_next = red[0];
+  const bool last_block = blockIdx.x == (unsigned)(nblk - 1);
   int64_t part = 0;
-  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kB) part += block_cnt[b];
-  sc[threadIdx.x] = (int)part;
+  for (int b = threadIdx.x; b < (int)blockIdx.x; b += kB)
+    if (block_min[b] == t_next) part += block_cnt[b];
+  sc[threadIdx.x] = part;
   __syncthreads();
   for (int o = kB / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) off_s = sc[0];
+  int64_t off = sc[0];
   __syncthreads();
-  int64_t off = off_s;
-  const int64_t base = (int64_t)blockIdx.x * kSchedBlock;
+  const int64_t base = (int64_t)blockIdx.x * kB * ppt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int r = 0; r < kSchedPerThread; ++r) {
+  for (int r = 0; r < ppt; ++r) {
     const int64_t i = base + r * kB + threadIdx.x;
     const bool flag = i < n && t_end_of(t_tick, level, i, max_level) == t_next;
     // rank among the flagged lanes of the wavefront, then the wavefronts in order
@@ -230,28 +209,30 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     __syncthreads();
-    if (lane == 0) sc[wave] = __popcll(mask);
+    if (lane == 0) wc[wave] = __popcll(mask);
     __syncthreads();
     int before = 0, total = 0;
     for (int w = 0; w < kB / 64; ++w) {
-      before += w < wave ? sc[w] : 0;
-      total += sc[w];
+      before += w < wave ? wc[w] : 0;
+      total += wc[w];
     }
     if (flag) active[off + before + rank] = (int32_t)i;
     off += total;
   }
-  if (blockIdx.x == (unsigned)(nblk - 1) && threadIdx.x == 0) {
+  if (pred.pos) predict_range(pred, t_tick, base, (int64_t)kB * ppt, n, t_next, kB);
+  if (last_block && threadIdx.x == 0) {
     // past the stop time the step is empty: every later kernel does nothing
     const int64_t t_stop = t_stop_dev ? *t_stop_dev : t_stop_host;
     const int64_t cnt = t_next <= t_stop ? off : 0;
+    sched[0] = t_next;
     sched[1] = cnt;
     if (n_active32) *n_active32 = (int32_t)cnt;
   }
 }
 
-// Small systems: one workgroup does all three passes (a launch costs more
-// than the passes themselves below a few thousand particles).  Same t_next,
-// same ascending active list as the three-kernel form.
+// Small systems: one workgroup does both passes (a launch costs more than
+// the passes themselves below a few thousand particles).  Same t_next, same
+// ascending active list, same predicted state as the two-kernel form.
 constexpr int kSchedSingleThreads = 1024;
 constexpr int64_t kSchedSingleMax = 16384;
 
@@ -261,7 +242,8 @@ __global__ __launch_bounds__(kSchedSingleThreads) void k_sched_single(const int6
                                                                       int64_t* __restrict__ sched,
                                                                       int32_t* __restrict__ n_active32,
                                                                       int64_t t_stop_host,
-                                                                      const int64_t* __restrict__ t_stop_dev) {
+                                                                      const int64_t* __restrict__ t_stop_dev,
+                                                                      PredictArgs pred) {
   constexpr int W = kSchedSingleThreads / 64;
   __shared__ int64_t red[kSchedSingleThreads];
   __shared__ int wc[W];
@@ -295,6 +277,9 @@ __global__ __launch_bounds__(kSchedSingleThreads) void k_sched_single(const int6
     }
     if (flag) active[off + before + rank] = (int32_t)i;
     off += total;
+  }
+  if (pred.pos) {
+    predict_range(pred, t_tick, 0, n, n, t_next, kSchedSingleThreads);
   }
   if (t == 0) {
     const int64_t t_stop = t_stop_dev ? *t_stop_dev : t_stop_host;
@@ -418,22 +403,26 @@ hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, doub
   return hipGetLastError();
 }
 
-int schedule_blocks(int64_t n) { return (int)((n + kSchedBlock - 1) / kSchedBlock); }
+int schedule_blocks(int64_t n) {
+  const int64_t sb = (int64_t)kB * sched_ppt(n);
+  return (int)((n + sb - 1) / sb);
+}
 
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level, int32_t* active,
                            int64_t* sched, int64_t* block_min, int32_t* block_cnt, int32_t* n_active32,
-                           int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st) {
+                           int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st, const PredictArgs* pred) {
+  const PredictArgs p = pred ? *pred : PredictArgs{};
   if (n <= kSchedSingleMax) {
     hipLaunchKernelGGL(k_sched_single, dim3(1), dim3(kSchedSingleThreads), 0, st, t_tick, level, n, max_level,
-                       active, sched, n_active32, t_stop, t_stop_dev);
+                       active, sched, n_active32, t_stop, t_stop_dev, p);
     return hipGetLastError();
   }
   const int nblk = schedule_blocks(n);
-  hipLaunchKernelGGL(k_sched_min, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min);
-  hipLaunchKernelGGL(k_sched_count, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_min, nblk,
-                     block_cnt, sched);
-  hipLaunchKernelGGL(k_sched_write, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, block_cnt, nblk,
-                     sched, active, sched, n_active32, t_stop, t_stop_dev);
+  const int ppt = sched_ppt(n);
+  hipLaunchKernelGGL(k_sched_minc, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, ppt, block_min,
+                     block_cnt);
+  hipLaunchKernelGGL(k_sched_write, dim3(nblk), dim3(kB), 0, st, t_tick, level, n, max_level, ppt, block_min,
+                     block_cnt, nblk, active, sched, n_active32, t_stop, t_stop_dev, p);
   return hipGetLastError();
 }
 

@@ -182,9 +182,41 @@ hipError_t launch_correct_step(const int32_t* active, int64_t n_max, const int64
                                int64_t* clamp_dev, int64_t* step_dev, hipStream_t st);
 hipError_t launch_startup(const double* acc, const double* jerk, int64_t n, double eta, double dt_max,
                           int max_level, int32_t* level, hipStream_t st);
+// The Hermite state a block step corrects after its force pass (the fused
+// reduce-and-correct kernel): predicted and current positions, velocities,
+// accelerations, jerks, ticks and levels of all particles, the step
+// parameters, and the device counters of clamped levels and of steps.
+struct StepArgs {
+  const double* pos_p;
+  const double* vel_p;
+  double* pos;
+  double* vel;
+  double* acc;
+  double* jerk;
+  int64_t* t_tick;
+  int32_t* level;
+  double eta, dt_max;
+  int max_level;
+  unsigned long long* clamp_dev;
+  unsigned long long* step_dev;
+};
+hipError_t launch_reduce_correct(int prec, const ForceArgs& a, const StepArgs& s, hipStream_t st);
+
+// The predictor folded into the scheduler's last pass (all pointers null:
+// no prediction).  Predicts every particle to the scheduled t_next.
+struct PredictArgs {
+  const double* pos;
+  const double* vel;
+  const double* acc;
+  const double* jerk;
+  double dt_min;
+  double* pos_p;
+  double* vel_p;
+};
 hipError_t launch_schedule(const int64_t* t_tick, const int32_t* level, int64_t n, int max_level,
                            int32_t* active, int64_t* sched, int64_t* block_min, int32_t* block_cnt,
-                           int32_t* n_active32, int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st);
+                           int32_t* n_active32, int64_t t_stop, const int64_t* t_stop_dev, hipStream_t st,
+                           const PredictArgs* pred = nullptr);
 int schedule_blocks(int64_t n);
 hipError_t launch_energy(const double* pos, const double* vel, const double* mass, const double* pot,
                          int64_t n, double* part, double* out, hipStream_t st);

@@ -221,14 +221,17 @@ def test_block_step_graph_replay_matches_eager(ctx):
         graph_run.step()
     torch.cuda.synchronize()
     for r in range(12):
-        g.replay()
+        # the replay goes to the context's stream too: calls on one context
+        # must not overlap on the device
         with torch.cuda.stream(s):
+            g.replay()
             eager.step()
         torch.cuda.synchronize()
         for a, b in ((graph_run.pos, eager.pos), (graph_run.vel, eager.vel), (graph_run.t, eager.t),
                      (graph_run.lev, eager.lev), (graph_run.sched, eager.sched)):
             assert torch.equal(a, b), r
     ctx.set_stream(None)
+    ctx.sync()  # raises if the work-queue counters were left non-zero
 
 
 @pytest.mark.parametrize("prec,n", [("fp64", 20000), ("mixed", 20000), ("fp64", 65536), ("mixed", 65536)])
