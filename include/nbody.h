@@ -147,6 +147,20 @@ int nb_get_launch(nb_ctx *ctx, int64_t N, int64_t n_active, int *K, int *L, int 
  * to load its cache. */
 int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int64_t act_max,
                 int K, int L, int items);
+/* One entry of the batched kernel's table (nbody_forces_batch and
+ * nb_block_step_batch use one shape for the whole batch): for this
+ * precision, use K and L (L = 0: the scalar j-path, K in {1, 2}; L in
+ * {1, 4, 16, 64}: the LDS layout, K = 1, or K = 2 with L <= 16) when the key
+ * lies in [key_min, key_max].  kind 1 keys nbody_forces_batch by the mean
+ * active rows per system, ceil(total active / C); kind 2 keys
+ * nb_block_step_batch by the mean system size, ceil(N / C).  Later entries
+ * take precedence.  Without an entry the batch takes K = 1 and the LDS
+ * layout nearest the single-system table's L for the mean size.
+ * nb_get_batch_launch reports the shape for a key (N = total rows).
+ * Errors: NB_EINVAL for a bad kind, range or K, NB_ENOTSUP for a shape the
+ * library does not build.  nb_tune_clear empties both tables. */
+int nb_tune_add_batch(nb_ctx *ctx, int precision, int kind, int64_t key_min, int64_t key_max, int K, int L);
+int nb_get_batch_launch(nb_ctx *ctx, int kind, int64_t key, int64_t N, int *K, int *L);
 int nb_tune_clear(nb_ctx *ctx);
 /* Time the force kernel for one configuration on the caller's arrays:
  * `reps` launches after one warm-up, on the context stream, with HIP

@@ -61,6 +61,8 @@ _lib.nb_get_precision.argtypes = [_vp]
 _sig("nb_set_launch", _vp, _int, _int, _int)
 _sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int)
+_sig("nb_tune_add_batch", _vp, _int, _int, _i64, _i64, _int, _int)
+_sig("nb_get_batch_launch", _vp, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_clear", _vp)
 _sig("nb_set_stop_source", _vp, _vp)
 _sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
@@ -216,6 +218,17 @@ class Context:
     def tune_add(self, precision, n_min, act_min, act_max, K, L, S=0):
         prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
         self._chk(_lib.nb_tune_add(self._h, prec, int(n_min), int(act_min), int(act_max), int(K), int(L), int(S)))
+
+    def tune_add_batch(self, precision, kind, key_min, key_max, K, L):
+        """kind 1: nbody_forces_batch keyed by mean active rows per system;
+        kind 2: batched block steps keyed by mean system size."""
+        prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
+        self._chk(_lib.nb_tune_add_batch(self._h, prec, int(kind), int(key_min), int(key_max), int(K), int(L)))
+
+    def get_batch_launch(self, kind, key, N):
+        K, L = _int(), _int()
+        self._chk(_lib.nb_get_batch_launch(self._h, int(kind), int(key), int(N), ctypes.byref(K), ctypes.byref(L)))
+        return K.value, L.value
 
     def tune_clear(self):
         self._chk(_lib.nb_tune_clear(self._h))

@@ -145,6 +145,108 @@ def tune(ctx, n, precisions=("fp64", "mixed", "mixed_ds"), buckets=BUCKETS, seed
     return entries
 
 
+# Shapes of the batched force kernel (L = 0: scalar j-path)
+BATCH_SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (2, 1), (2, 4), (2, 16), (1, 0), (2, 0)]
+# kind 1 (nbody_forces_batch) keys: mean active rows per system, timed on
+# all-active batches of equal systems of this size
+BATCH_BUCKETS = [128, 256, 512, 1024, 2048, 4096, 8192, 16384]
+# kind 2 (batched block steps) keys: mean system size, timed as
+# graph-replayed block steps over one synchronisation interval
+STEP_SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (1, 0), (2, 0)]
+STEP_BUCKETS = [256, 1024, 4096]
+
+
+def _equal_batch(size, total, seed):
+    import synth
+    return synth.cluster_batch(seed=seed, n_clusters=max(1, total // size), n_min=size, n_max=size)
+
+
+def _wall_ms(fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def tune_batch_forces(ctx, precisions=("fp64", "mixed", "mixed_ds"), buckets=BATCH_BUCKETS, total=1 << 19,
+                      reps=3, log=print):
+    """Kind 1 entries: the fastest batched shape for nbody_forces_batch on
+    all-active batches of `total` bodies in equal systems of each size (the
+    whole call: work list, force kernel and chunk sums)."""
+    dev = ctx.device
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    entries = []
+    ranges = _midpoints(list(buckets))
+    for size, (lo, hi) in zip(buckets, ranges):
+        b = _equal_batch(size, total, 11)
+        P, V, M = t(b.pos), t(b.vel), t(b.mass)
+        n = int(b.offsets[-1])
+        act = t(np.arange(n, dtype=np.int32))
+        acc = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        jerk = torch.empty_like(acc)
+        pot = torch.empty(n, dtype=torch.float64, device=dev)
+        inter = float(np.sum(b.sizes.astype(np.float64) ** 2))
+        for prec in precisions:
+            ctx.set_precision(prec)
+            best = None
+            for K, L in BATCH_SHAPES:
+                ctx.tune_clear()
+                ctx.tune_add_batch(prec, 1, 1, 2 ** 40, K, L)
+                ms = _wall_ms(lambda: ctx.forces_batch(b.offsets, b.eps2, P, V, M, act, b.offsets, acc, jerk, pot),
+                              reps)
+                if best is None or ms < best[0]:
+                    best = (ms, K, L)
+            ms, K, L = best
+            e = dict(kind=1, prec=prec, key_min=lo, key_max=hi, K=K, L=L, ms=round(ms, 4), rep_size=size,
+                     gint=round(inter / ms / 1e6, 1))
+            entries.append(e)
+            log(json.dumps(e))
+    ctx.tune_clear()
+    return entries
+
+
+def tune_batch_steps(ctx, precisions=("fp64", "mixed", "mixed_ds"), buckets=STEP_BUCKETS, total=1 << 18, log=print):
+    """Kind 2 entries: the fastest shape for graph-replayed batched block steps
+    over one synchronisation interval (dt_max = 1/16) of `total` bodies in
+    equal Plummer systems of each size, after a first interval that sizes the
+    buffers and captures the graphs."""
+    from .integrator import BlockIntegrator
+    dev = ctx.device
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    entries = []
+    ranges = _midpoints(list(buckets))
+    for size, (lo, hi) in zip(buckets, ranges):
+        b = _equal_batch(size, total, 12)
+        for prec in precisions:
+            ctx.set_precision(prec)
+            best = None
+            for K, L in STEP_SHAPES:
+                ctx.tune_clear()
+                ctx.tune_add_batch(prec, 2, 1, 2 ** 40, K, L)
+                bi = BlockIntegrator(ctx, t(b.pos), t(b.vel), t(b.mass), b.eps2, 0.01, 1.0 / 16, 30,
+                                     offsets=b.offsets)
+                bi.run_until(1.0 / 16, graph_steps=16)
+                torch.cuda.synchronize()
+                s0 = bi.steps
+                t0 = time.perf_counter()
+                bi.run_until(2.0 / 16, graph_steps=16)
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                if best is None or ms < best[0]:
+                    best = (ms, K, L, bi.steps - s0)
+                del bi
+            ms, K, L, steps = best
+            e = dict(kind=2, prec=prec, key_min=lo, key_max=hi, K=K, L=L, ms=round(ms, 3), rep_size=size,
+                     steps=int(steps))
+            entries.append(e)
+            log(json.dumps(e))
+    ctx.tune_clear()
+    return entries
+
+
 def forces_source_hash():
     """sha256 of the force kernels' source the table was measured on."""
     import hashlib
@@ -163,8 +265,12 @@ def load(ctx, path=DEFAULT_TABLE):
     """Install a saved table into a context (entries in file order)."""
     with open(path) as f:
         doc = json.load(f)
-    for e in sorted(doc["entries"], key=lambda e: e["n_min"]):
+    single = [e for e in doc["entries"] if e.get("kind", 0) == 0]
+    for e in sorted(single, key=lambda e: e["n_min"]):
         ctx.tune_add(e["prec"], e["n_min"], e["act_min"], e["act_max"], e["K"], e["L"], e["items"])
+    for e in doc["entries"]:
+        if e.get("kind", 0) in (1, 2):
+            ctx.tune_add_batch(e["prec"], e["kind"], e["key_min"], e["key_max"], e["K"], e["L"])
     return len(doc["entries"])
 
 
@@ -177,6 +283,9 @@ def main():
     ap.add_argument("--max-active", type=int, default=0,
                     help="largest active-set bucket to time (0: up to N); the top bucket's range then covers every larger count")
     ap.add_argument("--append", default="", help="start from the entries of this table")
+    ap.add_argument("--batch", action="store_true", help="also tune the batched kernel (nbody_forces_batch)")
+    ap.add_argument("--batch-steps", action="store_true", help="also tune the batched block steps")
+    ap.add_argument("--batch-only", action="store_true", help="tune only the batched kernel (no --n sweep)")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_1409_5474_amd as nb
@@ -187,9 +296,19 @@ def main():
         with open(args.append) as f:
             entries = json.load(f)["entries"]
     buckets = [b for b in BUCKETS if not args.max_active or b <= args.max_active]
-    for n in sorted(args.n):
-        entries += tune(ctx, n, args.prec, buckets=buckets, reps=args.reps, log=lambda m: print(m, flush=True))
-        print(f"# N={n} done after {time.time() - t0:.0f} s", flush=True)
+    say = lambda m: print(m, flush=True)
+    if args.batch_only:
+        entries = [e for e in entries if e.get("kind", 0) == 0]
+    else:
+        for n in sorted(args.n):
+            entries += tune(ctx, n, args.prec, buckets=buckets, reps=args.reps, log=say)
+            print(f"# N={n} done after {time.time() - t0:.0f} s", flush=True)
+    if args.batch or args.batch_only:
+        entries += tune_batch_forces(ctx, args.prec, reps=args.reps, log=say)
+        print(f"# batched forces done after {time.time() - t0:.0f} s", flush=True)
+    if args.batch_steps or args.batch_only:
+        entries += tune_batch_steps(ctx, args.prec, log=say)
+        print(f"# batched block steps done after {time.time() - t0:.0f} s", flush=True)
     props = torch.cuda.get_device_properties(0)
     save(entries, args.out, meta={"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
                                   "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1),

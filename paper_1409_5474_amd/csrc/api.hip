@@ -211,6 +211,21 @@ Launch choose(const nb_ctx* c, int64_t n, int64_t n_act) {
   return cfg;
 }
 
+// Shape of the batched force kernel: the last tuned entry of this kind whose
+// key range holds `key`, else one i-particle per lane (K = 1) in the LDS
+// layout the single-system table gives for a system of the mean size -- a
+// block step's active rows are spread over many small systems, and a wider
+// i-block would mostly carry empty lanes.
+Launch choose_batch(const nb_ctx* c, int kind, int64_t key, int64_t n_total, int64_t mean_size) {
+  for (auto it = c->batch_table.rbegin(); it != c->batch_table.rend(); ++it)
+    if (it->prec == c->prec && it->kind == kind && key >= it->key_min && key <= it->key_max) return it->cfg;
+  Launch cfg = choose(c, n_total, mean_size);
+  cfg.K = 1;
+  if (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64)
+    cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
+  return cfg;
+}
+
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 bool kernel_mask(int prec, double eps2) {
@@ -470,6 +485,23 @@ int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_
   return NB_OK;
 }
 
+int nb_tune_add_batch(nb_ctx* c, int precision, int kind, int64_t key_min, int64_t key_max, int K, int L) {
+  if (!c) return NB_EINVAL;
+  if (!valid_prec(precision) || (kind != 1 && kind != 2) || key_min > key_max || !valid_K(K) || L < 0)
+    return fail(c, NB_EINVAL, "bad batch tune entry%s");
+  if (!nb::batch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "batched kernel not built in this shape%s");
+  c->batch_table.push_back(nb::BatchTuneEntry{precision, kind, key_min, key_max, Launch{K, L, 0, 0}});
+  return NB_OK;
+}
+
+int nb_get_batch_launch(nb_ctx* c, int kind, int64_t key, int64_t n_total, int* K, int* L) {
+  if (!c || !K || !L || (kind != 1 && kind != 2) || n_total < 1 || key < 1) return NB_EINVAL;
+  const Launch cfg = choose_batch(c, kind, key, n_total, key);
+  *K = cfg.K;
+  *L = cfg.L;
+  return NB_OK;
+}
+
 int nb_set_stop_source(nb_ctx* c, const int64_t* t_stop_dev) {
   if (!c) return NB_EINVAL;
   c->stop_dev = t_stop_dev;
@@ -479,6 +511,7 @@ int nb_set_stop_source(nb_ctx* c, const int64_t* t_stop_dev) {
 int nb_tune_clear(nb_ctx* c) {
   if (!c) return NB_EINVAL;
   c->table.clear();
+  c->batch_table.clear();
   return NB_OK;
 }
 
@@ -594,54 +627,94 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
   if (!n_active_dev) return fail(c, NB_EINVAL, "n_active_dev is null%s");
   if (max_active == 0) return NB_OK;
   const bool mask = kernel_mask(c->prec, eps2);
-  // One fixed launch per regime; the count decides on the device which one works.
-  // Adjacent regimes with the same K and L share one launch (every launch,
-  // empty or not, costs a few microseconds in each block step); the shared
-  // launch carries each regime's work-item target, so a count gets the same
-  // j-split as a host-count launch.
+  // One fixed launch per group of regimes; the count decides on the device
+  // which one works.  Every launch, empty or not, costs a few microseconds
+  // in each block step, so adjacent regimes share a launch: those of one
+  // shape, and LDS regimes of different shapes that one kernel family holds
+  // (family_of).  A family kernel has the registers of its largest body, so
+  // a regime joins one only when it loses nothing: its whole grid fits in
+  // one round of the family's resident workgroups, or the family keeps as
+  // many resident as the regime's own kernel.  The shared launch carries
+  // each regime's shape and work-item target, so a count gets the shape and
+  // j-split of a host-count launch.
   struct Group {
-    Regime r;                   // merged count range and the shape
+    Regime r;   // merged count range; r.cfg: the shape of the first regime (fam set for a family launch)
     int n_sub;
     int64_t sub_lo[nb::kMaxSubRegimes];
+    int64_t sub_hi[nb::kMaxSubRegimes];
     int sub_items[nb::kMaxSubRegimes];
+    int64_t sub_grid[nb::kMaxSubRegimes];  // workgroups the regime can use
+    Launch sub_cfg[nb::kMaxSubRegimes];
+  };
+  auto own_rg = [&](const Launch& x) {
+    Launch o = x;
+    o.fam = x.L >= 1 ? nb::family_of(x.K, x.L) : 0;
+    return resident_grid(c, o, mask);
   };
   std::vector<Group> groups;
   for (const Regime& r : regimes(c, N)) {
     Launch cfg = c->have_forced ? c->forced : r.cfg;
     if (mask) cfg.K = 1;
+    cfg.fam = 0;
     const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
-    if (!groups.empty() && groups.back().r.cfg.K == r.cfg.K && groups.back().r.cfg.L == r.cfg.L &&
-        groups.back().n_sub < nb::kMaxSubRegimes) {
+    const int64_t top = r.hi < max_active ? r.hi : max_active;
+    const int IB = nb::ib_of(cfg);
+    const int64_t grid = items + (top > 0 ? (top + IB - 1) / IB : 0);
+    bool join = false;
+    int fam = 0;
+    if (!groups.empty() && groups.back().n_sub < nb::kMaxSubRegimes) {
+      const Group& g = groups.back();
+      if (g.r.cfg.fam == 0 && g.r.cfg.K == cfg.K && g.r.cfg.L == cfg.L) {
+        join = true;
+      } else if (cfg.L >= 1 && g.r.cfg.L >= 1) {
+        const int theirs = g.r.cfg.fam > 0 ? g.r.cfg.fam : nb::family_of(g.r.cfg.K, g.r.cfg.L);
+        fam = nb::family_cover(theirs, nb::family_of(cfg.K, cfg.L));
+        if (fam) {
+          Launch fcfg = cfg;
+          fcfg.fam = fam;
+          const int64_t frg = resident_grid(c, fcfg, mask);
+          join = grid <= frg || frg >= own_rg(cfg);
+          for (int k = 0; join && k < g.n_sub; ++k)
+            join = g.sub_grid[k] <= frg || frg >= own_rg(g.sub_cfg[k]);
+        }
+      }
+    }
+    if (join) {
       Group& g = groups.back();
+      if (fam) g.r.cfg.fam = fam;
       g.r.hi = r.hi;
       g.sub_lo[g.n_sub] = r.lo;
+      g.sub_hi[g.n_sub] = r.hi;
       g.sub_items[g.n_sub] = items;
+      g.sub_grid[g.n_sub] = grid;
+      g.sub_cfg[g.n_sub] = cfg;
       ++g.n_sub;
     } else {
       Group g{};
       g.r = r;
+      g.r.cfg = cfg;
       g.n_sub = 1;
       g.sub_lo[0] = r.lo;
+      g.sub_hi[0] = r.hi;
       g.sub_items[0] = items;
+      g.sub_grid[0] = grid;
+      g.sub_cfg[0] = cfg;
       groups.push_back(g);
     }
   }
-  auto max_items = [](const Group& g) {
-    int m = 0;
-    for (int k = 0; k < g.n_sub; ++k) m = std::max(m, g.sub_items[k]);
-    return m;
-  };
+  // per regime of a group: the rows of its partials and its part of the grid
+  auto sub_top = [&](const Group& g, int k) { return g.sub_hi[k] < max_active ? g.sub_hi[k] : max_active; };
   size_t ws_need = 0;
   for (const Group& g : groups) {
     if (g.r.lo > max_active) break;
-    const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
-    Launch cfg = c->have_forced ? c->forced : g.r.cfg;
-    if (mask) cfg.K = 1;
-    const int IB = nb::ib_of(cfg);
-    const int64_t n_iblk_max = (top + IB - 1) / IB;
-    const size_t rows = (size_t)(max_items(g) + n_iblk_max) * IB;
-    const size_t need = rows * 7 * sizeof(double);
-    if (need > ws_need) ws_need = need;
+    for (int k = 0; k < g.n_sub; ++k) {
+      if (g.sub_lo[k] > max_active) break;
+      const int IB = nb::ib_of(g.sub_cfg[k]);
+      const int64_t n_iblk_max = (sub_top(g, k) + IB - 1) / IB;
+      const size_t rows = (size_t)(g.sub_items[k] + n_iblk_max) * IB;
+      const size_t need = rows * 7 * sizeof(double);
+      if (need > ws_need) ws_need = need;
+    }
   }
   rc = ensure_ws(c, ws_need);
   if (rc) return rc;
@@ -665,7 +738,6 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
     Launch cfg = c->have_forced ? c->forced : g.r.cfg;
     if (mask) cfg.K = 1;
-    const int items = max_items(g);
     nb::ForceArgs a{};
     a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
     a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
@@ -673,19 +745,22 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     a.last = (top == max_active) ? 1 : 0;
     a.eps2 = eps2; a.S = 1; a.target_items = g.sub_items[0];
     a.n_sub = g.n_sub;
+    // persistent: at most one round of resident workgroups walks the items
+    int64_t grid = 1;
     for (int k = 0; k < g.n_sub; ++k) {
       a.sub_lo[k] = g.sub_lo[k];
       a.sub_items[k] = g.sub_items[k];
+      a.sub_shape[k] = nb::shape_code(g.sub_cfg[k].K, g.sub_cfg[k].L);
+      if (g.sub_lo[k] > max_active) continue;
+      const int IB = nb::ib_of(g.sub_cfg[k]);
+      grid = std::max<int64_t>(grid, g.sub_items[k] + (sub_top(g, k) + IB - 1) / IB);
     }
+    a.shape = a.sub_shape[0];
     a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = static_cast<double*>(c->ws); a.s_dev = c->s_dev;
     a.rec = c->mirror;
     a.wq = c->wq;
     a.row_lo = 0; a.row_hi = N; a.err = c->wq + nb::kErrorWord;
     red = a;
-    const int IB = nb::ib_of(cfg);
-    const int64_t n_iblk_max = (top + IB - 1) / IB;
-    // persistent: at most one round of resident workgroups walks the items
-    int64_t grid = items + n_iblk_max;
     const int64_t rg = resident_grid(c, cfg, mask);
     if (grid > rg) grid = rg;
     hipError_t e = nb::launch_forces(c->prec, cfg, mask, a, c->stream, (int)grid, 0);
@@ -992,11 +1067,8 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   }
   if (a_total == 0) return NB_OK;
   if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
-  // One kernel shape for the batch, from the typical active-set size.
-  Launch cfg = choose(c, n_total, (a_total + C - 1) / C);
-  cfg.K = 1;  // as in the batched block steps
-  if (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64)
-    cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
+  // One kernel shape for the batch, from the mean active rows per system.
+  const Launch cfg = choose_batch(c, 1, (a_total + C - 1) / C, n_total, (a_total + C - 1) / C);
   const int IB = nb::ib_of(cfg);
   // total work in (i-slot x j) units and the chunk length that splits it
   double work = 0.0;
@@ -1074,12 +1146,17 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   if (e != hipSuccess) return hip_fail(c, e, "batch event");
   int rc = ensure_ws(c, (size_t)(part_rows > 0 ? part_rows : 1) * 7 * sizeof(double));
   if (rc) return rc;
+  if (cfg.L == 0) {
+    rc = ensure_mirror(c, n_total);
+    if (rc) return rc;
+  }
   char* db = static_cast<char*>(c->batch_buf);
   const nb::BatchItem* d_items = reinterpret_cast<const nb::BatchItem*>(db);
   const nb::BatchSys* d_sys = reinterpret_cast<const nb::BatchSys*>(db + off_sys);
   const int32_t* d_nch = reinterpret_cast<const int32_t*>(db + off_nch);
   e = nb::launch_batch(c->prec, cfg, d_items, (int)items.size(), nullptr, d_sys, pos, vel, mass, active, acc, jerk,
-                       pot, static_cast<double*>(c->ws), part_rows, any_mask, 0, c->wq + nb::kErrorWord, c->stream);
+                       pot, static_cast<double*>(c->ws), part_rows, any_mask, 0, c->wq + nb::kErrorWord, c->mirror,
+                       n_total, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
   if (part_rows > 0) {
     e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, a_total, acc, jerk, pot,
@@ -1115,13 +1192,8 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
     return fail(c, NB_EINVAL, "null pointer%s");
   rc = ensure_sched(c, N);
   if (rc) return rc;
-  // one kernel shape for the batch, from the typical system size; one
-  // i-particle per lane (K = 1): a block step's active rows are spread over
-  // many small systems, and a wider i-block would mostly carry empty lanes
-  Launch cfg = choose(c, N, (N + C - 1) / C);
-  cfg.K = 1;
-  if (cfg.L != 1 && cfg.L != 4 && cfg.L != 16 && cfg.L != 64)
-    cfg.L = cfg.L >= 64 ? 64 : cfg.L >= 16 ? 16 : cfg.L >= 4 ? 4 : 1;
+  // one kernel shape for the batch, from the mean system size
+  const Launch cfg = choose_batch(c, 2, (N + C - 1) / C, N, (N + C - 1) / C);
   const int IB = nb::ib_of(cfg);
   const int rgrid = resident_grid(c, cfg, any_mask);
   const int target = 2 * rgrid;
@@ -1160,6 +1232,10 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   }
   rc = ensure_ws(c, (size_t)part_cap * 7 * sizeof(double));
   if (rc) return rc;
+  if (cfg.L == 0) {
+    rc = ensure_mirror(c, N);
+    if (rc) return rc;
+  }
   char* b = static_cast<char*>(c->bp_buf);
   const int64_t* d_off = reinterpret_cast<const int64_t*>(b + o_off);
   const double* d_eps = reinterpret_cast<const double*>(b + o_eps);
@@ -1176,15 +1252,15 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
                             d_nit, part_cap, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch plan launch");
   e = nb::launch_batch(c->prec, cfg, d_items, max_items, d_nit, d_sys, pos_p, vel_p, mass, active, acc1, jerk1, pot1,
-                       static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->wq + nb::kErrorWord, c->stream);
+                       static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->wq + nb::kErrorWord, c->mirror, N,
+                       c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
-  e = nb::launch_batch_reduce(c->prec, d_sys, (int)C, d_nch, mass, active, N, acc1, jerk1, pot1,
-                              static_cast<double*>(c->ws), c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "batch reduce launch");
-  e = nb::launch_correct_step(active, N, sched + 1, N, c->wq + nb::kErrorWord, pos_p, vel_p, acc1, jerk1, pos, vel, acc, jerk,
-                              t_tick, dt_level,
-                              eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
-  return e == hipSuccess ? NB_OK : hip_fail(c, e, "correct launch");
+  const nb::StepArgs sa{pos_p, vel_p, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max, max_level,
+                        reinterpret_cast<unsigned long long*>(sched + 3),
+                        reinterpret_cast<unsigned long long*>(sched + 2)};
+  e = nb::launch_batch_reduce_correct(c->prec, d_sys, d_nch, (int)C, sched + 1, N, mass, active, acc1, jerk1, pot1,
+                                      static_cast<double*>(c->ws), sa, c->wq + nb::kErrorWord, c->stream);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, "batch reduce-correct launch");
 }
 
 int nb_energy(nb_ctx* c, const double* pos, const double* vel, const double* mass, const double* pot, int64_t N,

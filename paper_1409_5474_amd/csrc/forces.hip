@@ -499,31 +499,67 @@ constexpr int kXcd = 8;
 constexpr int kQueueWords = kXcd + 1;
 static_assert(kQueueWords <= kWorkQueueWords, "work queue larger than its buffer");
 
+// Thread 0 turns an own-range take into an item: `own` is the counter value
+// the take returned.  When that range is exhausted it reads every range's
+// counter at once (independent loads, one round of latency: device-scope
+// atomics cost about a microsecond each, so the ranges are not visited one
+// by one) and takes from the first range with items left, in the order
+// x0 + 1, x0 + 2, ...  Returns the item, or `items` once all are exhausted.
+__device__ __forceinline__ int64_t queue_pick(unsigned int* wq, int64_t items, unsigned int own) {
+  const int x0 = blockIdx.x % kXcd;
+  const int64_t lo0 = items * x0 / kXcd, len0 = items * (x0 + 1) / kXcd - lo0;
+  if ((int64_t)own < len0) return lo0 + own;
+  for (int attempt = 0; attempt < kXcd; ++attempt) {
+    unsigned int cnt[kXcd];
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) cnt[x] = __hip_atomic_load(&wq[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int pick = -1, best = kXcd;
+#pragma unroll
+    for (int x = 0; x < kXcd; ++x) {
+      const int64_t len = items * (x + 1) / kXcd - items * x / kXcd;
+      const int order = (x - x0 - 1 + 2 * kXcd) % kXcd;  // 0 for range x0 + 1
+      if ((int64_t)cnt[x] < len && order < best) {
+        best = order;
+        pick = x;
+      }
+    }
+    if (pick < 0) return items;
+    const int64_t lo = items * pick / kXcd, len = items * (pick + 1) / kXcd - lo;
+    const int64_t k = atomicAdd(&wq[pick], 1u);
+    if (k < len) return lo + k;
+  }
+  return items;
+}
+
+// The first item of a workgroup (w_stride: its item without a queue).
 __device__ __forceinline__ int64_t queue_take(unsigned int* wq, unsigned int& slot, int64_t items,
                                               int64_t w_stride) {
   if (!wq) return w_stride;
-  __syncthreads();  // every thread has read `slot` before it is replaced
-  if (threadIdx.x == 0) {
-    const int x0 = blockIdx.x % kXcd;
-    int64_t got = items;
-    for (int d = 0; d < kXcd && got == items; ++d) {
-      const int x = (x0 + d) % kXcd;
-      const int64_t lo = items * x / kXcd, len = items * (x + 1) / kXcd - lo;
-      if ((int64_t)atomicAdd(&wq[x], 0u) >= len) continue;  // exhausted: look further
-      const int64_t k = atomicAdd(&wq[x], 1u);
-      if (k < len) got = lo + k;
-    }
-    slot = (unsigned int)got;
-  }
+  if (threadIdx.x == 0) slot = (unsigned int)queue_pick(wq, items, atomicAdd(&wq[blockIdx.x % kXcd], 1u));
   __syncthreads();
   // one value for the whole wave: read into a scalar register, so everything
   // derived from the item (chunk bounds, record addresses) stays uniform
   return (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)slot);
 }
 
-// Every workgroup calls this once, after its last queue_take.
-__device__ __forceinline__ void queue_done(unsigned int* wq) {
-  if (wq && threadIdx.x == 0 && atomicAdd(&wq[kXcd], 1u) == gridDim.x - 1) {
+// A workgroup's next item (w_stride: its next item without a queue).
+__device__ __forceinline__ int64_t queue_next(unsigned int* wq, unsigned int& slot, int64_t items, int64_t w_stride) {
+  if (!wq) return w_stride;
+  __syncthreads();  // every thread has read `slot` before it is replaced
+  if (threadIdx.x == 0) slot = (unsigned int)queue_pick(wq, items, atomicAdd(&wq[blockIdx.x % kXcd], 1u));
+  __syncthreads();
+  return (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)slot);
+}
+
+// Only the first min(items, grid) workgroups take part in a launch's queue
+// (one item each at least; the rest return at once, so a launch sized for
+// its largest count costs little at a small one).  Every member calls
+// queue_done once, after its last queue_next; the last one resets the queue.
+__device__ __forceinline__ bool queue_member(int64_t items) { return (int64_t)blockIdx.x < items; }
+
+__device__ __forceinline__ void queue_done(unsigned int* wq, int64_t items) {
+  const unsigned int members = items < (int64_t)gridDim.x ? (unsigned int)items : gridDim.x;
+  if (wq && threadIdx.x == 0 && atomicAdd(&wq[kXcd], 1u) == members - 1) {
     for (int x = 0; x < kQueueWords; ++x) atomicExch(&wq[x], 0u);
   }
 }
@@ -643,9 +679,36 @@ struct Smem {
   double red[(L > 64 ? kWG / 64 : 1) * 7];
 };
 
+// The items of one launch shape: (i-block, j-chunk) pairs taken from the
+// work queue until none is left.
+template <class P, int K, int L, bool MASK>
+__device__ __forceinline__ void run_items(typename P::JTile& tile, double* red, unsigned int& slot,
+                                          const ForceArgs& a, int64_t n_act, int S) {
+  constexpr int IB = (kWG / L) * K;
+  const int64_t n_iblk = (n_act + IB - 1) / IB;
+  const int64_t items = n_iblk * S;
+  const int64_t clen = chunk_len(a.n, S);
+  if (!queue_member(items)) return;
+  int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
+  while (w < items) {
+    const int64_t chunk = w / n_iblk;
+    const int64_t iblk = w - chunk * n_iblk;
+    const int64_t jb = chunk * clen;
+    const int64_t je = jb + clen < a.n ? jb + clen : a.n;
+    process_item<P, K, L, MASK>(tile, red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
+                                a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
+                                a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi,
+                                a.err);
+    w = queue_next(a.wq, slot, items, w + gridDim.x);
+  }
+  queue_done(a.wq, items);
+}
+
+// One shape (those outside the families below).
 template <class P, int K, int L, bool MASK>
 __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
   __shared__ Smem<P, L> sm;
+  __shared__ unsigned int slot;
   constexpr int IB = (kWG / L) * K;
   int64_t n_act = a.n_active;
   int S = a.S;
@@ -656,23 +719,53 @@ __global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
     S = choose_S(n_act, IB, target_for(a, d), a.n);
     if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
-  const int64_t n_iblk = (n_act + IB - 1) / IB;
-  const int64_t items = n_iblk * S;
-  const int64_t clen = chunk_len(a.n, S);
+  run_items<P, K, L, MASK>(sm.tile, sm.red, slot, a, n_act, S);
+}
+
+// The shape of a family launch for count d (unrolled like target_for).
+__device__ __forceinline__ int shape_for(const ForceArgs& a, int64_t d) {
+  int t = a.shape;
+#pragma unroll
+  for (int r = 0; r < kMaxSubRegimes; ++r)
+    if (r < a.n_sub && d >= a.sub_lo[r]) t = a.sub_shape[r];
+  return t;
+}
+
+// A kernel family (family_of): the shape -- fixed by the host, or in
+// device-count mode the one of the regime holding the count -- selects one
+// of the compiled bodies, so the regimes of a block step share one launch
+// whatever their shapes.  Every body is the single-shape kernel's, so a
+// shape gives the same sums in either kernel.
+template <class P, int FAM, bool MASK>
+__global__ __launch_bounds__(kWG) void k_forces_fam(ForceArgs a) {
+  __shared__ Smem<P, 256> sm;
   __shared__ unsigned int slot;
-  int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
-  while (w < items) {
-    const int64_t chunk = w / n_iblk;
-    const int64_t iblk = w - chunk * n_iblk;
-    const int64_t jb = chunk * clen;
-    const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item<P, K, L, MASK>(sm.tile, sm.red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
-                                a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
-                                a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi,
-                                a.err);
-    w = queue_take(a.wq, slot, items, w + gridDim.x);
+  int64_t n_act = a.n_active;
+  int S = a.S;
+  int shape = a.shape;
+  if (a.n_active_dev) {
+    const int64_t d = *a.n_active_dev;
+    if (d < a.act_lo || (d > a.n_active && !a.last)) return;  // another launch's range
+    n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
+    shape = shape_for(a, d);
+    const int K = shape >> 16, L = shape & 0xffff;
+    S = choose_S(n_act, (kWG / L) * K, target_for(a, d), a.n);
+    if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;
   }
-  queue_done(a.wq);
+#define NB_RUN(KK, LL)                                                           \
+  if (shape == shape_code(KK, LL)) {                                             \
+    run_items<P, KK, LL, MASK>(sm.tile, sm.red, slot, a, n_act, S);              \
+    return;                                                                      \
+  }
+  NB_RUN(1, 1) NB_RUN(1, 4) NB_RUN(1, 16) NB_RUN(1, 64) NB_RUN(1, 256)
+  if constexpr (FAM == 2 && !MASK) {
+    NB_RUN(2, 1) NB_RUN(2, 4) NB_RUN(2, 16)
+  }
+  if constexpr (FAM == 4 && !MASK) {
+    NB_RUN(4, 4)
+  }
+#undef NB_RUN
+  // a shape outside the family (the host never launches one): no items, queue untouched
 }
 
 // Fixed-order sum of the S partial blocks, self-term removal, output.
@@ -729,9 +822,10 @@ __global__ __launch_bounds__(256) void k_reduce(ForceArgs a, int S_host, int IB)
 // one): the sums of a pass run side by side, never one after another.  With
 // S = 1 the force kernel has written the final rows and only the
 // correction runs.
+constexpr int kReduceCorrectThreads = 512;
+
 template <class P>
-__global__ __launch_bounds__(256) void k_reduce_correct(ForceArgs a, StepArgs s) {
-  __shared__ double vals[256];
+__global__ __launch_bounds__(kReduceCorrectThreads) void k_reduce_correct(ForceArgs a, StepArgs s) {
   int64_t n_act = a.n_active;
   int S = 1;
   if (a.n_active_dev) {
@@ -741,55 +835,69 @@ __global__ __launch_bounds__(256) void k_reduce_correct(ForceArgs a, StepArgs s)
   }
   if (s.step_dev && n_act > 0 && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(s.step_dev, 1ull);
   const bool self_on = P::eps(a.eps2) > 0;
+  // g lanes per row (the lane grouping of sum_blocks, so every sum is the one
+  // k_reduce forms); each group adds all seven outputs of its row, two
+  // blocks ahead so the loads of both are in flight together
   const int g = S > 1 ? chunk_lanes(S) : 1;
   const int lane = threadIdx.x & (g - 1);
-  const int grp = threadIdx.x / g, ngrp = 256 / g;
-  const int R = ngrp >= 7 ? ngrp / 7 : 1;  // rows per pass; 7 R <= 256
-  for (int64_t row0 = (int64_t)blockIdx.x * R; row0 < n_act; row0 += (int64_t)gridDim.x * R) {
+  const int64_t grp = ((int64_t)blockIdx.x * kReduceCorrectThreads + threadIdx.x) / g;
+  const int64_t ngrp = ((int64_t)gridDim.x * kReduceCorrectThreads) / g;
+  const int64_t stride = 7 * n_act;
+  for (int64_t k = grp; k < n_act; k += ngrp) {
+    const int64_t i = a.active[k];
+    double v[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = 0.0;
     if (S > 1) {
-      // element e = (component c, row r), rows fastest so that neighbouring
-      // groups read neighbouring words; one g-lane group per element
-      for (int e = grp; e < 7 * R; e += ngrp) {
-        const int c = e / R, r = e - R * c;
-        const int64_t k = row0 + r;
-        if (k >= n_act) continue;  // the whole group alike
-        const double v = sum_blocks(a.part + c * n_act + k, 7 * n_act, S, lane, g);
-        if (lane == 0) vals[r * 7 + c] = v;
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x < R) {
-      const int64_t k = row0 + threadIdx.x;
-      if (k < n_act) {
-        const int64_t i = a.active[k];
-        if (row_in_range(i, a.row_lo, a.row_hi)) {
-          double a1[3], j1[3];
-          if (S > 1) {
-            const double* v = vals + threadIdx.x * 7;
+      const double* p = a.part + k;
+      int ch = lane;
+      for (; ch + g < S; ch += 2 * g) {
+        double x[7], y[7];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              a1[c] = v[c];
-              j1[c] = v[3 + c];
-              a.acc[3 * k + c] = a1[c];
-              a.jerk[3 * k + c] = j1[c];
-            }
-            const double self = (self_on && !a.no_self) ? P::self_term(a.mass[i], a.eps2) : 0.0;
-            a.pot[k] = -(v[6] - self);
-          } else {
+        for (int c = 0; c < 7; ++c) {
+          x[c] = p[(int64_t)ch * stride + c * n_act];
+          y[c] = p[(int64_t)(ch + g) * stride + c * n_act];
+        }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              a1[c] = a.acc[3 * k + c];
-              j1[c] = a.jerk[3 * k + c];
-            }
-          }
-          correct_particle(i, a1, j1, s.pos_p, s.vel_p, s.pos, s.vel, s.acc, s.jerk, s.t_tick, s.level, s.eta,
-                           s.dt_max, s.max_level, s.clamp_dev);
-        } else if (a.err) {
-          atomicOr(a.err, kErrActiveRange);
+        for (int c = 0; c < 7; ++c) {
+          v[c] += x[c];
+          v[c] += y[c];
         }
       }
+      if (ch < S) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] += p[(int64_t)ch * stride + c * n_act];
+      }
+      for (int m = g >> 1; m > 0; m >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] += __shfl_xor(v[c], m);
+      }
     }
-    __syncthreads();
+    if (lane != 0) continue;
+    if (!row_in_range(i, a.row_lo, a.row_hi)) {
+      if (a.err) atomicOr(a.err, kErrActiveRange);
+      continue;
+    }
+    double a1[3], j1[3];
+    if (S > 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = v[c];
+        j1[c] = v[3 + c];
+        a.acc[3 * k + c] = a1[c];
+        a.jerk[3 * k + c] = j1[c];
+      }
+      const double self = (self_on && !a.no_self) ? P::self_term(a.mass[i], a.eps2) : 0.0;
+      a.pot[k] = -(v[6] - self);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = a.acc[3 * k + c];
+        j1[c] = a.jerk[3 * k + c];
+      }
+    }
+    correct_particle(i, a1, j1, s.pos_p, s.vel_p, s.pos, s.vel, s.acc, s.jerk, s.t_tick, s.level, s.eta, s.dt_max,
+                     s.max_level, s.clamp_dev);
   }
 }
 
@@ -926,6 +1034,7 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
   const int64_t items = n_iblk * S;
   const int64_t clen = chunk_len(a.n, S);
   __shared__ unsigned int slot;
+  if (!queue_member(items)) return;
   int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
   while (w < items) {
     const int64_t chunk = w / n_iblk;
@@ -935,9 +1044,9 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
     process_item_sj<P, K, MASK>(rec, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass,
                                 jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                                 a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi, a.err);
-    w = queue_take(a.wq, slot, items, w + gridDim.x);
+    w = queue_next(a.wq, slot, items, w + gridDim.x);
   }
-  queue_done(a.wq);
+  queue_done(a.wq, items);
 }
 
 
@@ -1065,6 +1174,7 @@ __global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a
   const int64_t items = n_iblk * S;
   const int64_t clen = chunk_len(a.n, S);
   __shared__ unsigned int slot;
+  if (!queue_member(items)) return;
   int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
   while (w < items) {
     const int64_t chunk = w / n_iblk;
@@ -1074,9 +1184,9 @@ __global__ __launch_bounds__(kWG, (K == 2 ? 5 : 1)) void k_forces_hy(ForceArgs a
     process_item_hy<K>(rec, vm_tile, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel,
                        a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                        a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi, a.err);
-    w = queue_take(a.wq, slot, items, w + gridDim.x);
+    w = queue_next(a.wq, slot, items, w + gridDim.x);
   }
-  queue_done(a.wq);
+  queue_done(a.wq, items);
 }
 
 // ---------------------------------------------------------------- batch ----
@@ -1108,16 +1218,45 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
   }
 }
 
+// The same work list on the scalar j-path: j-records of the whole batch come
+// from one mirror through the scalar cache, each system's rows with its own
+// softening; an i-block is kWG * K of the system's active rows.
+template <class P, int K, bool MASK>
+__global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_batch_sj(
+    const BatchItem* __restrict__ items, int n_items, const int* __restrict__ n_items_dev,
+    const BatchSys* __restrict__ sys, const typename P::JReg* __restrict__ rec, const double* pos, const double* vel,
+    const double* mass, const int32_t* active, double* acc, double* jerk, double* pot, double* part,
+    unsigned int* err) {
+  constexpr int IB = kWG * K;
+  if (n_items_dev) {
+    const int d = *n_items_dev;
+    n_items = d < n_items ? (d < 0 ? 0 : d) : n_items;
+  }
+  for (int w = blockIdx.x; w < n_items; w += gridDim.x) {
+    const BatchItem it = items[w];
+    const BatchSys sy = sys[it.sys];
+    const int64_t nj = sy.j1 - sy.j0;
+    const int64_t n_act = sy.a1 - sy.a0;
+    const int64_t clen = chunk_len(nj, it.nchunk);
+    const int64_t jb = sy.j0 + (int64_t)it.chunk * clen;
+    const int64_t je = jb + clen < sy.j1 ? jb + clen : sy.j1;
+    process_item_sj<P, K, MASK>(rec, pos, vel, mass, jb, je, active + sy.a0, n_act, (int64_t)it.iblk * IB, sy.eps2,
+                                it.nchunk == 1, acc + 3 * sy.a0, jerk + 3 * sy.a0, pot + sy.a0,
+                                part + (sy.part_off + (int64_t)it.chunk * n_act) * 7, sy.j0, sy.j1, err);
+  }
+}
+
 // Systems with more than one chunk (grid y) over a few workgroups each (grid
 // x); each output is the fixed-order sum of its chunks.
 template <class P>
 __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict__ sys,
-                                                      const int32_t* __restrict__ nchunk, const double* mass,
-                                                      const int32_t* active, double* acc, double* jerk,
-                                                      double* pot, const double* part) {
-  const BatchSys sy = sys[blockIdx.y];
-  const int S = nchunk[blockIdx.y];
-  if (S <= 1) return;
+                                                      const int32_t* __restrict__ nchunk, int n_sys,
+                                                      const double* mass, const int32_t* active, double* acc,
+                                                      double* jerk, double* pot, const double* part) {
+  for (int cs = blockIdx.y; cs < n_sys; cs += gridDim.y) {  // more systems than grid rows
+  const BatchSys sy = sys[cs];
+  const int S = nchunk[cs];
+  if (S <= 1) continue;
   const int64_t n_act = sy.a1 - sy.a0;
   const double* pb = part + sy.part_off * 7;
   const bool self_on = P::eps(sy.eps2) > 0;
@@ -1141,8 +1280,96 @@ __global__ __launch_bounds__(256) void k_batch_reduce(const BatchSys* __restrict
       pot[row] = -(s - self);
     }
   }
+  }
 }
 
+
+// Batched block step: the chunk sums of k_batch_reduce and the corrector in
+// one pass.  Grid row y is system y (no search for a row's system); its
+// blocks stride over the system's active rows with g lanes per row (the
+// grouping of sum_blocks, so every sum is the one k_batch_reduce forms),
+// each group adding all seven outputs of its row two chunks ahead; lane 0
+// of the group then corrects the particle.
+template <class P>
+__global__ __launch_bounds__(256) void k_batch_reduce_correct(const BatchSys* __restrict__ sys,
+                                                              const int32_t* __restrict__ nchunk, int C,
+                                                              const int64_t* __restrict__ n_act_dev,
+                                                              const double* __restrict__ mass,
+                                                              const int32_t* __restrict__ active, double* acc1,
+                                                              double* jerk1, double* pot1, const double* part,
+                                                              StepArgs s, unsigned int* err) {
+  if (s.step_dev && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0 && *n_act_dev > 0)
+    atomicAdd(s.step_dev, 1ull);
+  for (int cs = blockIdx.y; cs < C; cs += gridDim.y) {  // more systems than grid rows
+  const BatchSys sy = sys[cs];
+  const int64_t na = sy.a1 - sy.a0;
+  if (na <= 0) continue;
+  const int S = nchunk[cs];
+  const int g = S > 1 ? chunk_lanes(S) : 1;
+  const int lane = threadIdx.x & (g - 1);
+  const int64_t grp = ((int64_t)blockIdx.x * 256 + threadIdx.x) / g;
+  const int64_t ngrp = ((int64_t)gridDim.x * 256) / g;
+  const double* pb = part + sy.part_off * 7;
+  const int64_t stride = 7 * na;
+  for (int64_t kk = grp; kk < na; kk += ngrp) {
+    const int64_t k = sy.a0 + kk;
+    const int64_t i = active[k];
+    double v[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) v[c] = 0.0;
+    if (S > 1) {
+      const double* p = pb + kk;
+      int ch = lane;
+      for (; ch + g < S; ch += 2 * g) {
+        double x[7], y[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          x[c] = p[(int64_t)ch * stride + c * na];
+          y[c] = p[(int64_t)(ch + g) * stride + c * na];
+        }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+          v[c] += x[c];
+          v[c] += y[c];
+        }
+      }
+      if (ch < S) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] += p[(int64_t)ch * stride + c * na];
+      }
+      for (int m = g >> 1; m > 0; m >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 7; ++c) v[c] += __shfl_xor(v[c], m);
+      }
+    }
+    if (lane != 0) continue;
+    if (!row_in_range(i, sy.j0, sy.j1)) {
+      if (err) atomicOr(err, kErrActiveRange);
+      continue;
+    }
+    double a1[3], j1[3];
+    if (S > 1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = v[c];
+        j1[c] = v[3 + c];
+        acc1[3 * k + c] = a1[c];
+        jerk1[3 * k + c] = j1[c];
+      }
+      const double self = P::eps(sy.eps2) > 0 ? P::self_term(mass[i], sy.eps2) : 0.0;
+      pot1[k] = -(v[6] - self);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a1[c] = acc1[3 * k + c];
+        j1[c] = jerk1[3 * k + c];
+      }
+    }
+    correct_particle(i, a1, j1, s.pos_p, s.vel_p, s.pos, s.vel, s.acc, s.jerk, s.t_tick, s.level, s.eta, s.dt_max,
+                     s.max_level, s.clamp_dev);
+  }
+  }
+}
 
 // ------------------------------------------------------------ batch plan ---
 // One workgroup turns the scheduled active set of a batch of independent
@@ -1285,18 +1512,36 @@ using ForceFn = void (*)(ForceArgs);
 using BatchFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const double*, const double*,
                          const double*, const int32_t*, double*, double*, double*, double*, unsigned int*);
 
+// Single-shape kernels: the shapes no family holds.
 template <class P, bool MASK>
 ForceFn pick_force(int K, int L) {
 #define NB_CASE(KK, LL) \
   if (K == KK && L == LL) return k_forces<P, KK, LL, MASK>;
-  NB_CASE(1, 1) NB_CASE(1, 2) NB_CASE(1, 4) NB_CASE(1, 8) NB_CASE(1, 16) NB_CASE(1, 32) NB_CASE(1, 64)
-  NB_CASE(1, 128) NB_CASE(1, 256)
+  NB_CASE(1, 2) NB_CASE(1, 8) NB_CASE(1, 32) NB_CASE(1, 128)
   if constexpr (!MASK) {
-    NB_CASE(2, 1) NB_CASE(2, 2) NB_CASE(2, 4) NB_CASE(2, 8) NB_CASE(2, 16) NB_CASE(2, 32) NB_CASE(2, 64)
-    NB_CASE(4, 1) NB_CASE(4, 2) NB_CASE(4, 4) NB_CASE(4, 8) NB_CASE(4, 16)
+    NB_CASE(2, 2) NB_CASE(2, 8) NB_CASE(2, 32) NB_CASE(2, 64)
+    NB_CASE(4, 1) NB_CASE(4, 2) NB_CASE(4, 8) NB_CASE(4, 16)
   }
 #undef NB_CASE
   return nullptr;
+}
+
+template <class P, bool MASK>
+ForceFn pick_fam(int fam) {
+  if (fam == 1) return k_forces_fam<P, 1, MASK>;
+  if constexpr (!MASK) {
+    if (fam == 2) return k_forces_fam<P, 2, MASK>;
+    if (fam == 4) return k_forces_fam<P, 4, MASK>;
+  }
+  return nullptr;
+}
+
+// The LDS kernel of a shape: its family's (cfg.fam, else the smallest
+// family holding it), else its single-shape kernel.
+template <class P, bool MASK>
+ForceFn pick_lds(const Launch& cfg, int K) {
+  const int fam = cfg.fam > 0 ? cfg.fam : family_of(K, cfg.L);
+  return fam ? pick_fam<P, MASK>(fam) : pick_force<P, MASK>(K, cfg.L);
 }
 
 template <class P, bool MASK>
@@ -1337,6 +1582,39 @@ HyFn pick_hy(int K) {
   return nullptr;
 }
 
+template <class P>
+using BatchSjFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const typename P::JReg*,
+                           const double*, const double*, const double*, const int32_t*, double*, double*, double*,
+                           double*, unsigned int*);
+
+template <class P, bool MASK>
+BatchSjFn<P> pick_batch_sj(int K) {
+  if (K == 1) return k_forces_batch_sj<P, 1, MASK>;
+  if constexpr (!MASK) {
+    if (K == 2) return k_forces_batch_sj<P, 2, MASK>;
+  }
+  return nullptr;
+}
+
+template <class P, bool MASK>
+hipError_t launch_batch_sj_p(int K, const BatchItem* items, int n_items, const int* n_items_dev, const BatchSys* sys,
+                             void* rec_buf, int64_t n_total, const double* pos, const double* vel, const double* mass,
+                             const int32_t* active, double* acc, double* jerk, double* pot, double* part,
+                             int max_grid, unsigned int* err, hipStream_t st) {
+  BatchSjFn<P> fn = pick_batch_sj<P, MASK>(K);
+  if (!fn || !rec_buf) return hipErrorInvalidValue;
+  typename P::JReg* rec = static_cast<typename P::JReg*>(rec_buf);
+  int64_t mg = (n_total + 256) / 256;
+  if (mg > 8192) mg = 8192;
+  hipLaunchKernelGGL(k_mirror<P>, dim3((int)mg), dim3(256), 0, st, pos, vel, mass, n_total, rec);
+  if (n_items <= 0) return hipGetLastError();
+  int grid = n_items;
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, items, n_items, n_items_dev, sys, rec, pos, vel, mass,
+                     active, acc, jerk, pot, part, err);
+  return hipGetLastError();
+}
+
 template <class P, bool MASK>
 BatchFn pick_batch(int K, int L) {
 #define NB_CASE(KK, LL) \
@@ -1354,7 +1632,7 @@ BatchFn pick_batch(int K, int L) {
 bool launch_supported(const Launch& c) {
   if (c.L < 0) return pick_hy(c.K) != nullptr && c.S >= 1;
   if (c.L == 0) return pick_sj<F64, false>(c.K) != nullptr && c.S >= 1;
-  return pick_force<F64, false>(c.K, c.L) != nullptr && c.S >= 1;
+  return (family_of(c.K, c.L) || pick_force<F64, false>(c.K, c.L) != nullptr) && c.S >= 1;
 }
 
 size_t mirror_bytes(int prec, int64_t n) {
@@ -1402,16 +1680,23 @@ hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs
   }
   ForceFn fn = nullptr;
   if (prec == NB_PREC_FP64)
-    fn = mask ? pick_force<F64, true>(K, cfg.L) : pick_force<F64, false>(K, cfg.L);
+    fn = mask ? pick_lds<F64, true>(cfg, K) : pick_lds<F64, false>(cfg, K);
   else if (prec == NB_PREC_MIXED_DS)
-    fn = mask ? pick_force<MixedDS, true>(K, cfg.L) : pick_force<MixedDS, false>(K, cfg.L);
+    fn = mask ? pick_lds<MixedDS, true>(cfg, K) : pick_lds<MixedDS, false>(cfg, K);
   else
-    fn = mask ? pick_force<Mixed, true>(K, cfg.L) : pick_force<Mixed, false>(K, cfg.L);
+    fn = mask ? pick_lds<Mixed, true>(cfg, K) : pick_lds<Mixed, false>(cfg, K);
   if (!fn) return hipErrorInvalidValue;
   int grid = grid_override > 0 ? grid_override : items_for(Launch{K, cfg.L, a.S}, a.n_active, a.S);
   if (max_grid > 0 && grid > max_grid) grid = max_grid;
   if (grid <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a);
+  if (a.n_sub == 0 && a.shape == 0) {
+    // a host-chosen shape: the family kernel runs the body of this shape
+    ForceArgs b = a;
+    b.shape = shape_code(K, cfg.L);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, b);
+  } else {
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -1433,11 +1718,11 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
     else
       fn = mask ? (const void*)pick_sj<Mixed, true>(K) : (const void*)pick_sj<Mixed, false>(K);
   } else if (prec == NB_PREC_FP64) {
-    fn = mask ? (const void*)pick_force<F64, true>(K, cfg.L) : (const void*)pick_force<F64, false>(K, cfg.L);
+    fn = mask ? (const void*)pick_lds<F64, true>(cfg, K) : (const void*)pick_lds<F64, false>(cfg, K);
   } else if (prec == NB_PREC_MIXED_DS) {
-    fn = mask ? (const void*)pick_force<MixedDS, true>(K, cfg.L) : (const void*)pick_force<MixedDS, false>(K, cfg.L);
+    fn = mask ? (const void*)pick_lds<MixedDS, true>(cfg, K) : (const void*)pick_lds<MixedDS, false>(cfg, K);
   } else {
-    fn = mask ? (const void*)pick_force<Mixed, true>(K, cfg.L) : (const void*)pick_force<Mixed, false>(K, cfg.L);
+    fn = mask ? (const void*)pick_lds<Mixed, true>(cfg, K) : (const void*)pick_lds<Mixed, false>(cfg, K);
   }
   if (!fn) return 1;
   std::lock_guard<std::mutex> lk(mu);
@@ -1453,17 +1738,18 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
 }
 
 hipError_t launch_reduce_correct(int prec, const ForceArgs& a, const StepArgs& s, hipStream_t st) {
-  // one block per row when the count is known only on the device and the
-  // split is wide (R = 1); a grid-stride loop covers the rest
-  int64_t grid = a.n_active;
+  // enough blocks for one row per thread at the largest count (a row takes
+  // up to 64 lanes when its split is wide, and the count is then small); a
+  // grid-stride loop covers the rest
+  int64_t grid = (a.n_active + kReduceCorrectThreads - 1) / kReduceCorrectThreads;
   if (grid > 1024) grid = 1024;
   if (grid < 1) grid = 1;
   if (prec == NB_PREC_FP64)
-    hipLaunchKernelGGL(k_reduce_correct<F64>, dim3((int)grid), dim3(256), 0, st, a, s);
+    hipLaunchKernelGGL(k_reduce_correct<F64>, dim3((int)grid), dim3(kReduceCorrectThreads), 0, st, a, s);
   else if (prec == NB_PREC_MIXED_DS)
-    hipLaunchKernelGGL(k_reduce_correct<MixedDS>, dim3((int)grid), dim3(256), 0, st, a, s);
+    hipLaunchKernelGGL(k_reduce_correct<MixedDS>, dim3((int)grid), dim3(kReduceCorrectThreads), 0, st, a, s);
   else
-    hipLaunchKernelGGL(k_reduce_correct<Mixed>, dim3((int)grid), dim3(256), 0, st, a, s);
+    hipLaunchKernelGGL(k_reduce_correct<Mixed>, dim3((int)grid), dim3(kReduceCorrectThreads), 0, st, a, s);
   return hipGetLastError();
 }
 
@@ -1491,12 +1777,29 @@ hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStre
   return hipGetLastError();
 }
 
+bool batch_supported(const Launch& c) {
+  if (c.L == 0) return pick_batch_sj<F64, false>(c.K) != nullptr;
+  return pick_batch<F64, false>(c.K, c.L) != nullptr;
+}
+
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
                         const BatchSys* sys, const double* pos, const double* vel, const double* mass,
                         const int32_t* active, double* acc, double* jerk, double* pot, double* part,
-                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, hipStream_t st) {
+                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, void* rec,
+                        int64_t n_total, hipStream_t st) {
   (void)part_rows;
   const int K = any_mask ? 1 : cfg.K;
+  if (cfg.L == 0) {
+#define NB_SJ(P)                                                                                                    \
+  (any_mask ? launch_batch_sj_p<P, true>(K, items, n_items, n_items_dev, sys, rec, n_total, pos, vel, mass, active, \
+                                         acc, jerk, pot, part, max_grid, err, st)                                   \
+            : launch_batch_sj_p<P, false>(K, items, n_items, n_items_dev, sys, rec, n_total, pos, vel, mass,       \
+                                          active, acc, jerk, pot, part, max_grid, err, st))
+    if (prec == NB_PREC_FP64) return NB_SJ(F64);
+    if (prec == NB_PREC_MIXED_DS) return NB_SJ(MixedDS);
+    return NB_SJ(Mixed);
+#undef NB_SJ
+  }
   BatchFn fn = nullptr;
   if (prec == NB_PREC_FP64)
     fn = any_mask ? pick_batch<F64, true>(K, cfg.L) : pick_batch<F64, false>(K, cfg.L);
@@ -1522,16 +1825,37 @@ hipError_t launch_batch_reduce(int prec, const BatchSys* sys, int n_sys, const i
   // system's blocks past its rows return at once
   int64_t nx = (7 * 16 * (n_act_total > 0 ? n_act_total : 1) + (int64_t)n_sys * 1024 - 1) / ((int64_t)n_sys * 1024);
   nx = nx < 1 ? 1 : (nx > 32 ? 32 : nx);
-  const dim3 grid((unsigned)nx, (unsigned)n_sys);
+  const dim3 grid((unsigned)nx, (unsigned)(n_sys < 65535 ? n_sys : 65535));
   if (prec == NB_PREC_FP64)
-    hipLaunchKernelGGL(k_batch_reduce<F64>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc, jerk,
-                       pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<F64>, grid, dim3(256), 0, st, sys, chunks_per_sys, n_sys, mass, active, acc,
+                       jerk, pot, part);
   else if (prec == NB_PREC_MIXED_DS)
-    hipLaunchKernelGGL(k_batch_reduce<MixedDS>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
-                       jerk, pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<MixedDS>, grid, dim3(256), 0, st, sys, chunks_per_sys, n_sys, mass, active,
+                       acc, jerk, pot, part);
   else
-    hipLaunchKernelGGL(k_batch_reduce<Mixed>, grid, dim3(256), 0, st, sys, chunks_per_sys, mass, active, acc,
-                       jerk, pot, part);
+    hipLaunchKernelGGL(k_batch_reduce<Mixed>, grid, dim3(256), 0, st, sys, chunks_per_sys, n_sys, mass, active,
+                       acc, jerk, pot, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reduce_correct(int prec, const BatchSys* sys, const int32_t* chunks_per_sys, int C,
+                                       const int64_t* n_act_dev, int64_t n_max, const double* mass,
+                                       const int32_t* active, double* acc1, double* jerk1, double* pot1,
+                                       const double* part, const StepArgs& s, unsigned int* err, hipStream_t st) {
+  if (C <= 0) return hipSuccess;
+  // blocks per system (grid x) as for k_batch_reduce: enough for a system of
+  // the mean size at up to 16 lanes per row; a system's blocks past its rows
+  // return at once
+  int64_t nx = (16 * (n_max > 0 ? n_max : 1) + (int64_t)C * 256 - 1) / ((int64_t)C * 256);
+  nx = nx < 1 ? 1 : (nx > 32 ? 32 : nx);
+  const dim3 grid((unsigned)nx, (unsigned)(C < 65535 ? C : 65535));
+#define NB_RC(P)                                                                                                  \
+  hipLaunchKernelGGL(k_batch_reduce_correct<P>, grid, dim3(256), 0, st, sys, chunks_per_sys, C, n_act_dev, mass, \
+                     active, acc1, jerk1, pot1, part, s, err)
+  if (prec == NB_PREC_FP64) NB_RC(F64);
+  else if (prec == NB_PREC_MIXED_DS) NB_RC(MixedDS);
+  else NB_RC(Mixed);
+#undef NB_RC
   return hipGetLastError();
 }
 

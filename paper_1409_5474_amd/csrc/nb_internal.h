@@ -27,7 +27,31 @@ struct Launch {
   int L = 1;      // lanes per i-particle
   int S = 1;      // j-subsets (0: choose by the saturation rule)
   int items = 0;  // work-item target of the saturation rule (0: 4 per CU)
+  int fam = 0;    // > 0: run in the LDS kernel family `fam`, which holds this
+                  // shape and, in device-count mode, every shape of the call
 };
+
+// LDS kernel families: one kernel holding the bodies of several (K, L)
+// shapes, so that device-count regimes of different shapes share one launch
+// (each launch costs a few microseconds in every block step).
+//   family 1: K = 1, L in {1, 4, 16, 64, 256}
+//   family 2: family 1 and K = 2, L in {1, 4, 16}
+//   family 4: family 1 and K = 4, L = 4
+// Returns the smallest family holding the shape, 0 for none.
+inline int family_of(int K, int L) {
+  if (K == 1 && (L == 1 || L == 4 || L == 16 || L == 64 || L == 256)) return 1;
+  if (K == 2 && (L == 1 || L == 4 || L == 16)) return 2;
+  if (K == 4 && L == 4) return 4;
+  return 0;
+}
+// The smallest family holding both families' shapes (0: none).
+inline int family_cover(int a, int b) {
+  if (a == 0 || b == 0) return 0;
+  if (a == b || b == 1) return a;
+  if (a == 1) return b;
+  return 0;  // families 2 and 4 hold different K
+}
+__host__ __device__ constexpr int shape_code(int K, int L) { return (K << 16) | L; }
 
 // i-particles per workgroup of a launch shape (L = 0: the scalar j-path,
 // one i-slot per lane like L = 1).
@@ -61,6 +85,16 @@ struct TuneEntry {
   Launch cfg;
 };
 
+// Tuned shape of the batched force kernel.  kind 1: nbody_forces_batch,
+// keyed by the mean active rows per system; kind 2: the batched block step,
+// keyed by the mean system size (the step's count is known only on the
+// device).
+struct BatchTuneEntry {
+  int prec, kind;
+  int64_t key_min, key_max;
+  Launch cfg;
+};
+
 // Arguments of one force launch.  j rows [0, n) of pos/vel/mass; i rows
 // active[0, n_active).  When n_active_dev is set the count is read on the
 // device and the j-split is chosen there.
@@ -89,6 +123,10 @@ struct ForceArgs {
   int n_sub;
   int64_t sub_lo[kMaxSubRegimes];
   int sub_items[kMaxSubRegimes];
+  // Family launches: the shape (shape_code) of the call, and in device-count
+  // mode that of regime r (the regimes of one launch may differ in shape).
+  int shape;
+  int sub_shape[kMaxSubRegimes];
   void* rec;                    // scalar j-path: mirror of n j-records (context-owned)
   // Work queue of the persistent grid (per-XCD item counters, then the count
   // of finished workgroups): zero before a launch, and the launch's last
@@ -156,7 +194,10 @@ int items_for(const Launch& cfg, int64_t n_active, int S);
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
                         const BatchSys* sys, const double* pos, const double* vel, const double* mass,
                         const int32_t* active, double* acc, double* jerk, double* pot, double* part,
-                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, hipStream_t st);
+                        int64_t part_rows, bool any_mask, int max_grid, unsigned int* err, void* rec,
+                        int64_t n_total, hipStream_t st);
+// whether the batched force kernel exists in this shape (L = 0: scalar j-path)
+bool batch_supported(const Launch& c);
 hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, const int32_t* active,
                              const int64_t* n_act_dev, int IB, int target, BatchSys* sys, int32_t* nchunk,
                              BatchItem* items, int max_items, int* n_items_dev, int64_t part_cap_rows,
@@ -201,6 +242,11 @@ struct StepArgs {
   unsigned long long* step_dev;
 };
 hipError_t launch_reduce_correct(int prec, const ForceArgs& a, const StepArgs& s, hipStream_t st);
+// the same for a batched block step (rows of every system, device count)
+hipError_t launch_batch_reduce_correct(int prec, const BatchSys* sys, const int32_t* chunks_per_sys, int C,
+                                       const int64_t* n_act_dev, int64_t n_max, const double* mass,
+                                       const int32_t* active, double* acc1, double* jerk1, double* pot1,
+                                       const double* part, const StepArgs& s, unsigned int* err, hipStream_t st);
 
 // The predictor folded into the scheduler's last pass (all pointers null:
 // no prediction).  Predicts every particle to the scheduled t_next.
@@ -283,6 +329,7 @@ struct nb_ctx {
   nb::Launch forced;            // K == 0: automatic
   bool have_forced = false;
   std::vector<nb::TuneEntry> table;
+  std::vector<nb::BatchTuneEntry> batch_table;
   // device workspace (grown on demand)
   void* ws = nullptr;
   size_t ws_bytes = 0;

@@ -257,10 +257,16 @@ def test_devcount_matches_host_count(ctx, prec, n):
     ctx.set_precision("fp64")
 
 
+@pytest.mark.parametrize("shape", [None, (1, 0), (2, 0), (2, 4)], ids=["table", "sj1", "sj2", "lds2x4"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_matches_oracle(ctx, prec):
+def test_batch_matches_oracle(nb, prec, shape):
+    # every batched kernel shape (default choice, the scalar j-path with one
+    # or two i-particles per lane, the LDS layout) on its own context
     import torch
-    ctx.set_precision(prec)
+    ctx = nb.Context(0, prec)
+    if shape is not None:
+        ctx.tune_add_batch(prec, 1, 1, 2 ** 40, *shape)
+        assert ctx.get_batch_launch(1, 500, 1000) == shape
     b = synth.cluster_batch(seed=4, n_clusters=24, n_min=64, n_max=3000)
     rng = np.random.default_rng(5)
     acts, aoff = [], [0]
@@ -284,4 +290,4 @@ def test_batch_matches_oracle(ctx, prec):
             check_fp64((A[rows], J[rows], Pt[rows]), ref)
         else:
             check_mixed((A[rows], J[rows], Pt[rows]), ref)
-    ctx.set_precision("fp64")
+    ctx.close()

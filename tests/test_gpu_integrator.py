@@ -50,9 +50,14 @@ def test_single_system_graph_equals_eager_and_oracle(ctx):
     assert g.time == 0.125
 
 
-def test_batch_block_steps_follow_per_system_oracle(ctx):
+@pytest.mark.parametrize("shape", [None, (1, 0), (2, 0)], ids=["table", "sj1", "sj2"])
+def test_batch_block_steps_follow_per_system_oracle(shape):
     import torch
+    import paper_1409_5474_amd as nb
     from paper_1409_5474_amd.integrator import BlockIntegrator
+    ctx = nb.Context(0, "fp64")
+    if shape is not None:
+        ctx.tune_add_batch("fp64", 2, 1, 2 ** 40, *shape)
     b = synth.cluster_batch(seed=4, n_clusters=10, n_min=64, n_max=1500)
     eta, dt_max, ML, t_end = 0.02, 1.0 / 16, 30, 0.0625
     bi = BlockIntegrator(ctx, T(b.pos), T(b.vel), T(b.mass), b.eps2, eta, dt_max, ML, offsets=b.offsets)
@@ -73,6 +78,8 @@ def test_batch_block_steps_follow_per_system_oracle(ctx):
     # block count is at least the largest per-system count
     assert bi.steps >= 1
     assert int(bi.t_tick.min().item()) * bi.tick == t_end
+    ctx.sync()
+    ctx.close()
 
 
 @pytest.mark.parametrize("batch", [False, True])
