@@ -383,16 +383,36 @@ def workloads(args):
             a_ref = a_ref.cpu().numpy()
             for prec, cx in (("fp64", ctx), ("mixed", cmx)):
                 for theta in (0.75, 0.5, 0.4):
-                    acc, pot, st = cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)   # warm-up
+                    # warm-up with the counts (synchronises), then timed calls without them
+                    acc, pot, st = cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
                     for _ in range(args.steps):
-                        acc, pot, st = cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16)
+                        cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16, acc=acc, pot=pot, stats=False)
                     torch.cuda.synchronize()
                     wall = (time.perf_counter() - t0) / args.steps
+                    # the same evaluation replayed from a graph (nothing read on the host)
+                    gs = torch.cuda.Stream(dev)
+                    cx.set_stream(gs)
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g, stream=gs):
+                        cx.tree_forces(P, M, 2.0 ** -16, theta, 16, 1.0 / 16, acc=acc, pot=pot, stats=False)
+                    cx.set_stream(None)
+                    torch.cuda.synchronize()
+                    with torch.cuda.stream(gs):
+                        g.replay()
+                        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                        e0.record(gs)
+                        for _ in range(args.steps):
+                            g.replay()
+                        e1.record(gs)
+                    torch.cuda.synchronize()
+                    ms_graph = e0.elapsed_time(e1) / args.steps
+                    del g
+                    cx.sync()
                     a = acc[sample].cpu().numpy()
                     rel = np.linalg.norm(a - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
-                    res[f"N{n}_theta{theta}_{prec}"] = dict(ms=round(1e3 * wall, 2),
+                    res[f"N{n}_theta{theta}_{prec}"] = dict(ms=round(1e3 * wall, 2), ms_graph=round(ms_graph, 2),
                                                             particles_per_s=round(n / wall, 0),
                                                             acc_rel_err_rms=float(np.sqrt(np.mean(rel ** 2))),
                                                             acc_rel_err_max=float(rel.max()), **st)

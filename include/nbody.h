@@ -132,21 +132,29 @@ const char *nb_version(void);
  * S = j-subsets, one work item each per i-block, whose partial sums a second
  * kernel adds in fixed order (>= 1).  The paper's rule is that the device is
  * saturated once N_i times the number of j-subsets exceeds the number of
- * threads.
+ * threads.  T = j-particles per LDS tile, also the length a j-subset is
+ * rounded up to (S <= ceil(N / T)); WG = threads per workgroup, so an
+ * i-block holds (WG / L) K i-particles (L = 0: WG K).  T and WG = 0 mean
+ * 256, the size every shape is built for; besides that the library builds
+ * (T, WG) = (128, 256), (128, 128) and (64, 64) for (K, L) in {(1, 1),
+ * (1, 4), (1, 16), (2, 1), (2, 4)}, and WG = 128 (T = 256) for the scalar
+ * j-path with K = 1, 2.  eps2 = 0 runs K = 1 with T = WG = 256.
  * nb_set_launch forces one configuration for every later force call
  * (K = 0 returns to automatic choice); nb_get_launch reports the
- * configuration the context would use for (N, n_active). */
-int nb_set_launch(nb_ctx *ctx, int K, int L, int S);
-int nb_get_launch(nb_ctx *ctx, int64_t N, int64_t n_active, int *K, int *L, int *S);
+ * configuration the context would use for (N, n_active) (T and WG may be
+ * NULL).  Errors: NB_EINVAL for values outside the ranges above,
+ * NB_ENOTSUP for a combination the library does not build. */
+int nb_set_launch(nb_ctx *ctx, int K, int L, int S, int T, int WG);
+int nb_get_launch(nb_ctx *ctx, int64_t N, int64_t n_active, int *K, int *L, int *S, int *T, int *WG);
 /* Install one entry of the automatic table: for this precision, N >= n_min
- * and n_active in [act_min, act_max], use K and L, and choose S by the
- * saturation rule aiming at `items` work items (i-blocks x j-subsets;
- * 0 = 4 per compute unit).  The same entry drives host-count and
+ * and n_active in [act_min, act_max], use the shape (K, L, T, WG), and
+ * choose S by the saturation rule aiming at `items` work items (i-blocks x
+ * j-subsets; 0 = 4 per compute unit).  The same entry drives host-count and
  * device-count launches, so both split the work identically.  Later
  * entries take precedence on their range.  Used by the autotuner front end
  * to load its cache. */
 int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int64_t act_max,
-                int K, int L, int items);
+                int K, int L, int items, int T, int WG);
 /* One entry of the batched kernel's table (nbody_forces_batch and
  * nb_block_step_batch use one shape for the whole batch): for this
  * precision, use K and L (L = 0: the scalar j-path, K in {1, 2}; L in
@@ -166,7 +174,7 @@ int nb_tune_clear(nb_ctx *ctx);
  * `reps` launches after one warm-up, on the context stream, with HIP
  * events; returns the mean milliseconds per launch in *ms.  Synchronises
  * the stream.  This is the measurement primitive of the autotuner. */
-int nb_time_forces(nb_ctx *ctx, int K, int L, int S,
+int nb_time_forces(nb_ctx *ctx, int K, int L, int S, int T, int WG,
                    const double *pos, const double *vel, const double *mass, int64_t N,
                    const int32_t *active_idx, int64_t n_active, double eps2,
                    double *acc, double *jerk, double *pot, int reps, double *ms);
@@ -350,15 +358,28 @@ int nb_block_step6(nb_ctx *ctx, int64_t N, double eps2, double eta, double dt_ma
  * theta = 0 opens every leaf: the direct sum.  pos [N][3], mass [N] in,
  * acc [N][3], pot [N] out, all in the caller's order (device pointers).
  * stats (host array of 5, may be NULL): cells, groups, accepted (group, cell)
- * pairs, opened (group, leaf) pairs, depth.  The call synchronises the stream
- * (the host reads one count per tree level) and cannot be captured in a
- * graph (NB_ENOTSUP).  Errors: NB_EINVAL for N outside [1, 2^31), negative
- * or non-finite eps2 or theta, n_crit < 1, non-finite g_frac, null
- * pointers; NB_ENOMEM when device memory runs out or a walk's stack would
- * exceed its bound (8 x 64 x 21 entries, which an octree of 21 levels cannot
- * reach); the outputs are then undefined. */
+ * pairs, opened (group, leaf) pairs, depth.  Nothing is read on the host
+ * while the tree is built (the level bounds stay in device memory and the
+ * buffers are sized from bounds known up front: at most 22 n / (n_crit + 1)
+ * + n + 1 cells), so with stats == NULL the call is asynchronous and can be
+ * captured in a graph, once a call outside the capture has sized the
+ * buffers for this N and n_crit (else NB_ENOTSUP); with stats it
+ * synchronises the stream.  Errors: NB_EINVAL for N outside [1, 2^31),
+ * negative or non-finite eps2 or theta, n_crit < 1, non-finite g_frac, null
+ * pointers; NB_ENOTSUP for stats under capture; NB_ENOMEM when device
+ * memory runs out or a walk's stack would exceed its bound (8 x 64 x 21
+ * entries, which an octree of 21 levels cannot reach) -- reported by this
+ * call when it synchronises, else by the next nb_sync; the outputs are then
+ * undefined. */
 int nb_tree_forces(nb_ctx *ctx, const double *pos, const double *mass, int64_t N, double eps2, double theta,
                    int32_t n_crit, double g_frac, double *acc, double *pot, int64_t *stats);
+/* The tree code's first stage: keys[k] is the 63-bit Peano-Hilbert index of
+ * the k-th particle along the curve and idx[k] its row in pos, i.e. the rows
+ * sorted by (key, row) with the library's stable radix sort (device arrays
+ * of N; same box and key rules as nb_tree_forces).  Asynchronous; not
+ * capturable (NB_ENOTSUP).  Errors: NB_EINVAL for N outside [1, 2^31) or a
+ * null pointer. */
+int nb_tree_keys(nb_ctx *ctx, const double *pos, int64_t N, uint64_t *keys, int32_t *idx);
 
 /* ---- Hamiltonian split (bridge) ------------------------------------------
  * Section "The multi-scale approach" evolves a collisional subsystem c and a

@@ -58,14 +58,15 @@ _sig("nb_set_precision", _vp, _int)
 _sig("nb_workspace_bytes", _vp, ctypes.POINTER(_i64))
 _lib.nb_get_precision.restype = _int
 _lib.nb_get_precision.argtypes = [_vp]
-_sig("nb_set_launch", _vp, _int, _int, _int)
-_sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int))
-_sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int)
+_sig("nb_set_launch", _vp, _int, _int, _int, _int, _int)
+_sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+     ctypes.POINTER(_int), ctypes.POINTER(_int))
+_sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int, _int, _int)
 _sig("nb_tune_add_batch", _vp, _int, _int, _i64, _i64, _int, _int)
 _sig("nb_get_batch_launch", _vp, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_clear", _vp)
 _sig("nb_set_stop_source", _vp, _vp)
-_sig("nb_time_forces", _vp, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
+_sig("nb_time_forces", _vp, _int, _int, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
      ctypes.POINTER(_dbl))
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
 _sig("nbody_forces_noalloc", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
@@ -79,6 +80,7 @@ _sig("hermite6_startup", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _vp)
 _sig("nb_block_step6", _vp, _i64, _dbl, _dbl, _dbl, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
      _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64)
 _sig("nb_tree_forces", _vp, _vp, _vp, _i64, _dbl, _dbl, _i32, _dbl, _vp, _vp, _vp)
+_sig("nb_tree_keys", _vp, _vp, _i64, _vp, _vp)
 _sig("nb_kick", _vp, _vp, _vp, _i64, _dbl)
 _sig("nb_kick_drift", _vp, _vp, _vp, _vp, _i64, _dbl, _dbl)
 _sig("hermite_predict", _vp, _vp, _vp, _vp, _vp, _vp, _i64, _dbl, _i64, _vp, _vp)
@@ -206,18 +208,24 @@ class Context:
         prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
         self._chk(_lib.nb_set_precision(self._h, prec))
 
-    def set_launch(self, K=0, L=1, S=0):
-        self._chk(_lib.nb_set_launch(self._h, int(K), int(L), int(S)))
+    def set_launch(self, K=0, L=1, S=0, T=0, WG=0):
+        """Force (K, L, S) and the tile T / workgroup size WG (0: 256); K = 0 restores automatic choice."""
+        self._chk(_lib.nb_set_launch(self._h, int(K), int(L), int(S), int(T), int(WG)))
+
+    def get_shape(self, N, n_active):
+        """(K, L, S, T, WG) of the launch the context would use."""
+        K, L, S, T, WG = _int(), _int(), _int(), _int(), _int()
+        self._chk(_lib.nb_get_launch(self._h, int(N), int(n_active), ctypes.byref(K), ctypes.byref(L),
+                                     ctypes.byref(S), ctypes.byref(T), ctypes.byref(WG)))
+        return K.value, L.value, S.value, T.value, WG.value
 
     def get_launch(self, N, n_active):
-        K, L, S = _int(), _int(), _int()
-        self._chk(_lib.nb_get_launch(self._h, int(N), int(n_active), ctypes.byref(K), ctypes.byref(L),
-                                     ctypes.byref(S)))
-        return K.value, L.value, S.value
+        return self.get_shape(N, n_active)[:3]
 
-    def tune_add(self, precision, n_min, act_min, act_max, K, L, S=0):
+    def tune_add(self, precision, n_min, act_min, act_max, K, L, S=0, T=0, WG=0):
         prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
-        self._chk(_lib.nb_tune_add(self._h, prec, int(n_min), int(act_min), int(act_max), int(K), int(L), int(S)))
+        self._chk(_lib.nb_tune_add(self._h, prec, int(n_min), int(act_min), int(act_max), int(K), int(L), int(S),
+                                   int(T), int(WG)))
 
     def tune_add_batch(self, precision, kind, key_min, key_max, K, L):
         """kind 1: nbody_forces_batch keyed by mean active rows per system;
@@ -344,11 +352,13 @@ class Context:
                                       _p(acc1), _p(jerk1), _p(snap1), _p(pot1), _p(sched), int(t_stop_tick)))
 
     # ---- tree code --------------------------------------------------------------
-    def tree_forces(self, pos, mass, eps2, theta=0.5, n_crit=16, g_frac=1.0 / 16, acc=None, pot=None):
+    def tree_forces(self, pos, mass, eps2, theta=0.5, n_crit=16, g_frac=1.0 / 16, acc=None, pot=None, stats=True):
         """Barnes-Hut acceleration and potential of every particle (``nb_tree_forces``).
 
         Returns (acc, pot, stats) with stats the numbers of cells, groups,
-        accepted (group, cell) pairs, opened (group, leaf) pairs and the depth."""
+        accepted (group, cell) pairs, opened (group, leaf) pairs and the depth;
+        with stats=False the call does not synchronise (and can be captured)
+        and returns None for them."""
         n = mass.shape[0]
         _check_vec(pos, n, "pos", self.device)
         _check_1d(mass, n, "mass", torch.float64, self.device)
@@ -356,11 +366,21 @@ class Context:
         pot = torch.empty((n,), dtype=torch.float64, device=self.device) if pot is None else pot
         _check_vec(acc, n, "acc", self.device)
         _check_1d(pot, n, "pot", torch.float64, self.device)
-        st = (ctypes.c_int64 * 5)()
+        st = (ctypes.c_int64 * 5)() if stats else None
         self._chk(_lib.nb_tree_forces(self._h, _p(pos), _p(mass), n, float(eps2), float(theta), int(n_crit),
                                       float(g_frac), _p(acc), _p(pot), st))
-        stats = dict(zip(("cells", "groups", "accepted", "opened_leaves", "depth"), list(st)))
-        return acc, pot, stats
+        if not stats:
+            return acc, pot, None
+        return acc, pot, dict(zip(("cells", "groups", "accepted", "opened_leaves", "depth"), list(st)))
+
+    def tree_keys(self, pos):
+        """(keys, idx): the particles' Peano-Hilbert keys in curve order and their rows (``nb_tree_keys``)."""
+        n = pos.shape[0]
+        _check_vec(pos, n, "pos", self.device)
+        keys = torch.empty(n, dtype=torch.int64, device=self.device)
+        idx = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._chk(_lib.nb_tree_keys(self._h, _p(pos), n, _p(keys), _p(idx)))
+        return keys, idx
 
     def kick(self, vel, acc, h):
         """vel += h acc (``nb_kick``)."""
@@ -384,9 +404,9 @@ class Context:
                                              int(max_active), float(eps2), _p(acc), _p(jerk), _p(pot)))
         return acc, jerk, pot
 
-    def time_forces(self, K, L, S, pos, vel, mass, active, eps2, acc, jerk, pot, reps=5):
+    def time_forces(self, K, L, S, pos, vel, mass, active, eps2, acc, jerk, pot, reps=5, T=0, WG=0):
         ms = _dbl()
-        self._chk(_lib.nb_time_forces(self._h, int(K), int(L), int(S), _p(pos), _p(vel), _p(mass),
+        self._chk(_lib.nb_time_forces(self._h, int(K), int(L), int(S), int(T), int(WG), _p(pos), _p(vel), _p(mass),
                                       mass.shape[0], _p(active), active.shape[0], float(eps2), _p(acc), _p(jerk),
                                       _p(pot), int(reps), ctypes.byref(ms)))
         return ms.value

@@ -2,11 +2,14 @@
 
 For each precision and each active-set bucket it times every built
 (K, L) shape over a range of j-subset counts S with ``nb_time_forces`` (HIP
-events on the context stream) and keeps the fastest.  The winner is stored
-as a table entry (K, L, work-item target = S x i-blocks) covering the active
-counts between the geometric midpoints of neighbouring buckets; the library
-derives S from that target with the paper's saturation rule, identically for
-host-count and device-count launches.
+events on the context stream); a second stage times the two fastest shapes
+with every other j-tile length T and workgroup size WG built for them.  The
+winner is stored as a table entry (K, L, T, WG, work-item target = S x
+i-blocks) covering the active counts between the geometric midpoints of
+neighbouring buckets; the library derives S from that target with the
+paper's saturation rule, identically for host-count and device-count
+launches.  ``tune_batch_forces`` and ``tune_batch_steps`` tune the batched
+kernel (the latter inside graph-replayed block steps).
 
 A block step launches one kernel per distinct shape of the table (each
 returns at once unless the device-held count falls in its range), so every
@@ -34,6 +37,11 @@ SHAPES = [(1, 1), (1, 4), (1, 16), (1, 64), (1, 256), (2, 1), (2, 4), (2, 16), (
 BUCKETS = [1, 8, 64, 256, 1024, 4096, 16384, 65536, 262144]
 DEFAULT_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_gfx950.json")
 TILE, WG = 256, 256
+# Second stage: the j-tile length T and workgroup size WG the library builds
+# besides (256, 256), per (K, L) (see nb_set_launch).
+TILE_WG = {(1, 1): [(128, 256), (128, 128), (64, 64)], (1, 4): [(128, 256), (128, 128), (64, 64)],
+           (1, 16): [(128, 256), (128, 128), (64, 64)], (2, 1): [(128, 256), (128, 128), (64, 64)],
+           (2, 4): [(128, 256), (128, 128), (64, 64)], (1, 0): [(256, 128)], (2, 0): [(256, 128)]}
 
 
 # j-split counts tried: every S up to 8, then steps of about a quarter.  The
@@ -43,16 +51,26 @@ TILE, WG = 256, 256
 _S_STEPS = [1, 2, 3, 4, 5, 6, 7, 8, 10, 12, 14, 16, 20, 24, 28, 32, 40, 48, 56, 64, 80, 96, 128, 160, 192, 256]
 
 
-def _s_candidates(n, n_act, K, L, num_cus):
-    ib = (WG // max(L, 1)) * K
+def _s_candidates(n, n_act, K, L, num_cus, tile=TILE, wg=WG):
+    ib = (wg // max(L, 1)) * K
     n_iblk = -(-n_act // ib)
-    max_s = -(-n // TILE)
+    max_s = -(-n // tile)
     out = {0}
     for s in _S_STEPS:
         if s > max_s or n_iblk * s > 32 * num_cus:
             break
         out.add(s)
     return sorted(out), n_iblk
+
+
+def _full(sh):
+    """(K, L) or (K, L, T, WG) -> (K, L, T, WG)."""
+    return tuple(sh) if len(sh) == 4 else (sh[0], sh[1], TILE, WG)
+
+
+def _shape_str(sh):
+    K, L, tl, wg = _full(sh)
+    return f"K={K} L={L} T={tl} WG={wg}"
 
 
 def _midpoints(buckets):
@@ -68,26 +86,66 @@ def _midpoints(buckets):
 LAUNCH_MS = 0.003
 
 
+def _family(sh):
+    """The library's family_of: the LDS kernel family holding a shape (0: none)."""
+    K, L, tl, wg = _full(sh)
+    if tl != TILE or wg != WG or L < 1:
+        return 0
+    if K == 1 and L in (1, 4, 16, 64, 256):
+        return 1
+    if K == 2 and L in (1, 4, 16):
+        return 2
+    if K == 4 and L == 4:
+        return 4
+    return 0
+
+
+def _cover(a, b):
+    """The library's family_cover."""
+    if not a or not b:
+        return 0
+    if a == b or b == 1:
+        return a
+    if a == 1:
+        return b
+    return 0
+
+
+def _launch_runs(choice):
+    """Runs of buckets that share one device-count launch: the same shape, or
+    shapes one kernel family holds.  Returns [(family or None, [buckets])]."""
+    runs = []
+    for b, sh in enumerate(choice):
+        if runs:
+            fam, bs = runs[-1]
+            if choice[bs[-1]] == sh and fam is None:
+                bs.append(b)
+                continue
+            joint = _cover(fam if fam else _family(choice[bs[-1]]), _family(sh))
+            if joint:
+                runs[-1] = (joint, bs + [b])
+                continue
+        runs.append((None, [b]))
+    return runs
+
+
 def _merge_shapes(choice, times, launch_ms):
-    """choice[b]: the (K, L) of bucket b; times[b]: {(K, L): best ms}.  Returns
-    the choice after merging shape runs into neighbours (see module doc)."""
+    """choice[b]: the shape of bucket b; times[b]: {shape: best ms}.  Returns
+    the choice after merging launch runs into neighbours (see module doc): a
+    run whose buckets all take the shape of the neighbouring run's nearest
+    bucket at a cost of at most launch_ms each saves one launch per step."""
     choice = list(choice)
     while True:
-        runs = []
-        for b, sh in enumerate(choice):
-            if runs and runs[-1][0] == sh:
-                runs[-1][1].append(b)
-            else:
-                runs.append((sh, [b]))
+        runs = _launch_runs(choice)
         best = None
-        for r, (sh, bs) in enumerate(runs):
+        for r, (_, bs) in enumerate(runs):
             for q in (r - 1, r + 1):
                 if not 0 <= q < len(runs):
                     continue
-                other = runs[q][0]
+                other = choice[runs[q][1][-1] if q < r else runs[q][1][0]]
                 if not all(other in times[b] for b in bs):
                     continue
-                pen = max(times[b][other] - times[b][sh] for b in bs)
+                pen = max(times[b][other] - times[b][choice[b]] for b in bs)
                 if pen <= launch_ms and (best is None or pen < best[0]):
                     best = (pen, bs, other)
         if best is None:
@@ -126,20 +184,37 @@ def tune(ctx, n, precisions=("fp64", "mixed", "mixed_ds"), buckets=BUCKETS, seed
                     ms = ctx.time_forces(K, L, S, P, V, M, act, eps2, acc, jerk, pot, reps=r)
                     if (K, L) not in per_shape or ms < per_shape[(K, L)][0]:
                         per_shape[(K, L)] = (ms, S, n_iblk)
+            # second stage: the two fastest shapes with every other (T, WG)
+            # built for them, at j-splits around their best (scaled to keep
+            # the work-item count)
+            base = sorted(per_shape.items(), key=lambda kv: kv[1][0])[:2]
+            for (K, L), (ms0, S0, _) in base:
+                for tl, wg in TILE_WG.get((K, L), []):
+                    svals, n_iblk = _s_candidates(n, b, K, L, num_cus, tl, wg)
+                    ib0 = (WG // max(L, 1)) * K
+                    ib = (wg // max(L, 1)) * K
+                    centre = max(1, round(S0 * (-(-b // ib0)) / max(1, -(-b // ib)))) if S0 else 0
+                    near = sorted({0} | {v for v in svals if centre and centre / 2 <= v <= centre * 2})
+                    for S in near:
+                        ms = ctx.time_forces(K, L, S, P, V, M, act, eps2, acc, jerk, pot, reps=reps, T=tl, WG=wg)
+                        key = (K, L, tl, wg)
+                        if key not in per_shape or ms < per_shape[key][0]:
+                            per_shape[key] = (ms, S, n_iblk)
             times.append({sh: v[0] for sh, v in per_shape.items()})
             best_of.append(per_shape)
             sh, v = min(per_shape.items(), key=lambda kv: kv[1][0])
-            log(f"# {prec} N={n} n_active={b}: fastest K={sh[0]} L={sh[1]} S={v[1]} {v[0]:.5f} ms")
+            log(f"# {prec} N={n} n_active={b}: fastest {_shape_str(sh)} S={v[1]} {v[0]:.5f} ms")
         fastest = [min(t, key=t.get) for t in times]
         choice = _merge_shapes(fastest, times, launch_ms)
         for i, (b, (lo, hi)) in enumerate(zip(bks, ranges)):
-            (K, L) = choice[i]
-            ms, S, n_iblk = best_of[i][(K, L)]
+            K, L, tl, wg = _full(choice[i])
+            ms, S, n_iblk = best_of[i][choice[i]]
             items = S * n_iblk if S else 0
-            e = dict(prec=prec, n_min=n, act_min=lo, act_max=hi, K=K, L=L, items=items, ms=round(ms, 5),
-                     rep_n_active=b, gint=round(b * n / ms / 1e6, 2))
+            e = dict(prec=prec, n_min=n, act_min=lo, act_max=hi, K=K, L=L, T=tl, WG=wg, items=items,
+                     ms=round(ms, 5), rep_n_active=b, gint=round(b * n / ms / 1e6, 2))
             if choice[i] != fastest[i]:
-                e["fastest"] = dict(K=fastest[i][0], L=fastest[i][1], ms=round(times[i][fastest[i]], 5))
+                fK, fL, fT, fW = _full(fastest[i])
+                e["fastest"] = dict(K=fK, L=fL, T=fT, WG=fW, ms=round(times[i][fastest[i]], 5))
             entries.append(e)
             log(json.dumps(e))
     return entries
@@ -267,7 +342,8 @@ def load(ctx, path=DEFAULT_TABLE):
         doc = json.load(f)
     single = [e for e in doc["entries"] if e.get("kind", 0) == 0]
     for e in sorted(single, key=lambda e: e["n_min"]):
-        ctx.tune_add(e["prec"], e["n_min"], e["act_min"], e["act_max"], e["K"], e["L"], e["items"])
+        ctx.tune_add(e["prec"], e["n_min"], e["act_min"], e["act_max"], e["K"], e["L"], e["items"],
+                     e.get("T", 0), e.get("WG", 0))
     for e in doc["entries"]:
         if e.get("kind", 0) in (1, 2):
             ctx.tune_add_batch(e["prec"], e["kind"], e["key_min"], e["key_max"], e["K"], e["L"])
@@ -297,22 +373,33 @@ def main():
             entries = json.load(f)["entries"]
     buckets = [b for b in BUCKETS if not args.max_active or b <= args.max_active]
     say = lambda m: print(m, flush=True)
+    props = torch.cuda.get_device_properties(0)
+
+    def checkpoint():
+        # the table so far, after every stage (a long run keeps what it finished)
+        save(entries, args.out, meta={"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
+                                      "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1),
+                                      "forces_hip_sha256": forces_source_hash()})
+
     if args.batch_only:
         entries = [e for e in entries if e.get("kind", 0) == 0]
     else:
         for n in sorted(args.n):
+            entries = [e for e in entries if not (e.get("kind", 0) == 0 and e["n_min"] == n)]
             entries += tune(ctx, n, args.prec, buckets=buckets, reps=args.reps, log=say)
+            checkpoint()
             print(f"# N={n} done after {time.time() - t0:.0f} s", flush=True)
     if args.batch or args.batch_only:
+        entries = [e for e in entries if e.get("kind", 0) != 1]
         entries += tune_batch_forces(ctx, args.prec, reps=args.reps, log=say)
+        checkpoint()
         print(f"# batched forces done after {time.time() - t0:.0f} s", flush=True)
     if args.batch_steps or args.batch_only:
+        entries = [e for e in entries if e.get("kind", 0) != 2]
         entries += tune_batch_steps(ctx, args.prec, log=say)
+        checkpoint()
         print(f"# batched block steps done after {time.time() - t0:.0f} s", flush=True)
-    props = torch.cuda.get_device_properties(0)
-    save(entries, args.out, meta={"device": props.name, "gcn_arch": getattr(props, "gcnArchName", ""),
-                                  "cus": props.multi_processor_count, "seconds": round(time.time() - t0, 1),
-                                  "forces_hip_sha256": forces_source_hash()})
+    checkpoint()
     print(f"wrote {args.out} ({len(entries)} entries)", flush=True)
 
 

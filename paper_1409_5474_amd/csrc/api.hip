@@ -205,10 +205,19 @@ Launch choose(const nb_ctx* c, int64_t n, int64_t n_act) {
   }
   if (cfg.items <= 0) cfg.items = default_items(c, cfg);
   const int IB = nb::ib_of(cfg);
-  if (cfg.S <= 0) cfg.S = nb::host_choose_S(n_act, IB, cfg.items, n);
-  const int64_t max_s = (n + nb::kTile - 1) / nb::kTile;
+  const int tile = cfg.L > 0 ? cfg.T : nb::kTile;
+  if (cfg.S <= 0) cfg.S = nb::host_choose_S(n_act, IB, cfg.items, n, tile);
+  const int64_t max_s = (n + tile - 1) / tile;
   if (cfg.S > max_s) cfg.S = (int)max_s;
   return cfg;
+}
+
+// A launch shape from the ABI's (K, L, T, WG); T, WG = 0 take the defaults.
+Launch make_shape(int K, int L, int S, int items, int T, int WG) {
+  Launch c{K, L, S, items};
+  c.T = T > 0 ? T : nb::kTile;
+  c.WG = WG > 0 ? WG : nb::kWG;
+  return c;
 }
 
 // Shape of the batched force kernel: the last tuned entry of this kind whose
@@ -290,8 +299,7 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
   a.acc = acc; a.jerk = jerk; a.pot = pot; a.part = nullptr; a.s_dev = nullptr; a.wq = c->wq;
   a.row_lo = 0; a.row_hi = n_rows >= 0 ? n_rows : N; a.err = c->wq + nb::kErrorWord;
   const bool mask = kernel_mask(c->prec, eps2);
-  Launch eff = cfg;
-  if (mask) eff.K = 1;
+  const Launch eff = mask ? nb::masked(cfg) : cfg;
   const int max_grid = resident_grid(c, eff, mask);
   if (eff.L <= 0) {
     if (fixed) {
@@ -411,6 +419,9 @@ int nb_sync(nb_ctx* c) {
   e = hipMemsetAsync(c->wq, 0, sizeof words, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "clearing the device work queue");
+  if (bits & nb::kErrTreeStack)
+    return fail(c, NB_ENOMEM, "a tree walk's stack reached its bound since the last nb_sync; its groups' forces "
+                              "were not written%s");
   if (queue_dirty)
     return fail(c, NB_EINVAL,
                 "the work-queue counters were not zero after synchronising: calls on this context overlapped on "
@@ -455,33 +466,35 @@ int nb_get_precision(const nb_ctx* c) { return c ? c->prec : NB_EINVAL; }
 
 const char* nb_last_error(const nb_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
-int nb_set_launch(nb_ctx* c, int K, int L, int S) {
+int nb_set_launch(nb_ctx* c, int K, int L, int S, int T, int WG) {
   if (!c) return NB_EINVAL;
   if (K == 0) {
     c->have_forced = false;
     return NB_OK;
   }
-  if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
-  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  c->forced = Launch{K, L, S, 0};
+  if (!valid_K(K) || !valid_L(L) || S < 0 || T < 0 || WG < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
+  if (!nb::launch_supported(make_shape(K, L, 1, 0, T, WG))) return fail(c, NB_ENOTSUP, "launch shape not built%s");
+  c->forced = make_shape(K, L, S, 0, T, WG);
   c->have_forced = true;
   return NB_OK;
 }
 
-int nb_get_launch(nb_ctx* c, int64_t N, int64_t n_active, int* K, int* L, int* S) {
+int nb_get_launch(nb_ctx* c, int64_t N, int64_t n_active, int* K, int* L, int* S, int* T, int* WG) {
   if (!c || !K || !L || !S || N < 1 || n_active < 0) return NB_EINVAL;
   const Launch cfg = choose(c, N, n_active < 1 ? 1 : n_active);
   *K = cfg.K; *L = cfg.L; *S = cfg.S;
+  if (T) *T = cfg.T;
+  if (WG) *WG = cfg.WG;
   return NB_OK;
 }
 
-int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_t act_max, int K, int L, int S) {  // S: work-item target
+int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_t act_max, int K, int L, int S,
+                int T, int WG) {  // S: work-item target
   if (!c) return NB_EINVAL;
-  if (!valid_prec(precision) || !valid_K(K) || !valid_L(L) || S < 0 ||
-      act_min > act_max)
+  if (!valid_prec(precision) || !valid_K(K) || !valid_L(L) || S < 0 || T < 0 || WG < 0 || act_min > act_max)
     return fail(c, NB_EINVAL, "bad tune entry%s");
-  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, Launch{K, L, 0, S}});
+  if (!nb::launch_supported(make_shape(K, L, 1, 0, T, WG))) return fail(c, NB_ENOTSUP, "launch shape not built%s");
+  c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, make_shape(K, L, 0, S, T, WG)});
   return NB_OK;
 }
 
@@ -575,18 +588,21 @@ int nbody_forces_ij(nb_ctx* c, const double* pos_j, const double* vel_j, const d
                     nullptr, N_i);
 }
 
-int nb_time_forces(nb_ctx* c, int K, int L, int S, const double* pos, const double* vel, const double* mass,
-                   int64_t N, const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk,
-                   double* pot, int reps, double* ms) {
+int nb_time_forces(nb_ctx* c, int K, int L, int S, int T, int WG, const double* pos, const double* vel,
+                   const double* mass, int64_t N, const int32_t* active, int64_t n_active, double eps2, double* acc,
+                   double* jerk, double* pot, int reps, double* ms) {
   int rc = check_forces_args(c, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
   if (rc) return rc;
   if (!ms || reps < 1 || n_active < 1) return fail(c, NB_EINVAL, "reps >= 1, n_active >= 1 and ms required%s");
-  if (!valid_K(K) || !valid_L(L) || S < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
-  if (!nb::launch_supported(Launch{K, L, 1})) return fail(c, NB_ENOTSUP, "K/L combination not built%s");
-  Launch cfg{K, L, S, 0};
+  if (!valid_K(K) || !valid_L(L) || S < 0 || T < 0 || WG < 0) return fail(c, NB_EINVAL, "bad launch configuration%s");
+  Launch cfg = make_shape(K, L, S, 0, T, WG);
+  if (!nb::launch_supported(make_shape(K, L, 1, 0, T, WG))) return fail(c, NB_ENOTSUP, "launch shape not built%s");
+  if (kernel_mask(c->prec, eps2) && !nb::default_tile(cfg))
+    return fail(c, NB_ENOTSUP, "eps2 = 0 runs the default tile and workgroup size only%s");
   cfg.items = default_items(c, cfg);
-  if (cfg.S == 0) cfg.S = nb::host_choose_S(n_active, nb::ib_of(cfg), cfg.items, N);
-  const int64_t max_s = (N + nb::kTile - 1) / nb::kTile;
+  const int tile = cfg.L > 0 ? cfg.T : nb::kTile;
+  if (cfg.S == 0) cfg.S = nb::host_choose_S(n_active, nb::ib_of(cfg), cfg.items, N, tile);
+  const int64_t max_s = (N + tile - 1) / tile;
   if (cfg.S > max_s) cfg.S = (int)max_s;
   rc = run_forces(c, cfg, pos, vel, mass, N, active, n_active, eps2, acc, jerk, pot);
   if (rc) return rc;
@@ -646,15 +662,16 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     int64_t sub_grid[nb::kMaxSubRegimes];  // workgroups the regime can use
     Launch sub_cfg[nb::kMaxSubRegimes];
   };
+  auto fam_of = [](const Launch& x) { return x.L >= 1 && nb::default_tile(x) ? nb::family_of(x.K, x.L) : 0; };
   auto own_rg = [&](const Launch& x) {
     Launch o = x;
-    o.fam = x.L >= 1 ? nb::family_of(x.K, x.L) : 0;
+    o.fam = fam_of(x);
     return resident_grid(c, o, mask);
   };
   std::vector<Group> groups;
   for (const Regime& r : regimes(c, N)) {
     Launch cfg = c->have_forced ? c->forced : r.cfg;
-    if (mask) cfg.K = 1;
+    if (mask) cfg = nb::masked(cfg);
     cfg.fam = 0;
     const int items = cfg.items > 0 ? cfg.items : default_items(c, cfg);
     const int64_t top = r.hi < max_active ? r.hi : max_active;
@@ -664,11 +681,12 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     int fam = 0;
     if (!groups.empty() && groups.back().n_sub < nb::kMaxSubRegimes) {
       const Group& g = groups.back();
-      if (g.r.cfg.fam == 0 && g.r.cfg.K == cfg.K && g.r.cfg.L == cfg.L) {
+      if (g.r.cfg.fam == 0 && g.r.cfg.K == cfg.K && g.r.cfg.L == cfg.L && g.r.cfg.T == cfg.T &&
+          g.r.cfg.WG == cfg.WG) {
         join = true;
       } else if (cfg.L >= 1 && g.r.cfg.L >= 1) {
-        const int theirs = g.r.cfg.fam > 0 ? g.r.cfg.fam : nb::family_of(g.r.cfg.K, g.r.cfg.L);
-        fam = nb::family_cover(theirs, nb::family_of(cfg.K, cfg.L));
+        const int theirs = g.r.cfg.fam > 0 ? g.r.cfg.fam : fam_of(g.r.cfg);
+        fam = nb::family_cover(theirs, fam_of(cfg));
         if (fam) {
           Launch fcfg = cfg;
           fcfg.fam = fam;
@@ -737,7 +755,7 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     if (g.r.lo > max_active) break;
     const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
     Launch cfg = c->have_forced ? c->forced : g.r.cfg;
-    if (mask) cfg.K = 1;
+    if (mask) cfg = nb::masked(cfg);
     nb::ForceArgs a{};
     a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
     a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
@@ -921,11 +939,15 @@ int nb_tree_forces(nb_ctx* c, const double* pos, const double* mass, int64_t N, 
   if (n_crit < 1) return fail(c, NB_EINVAL, "n_crit must be >= 1%s");
   if (!std::isfinite(g_frac)) return fail(c, NB_EINVAL, "g_frac must be finite%s");
   if (!pos || !mass || !acc || !pot) return fail(c, NB_EINVAL, "null pointer%s");
-  if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "the tree code reads counts on the host: no stream capture%s");
+  const bool cap = capturing(c->stream);
+  if (cap && stats) return fail(c, NB_ENOTSUP, "stats need a synchronisation: pass NULL under stream capture%s");
   const char* msg = "";
   nb::TreeStats st{};
   hipError_t e = nb::tree_forces_run(c->tree, c->stream, pos, mass, (int32_t)N, eps2, theta, n_crit, g_frac,
-                                     c->prec != NB_PREC_FP64, acc, pot, &st, &msg);
+                                     c->prec != NB_PREC_FP64, acc, pot, stats ? &st : nullptr, cap,
+                                     c->wq + nb::kErrorWord, &msg);
+  if (e == hipErrorStreamCaptureUnsupported)
+    return fail(c, NB_ENOTSUP, "the tree buffers must grow: call once outside the capture with this N first%s");
   if (e == hipErrorInvalidValue) return fail(c, NB_ENOMEM, "%s", msg);
   if (e != hipSuccess) return hip_fail(c, e, msg);
   if (stats) {
@@ -936,6 +958,16 @@ int nb_tree_forces(nb_ctx* c, const double* pos, const double* mass, int64_t N, 
     stats[4] = st.depth;
   }
   return NB_OK;
+}
+
+int nb_tree_keys(nb_ctx* c, const double* pos, int64_t N, uint64_t* keys, int32_t* idx) {
+  if (!c) return NB_EINVAL;
+  if (N < 1 || N >= ((int64_t)1 << 31)) return fail(c, NB_EINVAL, "N must be in [1, 2^31)%s");
+  if (!pos || !keys || !idx) return fail(c, NB_EINVAL, "null pointer%s");
+  if (capturing(c->stream)) return fail(c, NB_ENOTSUP, "nb_tree_keys cannot be captured%s");
+  const char* msg = "";
+  hipError_t e = nb::tree_sorted_keys(c->tree, c->stream, pos, (int32_t)N, keys, idx, &msg);
+  return e == hipSuccess ? NB_OK : hip_fail(c, e, msg);
 }
 
 int nb_kick(nb_ctx* c, double* vel, const double* acc, int64_t N, double h) {

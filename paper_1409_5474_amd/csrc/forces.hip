@@ -103,12 +103,14 @@ __device__ __forceinline__ void two_sum_add(double& hi, double& lo, double x) {
 // ------------------------------------------------------------------ F64 ----
 struct F64 {
   using T = double;
-  struct JTile {
-    double2 xy[kTile];
-    double2 zm[kTile];
-    double2 vxy[kTile];
-    double vz[kTile];
+  template <int TT>
+  struct JTileT {
+    double2 xy[TT];
+    double2 zm[TT];
+    double2 vxy[TT];
+    double vz[TT];
   };
+  using JTile = JTileT<kTile>;
   struct JReg {
     double x, y, z, vx, vy, vz, m;
   };
@@ -130,7 +132,8 @@ struct F64 {
     }
     return r;
   }
-  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+  template <class Tile>
+  static __device__ __forceinline__ void store(Tile& t, int s, const JReg& r) {
     t.xy[s] = make_double2(r.x, r.y);
     t.zm[s] = make_double2(r.z, r.m);
     t.vxy[s] = make_double2(r.vx, r.vy);
@@ -165,8 +168,8 @@ struct F64 {
     A[5] = fma(mq3, fma(c, dz, uz), A[5]);
     A[6] += mq;
   }
-  template <bool MASK>
-  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+  template <bool MASK, class Tile>
+  static __device__ __forceinline__ void pair_tile(const Tile& t, int s, const IPart* I, T e2, T (*A)[7],
                                                    int kcount) {
     const double2 xy = t.xy[s];
     const double2 zm = t.zm[s];
@@ -204,11 +207,13 @@ struct F64 {
 // ---------------------------------------------------------------- Mixed ----
 struct Mixed {
   using T = float;
-  struct JTile {
-    double2 xy[kTile];
-    double z[kTile];
-    float4 vm[kTile];
+  template <int TT>
+  struct JTileT {
+    double2 xy[TT];
+    double z[TT];
+    float4 vm[TT];
   };
+  using JTile = JTileT<kTile>;
   struct JReg {
     double x, y, z;
     float vx, vy, vz, m;
@@ -233,7 +238,8 @@ struct Mixed {
     }
     return r;
   }
-  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+  template <class Tile>
+  static __device__ __forceinline__ void store(Tile& t, int s, const JReg& r) {
     t.xy[s] = make_double2(r.x, r.y);
     t.z[s] = r.z;
     t.vm[s] = make_float4(r.vx, r.vy, r.vz, r.m);
@@ -272,8 +278,8 @@ struct Mixed {
     // dual-issue
     A[6] = add_nocontract(A[6], mq);
   }
-  template <bool MASK>
-  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+  template <bool MASK, class Tile>
+  static __device__ __forceinline__ void pair_tile(const Tile& t, int s, const IPart* I, T e2, T (*A)[7],
                                                    int kcount) {
     const double2 xy = t.xy[s];
     const double z = t.z[s];
@@ -324,11 +330,13 @@ struct Mixed {
 // conversion.  The error of r stays within a few float ulps of |r|.
 struct MixedDS {
   using T = float;
-  struct JTile {
-    float4 hm[kTile];   // x_hi, y_hi, z_hi, m
-    float4 lv[kTile];   // x_lo, y_lo, z_lo, vx
-    float2 vyz[kTile];  // vy, vz
+  template <int TT>
+  struct JTileT {
+    float4 hm[TT];   // x_hi, y_hi, z_hi, m
+    float4 lv[TT];   // x_lo, y_lo, z_lo, vx
+    float2 vyz[TT];  // vy, vz
   };
+  using JTile = JTileT<kTile>;
   struct JReg {
     float4 hm, lv;
     float2 vyz;
@@ -361,7 +369,8 @@ struct MixedDS {
     }
     return r;
   }
-  static __device__ __forceinline__ void store(JTile& t, int s, const JReg& r) {
+  template <class Tile>
+  static __device__ __forceinline__ void store(Tile& t, int s, const JReg& r) {
     t.hm[s] = r.hm;
     t.lv[s] = r.lv;
     t.vyz[s] = r.vyz;
@@ -399,8 +408,8 @@ struct MixedDS {
     A[5] = fmaf(mq3, fmaf(c, dz, uz), A[5]);
     A[6] = add_nocontract(A[6], mq);
   }
-  template <bool MASK>
-  static __device__ __forceinline__ void pair_tile(const JTile& t, int s, const IPart* I, T e2, T (*A)[7],
+  template <bool MASK, class Tile>
+  static __device__ __forceinline__ void pair_tile(const Tile& t, int s, const IPart* I, T e2, T (*A)[7],
                                                    int kcount) {
     const float4 hm = t.hm[s];
     const float4 lv = t.lv[s];
@@ -443,11 +452,11 @@ struct MixedDS {
 
 // The j-split chosen on the device (device-count mode) and on the host
 // alike: enough work items to fill the chip, chunks of at least one tile.
-__host__ __device__ inline int choose_S(int64_t n_act, int IB, int target_items, int64_t n) {
+__host__ __device__ inline int choose_S(int64_t n_act, int IB, int target_items, int64_t n, int tile = kTile) {
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   if (n_iblk <= 0) return 1;
   int64_t s = (target_items + n_iblk - 1) / n_iblk;
-  const int64_t max_s = (n + kTile - 1) / kTile;
+  const int64_t max_s = (n + tile - 1) / tile;
   if (s > max_s) s = max_s;
   if (s < 1) s = 1;
   return (int)s;
@@ -476,9 +485,9 @@ __device__ __forceinline__ int64_t checked_row(const int32_t* active, int64_t k,
   return -1;
 }
 
-__host__ __device__ inline int64_t chunk_len(int64_t n, int S) {
+__host__ __device__ inline int64_t chunk_len(int64_t n, int S, int tile = kTile) {
   const int64_t per = (n + S - 1) / S;
-  return ((per + kTile - 1) / kTile) * kTile;
+  return ((per + tile - 1) / tile) * tile;
 }
 
 // Work queues of the persistent force grids.  The items -- (i-block,
@@ -567,8 +576,8 @@ __device__ __forceinline__ void queue_done(unsigned int* wq, int64_t items) {
 // Shared body: one workgroup processes one (i-block, j-chunk) item.
 // Outputs: final rows (acc/jerk/pot at out_row0 + k) when `final_out`,
 // otherwise partial sums part[c * n_act + k] for c = 0..6.
-template <class P, int K, int L, bool MASK>
-__device__ __forceinline__ void process_item(typename P::JTile& tile, double* red, const double* __restrict__ pos,
+template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG>
+__device__ __forceinline__ void process_item(typename P::template JTileT<T>& tile, double* red, const double* __restrict__ pos,
                                              const double* __restrict__ vel, const double* __restrict__ mass,
                                              const double* __restrict__ ipos, const double* __restrict__ ivel,
                                              const double* __restrict__ smass,
@@ -577,8 +586,9 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
                                              double* __restrict__ acc, double* __restrict__ jerk,
                                              double* __restrict__ pot, double* __restrict__ part, int64_t row_lo,
                                              int64_t row_hi, unsigned int* err) {
-  constexpr int SLOTS = kWG / L;
-  constexpr int PER = kTile / L;                          // pairs per lane and tile
+  static_assert(L <= T && T <= WG && WG <= kWG, "a tile holds a pair for every lane and one record per thread");
+  constexpr int SLOTS = WG / L;
+  constexpr int PER = T / L;                              // pairs per lane and tile
   constexpr int RUN = P::kRun < PER ? P::kRun : PER;      // pairs per float run
   const int t = threadIdx.x;
   const int slot = t / L;
@@ -603,19 +613,20 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
     for (int c = 0; c < 7; ++c) A[kk][c] = 0;
   }
 
-  typename P::JReg nxt = P::load(pos, vel, mass, jbeg + t, jbeg + t < jend);
-  for (int64_t base = jbeg; base < jend; base += kTile) {
+  // threads t < T stage one record each
+  typename P::JReg nxt = P::load(pos, vel, mass, jbeg + t, t < T && jbeg + t < jend);
+  for (int64_t base = jbeg; base < jend; base += T) {
     __syncthreads();  // every lane is done with the previous tile
-    P::store(tile, t, nxt);
+    if (T == WG || t < T) P::store(tile, t, nxt);
     __syncthreads();
-    const int64_t nb = base + kTile;
-    if (nb < jend) nxt = P::load(pos, vel, mass, nb + t, nb + t < jend);
+    const int64_t nb = base + T;
+    if (nb < jend) nxt = P::load(pos, vel, mass, nb + t, t < T && nb + t < jend);
 #pragma unroll 1
-    for (int jb = 0; jb < kTile; jb += RUN * L) {
+    for (int jb = 0; jb < T; jb += RUN * L) {
 #pragma unroll NB_JJ_UNROLL
       for (int jj = jb + sub; jj < jb + RUN * L; jj += L) P::template pair_tile<MASK>(tile, jj, I, e2, A, K);
       if constexpr (RUN < PER) {
-        if (jb + RUN * L < kTile) {
+        if (jb + RUN * L < T) {
 #pragma unroll
           for (int kk = 0; kk < K; ++kk) P::fold_run(Tt[kk], A[kk]);
         }
@@ -673,21 +684,21 @@ __device__ __forceinline__ void process_item(typename P::JTile& tile, double* re
   }
 }
 
-template <class P, int L>
+template <class P, int L, int T = kTile, int WG = kWG>
 struct Smem {
-  typename P::JTile tile;
-  double red[(L > 64 ? kWG / 64 : 1) * 7];
+  typename P::template JTileT<T> tile;
+  double red[(L > 64 ? WG / 64 : 1) * 7];
 };
 
 // The items of one launch shape: (i-block, j-chunk) pairs taken from the
 // work queue until none is left.
-template <class P, int K, int L, bool MASK>
-__device__ __forceinline__ void run_items(typename P::JTile& tile, double* red, unsigned int& slot,
+template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG>
+__device__ __forceinline__ void run_items(typename P::template JTileT<T>& tile, double* red, unsigned int& slot,
                                           const ForceArgs& a, int64_t n_act, int S) {
-  constexpr int IB = (kWG / L) * K;
+  constexpr int IB = (WG / L) * K;
   const int64_t n_iblk = (n_act + IB - 1) / IB;
   const int64_t items = n_iblk * S;
-  const int64_t clen = chunk_len(a.n, S);
+  const int64_t clen = chunk_len(a.n, S, T);
   if (!queue_member(items)) return;
   int64_t w = queue_take(a.wq, slot, items, blockIdx.x);
   while (w < items) {
@@ -695,7 +706,7 @@ __device__ __forceinline__ void run_items(typename P::JTile& tile, double* red, 
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item<P, K, L, MASK>(tile, red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
+    process_item<P, K, L, MASK, T, WG>(tile, red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
                                 a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
                                 a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi,
                                 a.err);
@@ -704,22 +715,23 @@ __device__ __forceinline__ void run_items(typename P::JTile& tile, double* red, 
   queue_done(a.wq, items);
 }
 
-// One shape (those outside the families below).
-template <class P, int K, int L, bool MASK>
-__global__ __launch_bounds__(kWG) void k_forces(ForceArgs a) {
-  __shared__ Smem<P, L> sm;
+// One shape (those outside the families below), with its j-tile length T
+// and workgroup size WG.
+template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG>
+__global__ __launch_bounds__(WG) void k_forces(ForceArgs a) {
+  __shared__ Smem<P, L, T, WG> sm;
   __shared__ unsigned int slot;
-  constexpr int IB = (kWG / L) * K;
+  constexpr int IB = (WG / L) * K;
   int64_t n_act = a.n_active;
   int S = a.S;
   if (a.n_active_dev) {
     const int64_t d = *a.n_active_dev;
     if (d < a.act_lo || (d > a.n_active && !a.last)) return;  // another regime's launch
     n_act = d < n_act ? (d < 0 ? 0 : d) : n_act;
-    S = choose_S(n_act, IB, target_for(a, d), a.n);
+    S = choose_S(n_act, IB, target_for(a, d), a.n, T);
     if (a.s_dev && blockIdx.x == 0 && threadIdx.x == 0) *a.s_dev = S;  // for the shared reduce
   }
-  run_items<P, K, L, MASK>(sm.tile, sm.red, slot, a, n_act, S);
+  run_items<P, K, L, MASK, T, WG>(sm.tile, sm.red, slot, a, n_act, S);
 }
 
 // The shape of a family launch for count d (unrolled like target_for).
@@ -840,10 +852,14 @@ __global__ __launch_bounds__(kReduceCorrectThreads) void k_reduce_correct(ForceA
   // blocks ahead so the loads of both are in flight together
   const int g = S > 1 ? chunk_lanes(S) : 1;
   const int lane = threadIdx.x & (g - 1);
-  const int64_t grp = ((int64_t)blockIdx.x * kReduceCorrectThreads + threadIdx.x) / g;
-  const int64_t ngrp = ((int64_t)gridDim.x * kReduceCorrectThreads) / g;
+  // wavefronts are dealt to the blocks in turn (a few rows then run on as
+  // many compute units), rows consecutive within a wavefront (coalesced
+  // when g is small)
+  const int rpw = 64 / g;
+  const int64_t wave = (int64_t)(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+  const int64_t nwave = (int64_t)(kReduceCorrectThreads >> 6) * gridDim.x;
   const int64_t stride = 7 * n_act;
-  for (int64_t k = grp; k < n_act; k += ngrp) {
+  for (int64_t k = wave * rpw + (threadIdx.x & 63) / g; k < n_act; k += nwave * rpw) {
     const int64_t i = a.active[k];
     double v[7];
 #pragma unroll
@@ -918,7 +934,7 @@ __global__ __launch_bounds__(256) void k_mirror(const double* __restrict__ pos, 
     rec[j] = P::load(pos, vel, mass, j, j < n);
 }
 
-template <class P, int K, bool MASK>
+template <class P, int K, bool MASK, int WG = kWG>
 __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restrict__ rec,
                                                 const double* __restrict__ ipos, const double* __restrict__ ivel,
                                                 const double* __restrict__ smass, int64_t jbeg, int64_t jend,
@@ -933,7 +949,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
   int64_t irow[K];
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int64_t k = k0 + kk * kWG + t;
+    const int64_t k = k0 + kk * WG + t;
     irow[kk] = (k < n_act) ? checked_row(active, k, row_lo, row_hi, err) : -1;
     I[kk] = P::load_i(ipos, ivel, irow[kk] >= 0 ? irow[kk] : 0);
   }
@@ -990,7 +1006,7 @@ __device__ __forceinline__ void process_item_sj(const typename P::JReg* __restri
   }
 #pragma unroll
   for (int kk = 0; kk < K; ++kk) {
-    const int64_t k = k0 + kk * kWG + t;
+    const int64_t k = k0 + kk * WG + t;
     if (irow[kk] >= 0) {
       double v[7];
 #pragma unroll
@@ -1017,10 +1033,10 @@ struct SjWaves {
   static constexpr int value = (K == 2 && sizeof(typename P::T) == 4) ? 5 : 1;
 };
 
-template <class P, int K, bool MASK>
-__global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(ForceArgs a,
-                                                                        const typename P::JReg* __restrict__ rec) {
-  constexpr int IB = kWG * K;
+template <class P, int K, bool MASK, int WG = kWG>
+__global__ __launch_bounds__(WG, (SjWaves<P, K>::value)) void k_forces_sj(ForceArgs a,
+                                                                       const typename P::JReg* __restrict__ rec) {
+  constexpr int IB = WG * K;
   int64_t n_act = a.n_active;
   int S = a.S;
   if (a.n_active_dev) {
@@ -1041,7 +1057,7 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_sj(Force
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item_sj<P, K, MASK>(rec, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass,
+    process_item_sj<P, K, MASK, WG>(rec, a.ipos ? a.ipos : a.pos, a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass,
                                 jb, je, a.active, n_act, iblk * IB, a.eps2, S == 1,
                                 a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi, a.err);
     w = queue_next(a.wq, slot, items, w + gridDim.x);
@@ -1307,11 +1323,13 @@ __global__ __launch_bounds__(256) void k_batch_reduce_correct(const BatchSys* __
   const int S = nchunk[cs];
   const int g = S > 1 ? chunk_lanes(S) : 1;
   const int lane = threadIdx.x & (g - 1);
-  const int64_t grp = ((int64_t)blockIdx.x * 256 + threadIdx.x) / g;
-  const int64_t ngrp = ((int64_t)gridDim.x * 256) / g;
+  // wavefronts dealt to the system's blocks in turn, rows consecutive within one
+  const int rpw = 64 / g;
+  const int64_t wave = (int64_t)(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
+  const int64_t nwave = (int64_t)4 * gridDim.x;
   const double* pb = part + sy.part_off * 7;
   const int64_t stride = 7 * na;
-  for (int64_t kk = grp; kk < na; kk += ngrp) {
+  for (int64_t kk = wave * rpw + (threadIdx.x & 63) / g; kk < na; kk += nwave * rpw) {
     const int64_t k = sy.a0 + kk;
     const int64_t i = active[k];
     double v[7];
@@ -1512,9 +1530,25 @@ using ForceFn = void (*)(ForceArgs);
 using BatchFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const double*, const double*,
                          const double*, const int32_t*, double*, double*, double*, double*, unsigned int*);
 
+// Shapes with another j-tile length or workgroup size (no masked variant).
+template <class P, int T, int WG>
+ForceFn pick_force_tw(int K, int L) {
+#define NB_CASE(KK, LL) \
+  if (K == KK && L == LL) return k_forces<P, KK, LL, false, T, WG>;
+  NB_CASE(1, 1) NB_CASE(1, 4) NB_CASE(1, 16) NB_CASE(2, 1) NB_CASE(2, 4)
+#undef NB_CASE
+  return nullptr;
+}
+
 // Single-shape kernels: the shapes no family holds.
 template <class P, bool MASK>
-ForceFn pick_force(int K, int L) {
+ForceFn pick_force(int K, int L, int T = kTile, int WG = kWG) {
+  if constexpr (!MASK) {
+    if (T == 128 && WG == 256) return pick_force_tw<P, 128, 256>(K, L);
+    if (T == 128 && WG == 128) return pick_force_tw<P, 128, 128>(K, L);
+    if (T == 64 && WG == 64) return pick_force_tw<P, 64, 64>(K, L);
+  }
+  if (T != kTile || WG != kWG) return nullptr;
 #define NB_CASE(KK, LL) \
   if (K == KK && L == LL) return k_forces<P, KK, LL, MASK>;
   NB_CASE(1, 2) NB_CASE(1, 8) NB_CASE(1, 32) NB_CASE(1, 128)
@@ -1540,15 +1574,23 @@ ForceFn pick_fam(int fam) {
 // family holding it), else its single-shape kernel.
 template <class P, bool MASK>
 ForceFn pick_lds(const Launch& cfg, int K) {
-  const int fam = cfg.fam > 0 ? cfg.fam : family_of(K, cfg.L);
-  return fam ? pick_fam<P, MASK>(fam) : pick_force<P, MASK>(K, cfg.L);
+  const int fam = cfg.fam > 0 ? cfg.fam : (default_tile(cfg) ? family_of(K, cfg.L) : 0);
+  return fam ? pick_fam<P, MASK>(fam) : pick_force<P, MASK>(K, cfg.L, cfg.T, cfg.WG);
 }
 
 template <class P, bool MASK>
 using SjFn = void (*)(ForceArgs, const typename P::JReg*);
 
 template <class P, bool MASK>
-SjFn<P, MASK> pick_sj(int K) {
+SjFn<P, MASK> pick_sj(int K, int WG = kWG) {
+  if (WG == 128) {
+    if constexpr (!MASK) {
+      if (K == 1) return k_forces_sj<P, 1, MASK, 128>;
+      if (K == 2) return k_forces_sj<P, 2, MASK, 128>;
+    }
+    return nullptr;
+  }
+  if (WG != kWG) return nullptr;
   if (K == 1) return k_forces_sj<P, 1, MASK>;
   if constexpr (!MASK) {
     if (K == 2) return k_forces_sj<P, 2, MASK>;
@@ -1559,17 +1601,19 @@ SjFn<P, MASK> pick_sj(int K) {
 }
 
 template <class P, bool MASK>
-hipError_t launch_sj_p(int K, const ForceArgs& a, hipStream_t st, int grid_override, int max_grid) {
-  SjFn<P, MASK> fn = pick_sj<P, MASK>(K);
+hipError_t launch_sj_p(int K, int WG, const ForceArgs& a, hipStream_t st, int grid_override, int max_grid) {
+  SjFn<P, MASK> fn = pick_sj<P, MASK>(K, WG);
   if (!fn || !a.rec) return hipErrorInvalidValue;
   typename P::JReg* rec = static_cast<typename P::JReg*>(a.rec);
   int64_t mg = (a.n + 255) / 256;
   if (mg > 8192) mg = 8192;
   hipLaunchKernelGGL(k_mirror<P>, dim3((int)mg), dim3(256), 0, st, a.pos, a.vel, a.mass, a.n, rec);
-  int grid = grid_override > 0 ? grid_override : items_for(Launch{K, 1, a.S}, a.n_active, a.S);
+  Launch shape{K, 1, a.S};
+  shape.WG = WG;
+  int grid = grid_override > 0 ? grid_override : items_for(shape, a.n_active, a.S);
   if (max_grid > 0 && grid > max_grid) grid = max_grid;
   if (grid <= 0) return hipGetLastError();
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a, rec);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(WG), 0, st, a, rec);
   return hipGetLastError();
 }
 
@@ -1630,9 +1674,11 @@ BatchFn pick_batch(int K, int L) {
 }  // namespace
 
 bool launch_supported(const Launch& c) {
-  if (c.L < 0) return pick_hy(c.K) != nullptr && c.S >= 1;
-  if (c.L == 0) return pick_sj<F64, false>(c.K) != nullptr && c.S >= 1;
-  return (family_of(c.K, c.L) || pick_force<F64, false>(c.K, c.L) != nullptr) && c.S >= 1;
+  if (c.S < 1) return false;
+  if (c.L < 0) return pick_hy(c.K) != nullptr && default_tile(c);
+  if (c.L == 0) return pick_sj<F64, false>(c.K, c.WG) != nullptr && c.T == kTile;
+  if (default_tile(c) && family_of(c.K, c.L)) return true;
+  return pick_force<F64, false>(c.K, c.L, c.T, c.WG) != nullptr;
 }
 
 size_t mirror_bytes(int prec, int64_t n) {
@@ -1646,9 +1692,10 @@ int items_for(const Launch& c, int64_t n_active, int S) {
   return (int)(((n_active + IB - 1) / IB) * S);
 }
 
-hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
+hipError_t launch_forces(int prec, const Launch& cfg_in, bool mask, const ForceArgs& a, hipStream_t st,
                          int grid_override, int max_grid) {
-  const int K = mask ? 1 : cfg.K;
+  const Launch cfg = mask ? masked(cfg_in) : cfg_in;
+  const int K = cfg.K;
   if (cfg.L < 0) {
     // hybrid path: mixed precision with eps2 > 0 only (otherwise the scalar j-path)
     if (prec != NB_PREC_MIXED || mask) {
@@ -1669,14 +1716,15 @@ hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs
     return hipGetLastError();
   }
   if (cfg.L == 0) {
+    const int WG = cfg.WG;
     if (prec == NB_PREC_FP64)
-      return mask ? launch_sj_p<F64, true>(K, a, st, grid_override, max_grid)
-                  : launch_sj_p<F64, false>(K, a, st, grid_override, max_grid);
+      return mask ? launch_sj_p<F64, true>(K, WG, a, st, grid_override, max_grid)
+                  : launch_sj_p<F64, false>(K, WG, a, st, grid_override, max_grid);
     if (prec == NB_PREC_MIXED_DS)
-      return mask ? launch_sj_p<MixedDS, true>(K, a, st, grid_override, max_grid)
-                  : launch_sj_p<MixedDS, false>(K, a, st, grid_override, max_grid);
-    return mask ? launch_sj_p<Mixed, true>(K, a, st, grid_override, max_grid)
-                : launch_sj_p<Mixed, false>(K, a, st, grid_override, max_grid);
+      return mask ? launch_sj_p<MixedDS, true>(K, WG, a, st, grid_override, max_grid)
+                  : launch_sj_p<MixedDS, false>(K, WG, a, st, grid_override, max_grid);
+    return mask ? launch_sj_p<Mixed, true>(K, WG, a, st, grid_override, max_grid)
+                : launch_sj_p<Mixed, false>(K, WG, a, st, grid_override, max_grid);
   }
   ForceFn fn = nullptr;
   if (prec == NB_PREC_FP64)
@@ -1686,16 +1734,18 @@ hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs
   else
     fn = mask ? pick_lds<Mixed, true>(cfg, K) : pick_lds<Mixed, false>(cfg, K);
   if (!fn) return hipErrorInvalidValue;
-  int grid = grid_override > 0 ? grid_override : items_for(Launch{K, cfg.L, a.S}, a.n_active, a.S);
+  Launch shape = cfg;
+  shape.S = a.S;
+  int grid = grid_override > 0 ? grid_override : items_for(shape, a.n_active, a.S);
   if (max_grid > 0 && grid > max_grid) grid = max_grid;
   if (grid <= 0) return hipSuccess;
   if (a.n_sub == 0 && a.shape == 0) {
     // a host-chosen shape: the family kernel runs the body of this shape
     ForceArgs b = a;
     b.shape = shape_code(K, cfg.L);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, b);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.WG), 0, st, b);
   } else {
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, a);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.WG), 0, st, a);
   }
   return hipGetLastError();
 }
@@ -1703,20 +1753,21 @@ hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs
 // Workgroups of this kernel that one compute unit holds at once (from the
 // occupancy calculator, cached per kernel).  A grid of num_CUs times this
 // runs as one round, with no tail of lightly loaded SIMDs.
-int resident_wgs(int prec, const Launch& cfg, bool mask) {
+int resident_wgs(int prec, const Launch& cfg_in, bool mask) {
   static std::mutex mu;
   static std::map<const void*, int> cache;
-  const int K = mask ? 1 : cfg.K;
+  const Launch cfg = mask ? masked(cfg_in) : cfg_in;
+  const int K = cfg.K;
   const void* fn = nullptr;
   if (cfg.L < 0 && prec == NB_PREC_MIXED && !mask) {
     fn = (const void*)pick_hy(K);
   } else if (cfg.L <= 0) {
     if (prec == NB_PREC_FP64)
-      fn = mask ? (const void*)pick_sj<F64, true>(K) : (const void*)pick_sj<F64, false>(K);
+      fn = mask ? (const void*)pick_sj<F64, true>(K, cfg.WG) : (const void*)pick_sj<F64, false>(K, cfg.WG);
     else if (prec == NB_PREC_MIXED_DS)
-      fn = mask ? (const void*)pick_sj<MixedDS, true>(K) : (const void*)pick_sj<MixedDS, false>(K);
+      fn = mask ? (const void*)pick_sj<MixedDS, true>(K, cfg.WG) : (const void*)pick_sj<MixedDS, false>(K, cfg.WG);
     else
-      fn = mask ? (const void*)pick_sj<Mixed, true>(K) : (const void*)pick_sj<Mixed, false>(K);
+      fn = mask ? (const void*)pick_sj<Mixed, true>(K, cfg.WG) : (const void*)pick_sj<Mixed, false>(K, cfg.WG);
   } else if (prec == NB_PREC_FP64) {
     fn = mask ? (const void*)pick_lds<F64, true>(cfg, K) : (const void*)pick_lds<F64, false>(cfg, K);
   } else if (prec == NB_PREC_MIXED_DS) {
@@ -1729,7 +1780,7 @@ int resident_wgs(int prec, const Launch& cfg, bool mask) {
   auto it = cache.find(reinterpret_cast<const void*>(fn));
   if (it != cache.end()) return it->second;
   int nblk = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, kWG, 0) != hipSuccess || nblk < 1) {
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, cfg.WG, 0) != hipSuccess || nblk < 1) {
     (void)hipGetLastError();
     nblk = 1;
   }
@@ -1868,8 +1919,8 @@ hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, cons
   return hipGetLastError();
 }
 
-int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n) {
-  return choose_S(n_act, IB, target_items, n);
+int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n, int tile) {
+  return choose_S(n_act, IB, target_items, n, tile);
 }
 
 }  // namespace nb

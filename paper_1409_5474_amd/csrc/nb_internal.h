@@ -16,6 +16,7 @@ constexpr int kWorkQueueWords = 16;  // words of a context's work queue (9 used)
 constexpr int kMaxSubRegimes = 16;   // active-count regimes one device-count launch can serve
 constexpr int kErrorWord = kWorkQueueWords - 1;  // word of that buffer holding the device error bits
 constexpr unsigned int kErrActiveRange = 1u;     // an active_idx entry outside its valid range was skipped
+constexpr unsigned int kErrTreeStack = 2u;       // a tree walk's stack reached its bound (its group unwritten)
 
 // The range test of every kernel that reads an i-set entry: r must lie in
 // [lo, hi).  Host and device share it, so a host test exercises this code.
@@ -29,7 +30,20 @@ struct Launch {
   int items = 0;  // work-item target of the saturation rule (0: 4 per CU)
   int fam = 0;    // > 0: run in the LDS kernel family `fam`, which holds this
                   // shape and, in device-count mode, every shape of the call
+  int T = kTile;  // j-particles per LDS tile (L >= 1), also the j-chunk quantum
+  int WG = kWG;   // threads per workgroup
 };
+
+// The LDS tile length and workgroup size every kernel family, the masked
+// (eps2 = 0) kernels and the hybrid path are built for.
+inline bool default_tile(const Launch& c) { return c.T == kTile && c.WG == kWG; }
+// eps2 == 0 runs the masked kernels: one i-particle per lane, default tile.
+inline Launch masked(Launch c) {
+  c.K = 1;
+  c.T = kTile;
+  c.WG = kWG;
+  return c;
+}
 
 // LDS kernel families: one kernel holding the bodies of several (K, L)
 // shapes, so that device-count regimes of different shapes share one launch
@@ -55,7 +69,7 @@ __host__ __device__ constexpr int shape_code(int K, int L) { return (K << 16) | 
 
 // i-particles per workgroup of a launch shape (L = 0: the scalar j-path,
 // one i-slot per lane like L = 1).
-inline int ib_of(const Launch& c) { return (kWG / (c.L > 0 ? c.L : 1)) * c.K; }
+inline int ib_of(const Launch& c) { return (c.WG / (c.L > 0 ? c.L : 1)) * c.K; }
 
 // Lanes that share one output of a j-split sum over S partial blocks: the
 // fewest (a power of two, at most a wavefront) with no lane adding more than
@@ -188,7 +202,7 @@ hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs
 int resident_wgs(int prec, const Launch& cfg, bool mask);
 size_t mirror_bytes(int prec, int64_t n);  // j-record mirror of the scalar j-path
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st);
-int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n);
+int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n, int tile);
 bool launch_supported(const Launch& cfg);
 int items_for(const Launch& cfg, int64_t n_active, int S);
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,
@@ -288,9 +302,17 @@ struct TreeScratch {
   std::vector<std::pair<void*, size_t>> slots;
   void* host = nullptr;    // pinned, for the per-level counts
 };
+// The whole evaluation is enqueued without host reads; with `stats` set it
+// then synchronises and reads the counts (and reports a stack overflow as
+// hipErrorInvalidValue).  `capturing`: no buffer may grow (a call outside the
+// capture sizes them); a stack overflow is then flagged in *err only.
 hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
                            double eps2, double theta, int n_crit, double g_frac, bool mixed, double* acc,
-                           double* pot, TreeStats* stats, const char** msg);
+                           double* pot, TreeStats* stats, bool capturing, unsigned int* err, const char** msg);
+// The Peano-Hilbert keys of the positions in curve order and the input row
+// of each (the tree code's first stage).
+hipError_t tree_sorted_keys(TreeScratch& s, hipStream_t st, const double* pos, int32_t n, uint64_t* keys_out,
+                            int32_t* idx_out, const char** msg);
 void tree_scratch_free(TreeScratch& s);
 
 // Sixth-order force kernel (forces6.hip).

@@ -23,10 +23,12 @@
 //    Q = sum m (3 d d^T - |d|^2 I) about the centre of mass X
 //
 // Structure on the chip: the build is level-synchronous and data-parallel
-// -- one thread per particle or per cell, with stable scans (hipCUB) placing
-// the outputs, so every array keeps curve order and the results are
-// reproducible run to run; the host reads one count per level to size the
-// next launch.  The walk and the force evaluation are one kernel, as in the
+// -- one thread per particle or per cell, with the library's own stable
+// radix sort and exclusive scans placing the outputs, so every array keeps
+// curve order and the results are reproducible run to run.  The level
+// bounds stay in device memory and the buffers are sized from bounds known
+// up front, so nothing is read on the host until the forces are written and
+// a whole evaluation can be captured in a graph.  The walk and the force evaluation are one kernel, as in the
 // paper's GPU tree code: one wavefront per group walks the tree for its 64
 // particles and evaluates accepted cells and opened leaves 64 at a time from
 // LDS as it finds them, so no interaction list is written to memory.  The
@@ -35,8 +37,6 @@
 // with the context's precision.  The opening test and the cube geometry are
 // computed without fused multiply-adds, in the order stated above, so they
 // match any implementation that rounds each operation.
-#include <hipcub/hipcub.hpp>
-
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -47,6 +47,7 @@ namespace nb {
 namespace {
 
 constexpr int kBits = 21;
+constexpr int kLevels = kBits + 1;  // cell levels 0 .. kBits
 constexpr int kTB = 256;   // threads per block of the element-wise kernels
 constexpr int kGS = 64;    // particles per group (one wavefront)
 
@@ -202,9 +203,13 @@ __device__ __forceinline__ void set_geometry(TreeCell& c, const int32_t* ijk_s, 
   c.side = ldexp(b.h, shift);
 }
 
+// The root, and the level table: the cells of level l are [lvl[l], lvl[l+1])
+// (kept in device memory, so no count goes to the host while the tree grows).
 __global__ void k_root(TreeCell* __restrict__ cells, int32_t n, const int32_t* __restrict__ ijk_s,
-                       const Box* __restrict__ box) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                       const Box* __restrict__ box, int32_t* __restrict__ lvl) {
+  if (blockIdx.x != 0) return;
+  for (int l = threadIdx.x; l < kLevels + 1; l += blockDim.x) lvl[l] = l == 0 ? 0 : 1;
+  if (threadIdx.x != 0) return;
   TreeCell c{};
   c.begin = 0; c.end = n; c.child0 = -1; c.nchild = 0; c.level = 0;
   set_geometry(c, ijk_s, *box);
@@ -227,9 +232,12 @@ __device__ __forceinline__ int32_t lower_bound_key(const uint64_t* keys, int32_t
 // level l covers the keys [(p<<3|k) << s, (p<<3|k)+1 << s), s = 3(20 - l),
 // and the last child ends with the cell), and the cell's count of non-empty
 // children is summed over the eight lanes.
-__global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restrict__ cells, int32_t ncell,
+__global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restrict__ all_cells,
+                                                        const int32_t* __restrict__ lvl, int l,
                                                         const uint64_t* __restrict__ keys, int n_crit,
                                                         int32_t* __restrict__ cnt, int32_t* __restrict__ ends) {
+  const TreeCell* cells = all_cells + lvl[l];
+  const int32_t ncell = lvl[l + 1] - lvl[l];
   const int64_t total = 8 * (int64_t)ncell;  // whole groups of eight lanes
   for (int64_t t = (int64_t)blockIdx.x * kTB + threadIdx.x; t < total; t += (int64_t)gridDim.x * kTB) {
     const int32_t i = (int32_t)(t >> 3);
@@ -254,12 +262,15 @@ __global__ __launch_bounds__(kTB) void k_count_children(const TreeCell* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) cnt[ncell] = 0;
 }
 
-__global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
+__global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ cells, int32_t* __restrict__ lvl, int l,
                                                         const int32_t* __restrict__ ends,
                                                         const int32_t* __restrict__ ijk_s,
                                                         const Box* __restrict__ box, int n_crit,
-                                                        const int32_t* __restrict__ off, int32_t next) {
+                                                        const int32_t* __restrict__ off) {
+  const int32_t first = lvl[l], next = lvl[l + 1], ncell = next - first;
   const Box bx = *box;
+  // the next level's cells follow this one's; off[ncell] is their number
+  if (blockIdx.x == 0 && threadIdx.x == 0) lvl[l + 2] = next + off[ncell];
   for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
     TreeCell& c = cells[first + i];
     if (!(c.end - c.begin > n_crit && c.level < kBits)) {
@@ -286,8 +297,9 @@ __global__ __launch_bounds__(kTB) void k_write_children(TreeCell* __restrict__ c
 }
 
 // Moments: leaves from their particles, internal cells from their children.
-__global__ __launch_bounds__(kTB) void k_moments(TreeCell* __restrict__ cells, int32_t first, int32_t ncell,
+__global__ __launch_bounds__(kTB) void k_moments(TreeCell* __restrict__ cells, const int32_t* __restrict__ lvl, int l,
                                                  const double* __restrict__ pos_s, const double* __restrict__ mass_s) {
+  const int32_t first = lvl[l], ncell = lvl[l + 1] - lvl[l];
   for (int32_t i = blockIdx.x * kTB + threadIdx.x; i < ncell; i += gridDim.x * kTB) {
     TreeCell& c = cells[first + i];
     double M = 0.0, S[3] = {0.0, 0.0, 0.0}, Q[6] = {0, 0, 0, 0, 0, 0}, X[3];
@@ -436,8 +448,9 @@ __global__ __launch_bounds__(kTB) void k_groups(int32_t n, int32_t nchunk, const
 }
 
 __global__ __launch_bounds__(kTB) void k_group_box(const int32_t* __restrict__ gb, const int32_t* __restrict__ ge,
-                                                   int32_t ng, const double* __restrict__ pos_s,
+                                                   const int32_t* __restrict__ ng_dev, const double* __restrict__ pos_s,
                                                    double* __restrict__ gbox) {
+  const int32_t ng = *ng_dev;
   for (int32_t g = blockIdx.x * kTB + threadIdx.x; g < ng; g += gridDim.x * kTB) {
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int32_t j = gb[g]; j < ge[g]; ++j)
@@ -702,7 +715,8 @@ __device__ __forceinline__ void shift_list(int32_t* list, int n, int lane) {
 // (group, leaf) pairs, [3]: stack overflow flag
 template <bool MIXED>
 __global__ __launch_bounds__(kGS, NB_TREE_WAVES) void k_tree_walk_forces(const int32_t* __restrict__ gb,
-                                                          const int32_t* __restrict__ ge, int32_t ngroups,
+                                                          const int32_t* __restrict__ ge,
+                                                          const int32_t* __restrict__ ngroups_dev,
                                                           const double* __restrict__ gbox,
                                                           const TreeCell* __restrict__ cells, double theta,
                                                           const double* __restrict__ pos_s,
@@ -710,9 +724,11 @@ __global__ __launch_bounds__(kGS, NB_TREE_WAVES) void k_tree_walk_forces(const i
                                                           const int32_t* __restrict__ idx_s,
                                                           int32_t* __restrict__ stack_all, int32_t stack_cap,
                                                           unsigned long long* __restrict__ counters,
+                                                          unsigned int* __restrict__ err,
                                                           double* __restrict__ acc, double* __restrict__ pot) {
   __shared__ WalkLds<MIXED> L;
   const int lane = threadIdx.x;
+  const int32_t ngroups = *ngroups_dev;
   int32_t* stack = stack_all + (int64_t)blockIdx.x * stack_cap;
   const int32_t root_child0 = cells[0].child0, root_nchild = cells[0].nchild;
   for (;;) {
@@ -803,7 +819,10 @@ __global__ __launch_bounds__(kGS, NB_TREE_WAVES) void k_tree_walk_forces(const i
     if (lane == 0) {
       atomicAdd(&counters[1], tot_acc);
       atomicAdd(&counters[2], tot_leaf);
-      if (overflow) atomicOr(&counters[3], 1ull);
+      if (overflow) {
+        atomicOr(&counters[3], 1ull);
+        if (err) atomicOr(err, kErrTreeStack);
+      }
     }
     __syncthreads();
   }
@@ -813,18 +832,163 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
   if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
+// ---------------------------------------------------------------- scans -----
+// Exclusive prefix sum of n int32 counts by one workgroup (out may be in):
+// each thread sums a contiguous segment, the segment sums are scanned in LDS,
+// then each thread writes its segment's running sums.  n is n_host, or, when
+// lvl is set, the cell count of level l plus one (the extra zero count makes
+// the last entry the level's total).
+constexpr int kScanThreads = 1024;
+
+__global__ __launch_bounds__(kScanThreads) void k_exscan(const int32_t* in, int32_t* out, int64_t n_host,
+                                                         const int32_t* __restrict__ lvl, int l) {
+  __shared__ int64_t part[kScanThreads];
+  const int64_t n = lvl ? (int64_t)(lvl[l + 1] - lvl[l]) + 1 : n_host;
+  const int t = threadIdx.x;
+  const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+  const int64_t b = t * per, e = b + per < n ? b + per : n;
+  // segments are read eight entries at a time, so eight loads are in flight
+  constexpr int B = 8;
+  int64_t sum = 0;
+  for (int64_t k = b; k < e; k += B) {
+    int32_t v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = k + j < e ? in[k + j] : 0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) sum += v[j];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const int64_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - sum;
+  for (int64_t k = b; k < e; k += B) {
+    int32_t v[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) v[j] = k + j < e ? in[k + j] : 0;
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      if (k + j < e) out[k + j] = (int32_t)run;
+      run += v[j];
+    }
+  }
+}
+
+// ----------------------------------------------------------- radix sort -----
+// Stable least-significant-digit radix sort of (key, row) pairs, 8 bits per
+// pass.  A pass: each tile of kRsTile keys counts its digits (k_rs_hist);
+// one exclusive scan over the counts in digit-major order gives every
+// (digit, tile) its first output slot; each tile then writes its keys there
+// (k_rs_scatter), a key's place among the equal digits of its tile being
+// the number of such keys before it.  Within a tile, wavefront w takes the
+// w-th quarter in rounds of 64 consecutive keys; the lanes of a round that
+// share a digit find each other with eight ballots (one per digit bit), and
+// a per-wavefront count of each digit carries over between rounds, so the
+// order among equal digits is the input order.
+constexpr int kRsBits = 8;
+constexpr int kRsBuckets = 1 << kRsBits;
+constexpr int kRsThreads = 256;
+constexpr int kRsRounds = 8;                                 // rounds of 64 keys per wavefront
+constexpr int kRsTile = (kRsThreads / 64) * 64 * kRsRounds;  // 2048 keys per tile
+static_assert(kRsBuckets == kRsThreads, "one thread per digit in the tile tables");
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restrict__ keys, int32_t n, int shift,
+                                                        int32_t* __restrict__ hist, int32_t ntile) {
+  __shared__ int32_t h[kRsBuckets];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsTile / kRsThreads; ++r) {
+    const int64_t i = base + r * kRsThreads + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & (kRsBuckets - 1)], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
+                                                           const int32_t* __restrict__ vin,
+                                                           uint64_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                                           int32_t n, int shift, const int32_t* __restrict__ offs,
+                                                           int32_t ntile) {
+  __shared__ int32_t first[kRsBuckets];          // the tile's first output slot of each digit
+  __shared__ int32_t wcnt[kRsThreads / 64][kRsBuckets];
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  first[t] = offs[(int64_t)t * ntile + blockIdx.x];
+  for (int q = 0; q < kRsThreads / 64; ++q) wcnt[q][t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * 64 * kRsRounds;
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint64_t key[kRsRounds];
+  int32_t val[kRsRounds], rank[kRsRounds];
+  int dig[kRsRounds];
+#pragma unroll
+  for (int r = 0; r < kRsRounds; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    const bool valid = i < n;
+    key[r] = valid ? kin[i] : 0ull;
+    val[r] = valid ? vin[i] : 0;
+    const int d = (int)((key[r] >> shift) & (kRsBuckets - 1));
+    dig[r] = d;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRsBits; ++b) {
+      const bool bit = (d >> b) & 1;
+      const uint64_t m = __ballot(bit);
+      peers &= bit ? m : ~m;
+    }
+    const int before = __popcll(peers & below);
+    const int run = valid ? wcnt[w][d] : 0;
+    rank[r] = run + before;
+    if (valid && before == 0) wcnt[w][d] = run + __popcll(peers);  // the group's first lane
+  }
+  __syncthreads();
+  // per digit, where each wavefront's keys start within the tile
+  int32_t acc = 0;
+  for (int q = 0; q < kRsThreads / 64; ++q) {
+    const int32_t c = wcnt[q][t];
+    wcnt[q][t] = acc;
+    acc += c;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRsRounds; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    if (i < n) {
+      const int32_t dst = first[dig[r]] + wcnt[w][dig[r]] + rank[r];
+      kout[dst] = key[r];
+      vout[dst] = val[r];
+    }
+  }
+}
+
 // ------------------------------------------------------- host helpers -----
 struct Alloc {
   TreeScratch& s;
   hipStream_t st;
+  bool capturing;
   hipError_t err = hipSuccess;
   template <class T>
   T* get(int slot, int64_t count) {
     if (err != hipSuccess) return nullptr;
     const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    if ((int)s.slots.size() <= slot) s.slots.resize(slot + 1, {nullptr, 0});
+    if ((int)s.slots.size() <= slot) {
+      if (capturing) {
+        err = hipErrorStreamCaptureUnsupported;
+        return nullptr;
+      }
+      s.slots.resize(slot + 1, {nullptr, 0});
+    }
     auto& sl = s.slots[slot];
     if (sl.second < bytes) {
+      if (capturing) {  // no allocation inside a capture: a call outside it sizes the buffers
+        err = hipErrorStreamCaptureUnsupported;
+        return nullptr;
+      }
       if (sl.first) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(sl.first);
@@ -842,36 +1006,44 @@ struct Alloc {
 
 enum Slot {
   S_BOXPART, S_BOX, S_KEYS, S_KEYS2, S_IDX, S_IDX2, S_POS, S_MASS, S_IJK, S_CELLS, S_CNT, S_OFF, S_TMP,
-  S_GB, S_GE, S_GN, S_GBOX, S_STACK, S_CTR, S_ENDS
+  S_GB, S_GE, S_GN, S_GBOX, S_STACK, S_CTR, S_ENDS, S_LVL, S_HIST
 };
 
-template <class T>
-hipError_t exclusive_sum(Alloc& al, const T* in, T* out, int64_t n) {
-  size_t bytes = 0;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, in, out, n, al.st);
-  if (e != hipSuccess) return e;
-  void* tmp = al.get<char>(S_TMP, (int64_t)bytes);
-  if (!tmp) return al.err;
-  return hipcub::DeviceScan::ExclusiveSum(tmp, bytes, in, out, n, al.st);
+hipError_t exclusive_sum(hipStream_t st, const int32_t* in, int32_t* out, int64_t n) {
+  hipLaunchKernelGGL(k_exscan, dim3(1), dim3(kScanThreads), 0, st, in, out, n, nullptr, 0);
+  return hipGetLastError();
 }
 
-template <class K, class V>
-hipError_t sort_pairs(Alloc& al, const K* kin, K* kout, const V* vin, V* vout, int64_t n, int end_bit) {
-  size_t bytes = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, n, 0, end_bit, al.st);
-  if (e != hipSuccess) return e;
-  void* tmp = al.get<char>(S_TMP, (int64_t)bytes);
-  if (!tmp) return al.err;
-  return hipcub::DeviceRadixSort::SortPairs(tmp, bytes, kin, kout, vin, vout, n, 0, end_bit, al.st);
+// Sort (keys, idx) by the low `bits` bits of the keys; returns the buffers
+// holding the result (the inputs or the alternates, which are overwritten).
+hipError_t radix_sort(Alloc& al, uint64_t* keys, int32_t* idx, uint64_t* keys2, int32_t* idx2, int32_t n, int bits,
+                      uint64_t** keys_out, int32_t** idx_out) {
+  const int32_t ntile = (n + kRsTile - 1) / kRsTile;
+  int32_t* hist = al.get<int32_t>(S_HIST, (int64_t)kRsBuckets * ntile);
+  if (!hist) return al.err != hipSuccess ? al.err : hipErrorOutOfMemory;
+  uint64_t *ka = keys, *kb = keys2;
+  int32_t *va = idx, *vb = idx2;
+  for (int shift = 0; shift < bits; shift += kRsBits) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(ntile), dim3(kRsThreads), 0, al.st, ka, n, shift, hist, ntile);
+    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(kScanThreads), 0, al.st, hist, hist, (int64_t)kRsBuckets * ntile,
+                       nullptr, 0);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntile), dim3(kRsThreads), 0, al.st, ka, va, kb, vb, n, shift, hist, ntile);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  *keys_out = ka;
+  *idx_out = va;
+  return hipGetLastError();
 }
 
-// the entry at `pos` of a device array, read to the host (synchronises)
+// the entries at `pos`... of a device array, read to the host (synchronises)
 template <class T>
-hipError_t read_entry(TreeScratch& s, hipStream_t st, const T* a, int64_t pos, int64_t* out) {
+hipError_t read_entries(TreeScratch& s, hipStream_t st, const T* a, int64_t count, T* out) {
   T* h = static_cast<T*>(s.host);
-  hipError_t e = hipMemcpyAsync(h, a + pos, sizeof(T), hipMemcpyDeviceToHost, st);
+  hipError_t e = hipMemcpyAsync(h, a, count * sizeof(T), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e == hipSuccess) *out = (int64_t)h[0];
+  if (e == hipSuccess)
+    for (int64_t k = 0; k < count; ++k) out[k] = h[k];
   return e;
 }
 
@@ -886,110 +1058,114 @@ hipError_t read_entry(TreeScratch& s, hipStream_t st, const T* a, int64_t pos, i
     }                             \
   } while (0)
 
-hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
-                           double eps2, double theta, int n_crit, double g_frac, bool mixed, double* acc,
-                           double* pot, TreeStats* stats, const char** msg) {
-  *msg = "";
-  if (!s.host) NB_TRY(hipHostMalloc(&s.host, 64 * sizeof(int64_t), hipHostMallocDefault));
-  Alloc al{s, st};
-  auto need = [&](void* p) -> hipError_t { return p ? hipSuccess : (al.err != hipSuccess ? al.err : hipErrorOutOfMemory); };
+namespace {
 
-  // box, keys, sort along the curve
+// box, keys, the sort along the curve; sorted keys and rows go to *keys_s, *idx_s
+hipError_t keys_and_order(Alloc& al, const double* pos, int32_t n, Box** box_out, uint64_t** keys_s,
+                          int32_t** idx_s, const char** msg) {
+  auto need = [&](void* p) -> hipError_t { return p ? hipSuccess : (al.err != hipSuccess ? al.err : hipErrorOutOfMemory); };
   const int nbb = blocks_for(n, 1024);
   double* part = al.get<double>(S_BOXPART, 6 * nbb);
   Box* box = al.get<Box>(S_BOX, 1);
   uint64_t* keys = al.get<uint64_t>(S_KEYS, n);
-  uint64_t* keys_s = al.get<uint64_t>(S_KEYS2, n);
+  uint64_t* keys2 = al.get<uint64_t>(S_KEYS2, n);
   int32_t* idx = al.get<int32_t>(S_IDX, n);
-  int32_t* idx_s = al.get<int32_t>(S_IDX2, n);
+  int32_t* idx2 = al.get<int32_t>(S_IDX2, n);
+  NB_TRY(need(idx2));
+  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kTB), 0, al.st, pos, (int64_t)n, part);
+  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kTB), 0, al.st, part, nbb, box);
+  hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kTB), 0, al.st, pos, (int64_t)n, box, keys, idx);
+  NB_TRY(hipGetLastError());
+  NB_TRY(radix_sort(al, keys, idx, keys2, idx2, n, 3 * kBits, keys_s, idx_s));
+  *box_out = box;
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t tree_sorted_keys(TreeScratch& s, hipStream_t st, const double* pos, int32_t n, uint64_t* keys_out,
+                            int32_t* idx_out, const char** msg) {
+  *msg = "";
+  Alloc al{s, st, false};
+  Box* box = nullptr;
+  uint64_t* keys_s = nullptr;
+  int32_t* idx_s = nullptr;
+  hipError_t e = keys_and_order(al, pos, n, &box, &keys_s, &idx_s, msg);
+  if (e != hipSuccess) return e;
+  NB_TRY(hipMemcpyAsync(keys_out, keys_s, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+  NB_TRY(hipMemcpyAsync(idx_out, idx_s, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+  return hipSuccess;
+}
+
+hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, const double* mass, int32_t n,
+                           double eps2, double theta, int n_crit, double g_frac, bool mixed, double* acc,
+                           double* pot, TreeStats* stats, bool capturing, unsigned int* err, const char** msg) {
+  *msg = "";
+  if (!capturing && !s.host) NB_TRY(hipHostMalloc(&s.host, 64 * sizeof(int64_t), hipHostMallocDefault));
+  Alloc al{s, st, capturing};
+  auto need = [&](void* p) -> hipError_t { return p ? hipSuccess : (al.err != hipSuccess ? al.err : hipErrorOutOfMemory); };
+
+  // box, keys, sort along the curve
+  Box* box = nullptr;
+  uint64_t* keys_s = nullptr;
+  int32_t* idx_s = nullptr;
+  {
+    hipError_t e = keys_and_order(al, pos, n, &box, &keys_s, &idx_s, msg);
+    if (e != hipSuccess) return e;
+  }
   double* pos_s = al.get<double>(S_POS, 3 * (int64_t)n);
   double* mass_s = al.get<double>(S_MASS, n);
   int32_t* ijk_s = al.get<int32_t>(S_IJK, 3 * (int64_t)n);
   NB_TRY(need(ijk_s));
-  hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(kTB), 0, st, pos, (int64_t)n, part);
-  hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(kTB), 0, st, part, nbb, box);
-  hipLaunchKernelGGL(k_keys, dim3(blocks_for(n)), dim3(kTB), 0, st, pos, (int64_t)n, box, keys, idx);
-  NB_TRY(hipGetLastError());
-  NB_TRY(sort_pairs(al, keys, keys_s, idx, idx_s, n, 3 * kBits));
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(kTB), 0, st, pos, mass, idx_s, (int64_t)n, box, pos_s,
                      mass_s, ijk_s);
   NB_TRY(hipGetLastError());
 
-  // cells, level by level; cells of level l are [lvl[l], lvl[l + 1])
-  TreeCell* cells = al.get<TreeCell>(S_CELLS, 2 * (int64_t)n / (n_crit > 0 ? n_crit : 1) + 64);
-  NB_TRY(need(cells));
-  int64_t cap_cells = (int64_t)(s.slots[S_CELLS].second / sizeof(TreeCell));
-  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, st, cells, n, ijk_s, box);
-  std::vector<int64_t> lvl = {0, 1};
+  // cells, level by level, sized once by a bound: a cell that splits holds
+  // more than n_crit particles and the cells of one level are disjoint, so
+  // each level has at most n / (n_crit + 1) of them; the leaves hold at least
+  // one particle each, so there are at most n.  A level has at most
+  // min(n, 8 x that) cells.
+  const int64_t inner = n / ((int64_t)n_crit + 1);
+  const int64_t cap_cells = 1 + (int64_t)kLevels * inner + n;
+  const int64_t per_level = std::min<int64_t>(n, 8 * inner + 8);
+  TreeCell* cells = al.get<TreeCell>(S_CELLS, cap_cells);
+  int32_t* lvl = al.get<int32_t>(S_LVL, kLevels + 1);
+  const int32_t nchunk = (n + kGS - 1) / kGS;
+  int32_t* cnt = al.get<int32_t>(S_CNT, std::max<int64_t>(per_level + 1, nchunk));
+  int32_t* off = al.get<int32_t>(S_OFF, std::max<int64_t>(per_level + 1, nchunk));
+  int32_t* ends = al.get<int32_t>(S_ENDS, 8 * per_level);
+  NB_TRY(need(ends));
+  hipLaunchKernelGGL(k_root, dim3(1), dim3(64), 0, st, cells, n, ijk_s, box, lvl);
+  // grid-stride level kernels: a few hundred blocks cover the largest level
+  // and keep the launches of the empty levels below the tree cheap
+  const int gcount = blocks_for(8 * per_level, 256), gcell = blocks_for(per_level, 256);
   for (int l = 0; l < kBits; ++l) {
-    const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
-    // one extra zero count makes the last exclusive sum the level's total
-    int32_t* cntc = al.get<int32_t>(S_CNT, cnt + 1);
-    int32_t* offc = al.get<int32_t>(S_OFF, cnt + 1);
-    int32_t* ends = al.get<int32_t>(S_ENDS, 8 * cnt);
-    NB_TRY(need(ends));
-    hipLaunchKernelGGL(k_count_children, dim3(blocks_for(8 * cnt)), dim3(kTB), 0, st, cells + first,
-                       (int32_t)cnt, keys_s, n_crit, cntc, ends);
-    NB_TRY(hipGetLastError());
-    NB_TRY(exclusive_sum(al, cntc, offc, cnt + 1));
-    int64_t total = 0;
-    NB_TRY(read_entry(s, st, offc, cnt, &total));
-    if (total == 0) break;
-    const int64_t next = lvl[l + 1];
-    if (next + total > cap_cells) {
-      // grow, keeping the cells built so far
-      TreeCell* old = cells;
-      const int64_t newcap = 2 * (next + total);
-      TreeCell* fresh = nullptr;
-      NB_TRY(hipMalloc(&fresh, (size_t)newcap * sizeof(TreeCell)));
-      NB_TRY(hipMemcpyAsync(fresh, old, (size_t)next * sizeof(TreeCell), hipMemcpyDeviceToDevice, st));
-      NB_TRY(hipStreamSynchronize(st));
-      (void)hipFree(s.slots[S_CELLS].first);
-      s.slots[S_CELLS] = {fresh, (size_t)newcap * sizeof(TreeCell)};
-      cells = fresh;
-      cap_cells = newcap;
-    }
-    hipLaunchKernelGGL(k_write_children, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells, (int32_t)first,
-                       (int32_t)cnt, ends, ijk_s, box, n_crit, offc, (int32_t)next);
-    NB_TRY(hipGetLastError());
-    lvl.push_back(next + total);
-  }
-  // cells are created as leaves (no children); the last level visited made none
-  const int depth = (int)lvl.size() - 2;
-  for (int l = depth; l >= 0; --l) {
-    const int64_t first = lvl[l], cnt = lvl[l + 1] - lvl[l];
-    hipLaunchKernelGGL(k_moments, dim3(blocks_for(cnt)), dim3(kTB), 0, st, cells, (int32_t)first, (int32_t)cnt,
-                       pos_s, mass_s);
+    hipLaunchKernelGGL(k_count_children, dim3(gcount), dim3(kTB), 0, st, cells, lvl, l, keys_s, n_crit, cnt, ends);
+    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(kScanThreads), 0, st, cnt, off, (int64_t)0, lvl, l);
+    hipLaunchKernelGGL(k_write_children, dim3(gcell), dim3(kTB), 0, st, cells, lvl, l, ends, ijk_s, box, n_crit, off);
   }
   NB_TRY(hipGetLastError());
-  const int64_t ncells = lvl[depth + 1];
+  // moments from the deepest level up (empty levels return at once)
+  for (int l = kBits; l >= 0; --l)
+    hipLaunchKernelGGL(k_moments, dim3(gcell), dim3(kTB), 0, st, cells, lvl, l, pos_s, mass_s);
+  NB_TRY(hipGetLastError());
 
   // groups: chunks of 64, halved while wider than g_max (one pass to count,
   // one to write)
-  const int32_t nchunk = (n + kGS - 1) / kGS;
   int32_t* gb = al.get<int32_t>(S_GB, n);
   int32_t* ge = al.get<int32_t>(S_GE, n);
   int32_t* gn = al.get<int32_t>(S_GN, 1);
-  int32_t* gcnt = al.get<int32_t>(S_CNT, nchunk);
-  int32_t* goff = al.get<int32_t>(S_OFF, nchunk);
-  NB_TRY(need(goff));
-  const int gblocks = blocks_for((int64_t)nchunk * kGS);
-  hipLaunchKernelGGL(k_groups<false>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, gcnt,
-                     nullptr, nullptr, nullptr, nullptr);
-  NB_TRY(exclusive_sum(al, gcnt, goff, nchunk));
-  hipLaunchKernelGGL(k_groups<true>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, gcnt, goff,
-                     gb, ge, gn);
-  NB_TRY(hipGetLastError());
-  int32_t ngroups = 0;
-  {
-    int32_t* h = static_cast<int32_t*>(s.host);
-    NB_TRY(hipMemcpyAsync(h, gn, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    NB_TRY(hipStreamSynchronize(st));
-    ngroups = h[0];
-  }
-  double* gbox = al.get<double>(S_GBOX, 6 * (int64_t)ngroups);
+  double* gbox = al.get<double>(S_GBOX, 6 * (int64_t)n);
   NB_TRY(need(gbox));
-  hipLaunchKernelGGL(k_group_box, dim3(blocks_for(ngroups)), dim3(kTB), 0, st, gb, ge, ngroups, pos_s, gbox);
+  const int gblocks = blocks_for((int64_t)nchunk * kGS);
+  hipLaunchKernelGGL(k_groups<false>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, cnt,
+                     nullptr, nullptr, nullptr, nullptr);
+  NB_TRY(exclusive_sum(st, cnt, off, nchunk));
+  hipLaunchKernelGGL(k_groups<true>, dim3(gblocks), dim3(kTB), 0, st, n, nchunk, pos_s, box, g_frac, cnt, off,
+                     gb, ge, gn);
+  hipLaunchKernelGGL(k_group_box, dim3(blocks_for(n, 1024)), dim3(kTB), 0, st, gb, ge, gn, pos_s, gbox);
+  NB_TRY(hipGetLastError());
 
   // walk and forces: one wavefront per group, groups handed out by a counter
   int dev = 0, num_cus = 0, per_cu = 0;
@@ -1000,39 +1176,41 @@ hipError_t tree_forces_run(TreeScratch& s, hipStream_t st, const double* pos, co
   else
     NB_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tree_walk_forces<false>, kGS, 0));
   int64_t grid = (int64_t)(num_cus > 0 ? num_cus : 1) * (per_cu > 0 ? per_cu : 1);
-  if (grid > ngroups) grid = ngroups;
-  const int32_t cap = (int32_t)(ncells < kStackCap ? ncells : kStackCap);
+  // the counter hands out every group whatever the grid; a chunk of 64 rarely
+  // splits into more than two groups, so more workgroups would mostly find none
+  if (grid > 2 * (int64_t)nchunk) grid = 2 * (int64_t)nchunk;
+  const int32_t cap = (int32_t)(cap_cells < kStackCap ? cap_cells : kStackCap);
   int32_t* stack = al.get<int32_t>(S_STACK, grid * cap);
   unsigned long long* ctr = al.get<unsigned long long>(S_CTR, 4);
   NB_TRY(need(ctr));
   NB_TRY(need(stack));
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, ctr, 4);
   if (mixed)
-    hipLaunchKernelGGL(k_tree_walk_forces<true>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, ngroups, gbox,
-                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, acc, pot);
+    hipLaunchKernelGGL(k_tree_walk_forces<true>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, gn, gbox,
+                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, err, acc, pot);
   else
-    hipLaunchKernelGGL(k_tree_walk_forces<false>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, ngroups, gbox,
-                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, acc, pot);
+    hipLaunchKernelGGL(k_tree_walk_forces<false>, dim3((unsigned)grid), dim3(kGS), 0, st, gb, ge, gn, gbox,
+                       cells, theta, pos_s, mass_s, eps2, idx_s, stack, cap, ctr, err, acc, pot);
   NB_TRY(hipGetLastError());
-  int64_t na = 0, nl = 0;
-  {
-    unsigned long long* h = static_cast<unsigned long long*>(s.host);
-    NB_TRY(hipMemcpyAsync(h, ctr + 1, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
-    NB_TRY(hipStreamSynchronize(st));
-    if (h[2]) {
-      *msg = "tree walk stack exceeded its bound";
-      return hipErrorInvalidValue;
-    }
-    na = (int64_t)h[0];
-    nl = (int64_t)h[1];
+  if (!stats) return hipSuccess;
+  // counts for the caller (synchronises)
+  unsigned long long c[3];
+  NB_TRY(read_entries(s, st, ctr + 1, 3, c));
+  if (c[2]) {
+    *msg = "tree walk stack exceeded its bound";
+    return hipErrorInvalidValue;
   }
-  if (stats) {
-    stats->cells = ncells;
-    stats->groups = ngroups;
-    stats->accepted = na;
-    stats->opened_leaves = nl;
-    stats->depth = depth;
-  }
+  int32_t lv[kLevels + 1], ng = 0;
+  NB_TRY(read_entries(s, st, lvl, kLevels + 1, lv));
+  NB_TRY(read_entries(s, st, gn, 1, &ng));
+  int depth = 0;
+  for (int l = 0; l < kLevels; ++l)
+    if (lv[l + 1] > lv[l]) depth = l;
+  stats->cells = lv[kLevels];
+  stats->groups = ng;
+  stats->accepted = (int64_t)c[0];
+  stats->opened_leaves = (int64_t)c[1];
+  stats->depth = depth;
   return hipSuccess;
 }
 

@@ -33,11 +33,12 @@ def test_save_and_load_order(tmp_path):
 
 
 def test_shape_runs_merge_only_within_the_launch_cost():
-    # A run of buckets takes a neighbouring run's shape only when that costs
-    # each of its buckets at most one launch; merges repeat until none fits,
-    # and a bucket's loss never exceeds the launches saved.
-    from paper_1409_5474_amd.autotune import _merge_shapes
-    A, B, C, D = (1, 256), (1, 64), (1, 16), (2, 1)
+    # A run of buckets that needs a launch of its own takes a neighbouring
+    # run's shape only when that costs each of its buckets at most one launch;
+    # merges repeat until none fits, and a bucket's loss never exceeds the
+    # launches saved.
+    from paper_1409_5474_amd.autotune import _merge_shapes, _launch_runs
+    A, B, C, D = (1, 256), (2, 0), (4, 1), (2, 1)   # family 1, scalar path, single kernel, family 2
     times = [{A: 15, B: 17, C: 20, D: 90}, {A: 18, B: 19, C: 30, D: 80},
              {A: 30, B: 24, C: 25, D: 60}, {A: 60, B: 50, C: 44, D: 50}, {A: 900, B: 400, C: 300, D: 100}]
     fastest = [min(t, key=t.get) for t in times]
@@ -45,12 +46,53 @@ def test_shape_runs_merge_only_within_the_launch_cost():
     assert _merge_shapes(fastest, times, 0) == fastest
     got = _merge_shapes(fastest, times, 3)
     assert got == [A, A, C, C, D]          # B -> C costs 1 at bucket 2; nothing else within 3
-    saved = len({*fastest}) - len({*got})
+    saved = len(_launch_runs(fastest)) - len(_launch_runs(got))
+    assert saved == 1
     assert all(times[b][got[b]] - times[b][fastest[b]] <= 3 * saved for b in range(5))
-    assert _merge_shapes(fastest, times, 10**6) in ([A] * 5, [B] * 5, [C] * 5, [D] * 5)
+    assert len(_launch_runs(_merge_shapes(fastest, times, 10**6))) == 1
     # a shape not timed at some bucket of the run (K > 1 below 64 K rows) is never taken there
-    t2 = [{A: 10}, {A: 12, D: 12}]
-    assert _merge_shapes([A, D], t2, 5) == [A, A]
+    t2 = [{A: 10}, {A: 12, (2, 0): 12}]
+    assert _merge_shapes([A, (2, 0)], t2, 5) == [A, A]
+
+
+def test_shapes_one_family_holds_share_a_launch():
+    # LDS shapes of one kernel family run in one device-count launch, so the
+    # merge keeps each bucket's fastest shape there
+    from paper_1409_5474_amd.autotune import _merge_shapes, _launch_runs, _family
+    ch = [(1, 64), (1, 4), (2, 4), (2, 1), (2, 1)]
+    times = [{sh: 1.0 + 0.001 * k for k, sh in enumerate(ch)} for _ in ch]
+    assert len(_launch_runs(ch)) == 1
+    assert _merge_shapes(ch, times, 10**6) == ch
+    # other tile lengths / workgroup sizes, the scalar path and (4, 1) are single kernels
+    assert [_family(s) for s in [(1, 1, 128, 128), (2, 0), (4, 1), (4, 4), (1, 256)]] == [0, 0, 0, 4, 1]
+    assert len(_launch_runs([(1, 4), (4, 4), (2, 1)])) == 2   # families 2 and 4 hold different K
+
+
+def test_shipped_table_covers_every_tuned_workload():
+    # The table loaded by default: every precision has single-system entries
+    # for N = 65536, 262144 and 1441803 whose active-count ranges tile
+    # [0, 2^31), and batched entries (both kinds) over every key; the force
+    # kernels' source hash it was measured on is recorded.
+    from paper_1409_5474_amd import autotune as at
+    doc = json.load(open(at.DEFAULT_TABLE))
+    assert len(doc["meta"]["forces_hip_sha256"]) == 64
+    entries = doc["entries"]
+    for prec in ("fp64", "mixed", "mixed_ds"):
+        for n in (65536, 262144, 1441803):
+            es = sorted((e for e in entries if e.get("kind", 0) == 0 and e["prec"] == prec and e["n_min"] == n),
+                        key=lambda e: e["act_min"])
+            assert es and es[0]["act_min"] == 0 and es[-1]["act_max"] == 2 ** 31 - 1, (prec, n)
+            assert all(a["act_max"] + 1 == b["act_min"] for a, b in zip(es, es[1:])), (prec, n)
+            assert all("T" in e and "WG" in e for e in es)
+        for kind in (1, 2):
+            es = sorted((e for e in entries if e.get("kind", 0) == kind and e["prec"] == prec),
+                        key=lambda e: e["key_min"])
+            assert es and es[0]["key_min"] <= 1 and es[-1]["key_max"] == 2 ** 31 - 1, (prec, kind)
+            assert all(a["key_max"] + 1 == b["key_min"] for a, b in zip(es, es[1:])), (prec, kind)
+        # the batched workloads' systems (128 to 16384 bodies) each fall in a tuned kind-1 range
+        for size in (128, 1000, 3344, 16384):
+            assert any(e["key_min"] <= size <= e["key_max"] for e in entries
+                       if e.get("kind", 0) == 1 and e["prec"] == prec)
 
 
 @pytest.mark.gpu

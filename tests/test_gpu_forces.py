@@ -72,7 +72,10 @@ def test_small_plummer_all_active(ctx, prec):
 # (K, L, S); L = 0 is the scalar j-path
 LAUNCHES = [(1, 1, 1), (2, 1, 1), (4, 1, 1), (1, 1, 3), (2, 1, 5), (1, 2, 1), (1, 4, 2), (2, 8, 3), (4, 16, 1),
             (1, 32, 2), (2, 64, 4), (1, 128, 1), (1, 256, 7), (4, 4, 4), (2, 32, 2), (1, 0, 1), (2, 0, 3), (3, 0, 2), (1, -1, 1), (2, -1, 3), (3, -1, 2),
-            (4, 0, 1), (2, 0, 1)]
+            (4, 0, 1), (2, 0, 1),
+            # (K, L, S, T, WG): other j-tile lengths and workgroup sizes
+            (1, 1, 2, 128, 128), (2, 4, 3, 128, 256), (1, 16, 5, 64, 64), (2, 1, 1, 64, 64), (1, 4, 7, 128, 256),
+            (2, 1, 9, 128, 128), (1, 0, 3, 0, 128), (2, 0, 2, 0, 128)]
 
 
 @pytest.mark.parametrize("prec", PRECS)
@@ -348,3 +351,46 @@ def test_out_of_range_entries_in_the_other_entry_points(nb):
     assert changed[7] and changed[9] and changed.sum() == 2
     c.sync()
     c.close()
+
+
+def test_tuned_tile_and_workgroup_shapes_host_and_device_count(ctx):
+    # Table entries with other (T, WG) drive both launch kinds: every count
+    # gets the same bits from a host-count and a device-count launch, and
+    # the oracle's values.
+    import torch
+    n = 5000
+    p = _case(n, 13)
+    eps2 = 1e-3
+    P, V, M = _dev(p.pos), _dev(p.vel), _dev(p.mass)
+    for prec in PRECS:
+        c = __import__("paper_1409_5474_amd").Context(0, prec, load_tuning=False)
+        c.tune_add(prec, 1, 0, 40, 1, 16, 0, 64, 64)
+        c.tune_add(prec, 1, 41, 900, 2, 4, 0, 128, 256)
+        c.tune_add(prec, 1, 901, 2 ** 31 - 1, 2, 1, 0, 128, 128)
+        assert c.get_shape(n, 20)[3:] == (64, 64) and c.get_shape(n, 3000)[3:] == (128, 128)
+        for na in (7, 300, 3000):
+            act = np.sort(np.random.default_rng(na).choice(n, na, replace=False)).astype(np.int32)
+            a1, j1, p1 = c.forces(P, V, M, _dev(act), eps2)
+            cnt = torch.tensor([na], dtype=torch.int32, device="cuda")
+            a2 = torch.empty((n, 3), dtype=torch.float64, device="cuda"); j2 = torch.empty_like(a2)
+            p2 = torch.empty(n, dtype=torch.float64, device="cuda")
+            act_full = torch.zeros(n, dtype=torch.int32, device="cuda"); act_full[:na] = _dev(act)
+            c.forces_devcount(P, V, M, act_full, cnt, n, eps2, a2, j2, p2)
+            torch.cuda.synchronize()
+            assert torch.equal(a1, a2[:na]) and torch.equal(j1, j2[:na]) and torch.equal(p1, p2[:na]), (prec, na)
+            ref = oracle.forces_ld(p.pos, p.vel, p.mass, eps2, act)
+            res = (a1.cpu().numpy(), j1.cpu().numpy(), p1.cpu().numpy())
+            if prec == "fp64":
+                check_fp64(res, ref)
+            else:
+                check_mixed(res, ref)
+        c.sync()
+        c.close()
+
+
+def test_unbuilt_tile_shapes_are_rejected(ctx):
+    import paper_1409_5474_amd as nb
+    for shape in ((1, 64, 1, 128, 128), (4, 1, 1, 128, 256), (1, 4, 1, 96, 128), (3, 0, 1, 0, 128)):
+        with pytest.raises(nb.NbodyError):
+            ctx.set_launch(*shape)
+    ctx.set_launch(0)

@@ -198,3 +198,52 @@ def test_deep_clustered_tree(ctx, theta):
     assert st["accepted"] == sum(c for c, _, _ in rst)
     assert st["opened_leaves"] == sum(l for _, l, _ in rst)
     _close((acc, pot), (ra, rp), 1e-12)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2047, 2), (2048, 3), (2049, 4), (100000, 5)])
+def test_curve_order_is_the_oracles_lexsort(ctx, n, seed):
+    # The library's radix sort against numpy's: identical keys and rows
+    # (integer work, bit for bit), including ties (coincident particles).
+    import torch
+    pos = synth.plummer(n, seed).pos
+    if n > 10:
+        pos[n // 2: n // 2 + 7] = pos[3]  # equal keys: the order among them is the input order
+    keys, idx = ctx.tree_keys(T(pos))
+    torch.cuda.synchronize()
+    lo, side = TR.box(pos)
+    ref_keys = TR.hilbert_keys(TR.grid_coords(pos, lo, side))
+    order = np.lexsort((np.arange(n), ref_keys))
+    assert np.array_equal(idx.cpu().numpy(), order)
+    assert np.array_equal(keys.cpu().numpy().view(np.uint64), ref_keys[order].astype(np.uint64))
+
+
+def test_tree_forces_replay_from_a_graph(ctx):
+    # With stats off the evaluation reads nothing on the host, so it can be
+    # captured; every replay (with other work and synchronisations between)
+    # gives the eager bits.
+    import torch
+    p = synth.plummer(20000, 9)
+    P, M = T(p.pos), T(p.mass)
+    a0, f0, st = ctx.tree_forces(P, M, 1e-4, 0.5)          # eager, sizes the buffers
+    assert st["cells"] > 1
+    s = torch.cuda.Stream()
+    ctx.set_stream(s)
+    acc = torch.empty_like(a0)
+    pot = torch.empty_like(f0)
+    with torch.cuda.stream(s):
+        ctx.tree_forces(P, M, 1e-4, 0.5, acc=acc, pot=pot, stats=False)  # warm-up on the stream
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.tree_forces(P, M, 1e-4, 0.5, acc=acc, pot=pot, stats=False)
+    torch.cuda.synchronize()
+    for r in range(3):
+        with torch.cuda.stream(s):
+            acc.zero_()
+            pot.zero_()
+            g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(acc, a0) and torch.equal(pot, f0), r
+        ctx.tree_forces(P, M, 1e-4, 0.7)                      # other eager work between replays
+    ctx.set_stream(None)
+    ctx.sync()
