@@ -881,8 +881,9 @@ __global__ __launch_bounds__(kScanThreads) void k_exscan(const int32_t* in, int3
 // ----------------------------------------------------------- radix sort -----
 // Stable least-significant-digit radix sort of (key, row) pairs, 8 bits per
 // pass.  A pass: each tile of kRsTile keys counts its digits (k_rs_hist);
-// one exclusive scan over the counts in digit-major order gives every
-// (digit, tile) its first output slot; each tile then writes its keys there
+// the prefix of each digit's row of tile counts (k_rs_rowscan, one block
+// per digit) plus the prefix of the digit totals gives every (digit, tile)
+// its first output slot; each tile then writes its keys there
 // (k_rs_scatter), a key's place among the equal digits of its tile being
 // the number of such keys before it.  Within a tile, wavefront w takes the
 // w-th quarter in rounds of 64 consecutive keys; the lanes of a round that
@@ -910,15 +911,53 @@ __global__ __launch_bounds__(kRsThreads) void k_rs_hist(const uint64_t* __restri
   hist[(int64_t)threadIdx.x * ntile + blockIdx.x] = h[threadIdx.x];
 }
 
+// Per digit (block d): the exclusive prefix of its row of tile counts, in
+// place (the tile's place among the digit's keys), and the row total.
+__global__ __launch_bounds__(kRsThreads) void k_rs_rowscan(int32_t* __restrict__ hist, int32_t ntile,
+                                                           int32_t* __restrict__ total) {
+  __shared__ int32_t buf[kRsThreads];
+  const int t = threadIdx.x;
+  int32_t* row = hist + (int64_t)blockIdx.x * ntile;
+  int32_t carry = 0;
+  for (int64_t c0 = 0; c0 < ntile; c0 += kRsThreads) {
+    const int64_t k = c0 + t;
+    const int32_t v = k < ntile ? row[k] : 0;
+    buf[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kRsThreads; o <<= 1) {
+      const int32_t u = t >= o ? buf[t - o] : 0;
+      __syncthreads();
+      buf[t] += u;
+      __syncthreads();
+    }
+    if (k < ntile) row[k] = carry + buf[t] - v;
+    carry += buf[kRsThreads - 1];
+    __syncthreads();
+  }
+  if (t == 0) total[blockIdx.x] = carry;
+}
+
 __global__ __launch_bounds__(kRsThreads) void k_rs_scatter(const uint64_t* __restrict__ kin,
                                                            const int32_t* __restrict__ vin,
                                                            uint64_t* __restrict__ kout, int32_t* __restrict__ vout,
                                                            int32_t n, int shift, const int32_t* __restrict__ offs,
-                                                           int32_t ntile) {
+                                                           const int32_t* __restrict__ total, int32_t ntile) {
   __shared__ int32_t first[kRsBuckets];          // the tile's first output slot of each digit
   __shared__ int32_t wcnt[kRsThreads / 64][kRsBuckets];
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-  first[t] = offs[(int64_t)t * ntile + blockIdx.x];
+  // where each digit starts: the exclusive prefix of the digit totals
+  const int32_t tot = total[t];
+  first[t] = tot;
+  __syncthreads();
+  for (int o = 1; o < kRsBuckets; o <<= 1) {
+    const int32_t u = t >= o ? first[t - o] : 0;
+    __syncthreads();
+    first[t] += u;
+    __syncthreads();
+  }
+  const int32_t start = first[t] - tot;
+  __syncthreads();
+  first[t] = start + offs[(int64_t)t * ntile + blockIdx.x];
   for (int q = 0; q < kRsThreads / 64; ++q) wcnt[q][t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kRsTile + (int64_t)w * 64 * kRsRounds;
@@ -1019,15 +1058,16 @@ hipError_t exclusive_sum(hipStream_t st, const int32_t* in, int32_t* out, int64_
 hipError_t radix_sort(Alloc& al, uint64_t* keys, int32_t* idx, uint64_t* keys2, int32_t* idx2, int32_t n, int bits,
                       uint64_t** keys_out, int32_t** idx_out) {
   const int32_t ntile = (n + kRsTile - 1) / kRsTile;
-  int32_t* hist = al.get<int32_t>(S_HIST, (int64_t)kRsBuckets * ntile);
+  int32_t* hist = al.get<int32_t>(S_HIST, (int64_t)kRsBuckets * ntile + kRsBuckets);
   if (!hist) return al.err != hipSuccess ? al.err : hipErrorOutOfMemory;
+  int32_t* total = hist + (int64_t)kRsBuckets * ntile;
   uint64_t *ka = keys, *kb = keys2;
   int32_t *va = idx, *vb = idx2;
   for (int shift = 0; shift < bits; shift += kRsBits) {
     hipLaunchKernelGGL(k_rs_hist, dim3(ntile), dim3(kRsThreads), 0, al.st, ka, n, shift, hist, ntile);
-    hipLaunchKernelGGL(k_exscan, dim3(1), dim3(kScanThreads), 0, al.st, hist, hist, (int64_t)kRsBuckets * ntile,
-                       nullptr, 0);
-    hipLaunchKernelGGL(k_rs_scatter, dim3(ntile), dim3(kRsThreads), 0, al.st, ka, va, kb, vb, n, shift, hist, ntile);
+    hipLaunchKernelGGL(k_rs_rowscan, dim3(kRsBuckets), dim3(kRsThreads), 0, al.st, hist, ntile, total);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(ntile), dim3(kRsThreads), 0, al.st, ka, va, kb, vb, n, shift, hist, total,
+                       ntile);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
