@@ -170,6 +170,18 @@ int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int6
 int nb_tune_add_batch(nb_ctx *ctx, int precision, int kind, int64_t key_min, int64_t key_max, int K, int L);
 int nb_get_batch_launch(nb_ctx *ctx, int kind, int64_t key, int64_t N, int *K, int *L);
 int nb_tune_clear(nb_ctx *ctx);
+/* How nbody_forces and nbody_forces_ij add the S partial sums of a j-split
+ * (S > 1).  mode 0 (the default): each subset writes its partials and a
+ * second kernel adds them in a fixed order -- the results do not depend on
+ * the launch.  mode 1: the paper's alternative, where every subset's work
+ * item adds its part into the outputs with device-scope atomic adds (after
+ * a kernel that seeds them); no workspace and no second kernel, but the
+ * order of the additions, and so the last bits, vary from run to run.
+ * Mode 1 runs the LDS shapes with K <= 2 and T = WG = 256 (a call whose
+ * shape is another gets NB_ENOTSUP, as does eps2 = 0); device-count calls,
+ * block steps and nbody_forces_noalloc always use mode 0.  Errors:
+ * NB_EINVAL for another mode. */
+int nb_set_split_sum(nb_ctx *ctx, int mode);
 /* Time the force kernel for one configuration on the caller's arrays:
  * `reps` launches after one warm-up, on the context stream, with HIP
  * events; returns the mean milliseconds per launch in *ms.  Synchronises

@@ -63,6 +63,7 @@ _sig("nb_get_launch", _vp, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int
      ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_add", _vp, _int, _i64, _i64, _i64, _int, _int, _int, _int, _int)
 _sig("nb_tune_add_batch", _vp, _int, _int, _i64, _i64, _int, _int)
+_sig("nb_set_split_sum", _vp, _int)
 _sig("nb_get_batch_launch", _vp, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_clear", _vp)
 _sig("nb_set_stop_source", _vp, _vp)
@@ -237,6 +238,10 @@ class Context:
         K, L = _int(), _int()
         self._chk(_lib.nb_get_batch_launch(self._h, int(kind), int(key), int(N), ctypes.byref(K), ctypes.byref(L)))
         return K.value, L.value
+
+    def set_split_sum(self, mode):
+        """0: fixed-order two-kernel sum of the j-split (default); 1: atomic adds (the paper's alternative)."""
+        self._chk(_lib.nb_set_split_sum(self._h, int(mode)))
 
     def tune_clear(self):
         self._chk(_lib.nb_tune_clear(self._h))

@@ -310,6 +310,12 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
       a.rec = c->mirror;
     }
   }
+  if (cfg.S > 1 && c->split_atomic && !fixed) {
+    if (mask || !nb::atomic_split_supported(eff))
+      return fail(c, NB_ENOTSUP, "the atomic j-split sum runs the LDS families 1 and 2 with eps2 > 0 only%s");
+    hipError_t e = nb::launch_forces_atomic(c->prec, eff, a, c->stream, max_grid);
+    return e == hipSuccess ? NB_OK : hip_fail(c, e, "atomic force launch");
+  }
   if (cfg.S > 1) {
     if (fixed) {
       a.part = fixed->part;
@@ -495,6 +501,13 @@ int nb_tune_add(nb_ctx* c, int precision, int64_t n_min, int64_t act_min, int64_
     return fail(c, NB_EINVAL, "bad tune entry%s");
   if (!nb::launch_supported(make_shape(K, L, 1, 0, T, WG))) return fail(c, NB_ENOTSUP, "launch shape not built%s");
   c->table.push_back(nb::TuneEntry{precision, n_min, act_min, act_max, make_shape(K, L, 0, S, T, WG)});
+  return NB_OK;
+}
+
+int nb_set_split_sum(nb_ctx* c, int mode) {
+  if (!c) return NB_EINVAL;
+  if (mode != 0 && mode != 1) return fail(c, NB_EINVAL, "split-sum mode must be 0 (fixed order) or 1 (atomic)%s");
+  c->split_atomic = mode == 1;
   return NB_OK;
 }
 

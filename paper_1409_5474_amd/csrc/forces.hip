@@ -576,7 +576,7 @@ __device__ __forceinline__ void queue_done(unsigned int* wq, int64_t items) {
 // Shared body: one workgroup processes one (i-block, j-chunk) item.
 // Outputs: final rows (acc/jerk/pot at out_row0 + k) when `final_out`,
 // otherwise partial sums part[c * n_act + k] for c = 0..6.
-template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG>
+template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG, bool ATOMIC = false>
 __device__ __forceinline__ void process_item(typename P::template JTileT<T>& tile, double* red, const double* __restrict__ pos,
                                              const double* __restrict__ vel, const double* __restrict__ mass,
                                              const double* __restrict__ ipos, const double* __restrict__ ivel,
@@ -676,6 +676,16 @@ __device__ __forceinline__ void process_item(typename P::template JTileT<T>& til
         acc[3 * k] = v[0]; acc[3 * k + 1] = v[1]; acc[3 * k + 2] = v[2];
         jerk[3 * k] = v[3]; jerk[3 * k + 1] = v[4]; jerk[3 * k + 2] = v[5];
         pot[k] = -(v[6] - self);
+      } else if constexpr (ATOMIC) {
+        // the paper's alternative to the two-kernel sum: every j-subset adds
+        // its part into the outputs (seeded by k_atomic_init) with device-scope
+        // atomics, in whatever order the work items finish
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          atomicAdd(&acc[3 * k + c], v[c]);
+          atomicAdd(&jerk[3 * k + c], v[3 + c]);
+        }
+        atomicAdd(&pot[k], -v[6]);
       } else {
 #pragma unroll
         for (int c = 0; c < 7; ++c) part[c * n_act + k] = v[c];
@@ -692,7 +702,7 @@ struct Smem {
 
 // The items of one launch shape: (i-block, j-chunk) pairs taken from the
 // work queue until none is left.
-template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG>
+template <class P, int K, int L, bool MASK, int T = kTile, int WG = kWG, bool ATOMIC = false>
 __device__ __forceinline__ void run_items(typename P::template JTileT<T>& tile, double* red, unsigned int& slot,
                                           const ForceArgs& a, int64_t n_act, int S) {
   constexpr int IB = (WG / L) * K;
@@ -706,7 +716,7 @@ __device__ __forceinline__ void run_items(typename P::template JTileT<T>& tile, 
     const int64_t iblk = w - chunk * n_iblk;
     const int64_t jb = chunk * clen;
     const int64_t je = jb + clen < a.n ? jb + clen : a.n;
-    process_item<P, K, L, MASK, T, WG>(tile, red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
+    process_item<P, K, L, MASK, T, WG, ATOMIC>(tile, red, a.pos, a.vel, a.mass, a.ipos ? a.ipos : a.pos,
                                 a.ivel ? a.ivel : a.vel, a.no_self ? nullptr : a.mass, jb, je, a.active, n_act, iblk * IB,
                                 a.eps2, S == 1, a.acc, a.jerk, a.pot, a.part + chunk * 7 * n_act, a.row_lo, a.row_hi,
                                 a.err);
@@ -748,7 +758,7 @@ __device__ __forceinline__ int shape_for(const ForceArgs& a, int64_t d) {
 // of the compiled bodies, so the regimes of a block step share one launch
 // whatever their shapes.  Every body is the single-shape kernel's, so a
 // shape gives the same sums in either kernel.
-template <class P, int FAM, bool MASK>
+template <class P, int FAM, bool MASK, bool ATOMIC = false>
 __global__ __launch_bounds__(kWG) void k_forces_fam(ForceArgs a) {
   __shared__ Smem<P, 256> sm;
   __shared__ unsigned int slot;
@@ -766,7 +776,7 @@ __global__ __launch_bounds__(kWG) void k_forces_fam(ForceArgs a) {
   }
 #define NB_RUN(KK, LL)                                                           \
   if (shape == shape_code(KK, LL)) {                                             \
-    run_items<P, KK, LL, MASK>(sm.tile, sm.red, slot, a, n_act, S);              \
+    run_items<P, KK, LL, MASK, kTile, kWG, ATOMIC>(sm.tile, sm.red, slot, a, n_act, S); \
     return;                                                                      \
   }
   NB_RUN(1, 1) NB_RUN(1, 4) NB_RUN(1, 16) NB_RUN(1, 64) NB_RUN(1, 256)
@@ -1525,6 +1535,23 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
   }
 }
 
+// Seeds of the atomic j-split sum: zero acceleration and jerk, and the
+// potential at +self term, so that after every subset has added -(its part)
+// it is -(sum - self), as the fixed-order reduce writes it.
+template <class P>
+__global__ __launch_bounds__(256) void k_atomic_init(ForceArgs a) {
+  const bool self_on = P::eps(a.eps2) > 0 && !a.no_self;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < a.n_active; k += (int64_t)gridDim.x * 256) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a.acc[3 * k + c] = 0.0;
+      a.jerk[3 * k + c] = 0.0;
+    }
+    const int64_t i = a.active[k];
+    a.pot[k] = (self_on && row_in_range(i, a.row_lo, a.row_hi)) ? P::self_term(a.mass[i], a.eps2) : 0.0;
+  }
+}
+
 // ------------------------------------------------------------- dispatch ----
 using ForceFn = void (*)(ForceArgs);
 using BatchFn = void (*)(const BatchItem*, int, const int*, const BatchSys*, const double*, const double*,
@@ -1671,7 +1698,44 @@ BatchFn pick_batch(int K, int L) {
   return nullptr;
 }
 
+template <class P>
+ForceFn pick_fam_atomic(int fam) {
+  if (fam == 1) return k_forces_fam<P, 1, false, true>;
+  if (fam == 2) return k_forces_fam<P, 2, false, true>;
+  return nullptr;
+}
+
 }  // namespace
+
+bool atomic_split_supported(const Launch& c) {
+  const int fam = default_tile(c) && c.L >= 1 ? family_of(c.K, c.L) : 0;
+  return fam == 1 || fam == 2;
+}
+
+hipError_t launch_forces_atomic(int prec, const Launch& cfg, const ForceArgs& a, hipStream_t st, int max_grid) {
+  if (!atomic_split_supported(cfg)) return hipErrorInvalidValue;
+  const int fam = family_of(cfg.K, cfg.L);
+  ForceFn fn = prec == NB_PREC_FP64 ? pick_fam_atomic<F64>(fam)
+               : prec == NB_PREC_MIXED_DS ? pick_fam_atomic<MixedDS>(fam) : pick_fam_atomic<Mixed>(fam);
+  if (!fn) return hipErrorInvalidValue;
+  int64_t g0 = (a.n_active + 255) / 256;
+  g0 = g0 < 1 ? 1 : (g0 > 1024 ? 1024 : g0);
+  if (prec == NB_PREC_FP64)
+    hipLaunchKernelGGL(k_atomic_init<F64>, dim3((unsigned)g0), dim3(256), 0, st, a);
+  else if (prec == NB_PREC_MIXED_DS)
+    hipLaunchKernelGGL(k_atomic_init<MixedDS>, dim3((unsigned)g0), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(k_atomic_init<Mixed>, dim3((unsigned)g0), dim3(256), 0, st, a);
+  Launch shape = cfg;
+  shape.S = a.S;
+  int grid = items_for(shape, a.n_active, a.S);
+  if (max_grid > 0 && grid > max_grid) grid = max_grid;
+  if (grid <= 0) return hipGetLastError();
+  ForceArgs b = a;
+  b.shape = shape_code(cfg.K, cfg.L);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, b);
+  return hipGetLastError();
+}
 
 bool launch_supported(const Launch& c) {
   if (c.S < 1) return false;

@@ -200,6 +200,11 @@ struct BatchSys {
 hipError_t launch_forces(int prec, const Launch& cfg, bool mask, const ForceArgs& a, hipStream_t st,
                          int grid_override, int max_grid);
 int resident_wgs(int prec, const Launch& cfg, bool mask);
+// The paper's atomic alternative to the two-kernel j-split sum (LDS kernel
+// families 1 and 2, eps2 > 0): outputs seeded, then every work item adds
+// its partial sums with device-scope atomics.
+bool atomic_split_supported(const Launch& c);
+hipError_t launch_forces_atomic(int prec, const Launch& cfg, const ForceArgs& a, hipStream_t st, int max_grid);
 size_t mirror_bytes(int prec, int64_t n);  // j-record mirror of the scalar j-path
 hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStream_t st);
 int host_choose_S(int64_t n_act, int IB, int target_items, int64_t n, int tile);
@@ -350,6 +355,7 @@ struct nb_ctx {
   std::string err;
   nb::Launch forced;            // K == 0: automatic
   bool have_forced = false;
+  bool split_atomic = false;      // nb_set_split_sum: host-count j-split sums by atomics
   std::vector<nb::TuneEntry> table;
   std::vector<nb::BatchTuneEntry> batch_table;
   // device workspace (grown on demand)

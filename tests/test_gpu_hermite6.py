@@ -212,3 +212,19 @@ def test_checkpoint_resume6_is_bitwise(tmp_path):
     for k in ("pos", "vel", "acc", "jerk", "snap", "crackle", "t_tick", "level"):
         assert torch.equal(getattr(straight, k), getattr(resumed, k)), k
     ctx.close()
+
+
+def test_forces6_full_size_sampled(ctx):
+    # The snap kernel at the 262144-body Plummer workload's size, in the
+    # launch the block steps use: 256 evenly spaced rows against the oracle,
+    # element by element.  The j-accelerations (an input of the snap) are
+    # the Plummer model's own field -x (|x|^2 + 1)^-3/2, so no input comes
+    # from the library.
+    n = 262144
+    p = synth.plummer(n, 3)
+    r2 = np.sum(p.pos ** 2, axis=1, keepdims=True)
+    acc_j = -p.pos * (r2 + 1.0) ** -1.5
+    act = np.linspace(0, n - 1, 256).astype(np.int32)
+    eps2 = 2.0 ** -16
+    ref = oracle.snap_ld(p.pos, p.vel, acc_j, p.mass, eps2, act)
+    check_fp64(_gpu6(ctx, p, acc_j, eps2, act), ref, names=NAMES)

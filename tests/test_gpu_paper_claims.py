@@ -77,3 +77,26 @@ def test_mixed_energy_error_follows_fp64():
     print(drift)
     assert drift["fp64"] > 0
     assert math.isclose(drift["mixed"], drift["fp64"], rel_tol=0.05)
+
+
+def test_mixed_energy_error_follows_fp64_at_the_headline_size():
+    # The same claim on the headline workload (Plummer N = 262144, eps =
+    # 1/256, eta = 0.01, to t = 1/8): the energy errors agree to 5%, and the
+    # block-step counts to 0.5% (a level decision may fall the other way in
+    # float arithmetic).
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    p = synth.plummer(262144, 3)
+    drift, steps = {}, {}
+    for prec in ("fp64", "mixed"):
+        ctx = nb.Context(0, prec)
+        bi = BlockIntegrator(ctx, T(p.pos), T(p.vel), T(p.mass), 2.0 ** -16, 0.01, 1.0 / 16, 30)
+        E0 = bi.energy()["E"]
+        bi.run_until(1.0 / 8)
+        drift[prec] = abs(bi.energy()["E"] - E0) / abs(E0)
+        steps[prec] = bi.steps
+        ctx.close()
+    print(drift, steps)
+    assert abs(steps["fp64"] - steps["mixed"]) <= 0.005 * steps["fp64"]
+    assert 0 < drift["fp64"] < 1e-5
+    assert math.isclose(drift["mixed"], drift["fp64"], rel_tol=0.05)
