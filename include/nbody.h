@@ -48,6 +48,11 @@
  *    before anything is launched, leaving every output untouched.  The tree
  *    code keeps its own buffers (about 200 bytes per particle plus its
  *    interaction lists), which the cap does not cover.
+ *  - NB_LOG, read by nb_create: 1 prints every error a call on the context
+ *    returns (the nb_last_error text with its code) to stderr; 2 also prints
+ *    each launch shape the host chooses (K, L, S, T, WG, work items, and the
+ *    regimes of a count-on-device launch).  Lines start with "nbody:".
+ *    Unset, empty or 0: silent.
  */
 #ifndef NBODY_H
 #define NBODY_H
@@ -426,6 +431,23 @@ int nb_kick_drift(nb_ctx *ctx, double *pos, double *vel, const double *acc, int6
  * pointer it was captured with); nb_schedule has no stop tick and ignores
  * it. */
 int nb_set_stop_source(nb_ctx *ctx, const int64_t *t_stop_dev);
+
+/* Phase timing of block steps.  While on (on != 0), every block-step call
+ * on this context (nb_block_step, nb_block_step_batch, nb_block_step6)
+ * that is not being captured into a graph records four HIP events on the
+ * context stream: at its start, after the scheduler with the predictor (and
+ * the batch plan), after the force launches and after the corrector.  The
+ * events cost a few microseconds per step; steps captured into a graph
+ * record none.  Switching on creates the events (NB_EDEVICE if that fails);
+ * switching on or off forgets the last step's times. */
+int nb_set_phase_timing(nb_ctx *ctx, int on);
+
+/* Milliseconds of the three phases of the last timed block step: ms[0] the
+ * scheduler with the predictor (and the batch plan), ms[1] the forces,
+ * ms[2] the partial-sum reduction with the corrector.  Waits for that
+ * step's last event.  NB_EINVAL if timing is off or no eager block step
+ * has completed its launches since it was switched on. */
+int nb_phase_times(nb_ctx *ctx, float ms[3]);
 
 /* Predict every particle to t_next: d = (t_next_tick - t_tick[i]) dt_min,
  * pos_p = pos + vel d + acc d^2/2 + jerk d^3/6, vel_p = vel + acc d + jerk d^2/2.

@@ -11,6 +11,7 @@ there is no CPU fallback.
 """
 import ctypes
 import os
+import sys
 
 import torch
 
@@ -33,6 +34,16 @@ if not os.path.exists(lib_path):
     raise ImportError(f"{lib_path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
 
 _lib = ctypes.CDLL(lib_path)
+
+
+def _log_level():
+    """NB_LOG as an integer (0 when unset, empty or not a number); the
+    library reads the same variable when a context is created."""
+    try:
+        return max(0, int(os.environ.get("NB_LOG", "") or 0))
+    except ValueError:
+        return 0
+
 _vp = ctypes.c_void_p
 _i64 = ctypes.c_int64
 _i32 = ctypes.c_int32
@@ -67,6 +78,8 @@ _sig("nb_set_split_sum", _vp, _int)
 _sig("nb_get_batch_launch", _vp, _int, _i64, _i64, ctypes.POINTER(_int), ctypes.POINTER(_int))
 _sig("nb_tune_clear", _vp)
 _sig("nb_set_stop_source", _vp, _vp)
+_sig("nb_set_phase_timing", _vp, _int)
+_sig("nb_phase_times", _vp, ctypes.POINTER(ctypes.c_float))
 _sig("nb_time_forces", _vp, _int, _int, _int, _int, _int, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp, _int,
      ctypes.POINTER(_dbl))
 _sig("nbody_forces", _vp, _vp, _vp, _vp, _i64, _vp, _i64, _dbl, _vp, _vp, _vp)
@@ -144,8 +157,10 @@ class Context:
     """One library context on one GPU (``nb_create``)."""
 
     def __init__(self, device=0, precision="fp64", stream=None, load_tuning=True):
-        """load_tuning: install the autotuner's saved table for this GPU
-        (``tuning_gfx950.json`` next to this file) when it exists."""
+        """load_tuning: install a saved launch table -- the file named by the
+        environment variable NB_TUNE_CACHE when set, else the autotuner's
+        table for this GPU (``tuning_gfx950.json`` next to this file) when it
+        exists (``autotune.table_path``)."""
         prec = _PREC_NAMES[precision] if isinstance(precision, str) else int(precision)
         h = ctypes.c_void_p()
         rc = _lib.nb_create(ctypes.byref(h), int(device), prec)
@@ -154,10 +169,15 @@ class Context:
         self._h = h
         self.device = torch.device("cuda", int(device))
         self.set_stream(stream)
+        self.tuning_table = None
         if load_tuning:
             from . import autotune
-            if os.path.exists(autotune.DEFAULT_TABLE):
-                autotune.load(self, autotune.DEFAULT_TABLE)
+            path = autotune.table_path()
+            if path:
+                n = autotune.load(self, path)
+                self.tuning_table = path
+                if _log_level() >= 2:
+                    print(f"nbody: launch table {path} ({n} entries)", file=sys.stderr, flush=True)
 
     def _chk(self, rc):
         if rc != 0:
@@ -245,6 +265,17 @@ class Context:
 
     def tune_clear(self):
         self._chk(_lib.nb_tune_clear(self._h))
+
+    def set_phase_timing(self, on=True):
+        """Record phase events in every eager block step (``nb_set_phase_timing``)."""
+        self._chk(_lib.nb_set_phase_timing(self._h, 1 if on else 0))
+
+    def phase_times(self):
+        """(schedule, forces, reduce + correct) milliseconds of the last timed
+        eager block step (``nb_phase_times``); waits for that step."""
+        ms = (ctypes.c_float * 3)()
+        self._chk(_lib.nb_phase_times(self._h, ms))
+        return float(ms[0]), float(ms[1]), float(ms[2])
 
     def set_stop_source(self, stop=None):
         """Block steps read their stop tick from ``stop`` (a one-element int64

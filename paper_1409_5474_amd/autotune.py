@@ -28,6 +28,7 @@ import math
 import os
 import sys
 import time
+import warnings
 
 import numpy as np
 import torch
@@ -336,6 +337,21 @@ def save(entries, path, meta=None):
         json.dump(doc, f, indent=1)
 
 
+def table_path():
+    """The launch table a new context installs: the file named by the
+    environment variable NB_TUNE_CACHE when it is set, non-empty and exists
+    (the autotuner writes there by default); else the shipped table for this
+    GPU when it exists (with a warning when NB_TUNE_CACHE names a missing
+    file: the cache has not been written yet); else None."""
+    env = os.environ.get("NB_TUNE_CACHE", "")
+    if env:
+        if os.path.exists(env):
+            return env
+        warnings.warn(f"NB_TUNE_CACHE names {env}, which does not exist yet; using the shipped table",
+                      stacklevel=2)
+    return DEFAULT_TABLE if os.path.exists(DEFAULT_TABLE) else None
+
+
 def load(ctx, path=DEFAULT_TABLE):
     """Install a saved table into a context (entries in file order)."""
     with open(path) as f:
@@ -354,7 +370,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, nargs="+", default=[65536, 262144])
     ap.add_argument("--prec", nargs="+", default=["fp64", "mixed", "mixed_ds"])
-    ap.add_argument("--out", default="tuning.json")
+    ap.add_argument("--out", default=os.environ.get("NB_TUNE_CACHE") or "tuning.json",
+                    help="table to write (default: $NB_TUNE_CACHE, else tuning.json)")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--max-active", type=int, default=0,
                     help="largest active-set bucket to time (0: up to N); the top bucket's range then covers every larger count")

@@ -17,11 +17,21 @@ namespace {
 
 constexpr const char* kVersion = "nbody-mi355x 0.1 (gfx950)";
 
+// NB_LOG (read by nb_create): 1 prints every error a call returns, 2 also
+// each host-side launch choice; lines go to stderr, prefixed "nbody:".
+int log_level_from_env() {
+  const char* v = std::getenv("NB_LOG");
+  if (!v || !*v) return 0;
+  const int l = std::atoi(v);
+  return l < 0 ? 0 : l;
+}
+
 int fail(nb_ctx* c, int code, const char* fmt, const char* detail = nullptr) {
   if (c) {
     char buf[512];
     std::snprintf(buf, sizeof buf, fmt, detail ? detail : "");
     c->err = buf;
+    if (c->log_level >= 1) std::fprintf(stderr, "nbody: error %d: %s\n", code, buf);
   }
   return code;
 }
@@ -29,14 +39,42 @@ int fail(nb_ctx* c, int code, const char* fmt, const char* detail = nullptr) {
 int hip_fail(nb_ctx* c, hipError_t e, const char* where) {
   char buf[512];
   std::snprintf(buf, sizeof buf, "%s: %s", where, hipGetErrorString(e));
-  if (c) c->err = buf;
+  if (c) {
+    c->err = buf;
+    if (c->log_level >= 1) std::fprintf(stderr, "nbody: error %d: %s\n", NB_EDEVICE, buf);
+  }
   return NB_EDEVICE;
+}
+
+void log_launch(const nb_ctx* c, const char* what, const Launch& cfg, int64_t N, int64_t n_active) {
+  if (c->log_level < 2) return;
+  std::fprintf(stderr, "nbody: %s N=%lld n_active=%lld K=%d L=%d S=%d T=%d WG=%d items=%d\n", what, (long long)N,
+               (long long)n_active, cfg.K, cfg.L, cfg.S, cfg.T, cfg.WG, cfg.items);
 }
 
 bool capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
   return st != hipStreamCaptureStatusNone;
+}
+
+// Phase event k of an eager block step (0: start, 1: after the schedule and
+// plan, 2: after the forces, 3: after the corrector).  Steps inside a graph
+// capture record nothing and leave the last eager step's times in place.
+void phase_mark(nb_ctx* c, int k) {
+  if (!c->phase_on) return;
+  if (k == 0) {
+    if (capturing(c->stream)) return;
+    c->phase_valid = false;
+  } else if (!c->phase_ev[0] || capturing(c->stream)) {
+    return;
+  }
+  if (hipEventRecord(c->phase_ev[k], c->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    c->phase_valid = false;
+    return;
+  }
+  if (k == 3) c->phase_valid = true;
 }
 
 // Optional cap on the j-split workspace and on the j-record mirror
@@ -291,6 +329,7 @@ int run_forces(nb_ctx* c, const Launch& cfg, const double* pos, const double* ve
                const int32_t* active, int64_t n_active, double eps2, double* acc, double* jerk, double* pot,
                const double* ipos = nullptr, const double* ivel = nullptr, bool no_self = false,
                const FixedScratch* fixed = nullptr, int64_t n_rows = -1) {
+  log_launch(c, "forces", cfg, N, n_active);
   nb::ForceArgs a{};
   a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
   a.ipos = ipos; a.ivel = ivel; a.no_self = no_self ? 1 : 0;
@@ -368,6 +407,7 @@ int nb_create(nb_ctx** out, int device, int precision) {
   if (!c) return NB_ENOMEM;
   c->device = device;
   c->prec = precision;
+  c->log_level = log_level_from_env();
   hipDeviceProp_t p;
   if (hipGetDeviceProperties(&p, device) == hipSuccess && p.multiProcessorCount > 0) c->num_cus = p.multiProcessorCount;
   // the fixed scratch's address on this device, looked up once per device
@@ -404,6 +444,8 @@ int nb_destroy(nb_ctx* c) {
   if (c->batch_host) (void)hipHostFree(c->batch_host);
   if (c->batch_ev) (void)hipEventDestroy(c->batch_ev);
   if (c->bp_buf) (void)hipFree(c->bp_buf);
+  for (hipEvent_t& ev : c->phase_ev)
+    if (ev) (void)hipEventDestroy(ev);
   nb::tree_scratch_free(c->tree);
   delete c;
   return NB_OK;
@@ -531,6 +573,39 @@ int nb_get_batch_launch(nb_ctx* c, int kind, int64_t key, int64_t n_total, int* 
 int nb_set_stop_source(nb_ctx* c, const int64_t* t_stop_dev) {
   if (!c) return NB_EINVAL;
   c->stop_dev = t_stop_dev;
+  return NB_OK;
+}
+
+int nb_set_phase_timing(nb_ctx* c, int on) {
+  if (!c) return NB_EINVAL;
+  if (on && !c->phase_ev[0]) {
+    (void)hipSetDevice(c->device);
+    for (hipEvent_t& ev : c->phase_ev) {
+      if (hipEventCreate(&ev) != hipSuccess) {
+        const hipError_t e = hipGetLastError();
+        for (hipEvent_t& f : c->phase_ev) {
+          if (f) (void)hipEventDestroy(f);
+          f = nullptr;
+        }
+        return hip_fail(c, e, "phase timing events");
+      }
+    }
+  }
+  c->phase_on = on != 0;
+  c->phase_valid = false;
+  return NB_OK;
+}
+
+int nb_phase_times(nb_ctx* c, float ms[3]) {
+  if (!c || !ms) return NB_EINVAL;
+  if (!c->phase_on || !c->phase_valid)
+    return fail(c, NB_EINVAL, "no eager block step was timed since phase timing was switched on%s");
+  hipError_t e = hipEventSynchronize(c->phase_ev[3]);
+  if (e != hipSuccess) return hip_fail(c, e, "phase timing wait");
+  for (int k = 0; k < 3; ++k) {
+    e = hipEventElapsedTime(&ms[k], c->phase_ev[k], c->phase_ev[k + 1]);
+    if (e != hipSuccess) return hip_fail(c, e, "phase timing");
+  }
   return NB_OK;
 }
 
@@ -769,6 +844,12 @@ int devcount_forces(nb_ctx* c, const double* pos, const double* vel, const doubl
     const int64_t top = g.r.hi < max_active ? g.r.hi : max_active;
     Launch cfg = c->have_forced ? c->forced : g.r.cfg;
     if (mask) cfg = nb::masked(cfg);
+    if (c->log_level >= 2) {
+      std::fprintf(stderr, "nbody: count-on-device launch for n_active in [%lld, %lld], family %d:\n",
+                   (long long)g.r.lo, (long long)top, g.r.cfg.fam);
+      for (int k = 0; k < g.n_sub && g.sub_lo[k] <= max_active; ++k)
+        log_launch(c, "  regime", g.sub_cfg[k], N, g.sub_lo[k]);
+    }
     nb::ForceArgs a{};
     a.pos = pos; a.vel = vel; a.mass = mass; a.n = N;
     a.active = active; a.n_active = top; a.n_active_dev = n_active_dev;
@@ -928,18 +1009,23 @@ int nb_block_step6(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max,
   rc = ensure_sched(c, N);
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
+  phase_mark(c, 0);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
                                      c->nact32, t_stop_tick, c->stop_dev, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_predict6(pos, vel, acc, jerk, snap, crackle, t_tick, 0, sched, dt_min, N, pos_p, vel_p, acc_p,
                           c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "sixth-order predict launch");
+  phase_mark(c, 1);
   rc = run_forces6(c, pos_p, vel_p, acc_p, mass, N, active, N, c->nact32, eps2, acc1, jerk1, snap1, pot1);
   if (rc) return rc;
+  phase_mark(c, 2);
   e = nb::launch_correct6(active, N, sched + 1, N, c->wq + nb::kErrorWord, acc1, jerk1, snap1, pos, vel, acc, jerk, snap,
                           crackle, t_tick,
                           dt_level, eta, dt_max, max_level, sched + 3, sched + 2, c->stream);
-  return e == hipSuccess ? NB_OK : hip_fail(c, e, "sixth-order correct launch");
+  if (e != hipSuccess) return hip_fail(c, e, "sixth-order correct launch");
+  phase_mark(c, 3);
+  return NB_OK;
 }
 
 // ---- tree code -------------------------------------------------------------
@@ -1068,20 +1154,25 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
   rc = ensure_sched(c, N);
   if (rc) return rc;
   const double dt_min = std::ldexp(dt_max, -max_level);
+  phase_mark(c, 0);
   // schedule and predict (the predictor runs in the scheduler's last pass)
   const nb::PredictArgs pred{pos, vel, acc, jerk, dt_min, pos_p, vel_p};
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
                                      c->nact32, t_stop_tick, c->stop_dev, c->stream, &pred);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
+  phase_mark(c, 1);
   nb::ForceArgs red{};
   rc = devcount_forces(c, pos_p, vel_p, mass, N, active, c->nact32, N, eps2, acc1, jerk1, pot1, false, &red);
   if (rc) return rc;
+  phase_mark(c, 2);
   // the partial sums' reduce and the corrector in one pass
   const nb::StepArgs st{pos_p, vel_p, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max, max_level,
                         reinterpret_cast<unsigned long long*>(sched + 3),
                         reinterpret_cast<unsigned long long*>(sched + 2)};
   e = nb::launch_reduce_correct(c->prec, red, st, c->stream);
-  return e == hipSuccess ? NB_OK : hip_fail(c, e, "reduce and correct launch");
+  if (e != hipSuccess) return hip_fail(c, e, "reduce and correct launch");
+  phase_mark(c, 3);
+  return NB_OK;
 }
 
 
@@ -1114,6 +1205,7 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
   // One kernel shape for the batch, from the mean active rows per system.
   const Launch cfg = choose_batch(c, 1, (a_total + C - 1) / C, n_total, (a_total + C - 1) / C);
+  log_launch(c, "batch forces", cfg, n_total, a_total);
   const int IB = nb::ib_of(cfg);
   // total work in (i-slot x j) units and the chunk length that splits it
   double work = 0.0;
@@ -1239,6 +1331,7 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   if (rc) return rc;
   // one kernel shape for the batch, from the mean system size
   const Launch cfg = choose_batch(c, 2, (N + C - 1) / C, N, (N + C - 1) / C);
+  log_launch(c, "batch block step", cfg, N, N);
   const int IB = nb::ib_of(cfg);
   const int rgrid = resident_grid(c, cfg, any_mask);
   const int target = 2 * rgrid;
@@ -1290,22 +1383,27 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   int* d_nit = reinterpret_cast<int*>(b + o_nit);
   const double dt_min = std::ldexp(dt_max, -max_level);
   const nb::PredictArgs pred{pos, vel, acc, jerk, dt_min, pos_p, vel_p};
+  phase_mark(c, 0);
   hipError_t e = nb::launch_schedule(t_tick, dt_level, N, max_level, active, sched, c->sched_tmp, c->sched_cnt,
                                      c->nact32, t_stop_tick, c->stop_dev, c->stream, &pred);
   if (e != hipSuccess) return hip_fail(c, e, "schedule launch");
   e = nb::launch_batch_plan(d_off, d_eps, (int)C, active, sched + 1, IB, target, d_sys, d_nch, d_items, max_items,
                             d_nit, part_cap, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch plan launch");
+  phase_mark(c, 1);
   e = nb::launch_batch(c->prec, cfg, d_items, max_items, d_nit, d_sys, pos_p, vel_p, mass, active, acc1, jerk1, pot1,
                        static_cast<double*>(c->ws), part_cap, any_mask, rgrid, c->wq + nb::kErrorWord, c->mirror, N,
                        c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "batch force launch");
+  phase_mark(c, 2);
   const nb::StepArgs sa{pos_p, vel_p, pos, vel, acc, jerk, t_tick, dt_level, eta, dt_max, max_level,
                         reinterpret_cast<unsigned long long*>(sched + 3),
                         reinterpret_cast<unsigned long long*>(sched + 2)};
   e = nb::launch_batch_reduce_correct(c->prec, d_sys, d_nch, (int)C, sched + 1, N, mass, active, acc1, jerk1, pot1,
                                       static_cast<double*>(c->ws), sa, c->wq + nb::kErrorWord, c->stream);
-  return e == hipSuccess ? NB_OK : hip_fail(c, e, "batch reduce-correct launch");
+  if (e != hipSuccess) return hip_fail(c, e, "batch reduce-correct launch");
+  phase_mark(c, 3);
+  return NB_OK;
 }
 
 int nb_energy(nb_ctx* c, const double* pos, const double* vel, const double* mass, const double* pot, int64_t N,

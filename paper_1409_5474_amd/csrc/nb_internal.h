@@ -384,4 +384,10 @@ struct nb_ctx {
   void* bp_buf = nullptr;         // offsets, eps2, sys, nchunk, items, n_items
   size_t bp_cap = 0;
   int bp_max_items = 0;
+  int log_level = 0;              // NB_LOG at nb_create: 0 silent, 1 errors, 2 also launch choices
+  // phase timing of eager block steps (nb_set_phase_timing): events at the
+  // start, after the schedule (and plan), after the forces, after the corrector
+  bool phase_on = false;
+  bool phase_valid = false;       // the last block step recorded all four
+  hipEvent_t phase_ev[4] = {};
 };

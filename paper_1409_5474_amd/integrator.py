@@ -9,7 +9,15 @@ go on.  The stop time lives in device memory (``nb_set_stop_source``), so one
 captured graph serves every later stop time.
 
 Time is kept in integer ticks of dt_max 2^-max_level (see nbody.h).
+
+Metrics (``set_metrics``): a sink -- any callable, e.g. ``jsonl_sink(path)``
+-- receives one dict per eager block step (its active count, interactions
+and the device time of its three phases) and one per graph replay (steps
+and device time); ``run_until(log=...)`` adds one per synchronisation time
+(energy, momenta, virial ratio).
 """
+import json
+
 import torch
 
 from . import Context
@@ -17,10 +25,23 @@ from . import Context
 INT64_MAX = 2 ** 63 - 1
 
 
+def jsonl_sink(path):
+    """A metrics sink that appends each record to ``path`` as one JSON line."""
+    f = open(path, "a", buffering=1)
+
+    def sink(record):
+        f.write(json.dumps(record) + "\n")
+
+    sink.close = f.close
+    return sink
+
+
 class BlockIntegrator:
     """Block-step integration of one system, or of a batch of independent
     systems stored back to back (``offsets`` of length C+1 and one softening
     per system in ``eps2``; the block step is then global over the batch)."""
+
+    metrics = None   # per-step record sink (set_metrics)
 
     def __init__(self, ctx: Context, pos, vel, mass, eps2, eta=0.01, dt_max=1.0 / 16, max_level=30,
                  offsets=None):
@@ -67,6 +88,7 @@ class BlockIntegrator:
         self.active = torch.empty(n, dtype=torch.int32, device=dev)
         self.all_idx = torch.arange(n, dtype=torch.int32, device=dev)
         self._graphs = {}
+        self._capturing = False
 
     def _all_forces(self, pos, vel, acc, jerk, pot):
         if self.batch:
@@ -84,6 +106,35 @@ class BlockIntegrator:
             self._step(INT64_MAX if t_stop_tick is None else t_stop_tick)
         finally:
             self.ctx.set_stop_source(None)
+        if self.metrics is not None and not self._capturing:
+            self._emit_step()
+
+    # ---- metrics ------------------------------------------------------------
+    def set_metrics(self, sink):
+        """Send per-step records to ``sink`` (a callable taking a dict), or
+        stop with None.  Each eager step then waits for the device, so
+        metrics are for diagnosis, not for timed runs."""
+        self.metrics = sink
+        self.ctx.set_phase_timing(sink is not None)
+
+    def _interactions(self, n_act):
+        # n_active x N_j, summed per system for a batch
+        if not self.batch:
+            return n_act * self.n
+        import numpy as np
+        if n_act == 0:
+            return 0
+        rows = self.active[:n_act].cpu().numpy()
+        sys_of = np.searchsorted(self.offsets, rows, side="right") - 1
+        sizes = np.diff(self.offsets)
+        return int(sizes[sys_of].sum())
+
+    def _emit_step(self):
+        ms = self.ctx.phase_times()
+        t_next, n_act, steps, clamps = self.sched.cpu().tolist()
+        self.metrics(dict(kind="step", step=steps, t=t_next * self.tick, n_active=n_act,
+                          interactions=self._interactions(n_act), ms_schedule=ms[0], ms_forces=ms[1],
+                          ms_correct=ms[2], clamps=clamps))
 
     def _step(self, t_stop_tick):
         if self.batch:
@@ -102,12 +153,14 @@ class BlockIntegrator:
             prev = self.ctx.stream
             stream = torch.cuda.Stream(self.dev)
             self.ctx.set_stream(stream)
+            self._capturing = True
             try:
                 g = torch.cuda.CUDAGraph()
                 with torch.cuda.graph(g, stream=stream):
                     for _ in range(steps):
                         self.step()
             finally:
+                self._capturing = False
                 self.ctx.set_stream(prev)
             self._graphs[steps] = g
         return g
@@ -151,7 +204,17 @@ class BlockIntegrator:
             if use_graph:
                 g = self._graph(graph_steps)
                 torch.cuda.synchronize(self.dev)
-                g.replay()
+                if self.metrics is not None:
+                    s0 = self.steps
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    g.replay()
+                    e1.record()
+                    torch.cuda.synchronize(self.dev)
+                    self.metrics(dict(kind="replay", steps=self.steps - s0, t=self.time,
+                                      ms=e0.elapsed_time(e1)))
+                else:
+                    g.replay()
                 torch.cuda.synchronize(self.dev)
             else:
                 for _ in range(graph_steps):

@@ -32,6 +32,34 @@ def test_save_and_load_order(tmp_path):
     assert json.load(open(p))["meta"]["device"] == "test"
 
 
+def test_table_path_follows_nb_tune_cache(tmp_path, monkeypatch):
+    from paper_1409_5474_amd import autotune as at
+    monkeypatch.delenv("NB_TUNE_CACHE", raising=False)
+    assert at.table_path() == at.DEFAULT_TABLE
+    cache = tmp_path / "cache.json"
+    at.save([], str(cache))
+    monkeypatch.setenv("NB_TUNE_CACHE", str(cache))
+    assert at.table_path() == str(cache)
+    # not written yet: the shipped table, with a warning
+    monkeypatch.setenv("NB_TUNE_CACHE", str(tmp_path / "later.json"))
+    with pytest.warns(UserWarning, match="does not exist yet"):
+        assert at.table_path() == at.DEFAULT_TABLE
+    monkeypatch.setenv("NB_TUNE_CACHE", "")
+    assert at.table_path() == at.DEFAULT_TABLE
+
+
+def test_jsonl_metrics_sink(tmp_path):
+    from paper_1409_5474_amd.integrator import jsonl_sink
+    path = tmp_path / "m.jsonl"
+    sink = jsonl_sink(str(path))
+    sink(dict(kind="step", step=1, n_active=3, interactions=12, ms_forces=0.5))
+    sink(dict(kind="replay", steps=8, ms=1.25))
+    sink.close()
+    lines = [json.loads(l) for l in open(path)]
+    assert lines == [dict(kind="step", step=1, n_active=3, interactions=12, ms_forces=0.5),
+                     dict(kind="replay", steps=8, ms=1.25)]
+
+
 def test_shape_runs_merge_only_within_the_launch_cost():
     # A run of buckets that needs a launch of its own takes a neighbouring
     # run's shape only when that costs each of its buckets at most one launch;
