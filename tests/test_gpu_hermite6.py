@@ -139,6 +139,8 @@ def test_correct6_and_levels_match_oracle(ctx):
     bound = 1000 * 2.0 ** -53 * M / h ** 3
     assert np.all(np.abs(c1 - c_exact).max(1) <= bound)
     assert np.all(np.abs(dev[5].cpu().numpy() - c_exact).max(1) <= bound)
+    # and so the GPU's crackle against the oracle's, row by row
+    assert np.all(np.abs(dev[5].cpu().numpy() - c1).max(1) <= 2 * bound)
     np.testing.assert_array_equal(tt.cpu().numpy(), t_new)
     np.testing.assert_array_equal(lv.cpu().numpy(), lev)
     assert int(clamps.item()) == int(cl.sum())
