@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--batch", action="store_true", help="also tune the batched kernel (nbody_forces_batch)")
     ap.add_argument("--batch-steps", action="store_true", help="also tune the batched block steps")
     ap.add_argument("--batch-only", action="store_true", help="tune only the batched kernel (no --n sweep)")
+    ap.add_argument("--batch-forces-only", action="store_true",
+                    help="retune only the batched kernel's entries (nbody_forces_batch); keep every other entry")
     args = ap.parse_args()
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import paper_1409_5474_amd as nb
@@ -400,6 +402,8 @@ def main():
 
     if args.batch_only:
         entries = [e for e in entries if e.get("kind", 0) == 0]
+    elif args.batch_forces_only:
+        args.batch = True
     else:
         for n in sorted(args.n):
             entries = [e for e in entries if not (e.get("kind", 0) == 0 and e["n_min"] == n)]

@@ -174,8 +174,6 @@ bool valid_K(int K) { return K >= 1 && K <= 4; }  // K = 3 exists for the scalar
 // velocities and masses through LDS; mixed precision, else as L = 0)
 bool valid_L(int L) { return L == 0 || L == -1 || (L >= 1 && L <= 256 && (L & (L - 1)) == 0); }
 
-int target_items(const nb_ctx* c) { return c->num_cus * 4; }
-
 // Workgroups the whole chip holds at once for this kernel shape.
 int resident_grid(const nb_ctx* c, const Launch& cfg, bool mask) {
   return c->num_cus * nb::resident_wgs(c->prec, cfg, mask);
@@ -1178,8 +1176,10 @@ int nb_block_step(nb_ctx* c, int64_t N, double eps2, double eta, double dt_max, 
 
 // Batched forces: the work list (system, i-block, j-chunk) is built on the
 // host, largest items first, staged through pinned memory and walked by one
-// launch.  Each system's j-range is cut into chunks of about the same
-// length J, chosen so the whole batch yields ~2 work items per CU slot.
+// launch (one workgroup per item; the hardware hands them out in list
+// order, so the large items go first).  Each system's j-range is cut into
+// chunks of about the same length J, chosen so the whole batch yields the
+// item count below.
 int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const double* eps2, const double* pos,
                        const double* vel, const double* mass, const int32_t* active, const int64_t* act_offsets,
                        double* acc, double* jerk, double* pot) {
@@ -1204,7 +1204,8 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   if (a_total == 0) return NB_OK;
   if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
   // One kernel shape for the batch, from the mean active rows per system.
-  const Launch cfg = choose_batch(c, 1, (a_total + C - 1) / C, n_total, (a_total + C - 1) / C);
+  Launch cfg = choose_batch(c, 1, (a_total + C - 1) / C, n_total, (a_total + C - 1) / C);
+  if (cfg.L == 0) cfg.WG = nb::kBatchSjWG;
   log_launch(c, "batch forces", cfg, n_total, a_total);
   const int IB = nb::ib_of(cfg);
   // total work in (i-slot x j) units and the chunk length that splits it
@@ -1213,7 +1214,13 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
     const int64_t na = act_offsets[s + 1] - act_offsets[s];
     work += (double)((na + IB - 1) / IB) * IB * (double)(offsets[s + 1] - offsets[s]);
   }
-  double jt = work / ((double)IB * 2.0 * target_items(c));
+  // items wanted: three per resident workgroup on the scalar j-path (its
+  // items start cheaply; 1.5-3 per slot measured best), eight per CU in the
+  // LDS layout, whose items also stage tiles (more, shorter items measured
+  // slower there)
+  const double n_target = cfg.L == 0 ? 3.0 * c->num_cus * nb::batch_resident_wgs(c->prec, cfg, any_mask)
+                                     : 8.0 * c->num_cus;
+  double jt = work / ((double)IB * n_target);
   int64_t J = (int64_t)std::ceil(jt / nb::kTile) * nb::kTile;
   if (J < nb::kTile) J = nb::kTile;
   std::vector<nb::BatchSys> sys((size_t)C);
@@ -1330,10 +1337,14 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   rc = ensure_sched(c, N);
   if (rc) return rc;
   // one kernel shape for the batch, from the mean system size
-  const Launch cfg = choose_batch(c, 2, (N + C - 1) / C, N, (N + C - 1) / C);
+  Launch cfg = choose_batch(c, 2, (N + C - 1) / C, N, (N + C - 1) / C);
+  if (cfg.L == 0) cfg.WG = nb::kBatchSjWG;
   log_launch(c, "batch block step", cfg, N, N);
   const int IB = nb::ib_of(cfg);
-  const int rgrid = resident_grid(c, cfg, any_mask);
+  // the scalar j-path runs its own workgroup size, which the single-system
+  // occupancy table does not hold
+  const int rgrid = cfg.L == 0 ? c->num_cus * nb::batch_resident_wgs(c->prec, cfg, any_mask)
+                               : resident_grid(c, cfg, any_mask);
   const int target = 2 * rgrid;
   const int max_items = target + (int)((N + IB - 1) / IB) + (int)C + 64;
   const int64_t part_cap = (int64_t)IB * target + N;

@@ -1246,14 +1246,14 @@ __global__ __launch_bounds__(kWG) void k_forces_batch(const BatchItem* __restric
 
 // The same work list on the scalar j-path: j-records of the whole batch come
 // from one mirror through the scalar cache, each system's rows with its own
-// softening; an i-block is kWG * K of the system's active rows.
+// softening; an i-block is kBatchSjWG * K of the system's active rows.
 template <class P, int K, bool MASK>
-__global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_batch_sj(
+__global__ __launch_bounds__(kBatchSjWG, (SjWaves<P, K>::value)) void k_forces_batch_sj(
     const BatchItem* __restrict__ items, int n_items, const int* __restrict__ n_items_dev,
     const BatchSys* __restrict__ sys, const typename P::JReg* __restrict__ rec, const double* pos, const double* vel,
     const double* mass, const int32_t* active, double* acc, double* jerk, double* pot, double* part,
     unsigned int* err) {
-  constexpr int IB = kWG * K;
+  constexpr int IB = kBatchSjWG * K;
   if (n_items_dev) {
     const int d = *n_items_dev;
     n_items = d < n_items ? (d < 0 ? 0 : d) : n_items;
@@ -1266,7 +1266,7 @@ __global__ __launch_bounds__(kWG, (SjWaves<P, K>::value)) void k_forces_batch_sj
     const int64_t clen = chunk_len(nj, it.nchunk);
     const int64_t jb = sy.j0 + (int64_t)it.chunk * clen;
     const int64_t je = jb + clen < sy.j1 ? jb + clen : sy.j1;
-    process_item_sj<P, K, MASK>(rec, pos, vel, mass, jb, je, active + sy.a0, n_act, (int64_t)it.iblk * IB, sy.eps2,
+    process_item_sj<P, K, MASK, kBatchSjWG>(rec, pos, vel, mass, jb, je, active + sy.a0, n_act, (int64_t)it.iblk * IB, sy.eps2,
                                 it.nchunk == 1, acc + 3 * sy.a0, jerk + 3 * sy.a0, pot + sy.a0,
                                 part + (sy.part_off + (int64_t)it.chunk * n_act) * 7, sy.j0, sy.j1, err);
   }
@@ -1681,7 +1681,7 @@ hipError_t launch_batch_sj_p(int K, const BatchItem* items, int n_items, const i
   if (n_items <= 0) return hipGetLastError();
   int grid = n_items;
   if (max_grid > 0 && grid > max_grid) grid = max_grid;
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kWG), 0, st, items, n_items, n_items_dev, sys, rec, pos, vel, mass,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kBatchSjWG), 0, st, items, n_items, n_items_dev, sys, rec, pos, vel, mass,
                      active, acc, jerk, pot, part, err);
   return hipGetLastError();
 }
@@ -1895,6 +1895,33 @@ hipError_t launch_reduce_ib(int prec, const ForceArgs& a, int S, int IB, hipStre
 bool batch_supported(const Launch& c) {
   if (c.L == 0) return pick_batch_sj<F64, false>(c.K) != nullptr;
   return pick_batch<F64, false>(c.K, c.L) != nullptr;
+}
+
+template <class P>
+const void* batch_kernel(const Launch& cfg, bool mask) {
+  if (cfg.L == 0)
+    return mask ? (const void*)pick_batch_sj<P, true>(cfg.K) : (const void*)pick_batch_sj<P, false>(cfg.K);
+  return mask ? (const void*)pick_batch<P, true>(cfg.K, cfg.L) : (const void*)pick_batch<P, false>(cfg.K, cfg.L);
+}
+
+int batch_resident_wgs(int prec, const Launch& cfg, bool mask) {
+  static std::mutex mu;
+  static std::map<const void*, int> cache;
+  const void* fn = prec == NB_PREC_FP64        ? batch_kernel<F64>(cfg, mask)
+                   : prec == NB_PREC_MIXED_DS ? batch_kernel<MixedDS>(cfg, mask)
+                                              : batch_kernel<Mixed>(cfg, mask);
+  if (!fn) return 1;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int nblk = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, fn, cfg.L == 0 ? kBatchSjWG : kWG, 0) != hipSuccess ||
+      nblk < 1) {
+    (void)hipGetLastError();
+    nblk = 1;
+  }
+  cache[fn] = nblk;
+  return nblk;
 }
 
 hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int n_items, const int* n_items_dev,

@@ -10,7 +10,11 @@
 
 namespace nb {
 
-constexpr int kWG = 256;    // threads per workgroup of every force kernel
+constexpr int kWG = 256;    // threads per workgroup of the force kernels unless a launch names another
+// Threads per workgroup of the batched scalar j-path: its i-block, WG * K
+// rows of one system, is half the single-system one, so systems of a few
+// hundred rows leave fewer lanes idle in their last i-block
+constexpr int kBatchSjWG = 128;
 constexpr int kTile = 256;  // j-particles staged in LDS per tile
 constexpr int kWorkQueueWords = 16;  // words of a context's work queue (9 used)
 constexpr int kMaxSubRegimes = 16;   // active-count regimes one device-count launch can serve
@@ -217,6 +221,8 @@ hipError_t launch_batch(int prec, const Launch& cfg, const BatchItem* items, int
                         int64_t n_total, hipStream_t st);
 // whether the batched force kernel exists in this shape (L = 0: scalar j-path)
 bool batch_supported(const Launch& c);
+// Workgroups per CU the batched force kernel of this shape holds at once.
+int batch_resident_wgs(int prec, const Launch& cfg, bool mask);
 hipError_t launch_batch_plan(const int64_t* off, const double* eps2, int C, const int32_t* active,
                              const int64_t* n_act_dev, int IB, int target, BatchSys* sys, int32_t* nchunk,
                              BatchItem* items, int max_items, int* n_items_dev, int64_t part_cap_rows,
