@@ -833,48 +833,60 @@ __global__ void k_zero_u64(unsigned long long* p, int n) {
 }
 
 // ---------------------------------------------------------------- scans -----
-// Exclusive prefix sum of n int32 counts by one workgroup (out may be in):
-// each thread sums a contiguous segment, the segment sums are scanned in LDS,
-// then each thread writes its segment's running sums.  n is n_host, or, when
-// lvl is set, the cell count of level l plus one (the extra zero count makes
-// the last entry the level's total).
+// Exclusive prefix sum of n int32 counts by one workgroup (out may be in), in
+// rounds of kScanThreads x kScanPer consecutive entries: each thread loads
+// kScanPer consecutive counts, the thread sums are scanned within each
+// wavefront by shuffles and across the wavefronts through LDS (one barrier
+// per round: the wavefront totals alternate between two buffers, and a
+// wavefront can only overwrite a buffer after every wavefront has passed the
+// next round's barrier, i.e. finished reading it), and each thread writes its
+// entries' running sums.  Entries are read before they are written, by the
+// same thread, so out may be in.  n is n_host, or, when lvl is set, the cell
+// count of level l plus one (the extra zero count makes the last entry the
+// level's total).  Every sum counts cells or particles, so it stays below
+// 2^31.
 constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 16;
 
 __global__ __launch_bounds__(kScanThreads) void k_exscan(const int32_t* in, int32_t* out, int64_t n_host,
                                                          const int32_t* __restrict__ lvl, int l) {
-  __shared__ int64_t part[kScanThreads];
+  constexpr int W = kScanThreads / 64;
+  __shared__ int32_t wsum[2][W];
   const int64_t n = lvl ? (int64_t)(lvl[l + 1] - lvl[l]) + 1 : n_host;
-  const int t = threadIdx.x;
-  const int64_t per = (n + kScanThreads - 1) / kScanThreads;
-  const int64_t b = t * per, e = b + per < n ? b + per : n;
-  // segments are read eight entries at a time, so eight loads are in flight
-  constexpr int B = 8;
-  int64_t sum = 0;
-  for (int64_t k = b; k < e; k += B) {
-    int32_t v[B];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int32_t carry = 0;
+  int buf = 0;
+  for (int64_t base = 0; base < n; base += (int64_t)kScanThreads * kScanPer) {
+    const int64_t b = base + (int64_t)t * kScanPer;
+    int32_t v[kScanPer];
 #pragma unroll
-    for (int j = 0; j < B; ++j) v[j] = k + j < e ? in[k + j] : 0;
+    for (int j = 0; j < kScanPer; ++j) v[j] = b + j < n ? in[b + j] : 0;
+    int32_t sum = 0;
 #pragma unroll
-    for (int j = 0; j < B; ++j) sum += v[j];
-  }
-  part[t] = sum;
-  __syncthreads();
-  for (int o = 1; o < kScanThreads; o <<= 1) {
-    const int64_t v = t >= o ? part[t - o] : 0;
+    for (int j = 0; j < kScanPer; ++j) sum += v[j];
+    int32_t x = sum;  // inclusive scan of the thread sums over the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int32_t y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[buf][wave] = x;
     __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int64_t run = part[t] - sum;
-  for (int64_t k = b; k < e; k += B) {
-    int32_t v[B];
+    int32_t before = 0, total = 0;
 #pragma unroll
-    for (int j = 0; j < B; ++j) v[j] = k + j < e ? in[k + j] : 0;
+    for (int w = 0; w < W; ++w) {
+      const int32_t ws = wsum[buf][w];
+      before += w < wave ? ws : 0;
+      total += ws;
+    }
+    int32_t run = carry + before + x - sum;
 #pragma unroll
-    for (int j = 0; j < B; ++j) {
-      if (k + j < e) out[k + j] = (int32_t)run;
+    for (int j = 0; j < kScanPer; ++j) {
+      if (b + j < n) out[b + j] = run;
       run += v[j];
     }
+    carry += total;
+    buf ^= 1;
   }
 }
 
