@@ -1408,43 +1408,70 @@ __global__ __launch_bounds__(256) void k_batch_reduce_correct(const BatchSys* __
 //   batch yields about `target` items; S_c = ceil(nj / J) chunks (at least
 //   one tile each); items (system, i-block, chunk) and partial-sum offsets
 //   by exclusive scans over the systems.
+// The searches start in LDS, on every stride-th entry of the active list
+// (one entry per thread), and finish within one stride in global memory:
+// log2(stride) dependent loads instead of log2(n_active).  The sums and
+// scans over the threads use shuffles within each wavefront and one
+// exchange of the wavefront totals.
 constexpr int kPlanThreads = 1024;
+constexpr int kPlanWaves = kPlanThreads / 64;
 
-__device__ __forceinline__ int64_t lower_bound_i32(const int32_t* a, int64_t n, int64_t key) {
-  int64_t lo = 0, hi = n;
+// First index k in [0, n) with active[k] >= key (n if none).  samp[t] =
+// active[t * stride] for t < ns = ceil(n / stride).
+__device__ int64_t plan_lower_bound(const int32_t* active, int64_t n, const int32_t* samp, int ns, int64_t stride,
+                                    int64_t key) {
+  int lo = 0, hi = ns;
   while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)a[mid] < key) lo = mid + 1;
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)samp[mid] < key) lo = mid + 1;
     else hi = mid;
   }
-  return lo;
+  // every entry up to (lo - 1) stride is below key; entry lo stride (or n) is not
+  if (lo == 0) return 0;
+  int64_t a = (int64_t)(lo - 1) * stride + 1;
+  int64_t b = lo < ns ? (int64_t)lo * stride : n;
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if ((int64_t)active[mid] < key) a = mid + 1;
+    else b = mid;
+  }
+  return a;
 }
 
-__device__ int64_t block_sum_i64(int64_t v, int64_t* red) {
-  red[threadIdx.x] = v;
+// Sum of one value per thread.
+__device__ int64_t plan_sum(int64_t v, int64_t* wred) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane == 0) wred[wave] = v;
   __syncthreads();
-  for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const int64_t r = red[0];
-  __syncthreads();
+  int64_t r = 0;
+#pragma unroll
+  for (int w = 0; w < kPlanWaves; ++w) r += wred[w];
+  __syncthreads();  // wred is free again for the next call
   return r;
 }
 
-// exclusive scan of one value per thread (thread order); returns the total
-__device__ int64_t block_exscan_i64(int64_t v, int64_t* red, int64_t* excl) {
-  red[threadIdx.x] = v;
-  __syncthreads();
-  for (int o = 1; o < kPlanThreads; o <<= 1) {
-    const int64_t t = (int)threadIdx.x >= o ? red[threadIdx.x - o] : 0;
-    __syncthreads();
-    red[threadIdx.x] += t;
-    __syncthreads();
+// Exclusive scan of one value per thread (thread order); returns the total.
+__device__ int64_t plan_exscan(int64_t v, int64_t* wred, int64_t* excl) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  *excl = red[threadIdx.x] - v;
-  const int64_t total = red[kPlanThreads - 1];
+  if (lane == 63) wred[wave] = x;
   __syncthreads();
+  int64_t before = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < kPlanWaves; ++w) {
+    const int64_t t = wred[w];
+    before += w < wave ? t : 0;
+    total += t;
+  }
+  __syncthreads();
+  *excl = before + x - v;
   return total;
 }
 
@@ -1455,7 +1482,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
                                                             BatchSys* __restrict__ sys, int32_t* __restrict__ nchunk,
                                                             BatchItem* __restrict__ items, int max_items,
                                                             int* __restrict__ n_items_dev, int64_t part_cap_rows) {
-  __shared__ int64_t red[kPlanThreads];
+  __shared__ int64_t red[kPlanWaves];
+  __shared__ int32_t samp[kPlanThreads];
   __shared__ int64_t J_s;
   int64_t n_act = *n_act_dev;
   if (n_act < 0) n_act = 0;
@@ -1463,10 +1491,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
   const int c0 = threadIdx.x * per;
   const int c1 = c0 + per < C ? c0 + per : C;
   // 1. active rows per system and the total work (i-slots x j)
+  const int64_t stride = n_act > kPlanThreads ? (n_act + kPlanThreads - 1) / kPlanThreads : 1;
+  const int ns = (int)((n_act + stride - 1) / stride);
+  if ((int)threadIdx.x < ns) samp[threadIdx.x] = active[(int64_t)threadIdx.x * stride];
+  __syncthreads();
   int64_t work = 0;
+  int64_t a1 = c0 < c1 ? plan_lower_bound(active, n_act, samp, ns, stride, off[c0]) : 0;
   for (int c = c0; c < c1; ++c) {
-    const int64_t a0 = lower_bound_i32(active, n_act, off[c]);
-    const int64_t a1 = lower_bound_i32(active, n_act, off[c + 1]);
+    const int64_t a0 = a1;
+    a1 = plan_lower_bound(active, n_act, samp, ns, stride, off[c + 1]);
     const int64_t nib = (a1 - a0 + IB - 1) / IB;
     work += nib * IB * (off[c + 1] - off[c]);
     sys[c].j0 = off[c];
@@ -1475,7 +1508,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
     sys[c].a1 = a1;
     sys[c].eps2 = eps2[c];
   }
-  const int64_t W = block_sum_i64(work, red);
+  const int64_t W = plan_sum(work, red);
   if (threadIdx.x == 0) {
     int64_t J = (W + (int64_t)IB * target - 1) / ((int64_t)IB * target);
     J = (J + kTile - 1) / kTile * kTile;
@@ -1497,8 +1530,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
     if (S > 1) my_parts += S * na;
   }
   int64_t item_base, part_base;
-  const int64_t total_items = block_exscan_i64(my_items, red, &item_base);
-  const int64_t total_parts = block_exscan_i64(my_parts, red, &part_base);
+  const int64_t total_items = plan_exscan(my_items, red, &item_base);
+  const int64_t total_parts = plan_exscan(my_parts, red, &part_base);
   const bool fits = total_items <= max_items && total_parts <= part_cap_rows;
   // 3. the work list, system by system
   for (int c = c0; c < c1; ++c) {
@@ -1522,7 +1555,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_batch_plan(const int64_t* __re
     int64_t mine = 0;
     for (int c = c0; c < c1; ++c) mine += (sys[c].a1 - sys[c].a0 + IB - 1) / IB;
     int64_t base;
-    const int64_t tot = block_exscan_i64(mine, red, &base);
+    const int64_t tot = plan_exscan(mine, red, &base);
     for (int c = c0; c < c1; ++c) {
       const int64_t nib = (sys[c].a1 - sys[c].a0 + IB - 1) / IB;
       for (int64_t b = 0; b < nib; ++b)
