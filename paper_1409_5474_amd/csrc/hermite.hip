@@ -126,12 +126,44 @@ __device__ __forceinline__ void predict_range(const PredictArgs& p, const int64_
   }
 }
 
+// Minimum and sum over the NT threads of a block: shuffles within each
+// wavefront, then the wavefront results through LDS (two barriers; the
+// second frees wbuf for the next call).  Both are exact, so their order is
+// immaterial.
+template <int NT>
+__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t* wbuf) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t u = __shfl_xor(v, o, 64);
+    v = u < v ? u : v;
+  }
+  if ((threadIdx.x & 63) == 0) wbuf[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t r = wbuf[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) r = wbuf[w] < r ? wbuf[w] : r;
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t* wbuf) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) wbuf[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t r = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) r += wbuf[w];
+  __syncthreads();
+  return r;
+}
+
 __global__ __launch_bounds__(kB) void k_sched_minc(const int64_t* __restrict__ t_tick,
                                                    const int32_t* __restrict__ level, int64_t n, int max_level,
                                                    int ppt, int64_t* __restrict__ block_min,
                                                    int32_t* __restrict__ block_cnt) {
-  __shared__ int64_t red[kB];
-  __shared__ int cnt[kB];
+  __shared__ int64_t wbuf[kB / 64];
   int64_t m = INT64_MAX;
   const int64_t base = (int64_t)blockIdx.x * kB * ppt;
   for (int r = 0; r < ppt; ++r) {
@@ -139,30 +171,16 @@ __global__ __launch_bounds__(kB) void k_sched_minc(const int64_t* __restrict__ t
     const int64_t te = i < n ? t_end_of(t_tick, level, i, max_level) : INT64_MAX;
     m = te < m ? te : m;
   }
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const int64_t b = red[threadIdx.x + o];
-      if (b < red[threadIdx.x]) red[threadIdx.x] = b;
-    }
-    __syncthreads();
-  }
-  const int64_t bm = red[0];
-  int c = 0;
+  const int64_t bm = block_min_i64<kB>(m, wbuf);
+  int64_t c = 0;
   for (int r = 0; r < ppt; ++r) {
     const int64_t i = base + r * kB + threadIdx.x;
     c += (i < n && t_end_of(t_tick, level, i, max_level) == bm) ? 1 : 0;
   }
-  cnt[threadIdx.x] = c;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) cnt[threadIdx.x] += cnt[threadIdx.x + o];
-    __syncthreads();
-  }
+  const int64_t bc = block_sum_i64<kB>(c, wbuf);
   if (threadIdx.x == 0) {
     block_min[blockIdx.x] = bm;
-    block_cnt[blockIdx.x] = cnt[0];
+    block_cnt[blockIdx.x] = (int32_t)bc;
   }
 }
 
@@ -173,32 +191,18 @@ __global__ __launch_bounds__(kB) void k_sched_write(const int64_t* __restrict__ 
                                                     int32_t* __restrict__ active, int64_t* __restrict__ sched,
                                                     int32_t* __restrict__ n_active32, int64_t t_stop_host,
                                                     const int64_t* __restrict__ t_stop_dev, PredictArgs pred) {
-  __shared__ int64_t red[kB];
-  __shared__ int64_t sc[kB];
+  __shared__ int64_t wbuf[kB / 64];
   __shared__ int wc[kB / 64];
   // the global minimum, then this block's offset (earlier blocks reaching
-  // it) and the total count, both in a fixed order
+  // it); both exact, so independent of the order of the partial results
   int64_t m = INT64_MAX;
   for (int b = threadIdx.x; b < nblk; b += kB) m = block_min[b] < m ? block_min[b] : m;
-  red[threadIdx.x] = m;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o && red[threadIdx.x + o] < red[threadIdx.x]) red[threadIdx.x] = red[threadIdx.x + o];
-    __syncthreads();
-  }
-  const int64_t t_next = red[0];
+  const int64_t t_next = block_min_i64<kB>(m, wbuf);
   const bool last_block = blockIdx.x == (unsigned)(nblk - 1);
   int64_t part = 0;
   for (int b = threadIdx.x; b < (int)blockIdx.x; b += kB)
     if (block_min[b] == t_next) part += block_cnt[b];
-  sc[threadIdx.x] = part;
-  __syncthreads();
-  for (int o = kB / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
-    __syncthreads();
-  }
-  int64_t off = sc[0];
-  __syncthreads();
+  int64_t off = block_sum_i64<kB>(part, wbuf);
   const int64_t base = (int64_t)blockIdx.x * kB * ppt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int r = 0; r < ppt; ++r) {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kSchedSingleThreads) void k_sched_single(const int6
                                                                       const int64_t* __restrict__ t_stop_dev,
                                                                       PredictArgs pred) {
   constexpr int W = kSchedSingleThreads / 64;
-  __shared__ int64_t red[kSchedSingleThreads];
+  __shared__ int64_t wbuf[W];
   __shared__ int wc[W];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   int64_t m = INT64_MAX;
@@ -253,13 +257,7 @@ __global__ __launch_bounds__(kSchedSingleThreads) void k_sched_single(const int6
     const int64_t te = t_end_of(t_tick, level, i, max_level);
     m = te < m ? te : m;
   }
-  red[t] = m;
-  __syncthreads();
-  for (int o = kSchedSingleThreads / 2; o > 0; o >>= 1) {
-    if (t < o && red[t + o] < red[t]) red[t] = red[t + o];
-    __syncthreads();
-  }
-  const int64_t t_next = red[0];
+  const int64_t t_next = block_min_i64<kSchedSingleThreads>(m, wbuf);
   int64_t off = 0;
   for (int64_t base = 0; base < n; base += kSchedSingleThreads) {
     const int64_t i = base + t;
