@@ -17,6 +17,9 @@ shape run costs about one empty launch in every step.  After the sweep, a
 run of buckets takes a neighbouring run's shape when that costs it at most
 ``launch_ms`` at each of its buckets: a step's count falls in one bucket, so
 the switch loses at most that much in a step and always saves one launch.
+A single bucket likewise takes another shape when that alone saves a launch
+(e.g. a shape of one kernel family where its fastest keeps two families
+apart).
 
     python -m paper_1409_5474_amd.autotune --n 65536 262144 --out tuning.json
 
@@ -130,11 +133,44 @@ def _launch_runs(choice):
     return runs
 
 
+def _merge_buckets(choice, times, launch_ms):
+    """One bucket at a time: a bucket takes another of its timed shapes when
+    that lowers the number of launch runs at a cost of at most launch_ms
+    (the cheapest such change first, repeated until none fits) -- e.g. the
+    one bucket whose shape keeps two kernel families from sharing a launch."""
+    choice = list(choice)
+    while True:
+        n_runs = len(_launch_runs(choice))
+        best = None
+        for b, t in enumerate(times):
+            for sh, ms in t.items():
+                pen = ms - t[choice[b]]
+                if sh == choice[b] or pen > launch_ms or (best is not None and pen >= best[0]):
+                    continue
+                if len(_launch_runs(choice[:b] + [sh] + choice[b + 1:])) < n_runs:
+                    best = (pen, b, sh)
+        if best is None:
+            return choice
+        choice[best[1]] = best[2]
+
+
 def _merge_shapes(choice, times, launch_ms):
     """choice[b]: the shape of bucket b; times[b]: {shape: best ms}.  Returns
     the choice after merging launch runs into neighbours (see module doc): a
     run whose buckets all take the shape of the neighbouring run's nearest
-    bucket at a cost of at most launch_ms each saves one launch per step."""
+    bucket at a cost of at most launch_ms each saves one launch per step;
+    then single buckets as in _merge_buckets, and again until neither
+    changes anything.  Every change saves a launch and costs a bucket at
+    most launch_ms, so no bucket loses more than the launches saved."""
+    while True:
+        merged = _merge_runs(choice, times, launch_ms)
+        merged = _merge_buckets(merged, times, launch_ms)
+        if merged == list(choice):
+            return merged
+        choice = merged
+
+
+def _merge_runs(choice, times, launch_ms):
     choice = list(choice)
     while True:
         runs = _launch_runs(choice)

@@ -83,6 +83,22 @@ def test_shape_runs_merge_only_within_the_launch_cost():
     assert _merge_shapes([A, (2, 0)], t2, 5) == [A, A]
 
 
+def test_one_bucket_changes_shape_when_that_alone_saves_a_launch():
+    # K = 4, L = 4 (family 4) between K = 1 shapes and the K = 2 shapes of
+    # family 2 keeps two launches per step; the bucket takes its best family-2
+    # shape when that costs at most one launch, and keeps its own otherwise.
+    from paper_1409_5474_amd.autotune import _merge_shapes, _launch_runs
+    K1a, K1b, K44, K24, K21 = (1, 64), (1, 4), (4, 4), (2, 4), (2, 1)
+    fastest = [K1a, K1b, K44, K24, K21]
+    assert len(_launch_runs(fastest)) == 2
+    def times_with(pen):
+        return [{K1a: 10, K1b: 12}, {K1a: 20, K1b: 15}, {K44: 50, K1b: 50 + pen, K24: 50 + 2 * pen, K1a: 90},
+                {K24: 100, K21: 104}, {K21: 400, K24: 420}]
+    got = _merge_shapes(fastest, times_with(1.5), 3)
+    assert got == [K1a, K1b, K1b, K24, K21] and len(_launch_runs(got)) == 1
+    assert _merge_shapes(fastest, times_with(4), 3) == fastest
+
+
 def test_shapes_one_family_holds_share_a_launch():
     # LDS shapes of one kernel family run in one device-count launch, so the
     # merge keeps each bucket's fastest shape there
