@@ -168,7 +168,9 @@ int nb_tune_add(nb_ctx *ctx, int precision, int64_t n_min, int64_t act_min, int6
  * active rows per system, ceil(total active / C); kind 2 keys
  * nb_block_step_batch by the mean system size, ceil(N / C).  Later entries
  * take precedence.  Without an entry the batch takes K = 1 and the LDS
- * layout nearest the single-system table's L for the mean size.
+ * layout nearest the single-system table's L for the mean size.  A batch
+ * with any unsoftened system (eps2[c] = 0) runs the entry's L with K = 1
+ * (the masked kernels hold one i-particle per lane).
  * nb_get_batch_launch reports the shape for a key (N = total rows).
  * Errors: NB_EINVAL for a bad kind, range or K, NB_ENOTSUP for a shape the
  * library does not build.  nb_tune_clear empties both tables. */

@@ -1205,6 +1205,7 @@ int nbody_forces_batch(nb_ctx* c, const int64_t* offsets, int64_t C, const doubl
   if (!pos || !vel || !mass || !active || !acc || !jerk || !pot) return fail(c, NB_EINVAL, "null pointer argument%s");
   // One kernel shape for the batch, from the mean active rows per system.
   Launch cfg = choose_batch(c, 1, (a_total + C - 1) / C, n_total, (a_total + C - 1) / C);
+  if (any_mask) cfg.K = 1;  // an unsoftened system: the masked kernels hold one i-particle per lane
   if (cfg.L == 0) cfg.WG = nb::kBatchSjWG;
   log_launch(c, "batch forces", cfg, n_total, a_total);
   const int IB = nb::ib_of(cfg);
@@ -1338,6 +1339,7 @@ extern "C" int nb_block_step_batch(nb_ctx* c, const int64_t* offsets, int64_t C,
   if (rc) return rc;
   // one kernel shape for the batch, from the mean system size
   Launch cfg = choose_batch(c, 2, (N + C - 1) / C, N, (N + C - 1) / C);
+  if (any_mask) cfg.K = 1;  // as in nbody_forces_batch
   if (cfg.L == 0) cfg.WG = nb::kBatchSjWG;
   log_launch(c, "batch block step", cfg, N, N);
   const int IB = nb::ib_of(cfg);

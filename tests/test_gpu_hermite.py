@@ -291,3 +291,47 @@ def test_batch_matches_oracle(nb, prec, shape):
         else:
             check_mixed((A[rows], J[rows], Pt[rows]), ref)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,shape", [("fp64", None), ("fp64", (2, 1)), ("mixed", None), ("mixed", (2, 0)),
+                                        ("mixed", (2, 4))])
+def test_batch_with_an_unsoftened_system(nb, prec, shape):
+    # One system with eps2 = 0 among softened ones: the batch runs the masked
+    # kernels (one i-particle per lane) whatever K the table gives, for the
+    # all-active call and for a batched block step.
+    import torch
+    ctx = nb.Context(0, prec)
+    if shape is not None:
+        ctx.tune_add_batch(prec, 1, 1, 2 ** 40, *shape)
+        ctx.tune_add_batch(prec, 2, 1, 2 ** 40, *shape)
+    b = synth.cluster_batch(seed=6, n_clusters=5, n_min=300, n_max=4000)
+    eps2 = b.eps2.copy()
+    eps2[2] = 0.0
+    n = int(b.offsets[-1])
+    act = np.arange(n, dtype=np.int32)
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda"); jerk = torch.empty_like(acc)
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.forces_batch(b.offsets, eps2, T(b.pos), T(b.vel), T(b.mass), T(act), b.offsets, acc, jerk, pot)
+    A, J, Pt = N(acc), N(jerk), N(pot)
+    for c in range(5):
+        lo, hi = b.offsets[c], b.offsets[c + 1]
+        ref = oracle.forces_ld(b.pos[lo:hi], b.vel[lo:hi], b.mass[lo:hi], eps2[c], act[lo:hi] - lo)
+        res = (A[lo:hi], J[lo:hi], Pt[lo:hi])
+        if prec == "fp64":
+            check_fp64(res, ref)
+        elif eps2[c] > 0:
+            check_mixed(res, ref)
+        else:
+            # unsoftened: a row's float rounding is bounded by its terms'
+            # magnitudes (the single-system unsoftened gate)
+            for name, got in zip(("acc", "jerk", "pot"), res):
+                err = np.abs(got - ref[name]) if got.ndim == 1 else np.linalg.norm(got - ref[name], axis=1)
+                assert (err <= 64 * 2.0 ** -24 * ref["abs_" + name]).all(), name
+    # a batched block step over the same systems runs too
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    bi = BlockIntegrator(ctx, T(b.pos), T(b.vel), T(b.mass), eps2, 0.02, 1.0 / 16, 30, offsets=b.offsets)
+    for _ in range(3):
+        bi.step()
+    ctx.sync()
+    assert bi.steps == 3 and torch.isfinite(bi.pos).all()
+    ctx.close()
