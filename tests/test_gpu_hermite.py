@@ -258,7 +258,7 @@ def test_devcount_matches_host_count(ctx, prec, n):
 
 
 @pytest.mark.parametrize("shape", [None, (1, 0), (2, 0), (2, 4)], ids=["table", "sj1", "sj2", "lds2x4"])
-@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_ds"])
 def test_batch_matches_oracle(nb, prec, shape):
     # every batched kernel shape (default choice, the scalar j-path with one
     # or two i-particles per lane, the LDS layout) on its own context
@@ -294,7 +294,7 @@ def test_batch_matches_oracle(nb, prec, shape):
 
 
 @pytest.mark.parametrize("prec,shape", [("fp64", None), ("fp64", (2, 1)), ("mixed", None), ("mixed", (2, 0)),
-                                        ("mixed", (2, 4))])
+                                        ("mixed", (2, 4)), ("mixed_ds", None), ("mixed_ds", (2, 0))])
 def test_batch_with_an_unsoftened_system(nb, prec, shape):
     # One system with eps2 = 0 among softened ones: the batch runs the masked
     # kernels (one i-particle per lane) whatever K the table gives, for the
