@@ -6,6 +6,7 @@ import pytest
 
 import oracle
 import synth
+from errors import check_mixed
 from oracle import hermite as H
 
 pytestmark = pytest.mark.gpu
@@ -22,6 +23,10 @@ def ctx():
 def T(x):
     import torch
     return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def N(t):
+    return t.cpu().numpy()
 
 
 def _cpu_run(p, eps2, eta, dt_max, ML, t_end):
@@ -210,4 +215,50 @@ def test_unsoftened_kepler_orbit_follows_the_oracle(use_graph):
     E = g.energy()["E"]
     assert abs(E - (-0.125)) < 1e-6
     ctx.sync()
+    ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 0), (1, 16)], ids=["sj1", "lds1x16"])
+def test_batch_with_empty_systems_and_inactive_systems(shape):
+    # Empty systems (first, between and last) add no work, so with one shape
+    # forced the batch gives the same bits as the batch without them: the
+    # all-active call (one system also with no active rows there) and
+    # graph-replayed block steps.
+    import torch
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd.integrator import BlockIntegrator
+    b = synth.cluster_batch(seed=9, n_clusters=3, n_min=200, n_max=1500)
+    sizes = np.diff(b.offsets)
+    full = np.array([0, 0, sizes[0], sizes[0], sizes[0] + sizes[1], sizes[:3].sum(), sizes[:3].sum()], dtype=np.int64)
+    eps_full = np.array([1e-3, b.eps2[0], 2e-3, b.eps2[1], b.eps2[2], 5e-4])
+    ctx = nb.Context(0, "mixed")
+    for kind in (1, 2):
+        ctx.tune_add_batch("mixed", kind, 1, 2 ** 40, *shape)
+    n = int(b.offsets[-1])
+    # all-active call, system 2 of the compact batch without active rows
+    act = np.concatenate([np.arange(0, sizes[0]), np.arange(sizes[0] + sizes[1], n)]).astype(np.int32)
+    act_off = np.array([0, sizes[0], sizes[0], act.size], dtype=np.int64)
+    act_off_full = np.array([0, 0, sizes[0], sizes[0], sizes[0], act.size, act.size], dtype=np.int64)
+    outs = []
+    for offs, eps, aoff in ((b.offsets, b.eps2, act_off), (full, eps_full, act_off_full)):
+        acc = torch.empty((act.size, 3), dtype=torch.float64, device="cuda"); jerk = torch.empty_like(acc)
+        pot = torch.empty(act.size, dtype=torch.float64, device="cuda")
+        ctx.forces_batch(offs, eps, T(b.pos), T(b.vel), T(b.mass), T(act), aoff, acc, jerk, pot)
+        outs.append((acc, jerk, pot))
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(*outs))
+    for c, rows in ((0, slice(0, sizes[0])), (2, slice(sizes[0], act.size))):
+        lo, hi = b.offsets[c], b.offsets[c + 1]
+        ref = oracle.forces_ld(b.pos[lo:hi], b.vel[lo:hi], b.mass[lo:hi], b.eps2[c], act[rows] - lo)
+        check_mixed(tuple(N(o)[rows] for o in outs[0]), ref)
+    # block steps
+    runs = []
+    for offs, eps in ((b.offsets, b.eps2), (full, eps_full)):
+        bi = BlockIntegrator(ctx, T(b.pos), T(b.vel), T(b.mass), eps, 0.02, 1.0 / 16, 30, offsets=offs)
+        bi.run_until(1.0 / 16, graph_steps=8)
+        runs.append(bi)
+    ctx.sync()
+    assert runs[0].steps == runs[1].steps > 0
+    for k in ("pos", "vel", "t_tick", "level"):
+        assert torch.equal(getattr(runs[0], k), getattr(runs[1], k)), k
     ctx.close()
