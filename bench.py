@@ -79,8 +79,13 @@ def spread(xs):
     return {"median": round(med, 4), "min": round(ys[0], 4), "max": round(ys[-1], 4)}
 
 
+# vector-ISA flags that bear on the oracle's speed
+CPU_ISA_FLAGS = ("sse4_2", "avx", "avx2", "fma", "avx512f", "avx512dq", "avx512vl", "avx512_bf16")
+
+
 def cpu_model():
-    """The host CPU's model name and logical CPU count, from lscpu."""
+    """The host CPU's model name, logical CPU count, threads per core and the
+    vector-ISA flags among CPU_ISA_FLAGS that it reports, from lscpu."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -90,8 +95,10 @@ def cpu_model():
     for ln in out.splitlines():
         k, _, v = ln.partition(":")
         info[k.strip()] = v.strip()
+    flags = set(info.get("Flags", "").split())
     return {"model": info.get("Model name"), "logical_cpus": info.get("CPU(s)"),
-            "threads_per_core": info.get("Thread(s) per core")}
+            "threads_per_core": info.get("Thread(s) per core"),
+            "isa_flags": [f for f in CPU_ISA_FLAGS if f in flags]}
 
 
 class ClockSampler:
