@@ -1,6 +1,7 @@
 """GPU parity of the Hermite block-step kernels (predict, correct, start-up
 levels, scheduler, energy, whole block steps, graph replay) and of the
-batched and device-count force launches, against the CPU oracle."""
+batched and device-count force launches, against the CPU oracle; batches in
+every precision and shape, with an unsoftened system among softened ones."""
 import numpy as np
 import pytest
 

@@ -1,6 +1,8 @@
 """GPU integrator driver: graph replay equals eager stepping; block steps
 of a single system and of a batch of independent systems follow the CPU
-oracle's Hermite runs (per system) with no level flips."""
+oracle's Hermite runs (per system) with no level flips, unsoftened too (a
+two-body orbit); empty systems and systems without active rows leave a
+batch's bits unchanged; checkpoints resume bit for bit."""
 import numpy as np
 import pytest
 
