@@ -136,3 +136,21 @@ def test_phase_times_cover_the_step():
         assert all(x > 0 for x in ms)
         assert sum(ms) <= total * 1.05 + 0.01
     ctx.close()
+
+
+def test_nb_tune_cache_names_the_table_a_context_loads(monkeypatch, tmp_path):
+    # a table with one distinctive entry: a context created with NB_TUNE_CACHE
+    # naming it launches that shape; without the variable, the shipped table
+    import paper_1409_5474_amd as nb
+    from paper_1409_5474_amd import autotune
+    path = tmp_path / "cache.json"
+    autotune.save([dict(prec="fp64", n_min=1000, act_min=0, act_max=2 ** 31 - 1, K=1, L=64, items=96)], str(path))
+    monkeypatch.setenv("NB_TUNE_CACHE", str(path))
+    ctx = nb.Context(0, "fp64")
+    assert ctx.tuning_table == str(path)
+    assert ctx.get_launch(5000, 3000)[:2] == (1, 64)
+    ctx.close()
+    monkeypatch.delenv("NB_TUNE_CACHE")
+    ctx = nb.Context(0, "fp64")
+    assert ctx.tuning_table == autotune.DEFAULT_TABLE
+    ctx.close()
