@@ -336,3 +336,42 @@ def test_batch_with_an_unsoftened_system(nb, prec, shape):
     ctx.sync()
     assert bi.steps == 3 and torch.isfinite(bi.pos).all()
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 4), (2, 1), (1, 16)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_equals_per_cluster_calls_bit_for_bit(nb, prec, shape):
+    # In the LDS layout the batch cuts each system's j-range with the common
+    # chunk length J = ceil(work / (IB x 8 x CUs) / T) x T (work = sum over
+    # systems of the i-slots x j) into S_c = min(max(1, ceil(nj/J)), ceil(nj/T))
+    # chunks; each cluster computed alone with the same (K, L, S_c) gives the
+    # same bits, its sums being formed in the same order.
+    import math
+    import torch
+    K, L = shape
+    ctx = nb.Context(0, prec)
+    ctx.tune_add_batch(prec, 1, 1, 2 ** 40, K, L)
+    b = synth.cluster_batch(seed=12, n_clusters=6, n_min=300, n_max=6000)
+    n = int(b.offsets[-1])
+    act = np.arange(n, dtype=np.int32)
+    acc = torch.empty((n, 3), dtype=torch.float64, device="cuda"); jerk = torch.empty_like(acc)
+    pot = torch.empty(n, dtype=torch.float64, device="cuda")
+    ctx.forces_batch(b.offsets, b.eps2, T(b.pos), T(b.vel), T(b.mass), T(act), b.offsets, acc, jerk, pot)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    IB, tile = (256 // L) * K, 256
+    sizes = np.diff(b.offsets)
+    work = float(sum(-(-int(s) // IB) * IB * int(s) for s in sizes))
+    J = max(tile, math.ceil(work / (IB * 8.0 * cus) / tile) * tile)
+    splits = []
+    for c, nj in enumerate(sizes):
+        nj = int(nj)
+        S = max(1, min(-(-nj // J), -(-nj // tile)))
+        splits.append(S)
+        lo, hi = b.offsets[c], b.offsets[c + 1]
+        ctx.set_launch(K, L, S)
+        a1, j1, p1 = ctx.forces(T(b.pos[lo:hi]), T(b.vel[lo:hi]), T(b.mass[lo:hi]),
+                                T(np.arange(nj, dtype=np.int32)), float(b.eps2[c]))
+        torch.cuda.synchronize()
+        assert torch.equal(a1, acc[lo:hi]) and torch.equal(j1, jerk[lo:hi]) and torch.equal(p1, pot[lo:hi]), (c, S)
+    assert max(splits) > 1   # the case exercises the chunk sums
+    ctx.close()
